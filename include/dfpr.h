@@ -1,0 +1,161 @@
+/*
+ * dfpr — Dynamic Frontier PageRank on MI355X (gfx950).
+ *
+ * C ABI of the GPU library.  It implements the incremental PageRank update of
+ * Sahu, "DF* PageRank: Improved Incrementally Expanding Approaches for Updating
+ * PageRank on Dynamic Graphs" (arXiv 2401.15870): apply a batch of edge
+ * deletions and insertions to a graph held in device memory, then update the
+ * ranks from the previous ranks with Static, Naive-dynamic (ND), Dynamic
+ * Frontier (DF) or Dynamic Frontier with Pruning (DF-P).
+ *
+ * Conventions shared by every call:
+ *  - Every function returns an int status: DFPR_OK (0) or a negative error
+ *    code.  Nothing throws across the ABI.  dfpr_last_error() returns a
+ *    thread-local message describing the last failing call on this thread.
+ *  - Vertex ids are int32 in [0, n).  Ranks are IEEE binary64 (FP64).
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *    device work is enqueued on it.  dfpr_update_ranks returns only once its
+ *    outputs are final; create, apply and export return once their work is
+ *    complete on the stream.
+ *  - Pointers marked DFPR_HOST / DFPR_DEVICE by a `where` argument point to
+ *    host memory or to device memory of the current HIP device.  Input
+ *    pointers are borrowed for the duration of the call only; the library
+ *    copies what it keeps.
+ *  - Validation happens before mutation: on DFPR_EINVAL or DFPR_ERANGE the
+ *    graph is unchanged.  A HIP runtime failure returns DFPR_EHIP and poisons
+ *    the handle; later calls on it return DFPR_ESTATE.
+ *  - One writer per handle: calls on the same handle are serialised by an
+ *    internal mutex.  Different handles may be used from different threads.
+ */
+#ifndef DFPR_H
+#define DFPR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  DFPR_OK = 0,
+  DFPR_EINVAL = -1, /* bad argument: null pointer with count > 0, n <= 0, bad parameter */
+  DFPR_ERANGE = -2, /* a vertex id outside [0, n) */
+  DFPR_ENOMEM = -3, /* device or host allocation failed; the handle stays usable */
+  DFPR_EHIP = -4,   /* HIP runtime failure; the handle is poisoned */
+  DFPR_ESTATE = -5  /* the handle was poisoned by an earlier failure */
+};
+
+typedef enum { DFPR_STATIC = 0, DFPR_ND = 1, DFPR_DF = 2, DFPR_DFP = 3 } dfpr_mode;
+typedef enum { DFPR_HOST = 0, DFPR_DEVICE = 1 } dfpr_where;
+
+/* Parameters of the rank update (Section 5.1.2 and Sections 4.2-4.3).
+ * alpha: damping factor in (0,1).  tol: iteration tolerance on the L-inf norm
+ * of the rank change (> 0).  frontier_tol (tau_f): a processed vertex marks its
+ * out-neighbours when its relative change exceeds it.  prune_tol (tau_p): DF-P
+ * unmarks a processed vertex whose relative change is at most this.
+ * max_iters >= 1.  flags: DFPR_FLAG_* bits. */
+typedef struct {
+  double alpha, tol, frontier_tol, prune_tol;
+  int32_t max_iters;
+  int32_t flags;
+} dfpr_params;
+
+/* flags: record per-phase and per-kernel timings with HIP events into dfpr_stats. */
+#define DFPR_FLAG_TIMING 1
+
+/* Effective-batch counts of one dfpr_apply_batch call (Section 3.2). */
+typedef struct {
+  int64_t ins_in, ins_effective;   /* insertions given; of those, new edges      */
+  int64_t del_in, del_effective;   /* deletions given; of those, removed edges   */
+  int64_t self_loop_dels_ignored;  /* distinct (v,v) deletions (self-loops stay) */
+  int64_t m_after;                 /* |E| after the update, self-loops included  */
+} dfpr_batch_info;
+
+/* Result statistics of one dfpr_update_ranks call.  The pull work is split in
+ * three degree bins (see dfpr_set_tuning): [0] one vertex per lane, [1] one
+ * vertex per wavefront, [2] rows split in chunks over workgroups. */
+typedef struct {
+  int32_t iterations;       /* rank iterations run (the one that met tol counts)  */
+  int32_t converged;        /* 1 if the L-inf change fell to tol, 0 at max_iters  */
+  double last_delta;        /* L-inf rank change of the last iteration            */
+  int64_t ever_affected;    /* vertices processed in at least one iteration       */
+  int64_t vertex_updates;   /* sum over iterations of the affected-set size       */
+  int64_t edges_pulled;     /* sum over iterations of the affected in-degrees     */
+  int64_t bin_vertices[3];  /* vertex_updates split by bin                        */
+  int64_t bin_edges[3];     /* edges_pulled split by bin                          */
+  double ms_total;          /* time of the call on the stream (TIMING flag)       */
+  double ms_pull[3];        /* summed duration of each bin's pull kernel (TIMING) */
+  int32_t pull_launches[3]; /* launches timed in ms_pull (TIMING flag)            */
+  int32_t reserved;
+} dfpr_stats;
+
+typedef struct dfpr_graph dfpr_graph;
+
+/* Paper defaults: alpha 0.85, tol 1e-10, tau_f = tau_p = 1e-6, 500 iterations
+ * (Section 5.1.2; Sections 4.2-4.3). */
+void dfpr_params_default(dfpr_params* p);
+
+/* Create a graph on the current HIP device from a COO edge list of m pairs.
+ * The stored graph is canonical: duplicate pairs are dropped and a self-loop is
+ * added to every vertex (Sections 3.1 and 5.1.3), so |E| counts them.  The
+ * handle owns all its device memory (both CSRs, their rebuild buffers and the
+ * rank scratch), allocated here so that later updates allocate nothing unless a
+ * batch outgrows the edge capacity.  edge_capacity (0 = automatic) reserves room
+ * for that many edges.  Errors: EINVAL (n <= 0, m < 0, null arrays with m > 0,
+ * n or m beyond int32), ERANGE (an id outside [0,n)), ENOMEM, EHIP. */
+int dfpr_graph_create(int32_t n, int64_t m, const int32_t* src, const int32_t* dst,
+                      dfpr_where where, int64_t edge_capacity, void* stream, dfpr_graph** out);
+
+int dfpr_graph_destroy(dfpr_graph* g);
+
+/* |V| and |E| (self-loops included). */
+int dfpr_graph_size(const dfpr_graph* g, int32_t* n, int64_t* m);
+
+/* Copy the current canonical CSR out.  in_csr = 0: out-adjacency (row u lists
+ * out(u) ascending); in_csr = 1: in-adjacency (row v lists in(v) ascending).
+ * offsets has n+1 entries, indices m entries (m from dfpr_graph_size). */
+int dfpr_graph_export(const dfpr_graph* g, int in_csr, int32_t* offsets, int32_t* indices,
+                      dfpr_where where, void* stream);
+
+/* Apply one batch update (Section 3.2).  Deletions and insertions are read as
+ * sets: repeated pairs count once, a pair both deleted and inserted is present
+ * afterwards, deleting (v,v) is ignored, inserting an existing edge or deleting
+ * an absent one has no effect.  Both CSRs are rebuilt (canonical form).  The
+ * sources of the effective changes and the targets of effective deletions are
+ * remembered until the next DF/DF-P update, which marks out(u) of every such
+ * source u in the old and new graph (Algorithm 1, initial marking).
+ * info may be NULL.  Errors: EINVAL, ERANGE (graph unchanged), ENOMEM, EHIP. */
+int dfpr_apply_batch(dfpr_graph* g, int64_t n_del, const int32_t* del_src, const int32_t* del_dst,
+                     int64_t n_ins, const int32_t* ins_src, const int32_t* ins_dst,
+                     dfpr_where where, void* stream, dfpr_batch_info* info);
+
+/* Update ranks (Algorithm 1; Equations 1 and 2).  r_prev and r_out are device
+ * arrays of n doubles owned by the caller; they may alias.  STATIC ignores
+ * r_prev and starts from 1/n; ND processes every vertex from r_prev; DF and
+ * DF-P process the frontier grown from the pending batch marks.  Iterations are
+ * synchronous: all reads of iteration i see the ranks of iteration i.  p = NULL
+ * uses dfpr_params_default.  Non-convergence within max_iters is not an error
+ * (stats->converged = 0).  st may be NULL.  STATIC and ND discard pending marks;
+ * DF and DF-P consume them.  Errors: EINVAL (bad mode or parameters, null
+ * arrays), ENOMEM, EHIP. */
+int dfpr_update_ranks(dfpr_graph* g, dfpr_mode mode, const dfpr_params* p, const double* r_prev,
+                      double* r_out, void* stream, dfpr_stats* st);
+
+/* Degree thresholds of the pull kernels: vertices with in-degree <= t_thread
+ * are processed one per lane, up to t_wave one per wavefront, larger ones one
+ * per workgroup.  0 keeps the current value.  EINVAL unless
+ * 1 <= t_thread <= t_wave. */
+int dfpr_set_tuning(dfpr_graph* g, int32_t t_thread, int32_t t_wave);
+int dfpr_get_tuning(const dfpr_graph* g, int32_t* t_thread, int32_t* t_wave);
+
+/* Thread-local message for the last failing call on this thread ("" if none). */
+const char* dfpr_last_error(void);
+
+/* Library version string. */
+const char* dfpr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DFPR_H */

@@ -1,0 +1,165 @@
+"""Dynamic Frontier PageRank (DF / DF-P) on MI355X: Python binding of libdfpr.
+
+Thin marshalling over the C ABI declared in include/dfpr.h: every step of the
+update (batch sort and CSR rebuild, marking, pull iterations, expansion and
+pruning, the L-inf reduction) runs in the library's HIP kernels.  torch is used
+only for device memory (rank vectors, device-resident edge arrays) and streams.
+
+    import paper_2401_15870_amd as dfpr
+    g = dfpr.Graph.from_coo(n, src, dst)                 # numpy or torch int32
+    info = g.apply_batch(del_src, del_dst, ins_src, ins_dst)
+    r, st = g.update_ranks("dfp", r_prev)                 # torch float64 on the GPU
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _capi
+from ._capi import BatchInfo, Params, Stats
+
+MODES = {"static": _capi.STATIC, "nd": _capi.ND, "df": _capi.DF, "dfp": _capi.DFP}
+ERRORS = {_capi.DFPR_EINVAL: "EINVAL", _capi.DFPR_ERANGE: "ERANGE", _capi.DFPR_ENOMEM: "ENOMEM",
+          _capi.DFPR_EHIP: "EHIP", _capi.DFPR_ESTATE: "ESTATE"}
+
+
+class DfprError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def lib():
+    return _capi.load()
+
+
+def _check(rc):
+    if rc != _capi.DFPR_OK:
+        raise DfprError(rc, lib().dfpr_last_error().decode(errors="replace"))
+
+
+def _stream_ptr(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ids(a):
+    """(pointer, count, where, keepalive) for an int32 edge array (numpy/list or torch)."""
+    try:
+        import torch
+        if isinstance(a, torch.Tensor):
+            if a.dtype != torch.int32:
+                a = a.to(torch.int32)
+            a = a.contiguous()
+            return ctypes.c_void_p(a.data_ptr()), a.numel(), (_capi.DEVICE if a.is_cuda else _capi.HOST), a
+    except ImportError:
+        pass
+    arr = np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+    return ctypes.c_void_p(arr.ctypes.data if arr.size else 0), arr.size, _capi.HOST, arr
+
+
+def default_params() -> Params:
+    p = Params()
+    lib().dfpr_params_default(ctypes.byref(p))
+    return p
+
+
+class Graph:
+    """A graph held in device memory (canonical in- and out-CSR, self-loop on every vertex)."""
+
+    def __init__(self, handle, n):
+        self._h = handle
+        self.n = n
+
+    @classmethod
+    def from_coo(cls, n, src, dst, edge_capacity=0, stream=None):
+        ps, ms, ws, ks = _ids(src)
+        pd, md, wd, kd = _ids(dst)
+        if ms != md or ws != wd:
+            raise ValueError("src and dst must have the same length and location")
+        h = ctypes.c_void_p()
+        _check(lib().dfpr_graph_create(int(n), int(ms), ps, pd, ws, int(edge_capacity), _stream_ptr(stream),
+                                       ctypes.byref(h)))
+        return cls(h, int(n))
+
+    def close(self):
+        if self._h:
+            lib().dfpr_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 - interpreter shutdown
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def m(self) -> int:
+        n = ctypes.c_int32()
+        m = ctypes.c_int64()
+        _check(lib().dfpr_graph_size(self._h, ctypes.byref(n), ctypes.byref(m)))
+        return int(m.value)
+
+    def export(self, in_csr=False, stream=None):
+        """Canonical CSR as numpy arrays (offsets[n+1], indices[m])."""
+        off = np.empty(self.n + 1, np.int32)
+        idx = np.empty(max(self.m, 1), np.int32)
+        _check(lib().dfpr_graph_export(self._h, 1 if in_csr else 0, ctypes.c_void_p(off.ctypes.data),
+                                       ctypes.c_void_p(idx.ctypes.data), _capi.HOST, _stream_ptr(stream)))
+        return off, idx[: self.m]
+
+    def apply_batch(self, del_src=(), del_dst=(), ins_src=(), ins_dst=(), stream=None) -> dict:
+        a, nds, w1, k1 = _ids(del_src)
+        b, ndd, w2, k2 = _ids(del_dst)
+        c, nis, w3, k3 = _ids(ins_src)
+        d, nid, w4, k4 = _ids(ins_dst)
+        if nds != ndd or nis != nid:
+            raise ValueError("src/dst length mismatch")
+        wheres = {w for w, k in ((w1, nds), (w3, nis)) if k}
+        if len(wheres) > 1:
+            raise ValueError("deletions and insertions must live in the same memory")
+        where = wheres.pop() if wheres else _capi.HOST
+        info = BatchInfo()
+        _check(lib().dfpr_apply_batch(self._h, nds, a, b, nis, c, d, where, _stream_ptr(stream), ctypes.byref(info)))
+        return info.as_dict()
+
+    def update_ranks(self, mode, r_prev=None, out=None, stream=None, timing=False, **kw):
+        """Run Static / ND / DF / DF-P.  r_prev and out are float64 CUDA tensors of n entries."""
+        import torch
+        m = MODES[mode] if isinstance(mode, str) else int(mode)
+        p = default_params()
+        for k, v in kw.items():
+            setattr(p, k, v)
+        if timing:
+            p.flags |= _capi.FLAG_TIMING
+        if out is None:
+            out = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        for t in (out, r_prev):
+            if t is not None and (t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous()
+                                  or t.numel() != self.n):
+                raise ValueError("rank vectors must be contiguous float64 CUDA tensors of n entries")
+        st = Stats()
+        rp = ctypes.c_void_p(r_prev.data_ptr()) if r_prev is not None else None
+        _check(lib().dfpr_update_ranks(self._h, m, ctypes.byref(p), rp, ctypes.c_void_p(out.data_ptr()),
+                                       _stream_ptr(stream), ctypes.byref(st)))
+        return out, st.as_dict()
+
+    def set_tuning(self, t_thread=0, t_wave=0):
+        _check(lib().dfpr_set_tuning(self._h, int(t_thread), int(t_wave)))
+
+    def get_tuning(self):
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().dfpr_get_tuning(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+
+def version() -> str:
+    return lib().dfpr_version().decode()

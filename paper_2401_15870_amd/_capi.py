@@ -1,0 +1,93 @@
+"""ctypes declarations of the dfpr C ABI (include/dfpr.h).  Marshalling only."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdfpr.so")
+
+DFPR_OK, DFPR_EINVAL, DFPR_ERANGE, DFPR_ENOMEM, DFPR_EHIP, DFPR_ESTATE = 0, -1, -2, -3, -4, -5
+STATIC, ND, DF, DFP = 0, 1, 2, 3
+HOST, DEVICE = 0, 1
+FLAG_TIMING = 1
+
+# Every exported function declared in include/dfpr.h.
+EXPORTS = ("dfpr_params_default", "dfpr_graph_create", "dfpr_graph_destroy", "dfpr_graph_size",
+           "dfpr_graph_export", "dfpr_apply_batch", "dfpr_update_ranks", "dfpr_set_tuning",
+           "dfpr_get_tuning", "dfpr_last_error", "dfpr_version")
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_double), ("tol", ctypes.c_double), ("frontier_tol", ctypes.c_double),
+                ("prune_tol", ctypes.c_double), ("max_iters", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("ins_in", ctypes.c_int64), ("ins_effective", ctypes.c_int64), ("del_in", ctypes.c_int64),
+                ("del_effective", ctypes.c_int64), ("self_loop_dels_ignored", ctypes.c_int64),
+                ("m_after", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32), ("last_delta", ctypes.c_double),
+                ("ever_affected", ctypes.c_int64), ("vertex_updates", ctypes.c_int64),
+                ("edges_pulled", ctypes.c_int64), ("bin_vertices", ctypes.c_int64 * 3),
+                ("bin_edges", ctypes.c_int64 * 3), ("ms_total", ctypes.c_double), ("ms_pull", ctypes.c_double * 3),
+                ("pull_launches", ctypes.c_int32 * 3), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        out = {}
+        for k, _ in self._fields_:
+            v = getattr(self, k)
+            out[k] = list(v) if hasattr(v, "__len__") else v
+        out.pop("reserved", None)
+        return out
+
+
+def declare(lib):
+    P = ctypes.c_void_p
+    i32, i64 = ctypes.c_int32, ctypes.c_int64
+    lib.dfpr_params_default.argtypes = [ctypes.POINTER(Params)]
+    lib.dfpr_params_default.restype = None
+    lib.dfpr_graph_create.argtypes = [i32, i64, P, P, ctypes.c_int, i64, P, ctypes.POINTER(P)]
+    lib.dfpr_graph_create.restype = ctypes.c_int
+    lib.dfpr_graph_destroy.argtypes = [P]
+    lib.dfpr_graph_destroy.restype = ctypes.c_int
+    lib.dfpr_graph_size.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(i64)]
+    lib.dfpr_graph_size.restype = ctypes.c_int
+    lib.dfpr_graph_export.argtypes = [P, ctypes.c_int, P, P, ctypes.c_int, P]
+    lib.dfpr_graph_export.restype = ctypes.c_int
+    lib.dfpr_apply_batch.argtypes = [P, i64, P, P, i64, P, P, ctypes.c_int, P, ctypes.POINTER(BatchInfo)]
+    lib.dfpr_apply_batch.restype = ctypes.c_int
+    lib.dfpr_update_ranks.argtypes = [P, ctypes.c_int, ctypes.POINTER(Params), P, P, P, ctypes.POINTER(Stats)]
+    lib.dfpr_update_ranks.restype = ctypes.c_int
+    lib.dfpr_set_tuning.argtypes = [P, i32, i32]
+    lib.dfpr_set_tuning.restype = ctypes.c_int
+    lib.dfpr_get_tuning.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.dfpr_get_tuning.restype = ctypes.c_int
+    lib.dfpr_last_error.argtypes = []
+    lib.dfpr_last_error.restype = ctypes.c_char_p
+    lib.dfpr_version.argtypes = []
+    lib.dfpr_version.restype = ctypes.c_char_p
+    return lib
+
+
+_lib = None
+
+
+def load(path: str | None = None):
+    """Load the built HIP library.  Raises if it is missing: there is no fallback."""
+    global _lib
+    if path is None and _lib is not None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise ImportError(f"dfpr HIP library not built: {p} is missing (run __graft_entry__.build())")
+    lib = declare(ctypes.CDLL(p))
+    if path is None:
+        _lib = lib
+    return lib

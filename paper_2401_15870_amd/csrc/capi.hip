@@ -1,0 +1,200 @@
+// extern "C" entry points of libdfpr: argument validation, the per-handle
+// mutex, device selection and handle poisoning around the implementation.
+#include <cmath>
+#include <new>
+
+#include "dfpr_impl.hpp"
+
+namespace dfpr {
+const char* last_error();
+void clear_error();
+}  // namespace dfpr
+
+using namespace dfpr;
+
+namespace {
+
+// Run `fn` with the handle's device current; poison the handle on HIP failures.
+template <class Fn>
+int guarded(dfpr_graph* g, Fn&& fn) {
+  if (!g) {
+    set_error("null graph handle");
+    return DFPR_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(g->mu);
+  if (g->poisoned) {
+    set_error("graph handle is unusable after an earlier HIP failure");
+    return DFPR_ESTATE;
+  }
+  int prev = 0;
+  if (hipGetDevice(&prev) != hipSuccess) {
+    set_error("hipGetDevice failed");
+    return DFPR_EHIP;
+  }
+  if (prev != g->device && hipSetDevice(g->device) != hipSuccess) {
+    set_error("hipSetDevice(%d) failed", g->device);
+    return DFPR_EHIP;
+  }
+  int rc;
+  try {
+    rc = fn();
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    rc = DFPR_ENOMEM;
+  } catch (...) {
+    set_error("unexpected exception");
+    rc = DFPR_EHIP;
+  }
+  if (rc == DFPR_EHIP) g->poisoned = true;
+  if (prev != g->device) (void)hipSetDevice(prev);
+  return rc;
+}
+
+int check_params(const dfpr_params& p) {
+  if (!(p.alpha > 0.0 && p.alpha < 1.0)) {
+    set_error("alpha must lie in (0,1), got %g", p.alpha);
+    return DFPR_EINVAL;
+  }
+  if (!(p.tol > 0.0) || std::isnan(p.frontier_tol) || std::isnan(p.prune_tol)) {
+    set_error("tol must be > 0 and tolerances must not be NaN");
+    return DFPR_EINVAL;
+  }
+  if (p.max_iters < 1) {
+    set_error("max_iters must be >= 1, got %d", p.max_iters);
+    return DFPR_EINVAL;
+  }
+  return DFPR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void dfpr_params_default(dfpr_params* p) {
+  if (!p) return;
+  p->alpha = 0.85;
+  p->tol = 1e-10;
+  p->frontier_tol = 1e-6;
+  p->prune_tol = 1e-6;
+  p->max_iters = 500;
+  p->flags = 0;
+}
+
+const char* dfpr_last_error(void) { return last_error(); }
+
+const char* dfpr_version(void) { return "dfpr 0.1 (gfx950)"; }
+
+int dfpr_graph_create(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, dfpr_where where,
+                      int64_t edge_capacity, void* stream, dfpr_graph** out) {
+  clear_error();
+  if (!out) {
+    set_error("out is null");
+    return DFPR_EINVAL;
+  }
+  *out = nullptr;
+  if (n <= 0 || m < 0 || (m > 0 && (!src || !dst)) || (where != DFPR_HOST && where != DFPR_DEVICE) ||
+      edge_capacity < 0) {
+    set_error("invalid arguments: n=%d m=%lld", n, (long long)m);
+    return DFPR_EINVAL;
+  }
+  try {
+    return graph_create(n, m, src, dst, where, edge_capacity, (hipStream_t)stream, out);
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return DFPR_ENOMEM;
+  }
+}
+
+int dfpr_graph_destroy(dfpr_graph* g) {
+  clear_error();
+  if (!g) return DFPR_OK;
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  if (prev != g->device) (void)hipSetDevice(g->device);
+  const int dev = g->device;
+  graph_destroy(g);
+  if (prev != dev) (void)hipSetDevice(prev);
+  return DFPR_OK;
+}
+
+int dfpr_graph_size(const dfpr_graph* g, int32_t* n, int64_t* m) {
+  clear_error();
+  if (!g || !n || !m) {
+    set_error("null argument");
+    return DFPR_EINVAL;
+  }
+  *n = g->n;
+  *m = g->m;
+  return DFPR_OK;
+}
+
+int dfpr_graph_export(const dfpr_graph* g, int in_csr, int32_t* offsets, int32_t* indices, dfpr_where where,
+                      void* stream) {
+  clear_error();
+  if (!offsets || (!indices && g && g->m > 0) || (where != DFPR_HOST && where != DFPR_DEVICE)) {
+    set_error("null output array");
+    return DFPR_EINVAL;
+  }
+  dfpr_graph* gm = const_cast<dfpr_graph*>(g);
+  return guarded(gm, [&] { return graph_export(gm, in_csr, offsets, indices, where, (hipStream_t)stream); });
+}
+
+int dfpr_apply_batch(dfpr_graph* g, int64_t n_del, const int32_t* del_src, const int32_t* del_dst, int64_t n_ins,
+                     const int32_t* ins_src, const int32_t* ins_dst, dfpr_where where, void* stream,
+                     dfpr_batch_info* info) {
+  clear_error();
+  if (n_del < 0 || n_ins < 0 || (n_del > 0 && (!del_src || !del_dst)) || (n_ins > 0 && (!ins_src || !ins_dst)) ||
+      (where != DFPR_HOST && where != DFPR_DEVICE)) {
+    set_error("invalid batch arguments");
+    return DFPR_EINVAL;
+  }
+  return guarded(g, [&] {
+    return graph_apply(g, n_del, del_src, del_dst, n_ins, ins_src, ins_dst, where, (hipStream_t)stream, info);
+  });
+}
+
+int dfpr_update_ranks(dfpr_graph* g, dfpr_mode mode, const dfpr_params* p, const double* r_prev, double* r_out,
+                      void* stream, dfpr_stats* st) {
+  clear_error();
+  dfpr_params prm;
+  if (p) prm = *p; else dfpr_params_default(&prm);
+  if (mode < DFPR_STATIC || mode > DFPR_DFP) {
+    set_error("unknown mode %d", (int)mode);
+    return DFPR_EINVAL;
+  }
+  if (check_params(prm) != DFPR_OK) return DFPR_EINVAL;
+  if (!r_out || (mode != DFPR_STATIC && !r_prev)) {
+    set_error("rank arrays must not be null");
+    return DFPR_EINVAL;
+  }
+  return guarded(g, [&] { return update_ranks(g, mode, prm, r_prev, r_out, (hipStream_t)stream, st); });
+}
+
+int dfpr_set_tuning(dfpr_graph* g, int32_t t_thread, int32_t t_wave) {
+  clear_error();
+  return guarded(g, [&] {
+    const int32_t a = t_thread > 0 ? t_thread : g->t_thread;
+    const int32_t b = t_wave > 0 ? t_wave : g->t_wave;
+    if (a < 1 || b < a) {
+      set_error("need 1 <= t_thread <= t_wave, got %d, %d", a, b);
+      return (int)DFPR_EINVAL;
+    }
+    if (a != g->t_thread || b != g->t_wave) g->all_bins_valid = false;
+    g->t_thread = a;
+    g->t_wave = b;
+    return (int)DFPR_OK;
+  });
+}
+
+int dfpr_get_tuning(const dfpr_graph* g, int32_t* t_thread, int32_t* t_wave) {
+  clear_error();
+  if (!g || !t_thread || !t_wave) {
+    set_error("null argument");
+    return DFPR_EINVAL;
+  }
+  *t_thread = g->t_thread;
+  *t_wave = g->t_wave;
+  return DFPR_OK;
+}
+
+}  // extern "C"

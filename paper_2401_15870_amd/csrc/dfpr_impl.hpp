@@ -1,0 +1,202 @@
+// Internal declarations of the dfpr library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <mutex>
+#include <string>
+
+#include "dfpr.h"
+
+namespace dfpr {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------- errors
+void set_error(const char* fmt, ...);
+
+struct Status {
+  int code = DFPR_OK;
+  bool ok() const { return code == DFPR_OK; }
+};
+
+#define DFPR_HIP(expr)                                                              \
+  do {                                                                              \
+    hipError_t e_ = (expr);                                                         \
+    if (e_ != hipSuccess) {                                                         \
+      ::dfpr::set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_),      \
+                        __FILE__, __LINE__);                                        \
+      return (e_ == hipErrorOutOfMemory) ? DFPR_ENOMEM : DFPR_EHIP;                 \
+    }                                                                               \
+  } while (0)
+
+#define DFPR_TRY(expr)             \
+  do {                             \
+    int rc_ = (expr);              \
+    if (rc_ != DFPR_OK) return rc_; \
+  } while (0)
+
+// ---------------------------------------------------------------- buffers
+// A growable device buffer (bytes).  Growth frees and reallocates; contents
+// are not preserved.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  int ensure(size_t want);
+  void release();
+  template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+struct Csr {
+  int32_t* off = nullptr;  // n+1
+  int32_t* idx = nullptr;  // capacity
+};
+
+// Per-update control block in device memory, read back once per iteration.
+struct IterCtl {
+  unsigned long long dR[2];  // L-inf change (bit pattern of a non-negative double), double-buffered
+  int64_t bin_end[3];        // worklist end offsets of the thread, wave and chunk bins
+  int64_t bin_edges[3];      // summed in-degree of each bin
+  int64_t n_apply[6];        // apply: eff ins, eff del, self dels, eff count, error flag, m_new
+  int64_t big_count;         // entries in the big out-row list
+  int64_t ever_count;        // vertices processed at least once in this update
+};
+
+// Pull chunking for the workgroup bin and out-row chunking for big expansions.
+constexpr int kPullChunk = 1024;   // in-edges per workgroup work item
+constexpr int kMarkChunk = 2048;   // out-edges per workgroup work item
+constexpr int kBigRow = 4096;      // out-rows longer than this go to the chunked path
+
+}  // namespace dfpr
+
+struct dfpr_graph {
+  std::mutex mu;
+  int device = 0;
+  bool poisoned = false;
+  int32_t n = 0;
+  int64_t m = 0;
+  int64_t cap = 0;   // edge capacity of each index array
+  int id_bits = 1;   // bits per vertex id in packed sort keys
+  dfpr::Csr out, in;        // current canonical CSRs
+  dfpr::Csr out2, in2;      // rebuild targets (swapped in after a batch)
+  // rank scratch (n entries each)
+  double* contrib = nullptr;   // R[u]/|out(u)| of the current iterate
+  double* contrib2 = nullptr;  // ping-pong partner for Static/ND
+  double* rn = nullptr;        // ping-pong rank buffer for Static/ND
+  uint8_t* flag_cur = nullptr;   // affected in this iteration; between updates:
+                                 // pending targets of effective deletions
+  uint8_t* flag_next = nullptr;  // affected in the next iteration
+  uint8_t* xflag = nullptr;      // expands in this iteration
+  uint8_t* ever = nullptr;       // processed at least once in this update
+  uint8_t* pend_src = nullptr;   // pending sources of effective changes
+  uint8_t* touched_out = nullptr, *touched_in = nullptr;  // rows changed by the batch
+  int32_t* delta_out = nullptr, *delta_in = nullptr;      // row length changes
+  int32_t* worklist = nullptr;   // n entries: thread bin | wave bin | block bin
+  int32_t* all_bins = nullptr;   // n entries: every vertex, binned (Static/ND)
+  int64_t all_bin_end[3] = {0, 0, 0};
+  int64_t all_bin_edges[3] = {0, 0, 0};
+  bool all_bins_valid = false;
+  dfpr::IterCtl* ctl = nullptr;      // device
+  dfpr::IterCtl* ctl_host = nullptr; // pinned host mirror
+  int64_t* scan_tmp = nullptr;       // block sums for scans over n
+  size_t scan_tmp_n = 0;
+  int64_t* bin_blk = nullptr;        // per-block bin counts (3 * ceil(n/2048) + 1)
+  int64_t* chunk_pre = nullptr;      // n+1: chunk prefix of the workgroup bin
+  double* partial = nullptr;         // partial sums of pull chunks
+  int64_t partial_n = 0;
+  int32_t* big_list = nullptr;       // n: vertices with long out-rows to mark
+  int64_t* big_pre = nullptr;        // n+1: chunk prefix of big_list
+  // growable batch scratch
+  dfpr::DevBuf keys_a, keys_b, keys_c, sort_hist, eff_pre, batch_in, keys_in;
+  bool pending_any = false;  // an apply happened since the last DF/DF-P update
+  int32_t t_thread = 12, t_wave = 1024;
+};
+
+namespace dfpr {
+
+// ---- primitives (prim.hip)
+// Exclusive scan of in[0..n) (int64) into out[0..n]; out[n] = total.  tmp needs
+// scan_tmp_elems(n) entries.
+size_t scan_tmp_elems(int64_t n);
+int scan_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* tmp, hipStream_t s);
+// Row offsets: out[u] = sum_{w<u} (base_off[w+1]-base_off[w] + delta[w]), u in [0,n].
+int scan_row_offsets(const int32_t* base_off, const int32_t* delta, int32_t* out, int32_t n,
+                     int64_t* tmp, hipStream_t s);
+// LSD radix sort of n 64-bit keys on their low `bits` bits.  Result lands in
+// *keys (pointer may be swapped with alt).  hist must hold radix_hist_elems(n).
+size_t radix_hist_elems(int64_t n);
+int radix_sort(uint64_t** keys, uint64_t** alt, int64_t n, int bits, int64_t* hist,
+               int64_t* hist_scan_tmp, hipStream_t s);
+size_t radix_scan_tmp_elems(int64_t n);
+// Stable compaction: out[k] = in[i] for the i with keep(i); count written to *count_dev.
+int compact_keys(const uint64_t* in, const uint8_t* keep, uint64_t* out, int64_t n,
+                 int64_t* count_dev, int64_t* tmp_pre, int64_t* tmp, hipStream_t s);
+
+// ---- graph (graph.hip)
+int graph_create(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, dfpr_where where,
+                 int64_t edge_capacity, hipStream_t s, dfpr_graph** out);
+int graph_destroy(dfpr_graph* g);
+int graph_export(const dfpr_graph* g, int in_csr, int32_t* off, int32_t* idx, dfpr_where where,
+                 hipStream_t s);
+int graph_apply(dfpr_graph* g, int64_t n_del, const int32_t* del_src, const int32_t* del_dst,
+                int64_t n_ins, const int32_t* ins_src, const int32_t* ins_dst, dfpr_where where,
+                hipStream_t s, dfpr_batch_info* info);
+
+// ---- ranks (rank.hip)
+int update_ranks(dfpr_graph* g, dfpr_mode mode, const dfpr_params& p, const double* r_prev,
+                 double* r_out, hipStream_t s, dfpr_stats* st);
+
+inline int bits_for(int64_t n) {
+  int b = 1;
+  while ((int64_t(1) << b) < n) b++;
+  return b;
+}
+
+inline unsigned grid_for(int64_t items, int per_block, unsigned cap = 1u << 20) {
+  int64_t g = (items + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > (int64_t)cap) g = cap;
+  return (unsigned)g;
+}
+
+}  // namespace dfpr
+
+// ---------------------------------------------------------------- device helpers
+namespace dfpr {
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, kWave);
+  return x;
+}
+__device__ __forceinline__ double wave_max(double x) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) x = fmax(x, __shfl_xor(x, o, kWave));
+  return x;
+}
+__device__ __forceinline__ int64_t wave_sum_i64(int64_t x) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, kWave);
+  return x;
+}
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
+
+// lower_bound over a sorted int32 range
+__device__ __forceinline__ int32_t lower_bound_i32(const int32_t* a, int32_t lo, int32_t hi, int32_t x) {
+  while (lo < hi) {
+    int32_t mid = lo + ((hi - lo) >> 1);
+    if (a[mid] < x) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+__device__ __forceinline__ int64_t lower_bound_u64(const uint64_t* a, int64_t lo, int64_t hi, uint64_t x) {
+  while (lo < hi) {
+    int64_t mid = lo + ((hi - lo) >> 1);
+    if (a[mid] < x) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+}  // namespace dfpr

@@ -1,0 +1,663 @@
+// Device graph store: canonical in- and out-CSR, creation, export and batch
+// application (Section 3.2 batch semantics; self-loop on every vertex as in
+// Sections 3.1 and 5.1.3).
+//
+// Batch keys pack an edge as (row << (b+1)) | (col << 1) | tag with b bits
+// per id and tag 1 = insertion, 0 = deletion, so one radix sort orders a batch
+// by row, then column, with deletions of a pair before its insertion.
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+
+#include "prim.hpp"
+
+namespace dfpr {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+const char* last_error() { return g_err; }
+void clear_error() { g_err[0] = 0; }
+
+int DevBuf::ensure(size_t want) {
+  if (want <= bytes) return DFPR_OK;
+  release();
+  size_t nb = want + want / 4 + 4096;
+  hipError_t e = hipMalloc(&p, nb);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    p = nullptr;
+    bytes = 0;
+    set_error("device allocation of %zu bytes failed: %s", nb, hipGetErrorString(e));
+    return DFPR_ENOMEM;
+  }
+  bytes = nb;
+  return DFPR_OK;
+}
+void DevBuf::release() {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  bytes = 0;
+}
+
+template <class T>
+static int dalloc(T** p, size_t count) {
+  hipError_t e = hipMalloc((void**)p, std::max<size_t>(count, 1) * sizeof(T));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    set_error("device allocation of %zu bytes failed: %s", count * sizeof(T), hipGetErrorString(e));
+    return DFPR_ENOMEM;
+  }
+  return DFPR_OK;
+}
+template <class T>
+static void dfree(T*& p) {
+  if (p) (void)hipFree((void*)p);
+  p = nullptr;
+}
+
+// ------------------------------------------------------------------ kernels
+constexpr uint64_t kBadKey = ~0ull;
+
+__global__ void k_make_graph_keys(const int32_t* src, const int32_t* dst, int64_t m, int32_t n, int b,
+                                  uint64_t* keys, int64_t* err) {
+  const int64_t total = m + n;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t k;
+    if (i < m) {
+      const int32_t u = src[i], v = dst[i];
+      if (u < 0 || u >= n || v < 0 || v >= n) {
+        atomicOr((unsigned long long*)err, 1ull);
+        k = kBadKey;
+      } else {
+        k = ((uint64_t)u << b) | (uint64_t)v;
+      }
+    } else {
+      const uint64_t v = (uint64_t)(i - m);
+      k = (v << b) | v;  // the self-loop of every vertex
+    }
+    keys[i] = k;
+  }
+}
+
+__global__ void k_mark_unique(const uint64_t* keys, int64_t n, uint8_t* keep) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    keep[i] = (keys[i] != kBadKey) && (i == 0 || keys[i] != keys[i - 1]);
+}
+
+// Sorted unique (row << b | col) keys -> CSR (every row holds its self-loop,
+// so every row start is written).
+__global__ void k_csr_from_sorted(const uint64_t* keys, int64_t m, int b, int32_t n, int32_t* off, int32_t* idx) {
+  const uint64_t mask = (1ull << b) - 1;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t k = keys[i];
+    const uint64_t row = k >> b;
+    idx[i] = (int32_t)(k & mask);
+    if (i == 0 || (keys[i - 1] >> b) != row) off[row] = (int32_t)i;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) off[n] = (int32_t)m;
+}
+
+__global__ void k_transpose_keys(const uint64_t* in, int64_t m, int b, uint64_t* out) {
+  const uint64_t mask = (1ull << b) - 1;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t k = in[i];
+    out[i] = ((k & mask) << b) | (k >> b);
+  }
+}
+
+// Batch keys; out-of-range ids raise err and produce kBadKey.
+__global__ void k_make_batch_keys(const int32_t* del_src, const int32_t* del_dst, int64_t nd, const int32_t* ins_src,
+                                  const int32_t* ins_dst, int64_t ni, int32_t n, int b, uint64_t* keys, int64_t* err) {
+  const int64_t total = nd + ni;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const bool ins = i >= nd;
+    const int32_t u = ins ? ins_src[i - nd] : del_src[i];
+    const int32_t v = ins ? ins_dst[i - nd] : del_dst[i];
+    uint64_t k;
+    if (u < 0 || u >= n || v < 0 || v >= n) {
+      atomicOr((unsigned long long*)err, 1ull);
+      k = kBadKey;
+    } else {
+      k = ((uint64_t)u << (b + 1)) | ((uint64_t)v << 1) | (ins ? 1ull : 0ull);
+    }
+    keys[i] = k;
+  }
+}
+
+// Classify each distinct pair of a sorted batch against the old out-CSR.
+// The last key of a pair's run owns the pair: it is an insertion key iff the
+// pair was inserted; the pair was deleted iff (pair << 1) is present.
+//   effective insertion: inserted and not in E^{t-1}
+//   effective deletion:  deleted, in E^{t-1}, and not inserted (insert wins)
+// Effective pairs set row deltas, touched rows and the pending marks.
+__global__ void k_classify(const uint64_t* keys, int64_t nk, int b, const int32_t* ooff, const int32_t* oidx,
+                           uint8_t* keep, int32_t* delta_out, int32_t* delta_in, uint8_t* touched_out,
+                           uint8_t* touched_in, uint8_t* pend_src, uint8_t* pend_tgt, int64_t* counters) {
+  const uint64_t mask = (1ull << b) - 1;
+  int64_t n_ins = 0, n_del = 0, n_self = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nk; i += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t k = keys[i];
+    uint8_t kp = 0;
+    const uint64_t pair = k >> 1;
+    const bool owner = (k != kBadKey) && (i + 1 == nk || (keys[i + 1] >> 1) != pair);
+    if (owner) {
+      const bool has_ins = k & 1ull;
+      const int64_t q = lower_bound_u64(keys, 0, i + 1, pair << 1);
+      const bool has_del = keys[q] == (pair << 1);
+      const int32_t u = (int32_t)(pair >> b);
+      const int32_t v = (int32_t)(pair & mask);
+      if (u == v) {
+        if (has_del) n_self++;
+      } else {
+        const int32_t s = ooff[u], e = ooff[u + 1];
+        const int32_t p = lower_bound_i32(oidx, s, e, v);
+        const bool exists = p < e && oidx[p] == v;
+        const bool eff_ins = has_ins && !exists;
+        const bool eff_del = has_del && exists && !has_ins;
+        if (eff_ins || eff_del) {
+          const int32_t d = eff_ins ? 1 : -1;
+          atomicAdd(&delta_out[u], d);
+          atomicAdd(&delta_in[v], d);
+          touched_out[u] = 1;
+          touched_in[v] = 1;
+          pend_src[u] = 1;
+          if (eff_del) pend_tgt[v] = 1;
+          kp = 1;
+          if (eff_ins) n_ins++; else n_del++;
+        }
+      }
+    }
+    keep[i] = kp;
+  }
+  n_ins = wave_sum_i64(n_ins);
+  n_del = wave_sum_i64(n_del);
+  n_self = wave_sum_i64(n_self);
+  if (lane_id() == 0) {
+    if (n_ins) atomicAdd((unsigned long long*)&counters[0], (unsigned long long)n_ins);
+    if (n_del) atomicAdd((unsigned long long*)&counters[1], (unsigned long long)n_del);
+    if (n_self) atomicAdd((unsigned long long*)&counters[2], (unsigned long long)n_self);
+  }
+}
+
+// Effective list in out-order (row = u) -> in-order keys (row = v); entries
+// past *count become kBadKey so a sort over nk keys leaves them at the end.
+__global__ void k_in_order_keys(const uint64_t* eff, const int64_t* count, int64_t nk, int b, uint64_t* out) {
+  const uint64_t mask = (1ull << b) - 1;
+  const int64_t t = *count;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nk; i += (int64_t)gridDim.x * blockDim.x) {
+    if (i < t) {
+      const uint64_t k = eff[i];
+      const uint64_t u = k >> (b + 1), v = (k >> 1) & mask;
+      out[i] = (v << (b + 1)) | (u << 1) | (k & 1ull);
+    } else {
+      out[i] = kBadKey;
+    }
+  }
+}
+
+struct LoadIsDel {
+  const uint64_t* eff;
+  const int64_t* count;
+  __device__ int64_t operator()(int64_t i) const { return (i < *count && !(eff[i] & 1ull)) ? 1 : 0; }
+};
+struct StoreI64b {
+  int64_t* a;
+  __device__ void operator()(int64_t i, int64_t v) const { a[i] = v; }
+};
+
+// Rebuild one CSR.  Each wavefront owns 64 consecutive rows.  Untouched rows
+// keep their content and only shift, so a group without touched rows is one
+// contiguous copy.  A touched row is rebuilt by placing every element at its
+// merge position: an old element x lands at j - #del(<x) + #ins(<x), an
+// inserted y at k + #old(<y) - #del(<y), where the counts come from binary
+// searches over the row's sorted effective entries (delpre = prefix count of
+// deletions in that list).
+__global__ void __launch_bounds__(256) k_rebuild(const int32_t* ooff, const int32_t* oidx, const int32_t* noff,
+                                                 int32_t* nidx, const uint8_t* touched, const uint64_t* eff,
+                                                 const int64_t* delpre, const int64_t* count, int b, int32_t n,
+                                                 int64_t* err) {
+  const int lane = lane_id();
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
+  const int64_t groups = ((int64_t)n + kWave - 1) / kWave;
+  const int64_t T = *count;
+  for (int64_t g = blockIdx.x * (int64_t)(blockDim.x / kWave) + threadIdx.x / kWave; g < groups; g += waves) {
+    const int32_t r0 = (int32_t)(g * kWave);
+    const int32_t rend = (int32_t)std::min<int64_t>((int64_t)r0 + kWave, n);
+    const bool t = (r0 + lane < rend) ? touched[r0 + lane] != 0 : false;
+    const uint64_t any = __ballot(t);
+    if (!any) {
+      const int32_t s0 = ooff[r0], s1 = ooff[rend];
+      const int64_t shift = (int64_t)noff[r0] - s0;
+      if ((int64_t)s1 + shift != (int64_t)noff[rend]) {  // offsets disagree: refuse to write
+        if (lane == 0) atomicOr((unsigned long long*)err, 2ull);
+        continue;
+      }
+      for (int32_t p = s0 + lane; p < s1; p += kWave) nidx[p + shift] = oidx[p];
+      continue;
+    }
+    for (int32_t r = r0; r < rend; r++) {
+      const int32_t os = ooff[r], oe = ooff[r + 1];
+      const int32_t base = noff[r], lim = noff[r + 1];
+      if (!((any >> (r - r0)) & 1ull)) {
+        if (lim - base != oe - os) {
+          if (lane == 0) atomicOr((unsigned long long*)err, 2ull);
+          continue;
+        }
+        for (int32_t p = os + lane; p < oe; p += kWave) nidx[base + (p - os)] = oidx[p];
+        continue;
+      }
+      const uint64_t rk = (uint64_t)r << (b + 1);
+      const int64_t lo = lower_bound_u64(eff, 0, T, rk);
+      const int64_t hi = lower_bound_u64(eff, lo, T, rk + (1ull << (b + 1)));
+      const int64_t dlo = delpre[lo];
+      for (int32_t j = lane; j < oe - os; j += kWave) {
+        const int32_t x = oidx[os + j];
+        const uint64_t xk = rk | ((uint64_t)x << 1);
+        const int64_t q = lower_bound_u64(eff, lo, hi, xk);
+        if (q < hi && eff[q] == xk) continue;  // deleted
+        const int64_t dels = delpre[q] - dlo;
+        const int64_t inss = (q - lo) - dels;
+        const int64_t pos = base + j - dels + inss;
+        if (pos < base || pos >= lim) {
+          atomicOr((unsigned long long*)err, 2ull);
+          continue;
+        }
+        nidx[pos] = x;
+      }
+      for (int64_t e = lo + lane; e < hi; e += kWave) {
+        const uint64_t k = eff[e];
+        if (!(k & 1ull)) continue;
+        const int32_t y = (int32_t)((k >> 1) & ((1ull << b) - 1));
+        const int64_t dels = delpre[e] - dlo;
+        const int64_t kins = (e - lo) - dels;
+        const int32_t oless = lower_bound_i32(oidx, os, oe, y) - os;
+        const int64_t pos = base + kins + oless - dels;
+        if (pos < base || pos >= lim) {
+          atomicOr((unsigned long long*)err, 2ull);
+          continue;
+        }
+        nidx[pos] = y;
+      }
+    }
+  }
+}
+
+__global__ void k_clear_rows(const uint64_t* eff, const int64_t* count, int b, int32_t* delta_out, int32_t* delta_in,
+                             uint8_t* touched_out, uint8_t* touched_in) {
+  const uint64_t mask = (1ull << b) - 1;
+  const int64_t t = *count;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < t; i += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t k = eff[i];
+    const int32_t u = (int32_t)(k >> (b + 1)), v = (int32_t)((k >> 1) & mask);
+    delta_out[u] = 0;
+    touched_out[u] = 0;
+    delta_in[v] = 0;
+    touched_in[v] = 0;
+  }
+}
+
+__global__ void k_finish_apply(const int32_t* noff, int32_t n, int64_t* counters) { counters[5] = noff[n]; }
+
+// ------------------------------------------------------------------ host
+static int alloc_rank_scratch(dfpr_graph* g) {
+  const size_t n = (size_t)g->n;
+  DFPR_TRY(dalloc(&g->contrib, n));
+  DFPR_TRY(dalloc(&g->contrib2, n));
+  DFPR_TRY(dalloc(&g->rn, n));
+  DFPR_TRY(dalloc(&g->flag_cur, n));
+  DFPR_TRY(dalloc(&g->flag_next, n));
+  DFPR_TRY(dalloc(&g->xflag, n));
+  DFPR_TRY(dalloc(&g->ever, n));
+  DFPR_TRY(dalloc(&g->pend_src, n));
+  DFPR_TRY(dalloc(&g->touched_out, n));
+  DFPR_TRY(dalloc(&g->touched_in, n));
+  DFPR_TRY(dalloc(&g->delta_out, n));
+  DFPR_TRY(dalloc(&g->delta_in, n));
+  DFPR_TRY(dalloc(&g->worklist, n));
+  DFPR_TRY(dalloc(&g->all_bins, n));
+  DFPR_TRY(dalloc(&g->ctl, 1));
+  const int64_t nbins = ((int64_t)n + 2047) / 2048;
+  DFPR_TRY(dalloc(&g->bin_blk, (size_t)(3 * nbins + 2)));
+  DFPR_TRY(dalloc(&g->chunk_pre, n + 1));
+  DFPR_TRY(dalloc(&g->big_list, n));
+  DFPR_TRY(dalloc(&g->big_pre, n + 1));
+  g->partial_n = g->cap / kPullChunk + (int64_t)n + 1;
+  DFPR_TRY(dalloc(&g->partial, (size_t)g->partial_n));
+  g->scan_tmp_n = scan_tmp_elems((int64_t)n + 1);
+  DFPR_TRY(dalloc(&g->scan_tmp, g->scan_tmp_n));
+  DFPR_HIP(hipHostMalloc((void**)&g->ctl_host, sizeof(IterCtl), hipHostMallocDefault));
+  DFPR_HIP(hipMemset(g->flag_cur, 0, n));
+  DFPR_HIP(hipMemset(g->flag_next, 0, n));
+  DFPR_HIP(hipMemset(g->xflag, 0, n));
+  DFPR_HIP(hipMemset(g->ever, 0, n));
+  DFPR_HIP(hipMemset(g->pend_src, 0, n));
+  DFPR_HIP(hipMemset(g->touched_out, 0, n));
+  DFPR_HIP(hipMemset(g->touched_in, 0, n));
+  DFPR_HIP(hipMemset(g->delta_out, 0, n * sizeof(int32_t)));
+  DFPR_HIP(hipMemset(g->delta_in, 0, n * sizeof(int32_t)));
+  DFPR_HIP(hipMemset(g->ctl, 0, sizeof(IterCtl)));
+  return DFPR_OK;
+}
+
+static int alloc_csr(Csr* c, int32_t n, int64_t cap) {
+  DFPR_TRY(dalloc(&c->off, (size_t)n + 1));
+  DFPR_TRY(dalloc(&c->idx, (size_t)cap));
+  return DFPR_OK;
+}
+static void free_csr(Csr* c) {
+  dfree(c->off);
+  dfree(c->idx);
+}
+
+int graph_destroy(dfpr_graph* g) {
+  if (!g) return DFPR_OK;
+  (void)hipDeviceSynchronize();
+  free_csr(&g->out);
+  free_csr(&g->in);
+  free_csr(&g->out2);
+  free_csr(&g->in2);
+  dfree(g->contrib);
+  dfree(g->contrib2);
+  dfree(g->rn);
+  dfree(g->flag_cur);
+  dfree(g->flag_next);
+  dfree(g->xflag);
+  dfree(g->ever);
+  dfree(g->pend_src);
+  dfree(g->touched_out);
+  dfree(g->touched_in);
+  dfree(g->delta_out);
+  dfree(g->delta_in);
+  dfree(g->worklist);
+  dfree(g->all_bins);
+  dfree(g->ctl);
+  dfree(g->scan_tmp);
+  dfree(g->bin_blk);
+  dfree(g->chunk_pre);
+  dfree(g->big_list);
+  dfree(g->big_pre);
+  dfree(g->partial);
+  if (g->ctl_host) (void)hipHostFree(g->ctl_host);
+  g->ctl_host = nullptr;
+  g->keys_a.release();
+  g->keys_b.release();
+  g->keys_c.release();
+  g->sort_hist.release();
+  g->eff_pre.release();
+  g->batch_in.release();
+  g->keys_in.release();
+  delete g;
+  return DFPR_OK;
+}
+
+// Temporary device buffers of one create call.
+struct CreateTmp {
+  int32_t* coo = nullptr;
+  uint64_t *ka = nullptr, *kb = nullptr;
+  uint8_t* keep = nullptr;
+  int64_t *pre = nullptr, *hist = nullptr, *tmp = nullptr, *cnt = nullptr;
+  ~CreateTmp() {
+    dfree(coo);
+    dfree(ka);
+    dfree(kb);
+    dfree(keep);
+    dfree(pre);
+    dfree(hist);
+    dfree(tmp);
+    dfree(cnt);
+  }
+};
+
+static int build_csr_from_keys(uint64_t** ka, uint64_t** kb, int64_t m, int b, int32_t n, Csr* c, int64_t* hist,
+                               int64_t* tmp, hipStream_t s) {
+  DFPR_TRY(radix_sort(ka, kb, m, 2 * b, hist, tmp, s));
+  k_csr_from_sorted<<<grid_for(m, 256, 65536), 256, 0, s>>>(*ka, m, b, n, c->off, c->idx);
+  DFPR_HIP(hipGetLastError());
+  return DFPR_OK;
+}
+
+int graph_create(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, dfpr_where where,
+                 int64_t edge_capacity, hipStream_t s, dfpr_graph** out) {
+  *out = nullptr;
+  const int64_t total = m + n;
+  if (total > INT32_MAX) {
+    set_error("graph too large for int32 CSR offsets: %lld pairs", (long long)total);
+    return DFPR_EINVAL;
+  }
+  dfpr_graph* g = new (std::nothrow) dfpr_graph();
+  if (!g) {
+    set_error("host allocation failed");
+    return DFPR_ENOMEM;
+  }
+  DFPR_HIP(hipGetDevice(&g->device));
+  g->n = n;
+  g->id_bits = bits_for(n);
+  const int b = g->id_bits;
+  int rc = DFPR_OK;
+  {
+    CreateTmp t;
+    const int32_t *dsrc = src, *ddst = dst;
+    auto fail = [&](int code) {
+      graph_destroy(g);
+      return code;
+    };
+    if (m > 0 && where == DFPR_HOST) {
+      if ((rc = dalloc(&t.coo, (size_t)(2 * m))) != DFPR_OK) return fail(rc);
+      if (hipMemcpyAsync(t.coo, src, m * sizeof(int32_t), hipMemcpyHostToDevice, s) != hipSuccess ||
+          hipMemcpyAsync(t.coo + m, dst, m * sizeof(int32_t), hipMemcpyHostToDevice, s) != hipSuccess) {
+        set_error("edge upload failed");
+        return fail(DFPR_EHIP);
+      }
+      dsrc = t.coo;
+      ddst = t.coo + m;
+    }
+    if ((rc = dalloc(&t.ka, total)) || (rc = dalloc(&t.kb, total)) || (rc = dalloc(&t.keep, total)) ||
+        (rc = dalloc(&t.pre, total + 1)) || (rc = dalloc(&t.hist, radix_hist_elems(total))) ||
+        (rc = dalloc(&t.tmp, std::max(radix_scan_tmp_elems(total), scan_tmp_elems(total + 1)))) ||
+        (rc = dalloc(&t.cnt, 2)))
+      return fail(rc);
+    if (hipMemsetAsync(t.cnt, 0, 2 * sizeof(int64_t), s) != hipSuccess) return fail(DFPR_EHIP);
+    k_make_graph_keys<<<grid_for(total, 256, 65536), 256, 0, s>>>(dsrc, ddst, m, n, b, t.ka, t.cnt);
+    int64_t err = 0;
+    if (hipMemcpyAsync(&err, t.cnt, sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+      set_error("graph key construction failed");
+      return fail(DFPR_EHIP);
+    }
+    if (err) {
+      set_error("vertex id outside [0, %d)", n);
+      return fail(DFPR_ERANGE);
+    }
+    if ((rc = radix_sort(&t.ka, &t.kb, total, 2 * b, t.hist, t.tmp, s))) return fail(rc);
+    k_mark_unique<<<grid_for(total, 256, 65536), 256, 0, s>>>(t.ka, total, t.keep);
+    if ((rc = compact_keys(t.ka, t.keep, t.kb, total, t.cnt + 1, t.pre, t.tmp, s))) return fail(rc);
+    int64_t mu = 0;
+    if (hipMemcpyAsync(&mu, t.cnt + 1, sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+      set_error("unique count readback failed");
+      return fail(DFPR_EHIP);
+    }
+    g->m = mu;
+    int64_t cap = edge_capacity > 0 ? edge_capacity : mu + mu / 8 + 1024;
+    cap = std::max<int64_t>(cap, mu);
+    cap = std::min<int64_t>(cap, INT32_MAX);
+    g->cap = cap;
+    if ((rc = alloc_csr(&g->out, n, cap)) || (rc = alloc_csr(&g->in, n, cap)) || (rc = alloc_csr(&g->out2, n, cap)) ||
+        (rc = alloc_csr(&g->in2, n, cap)))
+      return fail(rc);
+    // out-CSR straight from the unique sorted keys (already row-major by source)
+    k_csr_from_sorted<<<grid_for(mu, 256, 65536), 256, 0, s>>>(t.kb, mu, b, n, g->out.off, g->out.idx);
+    // in-CSR: transpose the keys and sort again
+    k_transpose_keys<<<grid_for(mu, 256, 65536), 256, 0, s>>>(t.kb, mu, b, t.ka);
+    if ((rc = build_csr_from_keys(&t.ka, &t.kb, mu, b, n, &g->in, t.hist, t.tmp, s))) return fail(rc);
+    if ((rc = alloc_rank_scratch(g))) return fail(rc);
+    if (hipStreamSynchronize(s) != hipSuccess) {
+      set_error("graph creation failed on the device");
+      return fail(DFPR_EHIP);
+    }
+  }
+  *out = g;
+  return DFPR_OK;
+}
+
+int graph_export(const dfpr_graph* g, int in_csr, int32_t* off, int32_t* idx, dfpr_where where, hipStream_t s) {
+  const Csr& c = in_csr ? g->in : g->out;
+  const hipMemcpyKind kind = where == DFPR_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+  DFPR_HIP(hipMemcpyAsync(off, c.off, ((size_t)g->n + 1) * sizeof(int32_t), kind, s));
+  if (g->m > 0) DFPR_HIP(hipMemcpyAsync(idx, c.idx, (size_t)g->m * sizeof(int32_t), kind, s));
+  DFPR_HIP(hipStreamSynchronize(s));
+  return DFPR_OK;
+}
+
+// Grow the edge capacity of all four index arrays to at least `want`.
+static int grow_capacity(dfpr_graph* g, int64_t want, hipStream_t s) {
+  int64_t cap = std::min<int64_t>(std::max<int64_t>(want + want / 4, g->cap), INT32_MAX);
+  DFPR_HIP(hipStreamSynchronize(s));
+  for (Csr* c : {&g->out, &g->in, &g->out2, &g->in2}) {
+    int32_t* p = nullptr;
+    DFPR_TRY(dalloc(&p, (size_t)cap));
+    if (c == &g->out || c == &g->in)
+      DFPR_HIP(hipMemcpyAsync(p, c->idx, (size_t)g->m * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    DFPR_HIP(hipStreamSynchronize(s));
+    dfree(c->idx);
+    c->idx = p;
+  }
+  g->cap = cap;
+  const int64_t pn = cap / kPullChunk + (int64_t)g->n + 1;
+  if (pn > g->partial_n) {
+    dfree(g->partial);
+    DFPR_TRY(dalloc(&g->partial, (size_t)pn));
+    g->partial_n = pn;
+  }
+  return DFPR_OK;
+}
+
+int graph_apply(dfpr_graph* g, int64_t nd, const int32_t* del_src, const int32_t* del_dst, int64_t ni,
+                const int32_t* ins_src, const int32_t* ins_dst, dfpr_where where, hipStream_t s,
+                dfpr_batch_info* info) {
+  const int64_t nk = nd + ni;
+  const int32_t n = g->n;
+  const int b = g->id_bits;
+  if (info) {
+    *info = dfpr_batch_info{};
+    info->ins_in = ni;
+    info->del_in = nd;
+    info->m_after = g->m;
+  }
+  if (nk == 0) return DFPR_OK;
+  if (g->m + ni > INT32_MAX) {
+    set_error("batch would exceed int32 edge offsets");
+    return DFPR_EINVAL;
+  }
+  if (g->m + ni > g->cap) DFPR_TRY(grow_capacity(g, g->m + ni, s));
+
+  // ---- scratch
+  DFPR_TRY(g->keys_a.ensure(nk * sizeof(uint64_t)));
+  DFPR_TRY(g->keys_b.ensure(nk * sizeof(uint64_t)));
+  DFPR_TRY(g->keys_c.ensure(nk * sizeof(uint64_t) + nk));  // in-order keys + keep bytes
+  DFPR_TRY(g->sort_hist.ensure((radix_hist_elems(nk) + std::max(radix_scan_tmp_elems(nk), scan_tmp_elems(nk + 1))) *
+                               sizeof(int64_t)));
+  DFPR_TRY(g->eff_pre.ensure(2 * (nk + 1) * sizeof(int64_t)));
+  uint64_t* ka = g->keys_a.as<uint64_t>();
+  uint64_t* kb = g->keys_b.as<uint64_t>();
+  uint64_t* kc = g->keys_c.as<uint64_t>();
+  uint8_t* keep = reinterpret_cast<uint8_t*>(kc + nk);
+  int64_t* hist = g->sort_hist.as<int64_t>();
+  int64_t* tmp = hist + radix_hist_elems(nk);
+  int64_t* pre_out = g->eff_pre.as<int64_t>();
+  int64_t* pre_in = pre_out + (nk + 1);
+  int64_t* counters = g->ctl->n_apply;
+
+  const int32_t *ds = del_src, *dd = del_dst, *is = ins_src, *id = ins_dst;
+  if (where == DFPR_HOST) {
+    DFPR_TRY(g->batch_in.ensure(2 * nk * sizeof(int32_t)));
+    int32_t* bi = g->batch_in.as<int32_t>();
+    if (nd) {
+      DFPR_HIP(hipMemcpyAsync(bi, del_src, nd * sizeof(int32_t), hipMemcpyHostToDevice, s));
+      DFPR_HIP(hipMemcpyAsync(bi + nd, del_dst, nd * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    }
+    if (ni) {
+      DFPR_HIP(hipMemcpyAsync(bi + 2 * nd, ins_src, ni * sizeof(int32_t), hipMemcpyHostToDevice, s));
+      DFPR_HIP(hipMemcpyAsync(bi + 2 * nd + ni, ins_dst, ni * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    }
+    ds = bi;
+    dd = bi + nd;
+    is = bi + 2 * nd;
+    id = bi + 2 * nd + ni;
+  }
+
+  // ---- keys + validation (validation before mutation: one sync)
+  DFPR_HIP(hipMemsetAsync(counters, 0, 6 * sizeof(int64_t), s));
+  k_make_batch_keys<<<grid_for(nk, 256, 65536), 256, 0, s>>>(ds, dd, nd, is, id, ni, n, b, ka, counters + 4);
+  DFPR_HIP(hipGetLastError());
+  DFPR_HIP(hipMemcpyAsync(g->ctl_host->n_apply, counters, 6 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  DFPR_HIP(hipStreamSynchronize(s));
+  if (g->ctl_host->n_apply[4]) {
+    set_error("vertex id outside [0, %d) in batch", n);
+    return DFPR_ERANGE;
+  }
+
+  // ---- sort by (u, v, tag) and classify against the old out-CSR
+  DFPR_TRY(radix_sort(&ka, &kb, nk, 2 * b + 1, hist, tmp, s));
+  k_classify<<<grid_for(nk, 256, 65536), 256, 0, s>>>(ka, nk, b, g->out.off, g->out.idx, keep, g->delta_out,
+                                                       g->delta_in, g->touched_out, g->touched_in, g->pend_src,
+                                                       g->flag_cur, counters);
+  DFPR_HIP(hipGetLastError());
+  // effective entries, sorted by (u, v): count lands in counters[3]
+  DFPR_TRY(compact_keys(ka, keep, kb, nk, counters + 3, pre_out, tmp, s));
+  uint64_t* eff_out = kb;
+  const int64_t* cnt = counters + 3;
+  DFPR_TRY(scan_generic(LoadIsDel{eff_out, cnt}, StoreI64b{pre_out}, nk, tmp, s));
+
+  // ---- out-CSR
+  DFPR_TRY(scan_row_offsets(g->out.off, g->delta_out, g->out2.off, n, g->scan_tmp, s));
+  const unsigned rb_grid = grid_for(((int64_t)n + kWave - 1) / kWave, 4, 1u << 16);
+  k_rebuild<<<rb_grid, 256, 0, s>>>(g->out.off, g->out.idx, g->out2.off, g->out2.idx, g->touched_out, eff_out,
+                                    pre_out, cnt, b, n, counters + 4);
+  DFPR_HIP(hipGetLastError());
+
+  // ---- in-CSR: the same entries ordered by (v, u)
+  k_in_order_keys<<<grid_for(nk, 256, 65536), 256, 0, s>>>(eff_out, cnt, nk, b, ka);
+  uint64_t* eff_in = ka;
+  uint64_t* alt = kc;
+  DFPR_TRY(radix_sort(&eff_in, &alt, nk, 2 * b + 1, hist, tmp, s));
+  DFPR_TRY(scan_generic(LoadIsDel{eff_in, cnt}, StoreI64b{pre_in}, nk, tmp, s));
+  DFPR_TRY(scan_row_offsets(g->in.off, g->delta_in, g->in2.off, n, g->scan_tmp, s));
+  k_rebuild<<<rb_grid, 256, 0, s>>>(g->in.off, g->in.idx, g->in2.off, g->in2.idx, g->touched_in, eff_in, pre_in, cnt,
+                                    b, n, counters + 4);
+  DFPR_HIP(hipGetLastError());
+  k_clear_rows<<<grid_for(nk, 256, 65536), 256, 0, s>>>(eff_out, cnt, b, g->delta_out, g->delta_in, g->touched_out,
+                                                        g->touched_in);
+  k_finish_apply<<<1, 1, 0, s>>>(g->out2.off, n, counters);
+  DFPR_HIP(hipGetLastError());
+  DFPR_HIP(hipMemcpyAsync(g->ctl_host->n_apply, counters, 6 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  DFPR_HIP(hipStreamSynchronize(s));
+
+  const int64_t* h = g->ctl_host->n_apply;
+  if (h[4] != 0 || h[5] != g->m + h[0] - h[1]) {
+    set_error("internal inconsistency in the CSR rebuild (flag %lld, m %lld -> %lld)", (long long)h[4],
+              (long long)g->m, (long long)h[5]);
+    return DFPR_EHIP;
+  }
+  std::swap(g->out, g->out2);
+  std::swap(g->in, g->in2);
+  g->m = h[5];
+  g->all_bins_valid = false;
+  if (h[3] > 0) g->pending_any = true;
+  if (info) {
+    info->ins_effective = h[0];
+    info->del_effective = h[1];
+    info->self_loop_dels_ignored = h[2];
+    info->m_after = g->m;
+  }
+  return DFPR_OK;
+}
+
+}  // namespace dfpr

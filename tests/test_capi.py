@@ -1,0 +1,60 @@
+"""The C-ABI library loads and exports every symbol include/dfpr.h declares;
+argument checks that return before any device work (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2401_15870_amd import _capi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "dfpr.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dfpr_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_capi.LIB_PATH):
+        from paper_2401_15870_amd import build
+        build.build()
+    return _capi.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 11
+    assert set(names) == set(_capi.EXPORTS)
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_params_default(lib):
+    p = _capi.Params()
+    lib.dfpr_params_default(ctypes.byref(p))
+    assert (p.alpha, p.tol, p.frontier_tol, p.prune_tol, p.max_iters, p.flags) == (0.85, 1e-10, 1e-6, 1e-6, 500, 0)
+
+
+def test_invalid_arguments_rejected_before_device_work(lib):
+    h = ctypes.c_void_p()
+    assert lib.dfpr_graph_create(0, 0, None, None, 0, 0, None, ctypes.byref(h)) == _capi.DFPR_EINVAL
+    assert lib.dfpr_graph_create(5, 3, None, None, 0, 0, None, ctypes.byref(h)) == _capi.DFPR_EINVAL
+    assert lib.dfpr_graph_create(5, -1, None, None, 0, 0, None, ctypes.byref(h)) == _capi.DFPR_EINVAL
+    assert b"invalid" in lib.dfpr_last_error()
+    st = _capi.Stats()
+    assert lib.dfpr_update_ranks(None, 3, None, None, None, None, ctypes.byref(st)) == _capi.DFPR_EINVAL
+    assert lib.dfpr_set_tuning(None, 4, 8) == _capi.DFPR_EINVAL
+    assert lib.dfpr_apply_batch(None, -1, None, None, 0, None, None, 0, None, None) == _capi.DFPR_EINVAL
+    assert lib.dfpr_graph_destroy(None) == _capi.DFPR_OK
+    assert lib.dfpr_version().startswith(b"dfpr")
+
+
+def test_struct_layouts_match_header():
+    # field counts and sizes of the ABI structs as declared in include/dfpr.h
+    assert ctypes.sizeof(_capi.Params) == 4 * 8 + 2 * 4
+    assert ctypes.sizeof(_capi.BatchInfo) == 6 * 8
+    assert ctypes.sizeof(_capi.Stats) == 4 + 4 + 8 + 3 * 8 + 6 * 8 + 8 + 3 * 8 + 3 * 4 + 4

@@ -1,0 +1,224 @@
+"""GPU path against the CPU oracle through the C ABI: canonical CSRs bit-exact,
+effective batch counts equal, ranks within L-inf 1e-9 from the same R_prev bits
+(bit-exact when every vertex is in the one-lane-per-vertex bin)."""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from gpu_common import LINF, Pair, assert_csr_equal, hub_graph, rmat, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def _print(*a):
+    print(*a, flush=True)
+
+
+# ------------------------------------------------------------------ graph store
+@pytest.mark.parametrize("case", ["single_vertex", "no_edges", "dups_and_selfs", "rmat10", "rmat14", "hub"])
+def test_create_csr_bitexact(case):
+    torch_cuda()
+    _print("create", case)
+    if case == "single_vertex":
+        n, s, d = 1, np.zeros(0, np.int32), np.zeros(0, np.int32)
+    elif case == "no_edges":
+        n, s, d = 37, np.zeros(0, np.int32), np.zeros(0, np.int32)
+    elif case == "dups_and_selfs":
+        n = 300
+        rng = np.random.default_rng(3)
+        s = rng.integers(0, n, 5000).astype(np.int32)
+        d = rng.integers(0, n, 5000).astype(np.int32)
+        d[::7] = s[::7]
+    elif case == "rmat10":
+        n, s, d = rmat(10, seed=2)
+    elif case == "rmat14":
+        n, s, d = rmat(14, seed=3)
+    else:
+        n, s, d = hub_graph(30000, 9000, 12000, 60000, seed=4)
+    p = Pair(n, s, d)
+    assert p.g.m == p.og.m
+    assert_csr_equal(p.g, p.og)
+
+
+def test_apply_messy_batches_chained():
+    """Repeated pairs, self-loop deletes, absent deletes, existing inserts, a pair
+    both inserted and deleted: every step matches the oracle bit for bit."""
+    torch_cuda()
+    rng = np.random.default_rng(7)
+    for trial in range(12):
+        n = int(rng.integers(2, 400))
+        s, d = W.random_digraph(n, float(rng.uniform(0.002, 0.05)), seed=trial)
+        p = Pair(n, s, d)
+        for step in range(4):
+            ds, dd, is_, id_ = W.random_edit_batch(n, p.og.esrc, p.og.edst, int(rng.integers(0, 60)),
+                                                   int(rng.integers(0, 60)), seed=trial * 10 + step)
+            _print("apply", trial, step, n, len(ds), len(is_))
+            p.apply(ds, dd, is_, id_, device=(step % 2 == 1))
+            assert_csr_equal(p.g, p.og)
+
+
+@pytest.mark.parametrize("frac", [1e-5, 1e-3, 1e-1])
+def test_apply_8020_rmat14(frac):
+    """Batches below and above the one-block sort size; the inverse batch restores G0."""
+    torch_cuda()
+    n, s, d = rmat(14, seed=5)
+    p = Pair(n, s, d)
+    g0 = (p.og.out_off.copy(), p.og.out_idx.copy())
+    ds, dd, is_, id_ = W.batch_8020(n, s, d, frac, seed=6)
+    _print("apply8020", frac, len(ds), len(is_))
+    p.apply(ds, dd, is_, id_)
+    assert_csr_equal(p.g, p.og)
+    p.apply(is_, id_, ds, dd)  # inverse: delete what was inserted, insert what was deleted
+    assert_csr_equal(p.g, p.og)
+    assert np.array_equal(p.og.out_off, g0[0]) and np.array_equal(p.og.out_idx, g0[1])
+
+
+def test_apply_hub_rows():
+    torch_cuda()
+    n, s, d = hub_graph(20000, 7000, 9000, 40000, seed=8)
+    p = Pair(n, s, d)
+    rng = np.random.default_rng(9)
+    # delete half of the hub's in-edges and add new ones to and from the hub
+    hub_in = p.og.in_idx[p.og.in_off[0]:p.og.in_off[1]]
+    dels = hub_in[hub_in != 0][::2]
+    new = rng.integers(1, n, 3000).astype(np.int32)
+    p.apply(dels, np.zeros_like(dels), np.concatenate([new, np.zeros(3000, np.int32)]),
+            np.concatenate([np.zeros(3000, np.int32), new]))
+    assert_csr_equal(p.g, p.og)
+
+
+# ------------------------------------------------------------------ ranks
+def _setup(scale=12, frac=1e-3, seed=1, ef=16):
+    n, s, d = rmat(scale, ef=ef, seed=seed)
+    p = Pair(n, s, d)
+    r0 = O.rank("static", p.og).ranks
+    ds, dd, is_, id_ = W.batch_8020(n, s, d, frac, seed=seed + 100)
+    p.apply(ds, dd, is_, id_)
+    return p, r0
+
+
+@pytest.mark.parametrize("mode", ["static", "nd", "df", "dfp"])
+@pytest.mark.parametrize("scale,frac", [(10, 1e-2), (14, 1e-3)])
+def test_ranks_parity(mode, scale, frac):
+    p, r0 = _setup(scale, frac, seed=scale)
+    _print("ranks", mode, scale, frac)
+    r, st, ref = p.rank(mode, r0)
+    err = float(np.abs(r - ref.ranks).max())
+    _print(f"  linf={err:.3e} it gpu={st['iterations']} oracle={ref.iterations} "
+           f"ever gpu={st['ever_affected']} oracle={ref.ever_affected}")
+    assert err <= LINF
+    assert st["converged"] == ref.converged == 1
+    assert abs(st["iterations"] - ref.iterations) <= 1
+    assert (r >= (1 - 0.85) / p.n).all()
+
+
+@pytest.mark.parametrize("mode", ["static", "nd", "df", "dfp"])
+def test_ranks_bitexact_lane_bin(mode):
+    """With every vertex in the one-lane bin the sums run in the oracle's order:
+    ranks, iteration counts and frontier statistics are identical."""
+    p, r0 = _setup(13, 1e-3, seed=21)
+    maxdeg = int(np.diff(p.og.in_off).max())
+    p.g.set_tuning(maxdeg, maxdeg)
+    r, st, ref = p.rank(mode, r0)
+    assert np.array_equal(r, ref.ranks)
+    assert st["iterations"] == ref.iterations
+    assert st["vertex_updates"] == ref.vertex_updates
+    assert st["edges_pulled"] == ref.edges_pulled
+    assert st["ever_affected"] == ref.ever_affected
+
+
+@pytest.mark.parametrize("mode", ["static", "dfp", "df"])
+def test_chunk_and_wave_bins(mode):
+    """Tiny thresholds push most vertices into the wavefront and chunked bins."""
+    p, r0 = _setup(12, 1e-2, seed=31)
+    p.g.set_tuning(1, 2)
+    r, st, ref = p.rank(mode, r0)
+    assert np.abs(r - ref.ranks).max() <= LINF
+    assert st["bin_vertices"][2] > 0 and st["bin_vertices"][1] > 0
+
+
+@pytest.mark.parametrize("mode", ["static", "df", "dfp"])
+def test_hub_graph_ranks(mode):
+    """A vertex with thousands of in- and out-edges: chunked pull (several
+    chunks per row) and chunked marking of its out-row."""
+    n, s, d = hub_graph(30000, 9000, 12000, 90000, seed=41)
+    p = Pair(n, s, d)
+    r0 = O.rank("static", p.og).ranks
+    p.apply([], [], [0, 5], [77, 0])  # touches the hub as a source and as a target
+    r, st, ref = p.rank(mode, r0)
+    assert np.abs(r - ref.ranks).max() <= LINF
+    if mode != "static":
+        assert st["ever_affected"] == ref.ever_affected
+
+
+def test_empty_and_noop_batches():
+    p, r0 = _setup(10, 1e-2, seed=51)
+    r0b = O.rank("static", p.og).ranks
+    ex = (p.og.esrc[p.og.esrc != p.og.edst][:3], p.og.edst[p.og.esrc != p.og.edst][:3])
+    p.apply([4, 4], [4, 4], ex[0], ex[1])  # self-loop deletes + existing inserts
+    assert len(p.batch.dm_src) == 0 and len(p.batch.dp_src) == 0
+    for mode in ("df", "dfp"):
+        r, st, ref = p.rank(mode, r0b)
+        assert st["iterations"] == 1 and st["converged"] == 1 and st["ever_affected"] == 0
+        assert np.array_equal(r, r0b)
+
+
+def test_rank_alias_and_determinism():
+    torch = torch_cuda()
+    p, r0 = _setup(12, 1e-3, seed=61)
+    outs = []
+    for _ in range(2):
+        p.apply(*W.batch_8020(p.n, p.og.esrc[p.og.esrc != p.og.edst], p.og.edst[p.og.esrc != p.og.edst], 1e-3,
+                              seed=62))
+        p.apply(p.batch.dp_src, p.batch.dp_dst, p.batch.dm_src, p.batch.dm_dst)  # back to the same graph
+        p.apply(*W.batch_8020(p.n, p.og.esrc[p.og.esrc != p.og.edst], p.og.edst[p.og.esrc != p.og.edst], 1e-3,
+                              seed=62))
+        rp = torch.from_numpy(r0.copy()).cuda()
+        r, st = p.g.update_ranks("dfp", rp, out=rp)  # r_out aliases r_prev
+        torch.cuda.synchronize()
+        outs.append((r.cpu().numpy().copy(), st["iterations"], st["ever_affected"]))
+        p.apply(p.batch.dp_src, p.batch.dp_dst, p.batch.dm_src, p.batch.dm_dst)
+    assert np.array_equal(outs[0][0], outs[1][0]) and outs[0][1:] == outs[1][1:]
+
+
+def test_errors_leave_graph_unchanged():
+    torch = torch_cuda()
+    import paper_2401_15870_amd as dfpr
+    p, r0 = _setup(10, 1e-2, seed=71)
+    with pytest.raises(dfpr.DfprError) as e:
+        p.g.apply_batch([0, 1], [2, p.n], [], [])
+    assert e.value.code == -2
+    assert_csr_equal(p.g, p.og)
+    rp = torch.from_numpy(r0).cuda()
+    with pytest.raises(dfpr.DfprError) as e:
+        p.g.update_ranks("dfp", rp, alpha=1.5)
+    assert e.value.code == -1
+    with pytest.raises(dfpr.DfprError):
+        p.g.set_tuning(10, 5)
+    # the pending marks survived the failed calls: DF-P still matches the oracle
+    r, st, ref = p.rank("dfp", r0)
+    assert np.abs(r - ref.ranks).max() <= LINF
+    # iteration cap is not an error
+    r, st, ref = p.rank("static", None, max_iters=3)
+    assert st["converged"] == 0 and st["iterations"] == 3 == ref.iterations
+    assert np.abs(r - ref.ranks).max() <= LINF
+
+
+def test_temporal_chain():
+    """Insertion-only batches replayed in time order, each step from the
+    oracle's previous ranks (many inserts are repeats: no-ops)."""
+    torch_cuda()
+    src, dst = W.temporal_stream(4000, 60000, seed=81)
+    n = 4000
+    k0 = int(0.9 * len(src))
+    p = Pair(n, src[:k0], dst[:k0])
+    r = O.rank("static", p.og).ranks
+    B = (len(src) - k0) // 5
+    for i in range(5):
+        lo = k0 + i * B
+        p.apply([], [], src[lo:lo + B], dst[lo:lo + B])
+        assert_csr_equal(p.g, p.og)
+        gr, st, ref = p.rank("dfp", r)
+        assert np.abs(gr - ref.ranks).max() <= LINF
+        r = ref.ranks

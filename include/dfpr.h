@@ -64,12 +64,16 @@ typedef struct {
 /* flags: record per-phase and per-kernel timings with HIP events into dfpr_stats. */
 #define DFPR_FLAG_TIMING 1
 
-/* Effective-batch counts of one dfpr_apply_batch call (Section 3.2). */
+/* Effective-batch counts of one dfpr_apply_batch call (Section 3.2).  The ms_*
+ * fields are filled when timing is on (dfpr_set_timing), else 0. */
 typedef struct {
   int64_t ins_in, ins_effective;   /* insertions given; of those, new edges      */
   int64_t del_in, del_effective;   /* deletions given; of those, removed edges   */
   int64_t self_loop_dels_ignored;  /* distinct (v,v) deletions (self-loops stay) */
   int64_t m_after;                 /* |E| after the update, self-loops included  */
+  double ms_total;                 /* whole call on the stream                   */
+  double ms_sort;                  /* radix sorts of the batch                   */
+  double ms_rebuild[2];            /* out-CSR and in-CSR rebuild kernels         */
 } dfpr_batch_info;
 
 /* Result statistics of one dfpr_update_ranks call.  The pull work is split in
@@ -84,10 +88,15 @@ typedef struct {
   int64_t edges_pulled;     /* sum over iterations of the affected in-degrees     */
   int64_t bin_vertices[3];  /* vertex_updates split by bin                        */
   int64_t bin_edges[3];     /* edges_pulled split by bin                          */
-  double ms_total;          /* time of the call on the stream (TIMING flag)       */
-  double ms_pull[3];        /* summed duration of each bin's pull kernel (TIMING) */
-  int32_t pull_launches[3]; /* launches timed in ms_pull (TIMING flag)            */
+  /* Timings in milliseconds, measured with HIP events on the stream when the
+   * TIMING flag is set or timing is on for the graph (dfpr_set_timing). */
+  double ms_total;          /* the whole call                                     */
+  double ms_pull[3];        /* summed duration of each bin's pull kernels         */
+  int32_t pull_launches[3]; /* launches summed in ms_pull                         */
   int32_t reserved;
+  double ms_commit;         /* commit + expansion kernels                         */
+  double ms_bin;            /* affected-set binning (compaction) kernels          */
+  double ms_mark;           /* initial marking kernels                            */
 } dfpr_stats;
 
 typedef struct dfpr_graph dfpr_graph;
@@ -148,6 +157,11 @@ int dfpr_update_ranks(dfpr_graph* g, dfpr_mode mode, const dfpr_params* p, const
  * 1 <= t_thread <= t_wave. */
 int dfpr_set_tuning(dfpr_graph* g, int32_t t_thread, int32_t t_wave);
 int dfpr_get_tuning(const dfpr_graph* g, int32_t* t_thread, int32_t* t_wave);
+
+/* Turn HIP-event timing of every apply and update on this graph on (1) or
+ * off (0).  Events are recorded between kernels and read after the call's
+ * final synchronisation, so timing adds no host round trips. */
+int dfpr_set_timing(dfpr_graph* g, int on);
 
 /* Thread-local message for the last failing call on this thread ("" if none). */
 const char* dfpr_last_error(void);

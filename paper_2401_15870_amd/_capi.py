@@ -15,7 +15,7 @@ FLAG_TIMING = 1
 # Every exported function declared in include/dfpr.h.
 EXPORTS = ("dfpr_params_default", "dfpr_graph_create", "dfpr_graph_destroy", "dfpr_graph_size",
            "dfpr_graph_export", "dfpr_apply_batch", "dfpr_update_ranks", "dfpr_set_tuning",
-           "dfpr_get_tuning", "dfpr_last_error", "dfpr_version")
+           "dfpr_get_tuning", "dfpr_set_timing", "dfpr_last_error", "dfpr_version")
 
 
 class Params(ctypes.Structure):
@@ -26,10 +26,15 @@ class Params(ctypes.Structure):
 class BatchInfo(ctypes.Structure):
     _fields_ = [("ins_in", ctypes.c_int64), ("ins_effective", ctypes.c_int64), ("del_in", ctypes.c_int64),
                 ("del_effective", ctypes.c_int64), ("self_loop_dels_ignored", ctypes.c_int64),
-                ("m_after", ctypes.c_int64)]
+                ("m_after", ctypes.c_int64), ("ms_total", ctypes.c_double), ("ms_sort", ctypes.c_double),
+                ("ms_rebuild", ctypes.c_double * 2)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        out = {}
+        for k, _ in self._fields_:
+            v = getattr(self, k)
+            out[k] = list(v) if hasattr(v, "__len__") else v
+        return out
 
 
 class Stats(ctypes.Structure):
@@ -37,7 +42,8 @@ class Stats(ctypes.Structure):
                 ("ever_affected", ctypes.c_int64), ("vertex_updates", ctypes.c_int64),
                 ("edges_pulled", ctypes.c_int64), ("bin_vertices", ctypes.c_int64 * 3),
                 ("bin_edges", ctypes.c_int64 * 3), ("ms_total", ctypes.c_double), ("ms_pull", ctypes.c_double * 3),
-                ("pull_launches", ctypes.c_int32 * 3), ("reserved", ctypes.c_int32)]
+                ("pull_launches", ctypes.c_int32 * 3), ("reserved", ctypes.c_int32), ("ms_commit", ctypes.c_double),
+                ("ms_bin", ctypes.c_double), ("ms_mark", ctypes.c_double)]
 
     def as_dict(self):
         out = {}
@@ -69,6 +75,8 @@ def declare(lib):
     lib.dfpr_set_tuning.restype = ctypes.c_int
     lib.dfpr_get_tuning.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     lib.dfpr_get_tuning.restype = ctypes.c_int
+    lib.dfpr_set_timing.argtypes = [P, ctypes.c_int]
+    lib.dfpr_set_timing.restype = ctypes.c_int
     lib.dfpr_last_error.argtypes = []
     lib.dfpr_last_error.restype = ctypes.c_char_p
     lib.dfpr_version.argtypes = []

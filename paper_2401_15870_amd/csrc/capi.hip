@@ -186,6 +186,14 @@ int dfpr_set_tuning(dfpr_graph* g, int32_t t_thread, int32_t t_wave) {
   });
 }
 
+int dfpr_set_timing(dfpr_graph* g, int on) {
+  clear_error();
+  return guarded(g, [&] {
+    g->timing = on != 0;
+    return (int)DFPR_OK;
+  });
+}
+
 int dfpr_get_tuning(const dfpr_graph* g, int32_t* t_thread, int32_t* t_wave) {
   clear_error();
   if (!g || !t_thread || !t_wave) {

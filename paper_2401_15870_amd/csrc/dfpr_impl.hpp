@@ -7,6 +7,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "dfpr.h"
 
@@ -47,6 +48,64 @@ struct DevBuf {
   int ensure(size_t want);
   void release();
   template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+// HIP-event timing of kernel spans.  Events are recorded between launches and
+// read only after the caller's final stream synchronisation.
+enum TimeTag : int {
+  kTPull0 = 0, kTPull1, kTPull2, kTCommit, kTBin, kTMark, kTSort, kTRebuildOut, kTRebuildIn, kTTotal, kTNum
+};
+struct EventPool {
+  std::vector<hipEvent_t> ev;
+  struct Span { int tag; size_t a, b; };
+  std::vector<Span> spans;
+  size_t used = 0;
+  bool on = false;
+  hipStream_t s = nullptr;
+  void reset(bool enable, hipStream_t st) {
+    on = enable;
+    s = st;
+    used = 0;
+    spans.clear();
+  }
+  int record(size_t* idx) {
+    if (used == ev.size()) {
+      hipEvent_t e;
+      DFPR_HIP(hipEventCreate(&e));
+      ev.push_back(e);
+    }
+    DFPR_HIP(hipEventRecord(ev[used], s));
+    *idx = used++;
+    return DFPR_OK;
+  }
+  // start a span; *tok identifies it for stop()
+  int start(size_t* tok) {
+    *tok = 0;
+    return on ? record(tok) : DFPR_OK;
+  }
+  int stop(int tag, size_t tok) {
+    if (!on) return DFPR_OK;
+    size_t b;
+    DFPR_TRY(record(&b));
+    spans.push_back(Span{tag, tok, b});
+    return DFPR_OK;
+  }
+  // sum the spans per tag (stream must be synchronised)
+  int collect(double* ms, int* cnt) {
+    for (const Span& sp : spans) {
+      float t = 0.f;
+      DFPR_HIP(hipEventElapsedTime(&t, ev[sp.a], ev[sp.b]));
+      ms[sp.tag] += t;
+      cnt[sp.tag] += 1;
+    }
+    spans.clear();
+    used = 0;
+    return DFPR_OK;
+  }
+  void destroy() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    ev.clear();
+  }
 };
 
 struct Csr {
@@ -112,6 +171,8 @@ struct dfpr_graph {
   dfpr::DevBuf keys_a, keys_b, keys_c, sort_hist, eff_pre, batch_in, keys_in;
   bool pending_any = false;  // an apply happened since the last DF/DF-P update
   int32_t t_thread = 12, t_wave = 1024;
+  bool timing = false;        // record HIP-event timings of every call
+  dfpr::EventPool pool;
 };
 
 namespace dfpr {

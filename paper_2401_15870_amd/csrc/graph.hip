@@ -393,6 +393,7 @@ int graph_destroy(dfpr_graph* g) {
   g->eff_pre.release();
   g->batch_in.release();
   g->keys_in.release();
+  g->pool.destroy();
   delete g;
   return DFPR_OK;
 }
@@ -593,6 +594,10 @@ int graph_apply(dfpr_graph* g, int64_t nd, const int32_t* del_src, const int32_t
     id = bi + 2 * nd + ni;
   }
 
+  EventPool& ep = g->pool;
+  ep.reset(g->timing, s);
+  size_t t_total, tok;
+  DFPR_TRY(ep.start(&t_total));
   // ---- keys + validation (validation before mutation: one sync)
   DFPR_HIP(hipMemsetAsync(counters, 0, 6 * sizeof(int64_t), s));
   k_make_batch_keys<<<grid_for(nk, 256, 65536), 256, 0, s>>>(ds, dd, nd, is, id, ni, n, b, ka, counters + 4);
@@ -605,7 +610,9 @@ int graph_apply(dfpr_graph* g, int64_t nd, const int32_t* del_src, const int32_t
   }
 
   // ---- sort by (u, v, tag) and classify against the old out-CSR
+  DFPR_TRY(ep.start(&tok));
   DFPR_TRY(radix_sort(&ka, &kb, nk, 2 * b + 1, hist, tmp, s));
+  DFPR_TRY(ep.stop(kTSort, tok));
   k_classify<<<grid_for(nk, 256, 65536), 256, 0, s>>>(ka, nk, b, g->out.off, g->out.idx, keep, g->delta_out,
                                                        g->delta_in, g->touched_out, g->touched_in, g->pend_src,
                                                        g->flag_cur, counters);
@@ -619,25 +626,32 @@ int graph_apply(dfpr_graph* g, int64_t nd, const int32_t* del_src, const int32_t
   // ---- out-CSR
   DFPR_TRY(scan_row_offsets(g->out.off, g->delta_out, g->out2.off, n, g->scan_tmp, s));
   const unsigned rb_grid = grid_for(((int64_t)n + kWave - 1) / kWave, 4, 1u << 16);
+  DFPR_TRY(ep.start(&tok));
   k_rebuild<<<rb_grid, 256, 0, s>>>(g->out.off, g->out.idx, g->out2.off, g->out2.idx, g->touched_out, eff_out,
                                     pre_out, cnt, b, n, counters + 4);
   DFPR_HIP(hipGetLastError());
+  DFPR_TRY(ep.stop(kTRebuildOut, tok));
 
   // ---- in-CSR: the same entries ordered by (v, u)
   k_in_order_keys<<<grid_for(nk, 256, 65536), 256, 0, s>>>(eff_out, cnt, nk, b, ka);
   uint64_t* eff_in = ka;
   uint64_t* alt = kc;
+  DFPR_TRY(ep.start(&tok));
   DFPR_TRY(radix_sort(&eff_in, &alt, nk, 2 * b + 1, hist, tmp, s));
+  DFPR_TRY(ep.stop(kTSort, tok));
   DFPR_TRY(scan_generic(LoadIsDel{eff_in, cnt}, StoreI64b{pre_in}, nk, tmp, s));
   DFPR_TRY(scan_row_offsets(g->in.off, g->delta_in, g->in2.off, n, g->scan_tmp, s));
+  DFPR_TRY(ep.start(&tok));
   k_rebuild<<<rb_grid, 256, 0, s>>>(g->in.off, g->in.idx, g->in2.off, g->in2.idx, g->touched_in, eff_in, pre_in, cnt,
                                     b, n, counters + 4);
   DFPR_HIP(hipGetLastError());
+  DFPR_TRY(ep.stop(kTRebuildIn, tok));
   k_clear_rows<<<grid_for(nk, 256, 65536), 256, 0, s>>>(eff_out, cnt, b, g->delta_out, g->delta_in, g->touched_out,
                                                         g->touched_in);
   k_finish_apply<<<1, 1, 0, s>>>(g->out2.off, n, counters);
   DFPR_HIP(hipGetLastError());
   DFPR_HIP(hipMemcpyAsync(g->ctl_host->n_apply, counters, 6 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  DFPR_TRY(ep.stop(kTTotal, t_total));
   DFPR_HIP(hipStreamSynchronize(s));
 
   const int64_t* h = g->ctl_host->n_apply;
@@ -656,6 +670,17 @@ int graph_apply(dfpr_graph* g, int64_t nd, const int32_t* del_src, const int32_t
     info->del_effective = h[1];
     info->self_loop_dels_ignored = h[2];
     info->m_after = g->m;
+  }
+  if (ep.on) {
+    double ms[kTNum] = {0};
+    int c[kTNum] = {0};
+    DFPR_TRY(ep.collect(ms, c));
+    if (info) {
+      info->ms_total = ms[kTTotal];
+      info->ms_sort = ms[kTSort];
+      info->ms_rebuild[0] = ms[kTRebuildOut];
+      info->ms_rebuild[1] = ms[kTRebuildIn];
+    }
   }
   return DFPR_OK;
 }

@@ -405,6 +405,8 @@ static double bits_to_double(unsigned long long b) {
 
 static int bin_vertices(dfpr_graph* g, const uint8_t* flags, int32_t* wl, uint8_t* ever, hipStream_t s) {
   const int32_t n = g->n;
+  size_t tok;
+  DFPR_TRY(g->pool.start(&tok));
   const int64_t nb = ((int64_t)n + kBinTile - 1) / kBinTile;
   k_bin_count<<<(unsigned)nb, 256, 0, s>>>(flags, g->in.off, n, g->t_thread, g->t_wave, g->bin_blk, nb,
                                            g->ctl->bin_edges);
@@ -412,6 +414,7 @@ static int bin_vertices(dfpr_graph* g, const uint8_t* flags, int32_t* wl, uint8_
   k_bin_scatter<<<(unsigned)nb, 256, 0, s>>>(flags, g->in.off, n, g->t_thread, g->t_wave, g->bin_blk, nb, wl, ever,
                                              g->ctl->bin_end);
   DFPR_HIP(hipGetLastError());
+  DFPR_TRY(g->pool.stop(kTBin, tok));
   return DFPR_OK;
 }
 
@@ -429,73 +432,34 @@ static int mark_big(dfpr_graph* g, uint8_t* flags, hipStream_t s) {
   return DFPR_OK;
 }
 
-struct Timer {
-  bool on = false;
-  hipEvent_t a = nullptr, b = nullptr;
-  hipStream_t s = nullptr;
-  ~Timer() {
-    if (a) (void)hipEventDestroy(a);
-    if (b) (void)hipEventDestroy(b);
-  }
-  int init(bool enable, hipStream_t st) {
-    on = enable;
-    s = st;
-    if (!on) return DFPR_OK;
-    DFPR_HIP(hipEventCreate(&a));
-    DFPR_HIP(hipEventCreate(&b));
-    return DFPR_OK;
-  }
-  int start() {
-    if (on) DFPR_HIP(hipEventRecord(a, s));
-    return DFPR_OK;
-  }
-  // stop and add the elapsed milliseconds to *acc (synchronises on the event)
-  int stop(double* acc) {
-    if (!on) return DFPR_OK;
-    DFPR_HIP(hipEventRecord(b, s));
-    DFPR_HIP(hipEventSynchronize(b));
-    float ms = 0.f;
-    DFPR_HIP(hipEventElapsedTime(&ms, a, b));
-    *acc += ms;
-    return DFPR_OK;
-  }
-};
-
 // Launch the pull kernels of one iteration over worklist `wl` with bins
 // [0,e0) [e0,e1) [e1,e2); per-bin timing when t->on.
 template <int MODE>
 static int pull_all(dfpr_graph* g, const PullArgs& a, const int32_t* wl, const int64_t* be, const int64_t* bedges,
-                    hipStream_t s, Timer* t, dfpr_stats* st) {
+                    hipStream_t s) {
   const int64_t n0 = be[0], n1 = be[1] - be[0], n2 = be[2] - be[1];
+  EventPool& ep = g->pool;
+  size_t tok;
   if (n0 > 0) {
-    DFPR_TRY(t->start());
+    DFPR_TRY(ep.start(&tok));
     k_pull_lane<MODE><<<grid_for(n0, 256, 1u << 16), 256, 0, s>>>(a, wl, 0, be[0]);
     DFPR_HIP(hipGetLastError());
-    if (t->on) {
-      DFPR_TRY(t->stop(&st->ms_pull[0]));
-      st->pull_launches[0]++;
-    }
+    DFPR_TRY(ep.stop(kTPull0, tok));
   }
   if (n1 > 0) {
-    DFPR_TRY(t->start());
+    DFPR_TRY(ep.start(&tok));
     k_pull_wave<MODE><<<grid_for(n1, 4, 1u << 16), 256, 0, s>>>(a, wl, be[0], be[1]);
     DFPR_HIP(hipGetLastError());
-    if (t->on) {
-      DFPR_TRY(t->stop(&st->ms_pull[1]));
-      st->pull_launches[1]++;
-    }
+    DFPR_TRY(ep.stop(kTPull1, tok));
   }
   if (n2 > 0) {
-    DFPR_TRY(t->start());
+    DFPR_TRY(ep.start(&tok));
     DFPR_TRY(scan_generic(LoadChunks{wl, g->in.off, be[1]}, StoreI64r{g->chunk_pre}, n2, g->scan_tmp, s));
     const int64_t max_chunks = bedges[2] / kPullChunk + n2;
     k_pull_chunk<<<grid_for(max_chunks, 1, 1u << 16), 256, 0, s>>>(a, wl, be[1], n2, g->chunk_pre, g->partial);
     k_pull_chunk_finish<MODE><<<grid_for(n2, 256, 4096), 256, 0, s>>>(a, wl, be[1], n2, g->chunk_pre, g->partial);
     DFPR_HIP(hipGetLastError());
-    if (t->on) {
-      DFPR_TRY(t->stop(&st->ms_pull[2]));
-      st->pull_launches[2]++;
-    }
+    DFPR_TRY(ep.stop(kTPull2, tok));
   }
   return DFPR_OK;
 }
@@ -508,7 +472,7 @@ static void add_bins(dfpr_stats* st, const int64_t* be, const int64_t* bedges) {
 }
 
 static int run_sync(dfpr_graph* g, bool cold, const dfpr_params& p, const double* r_prev, double* r_out,
-                    hipStream_t s, dfpr_stats* st, Timer* t) {
+                    hipStream_t s, dfpr_stats* st) {
   const int32_t n = g->n;
   if (!g->all_bins_valid) {
     k_reset_all<<<1, 1, 0, s>>>(g->ctl);
@@ -538,7 +502,7 @@ static int run_sync(dfpr_graph* g, bool cold, const dfpr_params& p, const double
     a.Rw = Rb;
     a.cw = cb;
     a.dR = &g->ctl->dR[slot];
-    DFPR_TRY(pull_all<kSync>(g, a, g->all_bins, g->all_bin_end, g->all_bin_edges, s, t, st));
+    DFPR_TRY(pull_all<kSync>(g, a, g->all_bins, g->all_bin_end, g->all_bin_edges, s));
     k_iter_reset<<<1, 1, 0, s>>>(g->ctl, slot ^ 1);
     DFPR_TRY(readback(g, s));
     dR = bits_to_double(g->ctl_host->dR[slot]);
@@ -570,16 +534,19 @@ static int run_sync(dfpr_graph* g, bool cold, const dfpr_params& p, const double
 
 template <int MODE>
 static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_prev, double* r_out, hipStream_t s,
-                        dfpr_stats* st, Timer* t) {
+                        dfpr_stats* st) {
   const int32_t n = g->n;
   const unsigned gi = grid_for(n, 256, 1u << 16);
   k_init_prev<<<gi, 256, 0, s>>>(r_prev, r_out, g->contrib, g->out.off, n, r_prev != r_out);
   k_reset_all<<<1, 1, 0, s>>>(g->ctl);
   // initial marking: out(u) of pending sources (+ deletion targets already in flag_cur)
+  size_t tok;
+  DFPR_TRY(g->pool.start(&tok));
   k_mark_pending<<<gi, 256, 0, s>>>(g->pend_src, n, g->out.off, g->out.idx, g->flag_cur, g->big_list,
                                     &g->ctl->big_count);
   DFPR_HIP(hipGetLastError());
   DFPR_TRY(mark_big(g, g->flag_cur, s));
+  DFPR_TRY(g->pool.stop(kTMark, tok));
   g->pending_any = false;
   k_iter_reset<<<1, 1, 0, s>>>(g->ctl, 0);
   DFPR_TRY(bin_vertices(g, g->flag_cur, g->worklist, g->ever, s));
@@ -607,12 +574,14 @@ static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_pre
     }
     a.next = next;
     a.dR = &g->ctl->dR[slot];
-    DFPR_TRY(pull_all<MODE>(g, a, g->worklist, be, bedges, s, t, st));
+    DFPR_TRY(pull_all<MODE>(g, a, g->worklist, be, bedges, s));
+    DFPR_TRY(g->pool.start(&tok));
     k_commit_expand<<<grid_for(cnt, 256, 1u << 16), 256, 0, s>>>(g->worklist, cnt, r_out, g->contrib, g->out.off,
                                                                  g->out.idx, cur, next, g->xflag, g->big_list,
                                                                  &g->ctl->big_count);
     DFPR_HIP(hipGetLastError());
     DFPR_TRY(mark_big(g, next, s));
+    DFPR_TRY(g->pool.stop(kTCommit, tok));
     std::swap(cur, next);
     k_iter_reset<<<1, 1, 0, s>>>(g->ctl, slot ^ 1);
     DFPR_TRY(bin_vertices(g, cur, g->worklist, g->ever, s));
@@ -642,20 +611,33 @@ static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_pre
 int update_ranks(dfpr_graph* g, dfpr_mode mode, const dfpr_params& p, const double* r_prev, double* r_out,
                  hipStream_t s, dfpr_stats* st_out) {
   dfpr_stats st{};
-  Timer t;
-  DFPR_TRY(t.init((p.flags & DFPR_FLAG_TIMING) != 0, s));
-  Timer whole;
-  DFPR_TRY(whole.init((p.flags & DFPR_FLAG_TIMING) != 0, s));
-  DFPR_TRY(whole.start());
+  EventPool& ep = g->pool;
+  ep.reset(g->timing || (p.flags & DFPR_FLAG_TIMING) != 0, s);
+  size_t tok;
+  DFPR_TRY(ep.start(&tok));
   int rc;
   switch (mode) {
-    case DFPR_STATIC: rc = run_sync(g, true, p, r_prev, r_out, s, &st, &t); break;
-    case DFPR_ND: rc = run_sync(g, false, p, r_prev, r_out, s, &st, &t); break;
-    case DFPR_DF: rc = run_frontier<kDF>(g, p, r_prev, r_out, s, &st, &t); break;
-    default: rc = run_frontier<kDFP>(g, p, r_prev, r_out, s, &st, &t); break;
+    case DFPR_STATIC: rc = run_sync(g, true, p, r_prev, r_out, s, &st); break;
+    case DFPR_ND: rc = run_sync(g, false, p, r_prev, r_out, s, &st); break;
+    case DFPR_DF: rc = run_frontier<kDF>(g, p, r_prev, r_out, s, &st); break;
+    default: rc = run_frontier<kDFP>(g, p, r_prev, r_out, s, &st); break;
   }
   if (rc != DFPR_OK) return rc;
-  DFPR_TRY(whole.stop(&st.ms_total));
+  if (ep.on) {
+    DFPR_TRY(ep.stop(kTTotal, tok));
+    DFPR_HIP(hipStreamSynchronize(s));
+    double ms[kTNum] = {0};
+    int cnt[kTNum] = {0};
+    DFPR_TRY(ep.collect(ms, cnt));
+    st.ms_total = ms[kTTotal];
+    for (int k = 0; k < 3; k++) {
+      st.ms_pull[k] = ms[kTPull0 + k];
+      st.pull_launches[k] = cnt[kTPull0 + k];
+    }
+    st.ms_commit = ms[kTCommit];
+    st.ms_bin = ms[kTBin];
+    st.ms_mark = ms[kTMark];
+  }
   if (st_out) *st_out = st;
   return DFPR_OK;
 }

@@ -153,7 +153,8 @@ def test_hub_graph_ranks(mode):
 
 
 def test_empty_and_noop_batches():
-    p, r0 = _setup(10, 1e-2, seed=51)
+    n, s, d = rmat(10, seed=51)
+    p = Pair(n, s, d)
     r0b = O.rank("static", p.og).ranks
     ex = (p.og.esrc[p.og.esrc != p.og.edst][:3], p.og.edst[p.og.esrc != p.og.edst][:3])
     p.apply([4, 4], [4, 4], ex[0], ex[1])  # self-loop deletes + existing inserts
@@ -162,6 +163,14 @@ def test_empty_and_noop_batches():
         r, st, ref = p.rank(mode, r0b)
         assert st["iterations"] == 1 and st["converged"] == 1 and st["ever_affected"] == 0
         assert np.array_equal(r, r0b)
+    # marks accumulate over applies until the next DF/DF-P update consumes them
+    have = set(zip(p.og.esrc.tolist(), p.og.edst.tolist()))
+    u, v = next((a, b) for a in range(n) for b in range(n) if a != b and (a, b) not in have)
+    p.apply([], [], [u], [v])
+    r, st, ref = p.rank("dfp", r0b)
+    assert st["ever_affected"] == ref.ever_affected > 0
+    r, st, _ = p.rank("dfp", r0b)
+    assert st["ever_affected"] == 0 and np.array_equal(r, r0b)
 
 
 def test_rank_alias_and_determinism():

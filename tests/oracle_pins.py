@@ -251,6 +251,25 @@ def pin_dynamic_special_cases(lib):
             assert np.array_equal(df.ranks, nd.ranks) and df.iterations == nd.iterations
 
 
+def pin_relative_criterion(lib):
+    """The expansion test uses dr / max(previous, current rank) (Section 4.2).
+
+    3 vertices, G^{t-1} = {1->2}, insert 0->1, R_prev = (0.1, 0.3, 0.6), DF with
+    tau_f = 0.3.  Marked: out(0) = {0, 1}.  Iteration 1, vertex 1 (in(1) = {0, 1},
+    d = 2 for both): c = 0.1/2 + 0.3/2 = 0.2, r = 0.05 + 0.85*0.2 = 0.22,
+    dr = 0.08; dr/max = 0.08/0.3 = 0.267 <= 0.3 (no expansion), whereas dr/min
+    would be 0.364 > 0.3.  Vertex 0: r = 0.05 + 0.85*0.05 = 0.0925, rel 0.075.
+    Later changes only shrink, so vertex 2 is never processed and keeps 0.6."""
+    g0 = O.graph(3, [1], [2], lib=lib)
+    g1, b = O.apply(g0, [], [], [0], [1], lib=lib)
+    r = O.rank("df", g1, np.array([0.1, 0.3, 0.6]), g0, b, tol_f=0.3, lib=lib)
+    assert r.ever_affected == 2
+    assert r.ranks[2] == 0.6
+    # with a threshold below 0.267 vertex 1 expands and vertex 2 is processed
+    r = O.rank("df", g1, np.array([0.1, 0.3, 0.6]), g0, b, tol_f=0.25, lib=lib)
+    assert r.ever_affected == 3 and r.ranks[2] != 0.6
+
+
 def pin_lower_bound(lib):
     """Every iterate of every mode satisfies r >= (1-alpha)/N (all terms are
     non-negative and the Equation 2 factor 1/(1-alpha/d) is >= 1)."""
@@ -270,4 +289,5 @@ def pin_lower_bound(lib):
 
 
 ALL_PINS = [pin_canonical, pin_apply, pin_static_dense, pin_static_closed_forms, pin_nd_is_static_warm,
-            pin_dfp_closed_loop, pin_dynamic_bruteforce, pin_dynamic_special_cases, pin_lower_bound]
+            pin_dfp_closed_loop, pin_dynamic_bruteforce, pin_dynamic_special_cases, pin_relative_criterion,
+            pin_lower_bound]

@@ -33,6 +33,7 @@ MUTANTS = {
     "self_loop_replaced": ("{ fill[v] = start[v]; rows[fill[v]++] = v; }",
                            "{ fill[v] = start[v]; rows[fill[v]++] = (v + 1) % n; }"),
     "in_csr_keyed_by_source": ("const int32_t* key = by_dst ? edst : esrc;", "const int32_t* key = esrc;"),
+    "relative_change_over_min": ("const double rel = dr / fmax(r, R[v]);", "const double rel = dr / fmin(r, R[v]);"),
     "expand_before_commit_lost": ("if (rel > tol_f) X[v] = 1;", "if (rel > tol_f && mode == ORC_DFP) X[v] = 1;"),
 }
 

@@ -168,12 +168,11 @@ def main():
     r = torch.from_numpy(np.ascontiguousarray(r0)).to(dev)
 
     # ---- steps
-    dfpr.lib().dfpr_set_timing(g._h, 1)
+    g.set_timing(True)
     step_ms, apply_ms, rank_ms, iters, ever = [], [], [], [], []
-    kern = {"pull0": 0.0, "pull1": 0.0, "pull2": 0.0, "commit": 0.0, "bin": 0.0, "mark": 0.0, "sort": 0.0,
-            "rebuild_out": 0.0, "rebuild_in": 0.0}
-    launches = {"pull0": 0, "pull1": 0, "pull2": 0}
-    work = {"v0": 0, "v1": 0, "v2": 0, "e0": 0, "e1": 0, "e2": 0}
+    kern = {"pull": 0.0, "commit": 0.0, "bin": 0.0, "mark": 0.0, "sort": 0.0, "rebuild_out": 0.0,
+            "rebuild_in": 0.0}
+    pull_launches, v_upd, e_pull = 0, 0, 0
     m_sum = 0
     total = args.warmup + args.steps
     torch.cuda.synchronize()
@@ -199,11 +198,10 @@ def main():
             iters.append(st["iterations"])
             ever.append(st["ever_affected"])
             m_sum += info["m_after"]
-            for k in range(3):
-                kern[f"pull{k}"] += st["ms_pull"][k]
-                launches[f"pull{k}"] += st["pull_launches"][k]
-                work[f"v{k}"] += st["bin_vertices"][k]
-                work[f"e{k}"] += st["bin_edges"][k]
+            kern["pull"] += st["ms_pull"]
+            pull_launches += st["pull_launches"]
+            v_upd += st["vertex_updates"]
+            e_pull += st["edges_pulled"]
             kern["commit"] += st["ms_commit"]
             kern["bin"] += st["ms_bin"]
             kern["mark"] += st["ms_mark"]
@@ -211,7 +209,8 @@ def main():
             kern["rebuild_out"] += info["ms_rebuild"][0]
             kern["rebuild_in"] += info["ms_rebuild"][1]
             log(f"step {i - args.warmup}: {step_ms[-1]:.2f} ms (apply {apply_ms[-1]:.2f}, rank {rank_ms[-1]:.2f}) "
-                f"it={st['iterations']} ever={st['ever_affected']}")
+                f"it={st['iterations']} ever={st['ever_affected']} pull {st['ms_pull']:.2f} "
+                f"commit {st['ms_commit']:.2f} bin {st['ms_bin']:.2f}")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_begin
     K = args.steps
@@ -219,21 +218,18 @@ def main():
     m_mean = m_sum / K
     value = m_mean * K / elapsed
 
-    # ---- roofline of the dominant kernel group (largest summed time)
-    def pull_bytes(k):
-        vb = VERTEX_BYTES_DFP if args.mode in ("df", "dfp") else VERTEX_BYTES_SYNC
-        return work[f"v{k}"] * vb + work[f"e{k}"] * EDGE_BYTES
-
+    # ---- roofline of the dominant kernel (largest summed time)
+    vb = VERTEX_BYTES_DFP if args.mode in ("df", "dfp") else VERTEX_BYTES_SYNC
+    pull_bytes = v_upd * vb + e_pull * EDGE_BYTES
     # rebuild: 4 B read + 4 B write per edge, plus old/new offset and touched flag per row
     rebuild_bytes = K * (8 * m_mean + 9 * n)
-    cand = {f"pull{k}": (kern[f"pull{k}"], pull_bytes(k), max(launches[f"pull{k}"], 1)) for k in range(3)}
-    cand["rebuild"] = (kern["rebuild_out"] + kern["rebuild_in"], 2 * rebuild_bytes, 2 * K)
-    names = {"pull0": "k_pull_lane", "pull1": "k_pull_wave", "pull2": "k_pull_chunk", "rebuild": "k_rebuild"}
+    cand = {"k_pull": (kern["pull"], pull_bytes, max(pull_launches, 1)),
+            "k_rebuild": (kern["rebuild_out"] + kern["rebuild_in"], 2 * rebuild_bytes, 2 * K)}
     dom = max(cand, key=lambda k: cand[k][0])
     ms_k, bytes_k, nl = cand[dom]
     achieved = (bytes_k / nl) / (ms_k / nl * 1e-3) / 1e9 if ms_k > 0 else 0.0
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": names[dom],
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
             "launches": nl, "avg_launch_ms": round(ms_k / nl, 5), "bytes_per_launch": int(bytes_k / nl)}
 
     res = {

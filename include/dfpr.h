@@ -76,27 +76,28 @@ typedef struct {
   double ms_rebuild[2];            /* out-CSR and in-CSR rebuild kernels         */
 } dfpr_batch_info;
 
-/* Result statistics of one dfpr_update_ranks call.  The pull work is split in
- * three degree bins (see dfpr_set_tuning): [0] one vertex per lane, [1] one
- * vertex per wavefront, [2] rows split in chunks over workgroups. */
+/* Number of in-degree bins of the pull kernel (see dfpr_set_tuning). */
+#define DFPR_BINS 6
+
+/* Result statistics of one dfpr_update_ranks call. */
 typedef struct {
-  int32_t iterations;       /* rank iterations run (the one that met tol counts)  */
-  int32_t converged;        /* 1 if the L-inf change fell to tol, 0 at max_iters  */
-  double last_delta;        /* L-inf rank change of the last iteration            */
-  int64_t ever_affected;    /* vertices processed in at least one iteration       */
-  int64_t vertex_updates;   /* sum over iterations of the affected-set size       */
-  int64_t edges_pulled;     /* sum over iterations of the affected in-degrees     */
-  int64_t bin_vertices[3];  /* vertex_updates split by bin                        */
-  int64_t bin_edges[3];     /* edges_pulled split by bin                          */
+  int32_t iterations;              /* rank iterations run (the one that met tol counts) */
+  int32_t converged;               /* 1 if the L-inf change fell to tol, 0 at max_iters */
+  double last_delta;               /* L-inf rank change of the last iteration           */
+  int64_t ever_affected;           /* vertices processed in at least one iteration      */
+  int64_t vertex_updates;          /* sum over iterations of the affected-set size      */
+  int64_t edges_pulled;            /* sum over iterations of the affected in-degrees    */
+  int64_t bin_vertices[DFPR_BINS]; /* vertex_updates split by in-degree bin             */
+  int64_t bin_edges[DFPR_BINS];    /* edges_pulled split by in-degree bin               */
   /* Timings in milliseconds, measured with HIP events on the stream when the
    * TIMING flag is set or timing is on for the graph (dfpr_set_timing). */
-  double ms_total;          /* the whole call                                     */
-  double ms_pull[3];        /* summed duration of each bin's pull kernels         */
-  int32_t pull_launches[3]; /* launches summed in ms_pull                         */
+  double ms_total;                 /* the whole call                                    */
+  double ms_pull;                  /* summed duration of the pull kernel launches       */
+  int32_t pull_launches;           /* launches summed in ms_pull                        */
   int32_t reserved;
-  double ms_commit;         /* commit + expansion kernels                         */
-  double ms_bin;            /* affected-set binning (compaction) kernels          */
-  double ms_mark;           /* initial marking kernels                            */
+  double ms_commit;                /* commit + expansion kernels                        */
+  double ms_bin;                   /* affected-set binning (compaction) kernels         */
+  double ms_mark;                  /* initial marking kernels                           */
 } dfpr_stats;
 
 typedef struct dfpr_graph dfpr_graph;
@@ -151,12 +152,15 @@ int dfpr_apply_batch(dfpr_graph* g, int64_t n_del, const int32_t* del_src, const
 int dfpr_update_ranks(dfpr_graph* g, dfpr_mode mode, const dfpr_params* p, const double* r_prev,
                       double* r_out, void* stream, dfpr_stats* st);
 
-/* Degree thresholds of the pull kernels: vertices with in-degree <= t_thread
- * are processed one per lane, up to t_wave one per wavefront, larger ones one
- * per workgroup.  0 keeps the current value.  EINVAL unless
- * 1 <= t_thread <= t_wave. */
-int dfpr_set_tuning(dfpr_graph* g, int32_t t_thread, int32_t t_wave);
-int dfpr_get_tuning(const dfpr_graph* g, int32_t* t_thread, int32_t* t_wave);
+/* In-degree thresholds of the pull kernel.  An affected vertex v with in-degree
+ * d goes to bin 0 if d <= bounds[0] (one lane per vertex, sum in ascending
+ * source order), bin 1 if d <= bounds[1] (4 lanes), bin 2 if d <= bounds[2]
+ * (16 lanes), bin 3 if d <= bounds[3] (one wavefront), bin 4 if d <= bounds[4]
+ * (one workgroup), else bin 5 (the row split in chunks over workgroups).  The
+ * bins only change performance and the summation order.  EINVAL unless
+ * 1 <= bounds[0] <= ... <= bounds[4]. */
+int dfpr_set_tuning(dfpr_graph* g, const int32_t bounds[5]);
+int dfpr_get_tuning(const dfpr_graph* g, int32_t bounds[5]);
 
 /* Turn HIP-event timing of every apply and update on this graph on (1) or
  * off (0).  Events are recorded between kernels and read after the call's

@@ -152,13 +152,18 @@ class Graph:
                                        _stream_ptr(stream), ctypes.byref(st)))
         return out, st.as_dict()
 
-    def set_tuning(self, t_thread=0, t_wave=0):
-        _check(lib().dfpr_set_tuning(self._h, int(t_thread), int(t_wave)))
+    def set_tuning(self, bounds):
+        """In-degree bin limits of the pull kernel (5 non-decreasing ints >= 1)."""
+        arr = (ctypes.c_int32 * 5)(*[int(x) for x in bounds])
+        _check(lib().dfpr_set_tuning(self._h, arr))
 
     def get_tuning(self):
-        a, b = ctypes.c_int32(), ctypes.c_int32()
-        _check(lib().dfpr_get_tuning(self._h, ctypes.byref(a), ctypes.byref(b)))
-        return a.value, b.value
+        arr = (ctypes.c_int32 * 5)()
+        _check(lib().dfpr_get_tuning(self._h, arr))
+        return list(arr)
+
+    def set_timing(self, on=True):
+        _check(lib().dfpr_set_timing(self._h, 1 if on else 0))
 
 
 def version() -> str:

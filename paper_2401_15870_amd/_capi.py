@@ -37,12 +37,15 @@ class BatchInfo(ctypes.Structure):
         return out
 
 
+BINS = 6
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32), ("last_delta", ctypes.c_double),
                 ("ever_affected", ctypes.c_int64), ("vertex_updates", ctypes.c_int64),
-                ("edges_pulled", ctypes.c_int64), ("bin_vertices", ctypes.c_int64 * 3),
-                ("bin_edges", ctypes.c_int64 * 3), ("ms_total", ctypes.c_double), ("ms_pull", ctypes.c_double * 3),
-                ("pull_launches", ctypes.c_int32 * 3), ("reserved", ctypes.c_int32), ("ms_commit", ctypes.c_double),
+                ("edges_pulled", ctypes.c_int64), ("bin_vertices", ctypes.c_int64 * BINS),
+                ("bin_edges", ctypes.c_int64 * BINS), ("ms_total", ctypes.c_double), ("ms_pull", ctypes.c_double),
+                ("pull_launches", ctypes.c_int32), ("reserved", ctypes.c_int32), ("ms_commit", ctypes.c_double),
                 ("ms_bin", ctypes.c_double), ("ms_mark", ctypes.c_double)]
 
     def as_dict(self):
@@ -71,9 +74,9 @@ def declare(lib):
     lib.dfpr_apply_batch.restype = ctypes.c_int
     lib.dfpr_update_ranks.argtypes = [P, ctypes.c_int, ctypes.POINTER(Params), P, P, P, ctypes.POINTER(Stats)]
     lib.dfpr_update_ranks.restype = ctypes.c_int
-    lib.dfpr_set_tuning.argtypes = [P, i32, i32]
+    lib.dfpr_set_tuning.argtypes = [P, ctypes.POINTER(i32)]
     lib.dfpr_set_tuning.restype = ctypes.c_int
-    lib.dfpr_get_tuning.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.dfpr_get_tuning.argtypes = [P, ctypes.POINTER(i32)]
     lib.dfpr_get_tuning.restype = ctypes.c_int
     lib.dfpr_set_timing.argtypes = [P, ctypes.c_int]
     lib.dfpr_set_timing.restype = ctypes.c_int

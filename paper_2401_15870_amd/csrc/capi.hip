@@ -170,18 +170,23 @@ int dfpr_update_ranks(dfpr_graph* g, dfpr_mode mode, const dfpr_params* p, const
   return guarded(g, [&] { return update_ranks(g, mode, prm, r_prev, r_out, (hipStream_t)stream, st); });
 }
 
-int dfpr_set_tuning(dfpr_graph* g, int32_t t_thread, int32_t t_wave) {
+int dfpr_set_tuning(dfpr_graph* g, const int32_t bounds[5]) {
   clear_error();
+  if (!bounds) {
+    set_error("bounds is null");
+    return DFPR_EINVAL;
+  }
   return guarded(g, [&] {
-    const int32_t a = t_thread > 0 ? t_thread : g->t_thread;
-    const int32_t b = t_wave > 0 ? t_wave : g->t_wave;
-    if (a < 1 || b < a) {
-      set_error("need 1 <= t_thread <= t_wave, got %d, %d", a, b);
+    bool ok = bounds[0] >= 1;
+    for (int i = 1; i < 5; i++) ok = ok && bounds[i] >= bounds[i - 1];
+    if (!ok) {
+      set_error("need 1 <= bounds[0] <= ... <= bounds[4]");
       return (int)DFPR_EINVAL;
     }
-    if (a != g->t_thread || b != g->t_wave) g->all_bins_valid = false;
-    g->t_thread = a;
-    g->t_wave = b;
+    for (int i = 0; i < 5; i++) {
+      if (g->bounds[i] != bounds[i]) g->all_bins_valid = false;
+      g->bounds[i] = bounds[i];
+    }
     return (int)DFPR_OK;
   });
 }
@@ -194,14 +199,13 @@ int dfpr_set_timing(dfpr_graph* g, int on) {
   });
 }
 
-int dfpr_get_tuning(const dfpr_graph* g, int32_t* t_thread, int32_t* t_wave) {
+int dfpr_get_tuning(const dfpr_graph* g, int32_t bounds[5]) {
   clear_error();
-  if (!g || !t_thread || !t_wave) {
+  if (!g || !bounds) {
     set_error("null argument");
     return DFPR_EINVAL;
   }
-  *t_thread = g->t_thread;
-  *t_wave = g->t_wave;
+  for (int i = 0; i < 5; i++) bounds[i] = g->bounds[i];
   return DFPR_OK;
 }
 

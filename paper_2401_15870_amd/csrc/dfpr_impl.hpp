@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstddef>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -113,20 +114,34 @@ struct Csr {
   int32_t* idx = nullptr;  // capacity
 };
 
-// Per-update control block in device memory, read back once per iteration.
-struct IterCtl {
-  unsigned long long dR[2];  // L-inf change (bit pattern of a non-negative double), double-buffered
-  int64_t bin_end[3];        // worklist end offsets of the thread, wave and chunk bins
-  int64_t bin_edges[3];      // summed in-degree of each bin
-  int64_t n_apply[6];        // apply: eff ins, eff del, self dels, eff count, error flag, m_new
-  int64_t big_count;         // entries in the big out-row list
-  int64_t ever_count;        // vertices processed at least once in this update
-};
+// Reductions that many workgroups feed go to kSlots accumulators, each on its
+// own 128-byte line (workgroup b uses slot b % kSlots), and one small kernel
+// folds the slots: a single hot address would serialise the atomics of every
+// workgroup on the chip.
+constexpr int kSlots = 64;
+constexpr int kSlotStride = 16;  // 16 x 8 bytes = 128 bytes between slots
+constexpr int kBins = DFPR_BINS;
+enum AccRow : int { kAccEdges0 = 0, kAccEver = kBins, kAccRows = kBins + 1 };
 
-// Pull chunking for the workgroup bin and out-row chunking for big expansions.
-constexpr int kPullChunk = 1024;   // in-edges per workgroup work item
-constexpr int kMarkChunk = 2048;   // out-edges per workgroup work item
-constexpr int kBigRow = 4096;      // out-rows longer than this go to the chunked path
+// Per-update control block in device memory.  The compact head is read back
+// once per iteration; the slot arrays are the spread accumulators.
+struct IterCtl {
+  unsigned long long dR;     // L-inf change of the last finished pull (double bits)
+  int64_t bin_end[kBins];    // worklist end offset of each bin
+  int64_t bin_edges[kBins];  // summed in-degree of each bin
+  int64_t n_apply[6];        // apply: eff ins, eff del, self dels, eff count, error flag, m_new
+  int64_t big_count;         // entries in the long out-row list
+  int64_t ever_count;        // vertices processed at least once in this update
+  int64_t pad[2];
+  unsigned long long dR_slots[kSlots * kSlotStride];
+  unsigned long long acc_slots[kAccRows][kSlots * kSlotStride];
+};
+constexpr size_t kCtlHead = offsetof(IterCtl, pad);
+
+// Work split of the pull kernel's chunked bin and of long out-rows.
+constexpr int kPullChunk = 4096;   // in-edges per workgroup work item (bin 5)
+constexpr int kMarkChunk = 4096;   // out-edges per workgroup work item
+constexpr int kBigRow = 4096;      // out-rows longer than this go to the chunked marking
 
 }  // namespace dfpr
 
@@ -154,14 +169,14 @@ struct dfpr_graph {
   int32_t* delta_out = nullptr, *delta_in = nullptr;      // row length changes
   int32_t* worklist = nullptr;   // n entries: thread bin | wave bin | block bin
   int32_t* all_bins = nullptr;   // n entries: every vertex, binned (Static/ND)
-  int64_t all_bin_end[3] = {0, 0, 0};
-  int64_t all_bin_edges[3] = {0, 0, 0};
+  int64_t all_bin_end[DFPR_BINS] = {0};
+  int64_t all_bin_edges[DFPR_BINS] = {0};
   bool all_bins_valid = false;
   dfpr::IterCtl* ctl = nullptr;      // device
   dfpr::IterCtl* ctl_host = nullptr; // pinned host mirror
   int64_t* scan_tmp = nullptr;       // block sums for scans over n
   size_t scan_tmp_n = 0;
-  int64_t* bin_blk = nullptr;        // per-block bin counts (3 * ceil(n/2048) + 1)
+  int64_t* bin_blk = nullptr;        // per-block bin counts (kBins * ceil(n/2048) + 1)
   int64_t* chunk_pre = nullptr;      // n+1: chunk prefix of the workgroup bin
   double* partial = nullptr;         // partial sums of pull chunks
   int64_t partial_n = 0;
@@ -170,7 +185,8 @@ struct dfpr_graph {
   // growable batch scratch
   dfpr::DevBuf keys_a, keys_b, keys_c, sort_hist, eff_pre, batch_in, keys_in;
   bool pending_any = false;  // an apply happened since the last DF/DF-P update
-  int32_t t_thread = 12, t_wave = 1024;
+  int32_t bounds[5] = {4, 16, 64, 512, 4096};  // in-degree bin limits (dfpr_set_tuning)
+  int32_t* arrive = nullptr;  // n: per-vertex chunk arrival counters of bin 5
   bool timing = false;        // record HIP-event timings of every call
   dfpr::EventPool pool;
 };

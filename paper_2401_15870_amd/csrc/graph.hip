@@ -219,8 +219,8 @@ struct StoreI64b {
 // inserted y at k + #old(<y) - #del(<y), where the counts come from binary
 // searches over the row's sorted effective entries (delpre = prefix count of
 // deletions in that list).
-__global__ void __launch_bounds__(256) k_rebuild(const int32_t* ooff, const int32_t* oidx, const int32_t* noff,
-                                                 int32_t* nidx, const uint8_t* touched, const uint64_t* eff,
+__global__ void __launch_bounds__(256) k_rebuild(const int32_t* __restrict__ ooff, const int32_t* __restrict__ oidx,
+                                                 const int32_t* __restrict__ noff, int32_t* __restrict__ nidx, const uint8_t* touched, const uint64_t* eff,
                                                  const int64_t* delpre, const int64_t* count, int b, int32_t n,
                                                  int64_t* err) {
   const int lane = lane_id();
@@ -239,7 +239,15 @@ __global__ void __launch_bounds__(256) k_rebuild(const int32_t* ooff, const int3
         if (lane == 0) atomicOr((unsigned long long*)err, 2ull);
         continue;
       }
-      for (int32_t p = s0 + lane; p < s1; p += kWave) nidx[p + shift] = oidx[p];
+      int32_t p = s0 + lane;
+      for (; p + 3 * kWave < s1; p += 4 * kWave) {
+        const int32_t x0 = oidx[p], x1 = oidx[p + kWave], x2 = oidx[p + 2 * kWave], x3 = oidx[p + 3 * kWave];
+        nidx[p + shift] = x0;
+        nidx[p + kWave + shift] = x1;
+        nidx[p + 2 * kWave + shift] = x2;
+        nidx[p + 3 * kWave + shift] = x3;
+      }
+      for (; p < s1; p += kWave) nidx[p + shift] = oidx[p];
       continue;
     }
     for (int32_t r = r0; r < rend; r++) {
@@ -324,7 +332,9 @@ static int alloc_rank_scratch(dfpr_graph* g) {
   DFPR_TRY(dalloc(&g->all_bins, n));
   DFPR_TRY(dalloc(&g->ctl, 1));
   const int64_t nbins = ((int64_t)n + 2047) / 2048;
-  DFPR_TRY(dalloc(&g->bin_blk, (size_t)(3 * nbins + 2)));
+  DFPR_TRY(dalloc(&g->bin_blk, (size_t)(kBins * nbins + 2)));
+  DFPR_TRY(dalloc(&g->arrive, n));
+  DFPR_HIP(hipMemset(g->arrive, 0, n * sizeof(int32_t)));
   DFPR_TRY(dalloc(&g->chunk_pre, n + 1));
   DFPR_TRY(dalloc(&g->big_list, n));
   DFPR_TRY(dalloc(&g->big_pre, n + 1));
@@ -384,6 +394,7 @@ int graph_destroy(dfpr_graph* g) {
   dfree(g->big_list);
   dfree(g->big_pre);
   dfree(g->partial);
+  dfree(g->arrive);
   if (g->ctl_host) (void)hipHostFree(g->ctl_host);
   g->ctl_host = nullptr;
   g->keys_a.release();

@@ -1,16 +1,22 @@
 // Rank engine: Static, Naive-dynamic, Dynamic Frontier and Dynamic Frontier
 // with Pruning (Algorithm 1; Equations 1 and 2), pull-based (Section 4.4),
 // iterated synchronously: every read of iteration i sees the ranks of
-// iteration i, prunes and marks take effect in iteration i+1.
+// iteration i; prunes and marks take effect in iteration i+1.
 //
 // Per iteration:
-//   bin      affected flags -> worklist split by in-degree (lane / wave / chunk)
-//   pull     c = sum of contrib[u] over in(v); the Equation 1 or 2 rank; the
-//            L-inf change reduced per workgroup into one 64-bit atomicMax
+//   pull     one fused launch over the affected set, binned by in-degree:
+//            c = sum of contrib[u] over in(v), the rank of Equation 1 or 2,
+//            |r - R[v]| folded into a spread max
 //   commit   contrib[v] = R[v]/|out(v)| for the processed vertices (DF, DF-P)
-//            and marking of out(v) for vertices whose relative change > tau_f
+//            and marking of out(v) where the relative change exceeds tau_f
+//   bin      next affected flags -> worklist split in degree bins
 // Static and ND process every vertex and ping-pong two rank/contribution
 // buffers instead of committing.
+//
+// Memory-level parallelism is the design rule: every lane keeps up to four
+// independent gathers in flight, short rows are processed by sub-wave groups,
+// out-row marking is balanced across the wave by a prefix sum of row lengths,
+// and no reduction funnels the whole chip into one atomic address.
 #include <algorithm>
 
 #include "prim.hpp"
@@ -29,8 +35,20 @@ struct PullArgs {
   double* cw;      // Static/ND: contributions of the next iteration
   uint8_t* next;   // DF/DF-P: affected in the next iteration
   uint8_t* xflag;  // DF/DF-P: expands
-  unsigned long long* dR;
+  unsigned long long* dR_slots;
+  double* partial;   // bin 5: per-chunk partial sums
+  int32_t* arrive;   // bin 5: chunks finished per vertex
   double alpha, C0, tf, tp;
+};
+
+// Bin k covers worklist [lo[k], hi[k]) and workgroups [blk[k], blk[k+1]).
+struct PullLayout {
+  int64_t lo[kBins], hi[kBins];
+  int32_t blk[kBins + 1];
+};
+
+struct Bounds {
+  int32_t b[5];
 };
 
 // Equation 1 (DF, Static, ND) or Equation 2 (DF-P) for vertex v from its
@@ -58,9 +76,9 @@ __device__ __forceinline__ double vertex_finish(const PullArgs& a, int32_t v, do
   return dr;
 }
 
-// Workgroup max of non-negative doubles, then one atomicMax on the bit
-// pattern (monotone for non-negative IEEE doubles).
-__device__ __forceinline__ void block_max_commit(double x, unsigned long long* dR) {
+// Workgroup max of non-negative doubles into one of kSlots spread slots (the
+// bit pattern of a non-negative IEEE double orders like the value).
+__device__ __forceinline__ void block_max_to_slots(double x, unsigned long long* slots) {
   __shared__ double sh[1024 / kWave];
   x = wave_max(x);
   if (lane_id() == 0) sh[threadIdx.x / kWave] = x;
@@ -68,130 +86,206 @@ __device__ __forceinline__ void block_max_commit(double x, unsigned long long* d
   if (threadIdx.x == 0) {
     double m = 0.0;
     for (int w = 0; w < (int)(blockDim.x / kWave); w++) m = fmax(m, sh[w]);
-    if (m > 0.0) atomicMax(dR, (unsigned long long)__double_as_longlong(m));
+    if (m > 0.0) atomicMax(&slots[(blockIdx.x % kSlots) * kSlotStride], (unsigned long long)__double_as_longlong(m));
   }
 }
 
-// ---- lane bin: one vertex per lane, left fold in ascending source order
-template <int MODE>
-__global__ void __launch_bounds__(256) k_pull_lane(PullArgs a, const int32_t* __restrict__ wl, int64_t lo,
-                                                   int64_t hi) {
-  double mx = 0.0;
-  for (int64_t k = lo + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < hi;
-       k += (int64_t)gridDim.x * blockDim.x) {
+// ---- bins 0-3: groups of G lanes per vertex.  G = 1 folds in ascending
+// source order (the order of the algorithm's sum); G > 1 lanes take strided
+// edges and combine with a butterfly.  Up to four gathers in flight per lane.
+template <int MODE, int G>
+__device__ __forceinline__ void pull_groups(const PullArgs& a, const int32_t* __restrict__ wl, int64_t lo, int64_t hi,
+                                            int lb, int nb, double& mx) {
+  constexpr int kGroups = 256 / G;
+  const int gl = threadIdx.x % G;
+  for (int64_t k = lo + (int64_t)lb * kGroups + threadIdx.x / G; k < hi; k += (int64_t)nb * kGroups) {
     const int32_t v = wl[k];
     const int32_t s = a.in_off[v], e = a.in_off[v + 1];
     double c = 0.0;
-    for (int32_t p = s; p < e; p++) c = c + a.contrib[a.in_idx[p]];
-    mx = fmax(mx, vertex_finish<MODE>(a, v, c));
+    if (G == 1) {
+      int32_t p = s;
+      for (; p + 4 <= e; p += 4) {
+        const int32_t u0 = a.in_idx[p], u1 = a.in_idx[p + 1], u2 = a.in_idx[p + 2], u3 = a.in_idx[p + 3];
+        const double x0 = a.contrib[u0], x1 = a.contrib[u1], x2 = a.contrib[u2], x3 = a.contrib[u3];
+        c = c + x0;
+        c = c + x1;
+        c = c + x2;
+        c = c + x3;
+      }
+      const int32_t r = e - p;  // 0..3 left
+      const int32_t u0 = r > 0 ? a.in_idx[p] : 0;
+      const int32_t u1 = r > 1 ? a.in_idx[p + 1] : 0;
+      const int32_t u2 = r > 2 ? a.in_idx[p + 2] : 0;
+      const double x0 = r > 0 ? a.contrib[u0] : 0.0;
+      const double x1 = r > 1 ? a.contrib[u1] : 0.0;
+      const double x2 = r > 2 ? a.contrib[u2] : 0.0;
+      if (r > 0) c = c + x0;
+      if (r > 1) c = c + x1;
+      if (r > 2) c = c + x2;
+    } else {
+      int32_t p = s + gl;
+      for (; p + 3 * G < e; p += 4 * G) {
+        const int32_t u0 = a.in_idx[p], u1 = a.in_idx[p + G], u2 = a.in_idx[p + 2 * G], u3 = a.in_idx[p + 3 * G];
+        const double x0 = a.contrib[u0], x1 = a.contrib[u1], x2 = a.contrib[u2], x3 = a.contrib[u3];
+        c += x0;
+        c += x1;
+        c += x2;
+        c += x3;
+      }
+      for (; p < e; p += G) c += a.contrib[a.in_idx[p]];
+#pragma unroll
+      for (int o = G / 2; o >= 1; o >>= 1) c += __shfl_xor(c, o, kWave);
+    }
+    if (gl == 0) mx = fmax(mx, vertex_finish<MODE>(a, v, c));
   }
-  block_max_commit(mx, a.dR);
 }
 
-// ---- wave bin: one vertex per wavefront; per-lane strided sums + butterfly
+// Strided sum of contrib over in_idx[s, e) by the 256 threads of a workgroup,
+// combined in a fixed order; valid in thread 0.
+__device__ __forceinline__ double block_row_sum(const PullArgs& a, int32_t s, int32_t e, double* sh) {
+  double part = 0.0;
+  int32_t p = s + (int32_t)threadIdx.x;
+  for (; p + 3 * 256 < e; p += 4 * 256) {
+    const int32_t u0 = a.in_idx[p], u1 = a.in_idx[p + 256], u2 = a.in_idx[p + 512], u3 = a.in_idx[p + 768];
+    const double x0 = a.contrib[u0], x1 = a.contrib[u1], x2 = a.contrib[u2], x3 = a.contrib[u3];
+    part += x0;
+    part += x1;
+    part += x2;
+    part += x3;
+  }
+  for (; p < e; p += 256) part += a.contrib[a.in_idx[p]];
+  part = wave_sum(part);
+  if (lane_id() == 0) sh[threadIdx.x / kWave] = part;
+  __syncthreads();
+  double c = 0.0;
+  if (threadIdx.x == 0) c = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+  __syncthreads();
+  return c;
+}
+
+// ---- bin 4: one workgroup per vertex
 template <int MODE>
-__global__ void __launch_bounds__(256) k_pull_wave(PullArgs a, const int32_t* __restrict__ wl, int64_t lo,
-                                                   int64_t hi) {
-  const int lane = lane_id();
-  const int64_t nw = (int64_t)gridDim.x * (blockDim.x / kWave);
-  double mx = 0.0;
-  for (int64_t k = lo + blockIdx.x * (int64_t)(blockDim.x / kWave) + threadIdx.x / kWave; k < hi; k += nw) {
+__device__ __forceinline__ void pull_block(const PullArgs& a, const int32_t* __restrict__ wl, int64_t lo, int64_t hi,
+                                           int lb, int nb, double& mx) {
+  __shared__ double sh[256 / kWave];
+  for (int64_t k = lo + lb; k < hi; k += nb) {
     const int32_t v = wl[k];
-    const int32_t s = a.in_off[v], e = a.in_off[v + 1];
-    double part = 0.0;
-    for (int32_t p = s + lane; p < e; p += kWave) part += a.contrib[a.in_idx[p]];
-    const double c = wave_sum(part);
-    if (lane == 0) mx = fmax(mx, vertex_finish<MODE>(a, v, c));
+    const double c = block_row_sum(a, a.in_off[v], a.in_off[v + 1], sh);
+    if (threadIdx.x == 0) mx = fmax(mx, vertex_finish<MODE>(a, v, c));
   }
-  block_max_commit(mx, a.dR);
 }
 
-// ---- chunk bin: rows split into kPullChunk-edge work items over workgroups;
-// partial sums land in `partial`, combined in chunk order by k_pull_chunk_finish.
-struct LoadChunks {
-  const int32_t* wl;
-  const int32_t* in_off;
-  int64_t lo;
-  __device__ int64_t operator()(int64_t i) const {
-    const int32_t v = wl[lo + i];
-    return ((int64_t)(in_off[v + 1] - in_off[v]) + kPullChunk - 1) / kPullChunk;
+// ---- bin 5: rows split in kPullChunk-edge chunks dealt round-robin to the
+// bin's workgroups.  Each chunk's sum goes to `partial`; the workgroup that
+// finishes a vertex's last chunk (arrival counter) adds the partials in chunk
+// order and computes the rank.
+template <int MODE>
+__device__ __forceinline__ void pull_chunks(const PullArgs& a, const int32_t* __restrict__ wl, int64_t lo, int64_t hi,
+                                            int lb, int nb, double& mx) {
+  __shared__ double sh[256 / kWave];
+  __shared__ int last;
+  int64_t base = 0;
+  for (int64_t j = 0; j < hi - lo; j++) {
+    const int32_t v = wl[lo + j];
+    const int32_t s = a.in_off[v], e = a.in_off[v + 1];
+    const int64_t nch = ((int64_t)(e - s) + kPullChunk - 1) / kPullChunk;
+    int64_t q = base + ((lb - base % nb) % nb + nb) % nb;
+    for (; q < base + nch; q += nb) {
+      const int32_t cs = s + (int32_t)((q - base) * kPullChunk);
+      const int32_t ce = min(cs + kPullChunk, e);
+      const double part = block_row_sum(a, cs, ce, sh);
+      if (threadIdx.x == 0) {
+        a.partial[q] = part;
+        __threadfence();
+        last = atomicAdd(&a.arrive[j], 1) == (int)(nch - 1);
+      }
+      __syncthreads();
+      if (threadIdx.x == 0 && last) {
+        __threadfence();
+        double c = 0.0;
+        for (int64_t t = base; t < base + nch; t++)
+          c += __hip_atomic_load(&a.partial[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        a.arrive[j] = 0;
+        mx = fmax(mx, vertex_finish<MODE>(a, v, c));
+      }
+      __syncthreads();
+    }
+    base += nch;
   }
-};
-struct StoreI64r {
-  int64_t* a;
-  __device__ void operator()(int64_t i, int64_t v) const { a[i] = v; }
-};
+}
 
-__device__ __forceinline__ int64_t upper_bound_i64(const int64_t* a, int64_t lo, int64_t hi, int64_t x) {
-  while (lo < hi) {
-    int64_t mid = lo + ((hi - lo) >> 1);
-    if (a[mid] <= x) lo = mid + 1; else hi = mid;
+template <int MODE>
+__global__ void __launch_bounds__(256) k_pull(PullArgs a, const int32_t* __restrict__ wl, PullLayout L) {
+  const int b = blockIdx.x;
+  int k = 0;
+  while (k < kBins - 1 && b >= L.blk[k + 1]) k++;
+  const int lb = b - L.blk[k], nb = L.blk[k + 1] - L.blk[k];
+  double mx = 0.0;
+  switch (k) {
+    case 0: pull_groups<MODE, 1>(a, wl, L.lo[0], L.hi[0], lb, nb, mx); break;
+    case 1: pull_groups<MODE, 4>(a, wl, L.lo[1], L.hi[1], lb, nb, mx); break;
+    case 2: pull_groups<MODE, 16>(a, wl, L.lo[2], L.hi[2], lb, nb, mx); break;
+    case 3: pull_groups<MODE, 64>(a, wl, L.lo[3], L.hi[3], lb, nb, mx); break;
+    case 4: pull_block<MODE>(a, wl, L.lo[4], L.hi[4], lb, nb, mx); break;
+    default: pull_chunks<MODE>(a, wl, L.lo[5], L.hi[5], lb, nb, mx); break;
+  }
+  block_max_to_slots(mx, a.dR_slots);
+}
+
+// ---- marking of out-rows, balanced over the wave: every lane that wants its
+// row [os, oe) marked contributes its length to a wave prefix sum, then the
+// 64 lanes sweep the concatenated rows four edges at a time, locating each
+// edge's row by a binary search over the lanes' start offsets (cross-lane
+// reads).  Rows longer than kBigRow go to big_list for the chunked pass.
+// Must be called with all 64 lanes active.
+__device__ __forceinline__ int seg_of(int32_t st, int32_t e) {
+  int lo = 0, hi = kWave;
+#pragma unroll
+  for (int i = 0; i < 6; i++) {
+    const int mid = (lo + hi) >> 1;
+    const int32_t sm = __shfl(st, mid, kWave);
+    if (sm <= e) lo = mid; else hi = mid;
   }
   return lo;
 }
 
-__global__ void __launch_bounds__(256) k_pull_chunk(PullArgs a, const int32_t* __restrict__ wl, int64_t lo,
-                                                    int64_t nv, const int64_t* __restrict__ chunk_pre,
-                                                    double* partial) {
-  __shared__ double sh[256 / kWave];
-  const int64_t total = chunk_pre[nv];
-  for (int64_t q = blockIdx.x; q < total; q += gridDim.x) {
-    const int64_t j = upper_bound_i64(chunk_pre, 0, nv + 1, q) - 1;
-    const int32_t v = wl[lo + j];
-    const int32_t s = a.in_off[v] + (int32_t)((q - chunk_pre[j]) * kPullChunk);
-    const int32_t e = min(s + kPullChunk, a.in_off[v + 1]);
-    double part = 0.0;
-    for (int32_t p = s + (int32_t)threadIdx.x; p < e; p += (int32_t)blockDim.x) part += a.contrib[a.in_idx[p]];
-    part = wave_sum(part);
-    if (lane_id() == 0) sh[threadIdx.x / kWave] = part;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double t = 0.0;
-      for (int w = 0; w < 256 / kWave; w++) t += sh[w];
-      partial[q] = t;
-    }
-    __syncthreads();
-  }
-}
-
-template <int MODE>
-__global__ void __launch_bounds__(256) k_pull_chunk_finish(PullArgs a, const int32_t* __restrict__ wl, int64_t lo,
-                                                           int64_t nv, const int64_t* __restrict__ chunk_pre,
-                                                           const double* __restrict__ partial) {
-  double mx = 0.0;
-  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < nv; j += (int64_t)gridDim.x * blockDim.x) {
-    double c = 0.0;
-    for (int64_t q = chunk_pre[j]; q < chunk_pre[j + 1]; q++) c += partial[q];
-    mx = fmax(mx, vertex_finish<MODE>(a, wl[lo + j], c));
-  }
-  block_max_commit(mx, a.dR);
-}
-
-// ---- marking of out-rows.  Short rows by their lane, medium rows by the
-// whole wavefront, rows longer than kBigRow appended to big_list for the
-// chunked pass.  Used by the initial marking and by the expansion.
-__device__ __forceinline__ void mark_out_rows(bool want, int32_t v, int32_t os, int32_t oe,
-                                              const int32_t* __restrict__ out_idx, uint8_t* flags,
-                                              int32_t* big_list, int64_t* big_count) {
-  const int32_t d = oe - os;
-  if (want && d <= 16)
-    for (int32_t p = os; p < oe; p++) flags[out_idx[p]] = 1;
-  uint64_t mask = __ballot(want && d > 16 && d <= kBigRow);
-  while (mask) {
-    const int l = __ffsll((long long)mask) - 1;
-    mask &= mask - 1;
-    const int32_t s = __shfl(os, l, kWave), e = __shfl(oe, l, kWave);
-    for (int32_t p = s + lane_id(); p < e; p += kWave) flags[out_idx[p]] = 1;
-  }
-  if (want && d > kBigRow) {
+__device__ __forceinline__ void wave_mark_rows(bool want, int32_t v, int32_t os, int32_t oe,
+                                               const int32_t* __restrict__ out_idx, uint8_t* flags,
+                                               int32_t* big_list, int64_t* big_count) {
+  const int lane = lane_id();
+  int32_t len = want ? oe - os : 0;
+  if (len > kBigRow) {
     const int64_t pos = (int64_t)atomicAdd((unsigned long long*)big_count, 1ull);
     big_list[pos] = v;
+    len = 0;
+  }
+  int32_t incl = len;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int32_t y = __shfl_up(incl, o, kWave);
+    if (lane >= o) incl += y;
+  }
+  const int32_t total = __shfl(incl, kWave - 1, kWave);
+  const int32_t st = incl - len;
+  for (int32_t e0 = 0; e0 < total; e0 += 4 * kWave) {
+    int32_t w[4];
+#pragma unroll
+    for (int t = 0; t < 4; t++) {
+      const int32_t e = e0 + lane + t * kWave;
+      const bool ok = e < total;
+      const int j = seg_of(st, ok ? e : 0);
+      const int32_t p = __shfl(os, j, kWave) + (e - __shfl(st, j, kWave));
+      w[t] = ok ? out_idx[p] : -1;
+    }
+#pragma unroll
+    for (int t = 0; t < 4; t++)
+      if (w[t] >= 0) flags[w[t]] = 1;
   }
 }
 
 // Initial marking (Algorithm 1): for every pending source u mark out(u) in
 // G^t; the targets of effective deletions (the rest of out(u) in G^{t-1})
-// were already set in `flags` when the batch was applied.
+// were set in `flags` when the batch was applied.
 __global__ void __launch_bounds__(256) k_mark_pending(uint8_t* pend_src, int32_t n, const int32_t* __restrict__ out_off,
                                                       const int32_t* __restrict__ out_idx, uint8_t* flags,
                                                       int32_t* big_list, int64_t* big_count) {
@@ -206,7 +300,7 @@ __global__ void __launch_bounds__(256) k_mark_pending(uint8_t* pend_src, int32_t
       os = out_off[u];
       oe = out_off[u + 1];
     }
-    mark_out_rows(want, (int32_t)u, os, oe, out_idx, flags, big_list, big_count);
+    wave_mark_rows(want, (int32_t)u, os, oe, out_idx, flags, big_list, big_count);
   }
 }
 
@@ -233,11 +327,11 @@ __global__ void __launch_bounds__(256) k_commit_expand(const int32_t* __restrict
         want = true;
       }
     }
-    mark_out_rows(want, v, os, oe, out_idx, next, big_list, big_count);
+    wave_mark_rows(want, v, os, oe, out_idx, next, big_list, big_count);
   }
 }
 
-// Chunk prefix of the big out-row list (one workgroup; the list is short).
+// Chunk prefix of the long out-row list (one workgroup; the list is short).
 __global__ void __launch_bounds__(1024) k_big_scan(const int32_t* big_list, const int64_t* big_count,
                                                    const int32_t* out_off, int64_t* big_pre) {
   __shared__ int64_t sh[1024 / kWave + 1];
@@ -260,6 +354,14 @@ __global__ void __launch_bounds__(1024) k_big_scan(const int32_t* big_list, cons
   if (threadIdx.x == 0) big_pre[nb] = tot;
 }
 
+__device__ __forceinline__ int64_t upper_bound_i64(const int64_t* a, int64_t lo, int64_t hi, int64_t x) {
+  while (lo < hi) {
+    int64_t mid = lo + ((hi - lo) >> 1);
+    if (a[mid] <= x) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
 __global__ void __launch_bounds__(256) k_big_mark(const int32_t* big_list, const int64_t* big_count,
                                                   const int64_t* big_pre, const int32_t* __restrict__ out_off,
                                                   const int32_t* __restrict__ out_idx, uint8_t* flags) {
@@ -270,87 +372,171 @@ __global__ void __launch_bounds__(256) k_big_mark(const int32_t* big_list, const
     const int32_t v = big_list[j];
     const int32_t s = out_off[v] + (int32_t)((q - big_pre[j]) * kMarkChunk);
     const int32_t e = min(s + kMarkChunk, out_off[v + 1]);
-    for (int32_t p = s + (int32_t)threadIdx.x; p < e; p += (int32_t)blockDim.x) flags[out_idx[p]] = 1;
+    for (int32_t p = s + (int32_t)threadIdx.x; p < e; p += 4 * (int32_t)blockDim.x) {
+      int32_t w[4];
+#pragma unroll
+      for (int t = 0; t < 4; t++) w[t] = p + t * (int32_t)blockDim.x < e ? out_idx[p + t * blockDim.x] : -1;
+#pragma unroll
+      for (int t = 0; t < 4; t++)
+        if (w[t] >= 0) flags[w[t]] = 1;
+    }
   }
 }
 
 // ---- binning: affected vertices (flags == nullptr: all) -> worklist in
-// ascending vertex order within each bin; bins laid out back to back.
+// ascending vertex order within each bin, bins back to back.  Each thread
+// owns 8 consecutive vertices (one 8-byte flag load).
 constexpr int kBinItems = 8;
 constexpr int kBinTile = 256 * kBinItems;
-constexpr int kBinShift = 20;  // three 20-bit counters packed in one int64
+constexpr int kBinShift = 20;  // three 20-bit counters per int64
 
-__device__ __forceinline__ int bin_of(int32_t deg, int32_t t1, int32_t t2) { return deg <= t1 ? 0 : (deg <= t2 ? 1 : 2); }
+__device__ __forceinline__ int bin_of(int32_t d, const Bounds& B) {
+  return d <= B.b[0] ? 0 : d <= B.b[1] ? 1 : d <= B.b[2] ? 2 : d <= B.b[3] ? 3 : d <= B.b[4] ? 4 : 5;
+}
+
+// Flags of vertices base..base+7 as a bit mask.
+__device__ __forceinline__ unsigned tile_flags(const uint8_t* flags, int64_t base, int32_t n) {
+  unsigned m = 0;
+  if (base + kBinItems <= n) {
+    if (flags == nullptr) return 0xFFu;
+    const uint64_t w = *reinterpret_cast<const uint64_t*>(flags + base);
+#pragma unroll
+    for (int j = 0; j < kBinItems; j++) m |= ((w >> (8 * j)) & 0xFFull) ? (1u << j) : 0u;
+    return m;
+  }
+  for (int j = 0; j < kBinItems; j++)
+    if (base + j < n && (flags == nullptr || flags[base + j])) m |= 1u << j;
+  return m;
+}
 
 __global__ void __launch_bounds__(256) k_bin_count(const uint8_t* flags, const int32_t* __restrict__ in_off, int32_t n,
-                                                   int32_t t1, int32_t t2, int64_t* blk, int64_t nb,
-                                                   int64_t* bin_edges) {
+                                                   Bounds B, int64_t* blk, int64_t nb, unsigned long long* acc) {
   __shared__ int64_t sh[256 / kWave + 1];
+  __shared__ int64_t she[256 / kWave][kBins];
   const int64_t base = (int64_t)blockIdx.x * kBinTile + (int64_t)threadIdx.x * kBinItems;
-  int64_t packed = 0, e0 = 0, e1 = 0, e2 = 0;
+  const unsigned m = tile_flags(flags, base, n);
+  int64_t p0 = 0, p1 = 0;
+  int64_t ed[kBins] = {0, 0, 0, 0, 0, 0};
+  if (m) {
+    int32_t o[kBinItems + 1];
 #pragma unroll
-  for (int j = 0; j < kBinItems; j++) {
-    const int64_t v = base + j;
-    if (v < n && (flags == nullptr || flags[v])) {
-      const int32_t deg = in_off[v + 1] - in_off[v];
-      const int b = bin_of(deg, t1, t2);
-      packed += (int64_t)1 << (kBinShift * b);
-      if (b == 0) e0 += deg; else if (b == 1) e1 += deg; else e2 += deg;
+    for (int j = 0; j <= kBinItems; j++) o[j] = base + j <= n ? in_off[base + j] : 0;
+#pragma unroll
+    for (int j = 0; j < kBinItems; j++) {
+      if (m & (1u << j)) {
+        const int32_t d = o[j + 1] - o[j];
+        const int b = bin_of(d, B);
+        if (b < 3) p0 += (int64_t)1 << (kBinShift * b); else p1 += (int64_t)1 << (kBinShift * (b - 3));
+#pragma unroll
+        for (int t = 0; t < kBins; t++) ed[t] += (t == b) ? d : 0;
+      }
     }
   }
-  int64_t tot;
-  block_exclusive_scan(packed, sh, &tot);
+  int64_t t0, t1;
+  block_exclusive_scan(p0, sh, &t0);
+  block_exclusive_scan(p1, sh, &t1);
   if (threadIdx.x == 0) {
-    const int64_t m = ((int64_t)1 << kBinShift) - 1;
-    blk[0 * nb + blockIdx.x] = tot & m;
-    blk[1 * nb + blockIdx.x] = (tot >> kBinShift) & m;
-    blk[2 * nb + blockIdx.x] = (tot >> (2 * kBinShift)) & m;
+    const int64_t mk = ((int64_t)1 << kBinShift) - 1;
+    for (int b = 0; b < 3; b++) {
+      blk[b * nb + blockIdx.x] = (t0 >> (kBinShift * b)) & mk;
+      blk[(b + 3) * nb + blockIdx.x] = (t1 >> (kBinShift * b)) & mk;
+    }
   }
-  e0 = wave_sum_i64(e0);
-  e1 = wave_sum_i64(e1);
-  e2 = wave_sum_i64(e2);
-  if (lane_id() == 0) {
-    if (e0) atomicAdd((unsigned long long*)&bin_edges[0], (unsigned long long)e0);
-    if (e1) atomicAdd((unsigned long long*)&bin_edges[1], (unsigned long long)e1);
-    if (e2) atomicAdd((unsigned long long*)&bin_edges[2], (unsigned long long)e2);
+#pragma unroll
+  for (int t = 0; t < kBins; t++) ed[t] = wave_sum_i64(ed[t]);
+  if (lane_id() == 0)
+    for (int t = 0; t < kBins; t++) she[threadIdx.x / kWave][t] = ed[t];
+  __syncthreads();
+  if (threadIdx.x < kBins) {
+    const int64_t s = she[0][threadIdx.x] + she[1][threadIdx.x] + she[2][threadIdx.x] + she[3][threadIdx.x];
+    if (s) atomicAdd(&acc[(kAccEdges0 + threadIdx.x) * (kSlots * kSlotStride) + (blockIdx.x % kSlots) * kSlotStride],
+                     (unsigned long long)s);
   }
 }
 
 __global__ void __launch_bounds__(256) k_bin_scatter(const uint8_t* flags, const int32_t* __restrict__ in_off,
-                                                     int32_t n, int32_t t1, int32_t t2, const int64_t* offs,
-                                                     int64_t nb, int32_t* wl, uint8_t* ever, int64_t* bin_end) {
+                                                     int32_t n, Bounds B, const int64_t* offs, int64_t nb, int32_t* wl,
+                                                     uint8_t* ever, int64_t* bin_end) {
   __shared__ int64_t sh[256 / kWave + 1];
   const int64_t base = (int64_t)blockIdx.x * kBinTile + (int64_t)threadIdx.x * kBinItems;
+  const unsigned m = tile_flags(flags, base, n);
   uint8_t bins[kBinItems];
-  int64_t packed = 0;
+  int64_t p0 = 0, p1 = 0;
 #pragma unroll
-  for (int j = 0; j < kBinItems; j++) {
-    const int64_t v = base + j;
-    bins[j] = 3;
-    if (v < n && (flags == nullptr || flags[v])) {
-      const int b = bin_of(in_off[v + 1] - in_off[v], t1, t2);
-      bins[j] = (uint8_t)b;
-      packed += (int64_t)1 << (kBinShift * b);
+  for (int j = 0; j < kBinItems; j++) bins[j] = 0xFF;
+  if (m) {
+    int32_t o[kBinItems + 1];
+#pragma unroll
+    for (int j = 0; j <= kBinItems; j++) o[j] = base + j <= n ? in_off[base + j] : 0;
+#pragma unroll
+    for (int j = 0; j < kBinItems; j++) {
+      if (m & (1u << j)) {
+        const int b = bin_of(o[j + 1] - o[j], B);
+        bins[j] = (uint8_t)b;
+        if (b < 3) p0 += (int64_t)1 << (kBinShift * b); else p1 += (int64_t)1 << (kBinShift * (b - 3));
+      }
     }
   }
-  int64_t tot;
-  const int64_t pre = block_exclusive_scan(packed, sh, &tot);
-  const int64_t m = ((int64_t)1 << kBinShift) - 1;
-  int64_t pos[3] = {offs[0 * nb + blockIdx.x] + (pre & m), offs[1 * nb + blockIdx.x] + ((pre >> kBinShift) & m),
-                    offs[2 * nb + blockIdx.x] + ((pre >> (2 * kBinShift)) & m)};
+  int64_t t0, t1;
+  const int64_t e0 = block_exclusive_scan(p0, sh, &t0);
+  const int64_t e1 = block_exclusive_scan(p1, sh, &t1);
+  if (m) {
+    const int64_t mk = ((int64_t)1 << kBinShift) - 1;
+    int64_t pos[kBins];
 #pragma unroll
-  for (int j = 0; j < kBinItems; j++) {
-    if (bins[j] < 3) {
-      const int32_t v = (int32_t)(base + j);
-      wl[pos[bins[j]]++] = v;
-      if (ever) ever[v] = 1;
+    for (int b = 0; b < 3; b++) {
+      pos[b] = offs[b * nb + blockIdx.x] + ((e0 >> (kBinShift * b)) & mk);
+      pos[b + 3] = offs[(b + 3) * nb + blockIdx.x] + ((e1 >> (kBinShift * b)) & mk);
+    }
+#pragma unroll
+    for (int j = 0; j < kBinItems; j++) {
+      if (bins[j] != 0xFF) {
+        const int32_t v = (int32_t)(base + j);
+        int64_t ps = 0;
+#pragma unroll
+        for (int b = 0; b < kBins; b++)
+          if (bins[j] == b) ps = pos[b]++;
+        wl[ps] = v;
+        if (ever) ever[v] = 1;
+      }
     }
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    bin_end[0] = offs[nb];
-    bin_end[1] = offs[2 * nb];
-    bin_end[2] = offs[3 * nb];
+  if (blockIdx.x == 0 && threadIdx.x < kBins) bin_end[threadIdx.x] = offs[(threadIdx.x + 1) * nb];
+}
+
+// ---- control block
+// Fold the spread slots into the compact head and clear them; also clears the
+// long-row list count for the next marking pass.
+__global__ void __launch_bounds__(kSlots) k_iter_finish(IterCtl* c) {
+  const int t = threadIdx.x;
+  unsigned long long m = c->dR_slots[t * kSlotStride];
+  c->dR_slots[t * kSlotStride] = 0ull;
+#pragma unroll
+  for (int o = kSlots / 2; o >= 1; o >>= 1) {
+    const unsigned long long y = __shfl_xor(m, o, kSlots);
+    m = y > m ? y : m;
   }
+  int64_t r[kAccRows];
+#pragma unroll
+  for (int a = 0; a < kAccRows; a++) {
+    r[a] = (int64_t)c->acc_slots[a][t * kSlotStride];
+    c->acc_slots[a][t * kSlotStride] = 0ull;
+    r[a] = wave_sum_i64(r[a]);
+  }
+  if (t == 0) {
+    c->dR = m;
+    for (int b = 0; b < kBins; b++) c->bin_edges[b] = r[kAccEdges0 + b];
+    c->ever_count = r[kAccEver];
+    c->big_count = 0;
+  }
+}
+
+__global__ void k_reset_ctl(IterCtl* c) {
+  unsigned long long* w = reinterpret_cast<unsigned long long*>(c);
+  const int64_t nw = (int64_t)(sizeof(IterCtl) / sizeof(unsigned long long));
+  const int64_t keep0 = offsetof(IterCtl, n_apply) / 8, keep1 = keep0 + 6;  // apply counters stay
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nw; i += (int64_t)gridDim.x * blockDim.x)
+    if (i < keep0 || i >= keep1) w[i] = 0ull;
 }
 
 // ---- small helpers
@@ -369,19 +555,7 @@ __global__ void k_init_prev(const double* r_prev, double* R, double* contrib, co
     contrib[v] = r / (double)(out_off[v + 1] - out_off[v]);
   }
 }
-// Reset the per-iteration counters; slot = the dR slot the next pull uses.
-__global__ void k_iter_reset(IterCtl* c, int slot) {
-  c->dR[slot] = 0ull;
-  c->bin_edges[0] = c->bin_edges[1] = c->bin_edges[2] = 0;
-  c->big_count = 0;
-}
-__global__ void k_reset_all(IterCtl* c) {
-  c->dR[0] = c->dR[1] = 0ull;
-  c->bin_edges[0] = c->bin_edges[1] = c->bin_edges[2] = 0;
-  c->big_count = 0;
-  c->ever_count = 0;
-}
-__global__ void __launch_bounds__(256) k_count_clear_ever(uint8_t* ever, int32_t n, int64_t* count) {
+__global__ void __launch_bounds__(256) k_count_clear_ever(uint8_t* ever, int32_t n, unsigned long long* acc) {
   int64_t c = 0;
   for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
     if (ever[v]) {
@@ -390,7 +564,9 @@ __global__ void __launch_bounds__(256) k_count_clear_ever(uint8_t* ever, int32_t
     }
   }
   c = wave_sum_i64(c);
-  if (lane_id() == 0 && c) atomicAdd((unsigned long long*)count, (unsigned long long)c);
+  if (lane_id() == 0 && c)
+    atomicAdd(&acc[kAccEver * (kSlots * kSlotStride) + ((blockIdx.x * 4 + threadIdx.x / kWave) % kSlots) * kSlotStride],
+              (unsigned long long)c);
 }
 __global__ void k_fill_u8(uint8_t* p, int64_t n, uint8_t v) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
@@ -403,23 +579,30 @@ static double bits_to_double(unsigned long long b) {
   return d;
 }
 
+static Bounds bounds_of(const dfpr_graph* g) {
+  Bounds B;
+  for (int i = 0; i < 5; i++) B.b[i] = g->bounds[i];
+  return B;
+}
+
 static int bin_vertices(dfpr_graph* g, const uint8_t* flags, int32_t* wl, uint8_t* ever, hipStream_t s) {
   const int32_t n = g->n;
   size_t tok;
   DFPR_TRY(g->pool.start(&tok));
   const int64_t nb = ((int64_t)n + kBinTile - 1) / kBinTile;
-  k_bin_count<<<(unsigned)nb, 256, 0, s>>>(flags, g->in.off, n, g->t_thread, g->t_wave, g->bin_blk, nb,
-                                           g->ctl->bin_edges);
-  DFPR_TRY(scan_i64(g->bin_blk, g->bin_blk, 3 * nb, g->scan_tmp, s));
-  k_bin_scatter<<<(unsigned)nb, 256, 0, s>>>(flags, g->in.off, n, g->t_thread, g->t_wave, g->bin_blk, nb, wl, ever,
+  k_bin_count<<<(unsigned)nb, 256, 0, s>>>(flags, g->in.off, n, bounds_of(g), g->bin_blk, nb, &g->ctl->acc_slots[0][0]);
+  DFPR_TRY(scan_i64(g->bin_blk, g->bin_blk, kBins * nb, g->scan_tmp, s));
+  k_bin_scatter<<<(unsigned)nb, 256, 0, s>>>(flags, g->in.off, n, bounds_of(g), g->bin_blk, nb, wl, ever,
                                              g->ctl->bin_end);
   DFPR_HIP(hipGetLastError());
   DFPR_TRY(g->pool.stop(kTBin, tok));
   return DFPR_OK;
 }
 
-static int readback(dfpr_graph* g, hipStream_t s) {
-  DFPR_HIP(hipMemcpyAsync(g->ctl_host, g->ctl, sizeof(IterCtl), hipMemcpyDeviceToHost, s));
+static int finish_and_read(dfpr_graph* g, hipStream_t s) {
+  k_iter_finish<<<1, kSlots, 0, s>>>(g->ctl);
+  DFPR_HIP(hipGetLastError());
+  DFPR_HIP(hipMemcpyAsync(g->ctl_host, g->ctl, kCtlHead, hipMemcpyDeviceToHost, s));
   DFPR_HIP(hipStreamSynchronize(s));
   return DFPR_OK;
 }
@@ -427,85 +610,98 @@ static int readback(dfpr_graph* g, hipStream_t s) {
 // Chunked marking of the rows collected in big_list.
 static int mark_big(dfpr_graph* g, uint8_t* flags, hipStream_t s) {
   k_big_scan<<<1, 1024, 0, s>>>(g->big_list, &g->ctl->big_count, g->out.off, g->big_pre);
-  k_big_mark<<<512, 256, 0, s>>>(g->big_list, &g->ctl->big_count, g->big_pre, g->out.off, g->out.idx, flags);
+  k_big_mark<<<256, 256, 0, s>>>(g->big_list, &g->ctl->big_count, g->big_pre, g->out.off, g->out.idx, flags);
   DFPR_HIP(hipGetLastError());
   return DFPR_OK;
 }
 
-// Launch the pull kernels of one iteration over worklist `wl` with bins
-// [0,e0) [e0,e1) [e1,e2); per-bin timing when t->on.
+// Launch layout of the fused pull kernel from the bin ends and edge counts.
+static bool make_layout(const int64_t* be, const int64_t* bedges, PullLayout* L) {
+  static const int per_block[kBins - 1] = {256, 64, 16, 4, 1};
+  const int64_t cap = 2048;
+  L->blk[0] = 0;
+  for (int k = 0; k < kBins; k++) {
+    L->lo[k] = k ? be[k - 1] : 0;
+    L->hi[k] = be[k];
+    const int64_t cnt = L->hi[k] - L->lo[k];
+    int64_t nb = 0;
+    if (cnt > 0) {
+      if (k < kBins - 1)
+        nb = std::min(cap, (cnt + per_block[k] - 1) / per_block[k]);
+      else
+        nb = std::min<int64_t>(1024, bedges[k] / kPullChunk + cnt);
+    }
+    L->blk[k + 1] = L->blk[k] + (int32_t)nb;
+  }
+  return L->blk[kBins] > 0;
+}
+
 template <int MODE>
 static int pull_all(dfpr_graph* g, const PullArgs& a, const int32_t* wl, const int64_t* be, const int64_t* bedges,
-                    hipStream_t s) {
-  const int64_t n0 = be[0], n1 = be[1] - be[0], n2 = be[2] - be[1];
-  EventPool& ep = g->pool;
+                    hipStream_t s, dfpr_stats* st) {
+  PullLayout L;
+  if (!make_layout(be, bedges, &L)) return DFPR_OK;
   size_t tok;
-  if (n0 > 0) {
-    DFPR_TRY(ep.start(&tok));
-    k_pull_lane<MODE><<<grid_for(n0, 256, 1u << 16), 256, 0, s>>>(a, wl, 0, be[0]);
-    DFPR_HIP(hipGetLastError());
-    DFPR_TRY(ep.stop(kTPull0, tok));
-  }
-  if (n1 > 0) {
-    DFPR_TRY(ep.start(&tok));
-    k_pull_wave<MODE><<<grid_for(n1, 4, 1u << 16), 256, 0, s>>>(a, wl, be[0], be[1]);
-    DFPR_HIP(hipGetLastError());
-    DFPR_TRY(ep.stop(kTPull1, tok));
-  }
-  if (n2 > 0) {
-    DFPR_TRY(ep.start(&tok));
-    DFPR_TRY(scan_generic(LoadChunks{wl, g->in.off, be[1]}, StoreI64r{g->chunk_pre}, n2, g->scan_tmp, s));
-    const int64_t max_chunks = bedges[2] / kPullChunk + n2;
-    k_pull_chunk<<<grid_for(max_chunks, 1, 1u << 16), 256, 0, s>>>(a, wl, be[1], n2, g->chunk_pre, g->partial);
-    k_pull_chunk_finish<MODE><<<grid_for(n2, 256, 4096), 256, 0, s>>>(a, wl, be[1], n2, g->chunk_pre, g->partial);
-    DFPR_HIP(hipGetLastError());
-    DFPR_TRY(ep.stop(kTPull2, tok));
-  }
+  DFPR_TRY(g->pool.start(&tok));
+  k_pull<MODE><<<(unsigned)L.blk[kBins], 256, 0, s>>>(a, wl, L);
+  DFPR_HIP(hipGetLastError());
+  DFPR_TRY(g->pool.stop(kTPull0, tok));
+  st->pull_launches++;
   return DFPR_OK;
 }
 
 static void add_bins(dfpr_stats* st, const int64_t* be, const int64_t* bedges) {
-  st->bin_vertices[0] += be[0];
-  st->bin_vertices[1] += be[1] - be[0];
-  st->bin_vertices[2] += be[2] - be[1];
-  for (int k = 0; k < 3; k++) st->bin_edges[k] += bedges[k];
+  for (int k = 0; k < kBins; k++) {
+    st->bin_vertices[k] += be[k] - (k ? be[k - 1] : 0);
+    st->bin_edges[k] += bedges[k];
+  }
+}
+
+static PullArgs make_args(dfpr_graph* g, const dfpr_params& p) {
+  PullArgs a{};
+  a.in_off = g->in.off;
+  a.in_idx = g->in.idx;
+  a.out_off = g->out.off;
+  a.dR_slots = g->ctl->dR_slots;
+  a.partial = g->partial;
+  a.arrive = g->arrive;
+  a.alpha = p.alpha;
+  a.C0 = (1.0 - p.alpha) / (double)g->n;
+  a.tf = p.frontier_tol;
+  a.tp = p.prune_tol;
+  return a;
 }
 
 static int run_sync(dfpr_graph* g, bool cold, const dfpr_params& p, const double* r_prev, double* r_out,
                     hipStream_t s, dfpr_stats* st) {
   const int32_t n = g->n;
+  k_reset_ctl<<<64, 256, 0, s>>>(g->ctl);
   if (!g->all_bins_valid) {
-    k_reset_all<<<1, 1, 0, s>>>(g->ctl);
     DFPR_TRY(bin_vertices(g, nullptr, g->all_bins, nullptr, s));
-    DFPR_TRY(readback(g, s));
-    std::copy(g->ctl_host->bin_end, g->ctl_host->bin_end + 3, g->all_bin_end);
-    std::copy(g->ctl_host->bin_edges, g->ctl_host->bin_edges + 3, g->all_bin_edges);
+    DFPR_TRY(finish_and_read(g, s));
+    std::copy(g->ctl_host->bin_end, g->ctl_host->bin_end + kBins, g->all_bin_end);
+    std::copy(g->ctl_host->bin_edges, g->ctl_host->bin_edges + kBins, g->all_bin_edges);
     g->all_bins_valid = true;
   }
-  const unsigned gi = grid_for(n, 256, 1u << 16);
+  const unsigned gi = grid_for(n, 256, 2048);
   if (cold)
     k_init_static<<<gi, 256, 0, s>>>(r_out, g->contrib, g->out.off, n);
   else
     k_init_prev<<<gi, 256, 0, s>>>(r_prev, r_out, g->contrib, g->out.off, n, r_prev != r_out);
-  k_reset_all<<<1, 1, 0, s>>>(g->ctl);
   DFPR_HIP(hipGetLastError());
   double *Ra = r_out, *Rb = g->rn, *ca = g->contrib, *cb = g->contrib2;
-  PullArgs a{g->in.off, g->in.idx, g->out.off, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
-             p.alpha, (1.0 - p.alpha) / (double)n, p.frontier_tol, p.prune_tol};
+  PullArgs a = make_args(g, p);
   int it = 0;
   double dR = 0.0;
   bool conv = false;
   for (it = 0; it < p.max_iters; it++) {
-    const int slot = it & 1;
     a.contrib = ca;
     a.R = Ra;
     a.Rw = Rb;
     a.cw = cb;
-    a.dR = &g->ctl->dR[slot];
-    DFPR_TRY(pull_all<kSync>(g, a, g->all_bins, g->all_bin_end, g->all_bin_edges, s));
-    k_iter_reset<<<1, 1, 0, s>>>(g->ctl, slot ^ 1);
-    DFPR_TRY(readback(g, s));
-    dR = bits_to_double(g->ctl_host->dR[slot]);
+    DFPR_TRY(pull_all<kSync>(g, a, g->all_bins, g->all_bin_end, g->all_bin_edges, s, st));
+    DFPR_TRY(finish_and_read(g, s));
+    dR = bits_to_double(g->ctl_host->dR);
     st->vertex_updates += n;
     st->edges_pulled += g->m;
     add_bins(st, g->all_bin_end, g->all_bin_edges);
@@ -536,9 +732,9 @@ template <int MODE>
 static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_prev, double* r_out, hipStream_t s,
                         dfpr_stats* st) {
   const int32_t n = g->n;
-  const unsigned gi = grid_for(n, 256, 1u << 16);
+  const unsigned gi = grid_for(n, 256, 2048);
+  k_reset_ctl<<<64, 256, 0, s>>>(g->ctl);
   k_init_prev<<<gi, 256, 0, s>>>(r_prev, r_out, g->contrib, g->out.off, n, r_prev != r_out);
-  k_reset_all<<<1, 1, 0, s>>>(g->ctl);
   // initial marking: out(u) of pending sources (+ deletion targets already in flag_cur)
   size_t tok;
   DFPR_TRY(g->pool.start(&tok));
@@ -548,45 +744,43 @@ static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_pre
   DFPR_TRY(mark_big(g, g->flag_cur, s));
   DFPR_TRY(g->pool.stop(kTMark, tok));
   g->pending_any = false;
-  k_iter_reset<<<1, 1, 0, s>>>(g->ctl, 0);
   DFPR_TRY(bin_vertices(g, g->flag_cur, g->worklist, g->ever, s));
-  DFPR_TRY(readback(g, s));
+  DFPR_TRY(finish_and_read(g, s));
   uint8_t *cur = g->flag_cur, *next = g->flag_next;
-  PullArgs a{g->in.off, g->in.idx, g->out.off, g->contrib, r_out, nullptr, nullptr, nullptr, g->xflag, nullptr,
-             p.alpha, (1.0 - p.alpha) / (double)n, p.frontier_tol, p.prune_tol};
+  PullArgs a = make_args(g, p);
+  a.contrib = g->contrib;
+  a.R = r_out;
+  a.xflag = g->xflag;
   int it = 0;
   double dR = 0.0;
   bool conv = false;
   for (it = 0; it < p.max_iters; it++) {
-    const int slot = it & 1;
-    int64_t be[3], bedges[3];
-    std::copy(g->ctl_host->bin_end, g->ctl_host->bin_end + 3, be);
-    std::copy(g->ctl_host->bin_edges, g->ctl_host->bin_edges + 3, bedges);
-    const int64_t cnt = be[2];
+    int64_t be[kBins], bedges[kBins];
+    std::copy(g->ctl_host->bin_end, g->ctl_host->bin_end + kBins, be);
+    std::copy(g->ctl_host->bin_edges, g->ctl_host->bin_edges + kBins, bedges);
+    const int64_t cnt = be[kBins - 1];
     st->vertex_updates += cnt;
-    st->edges_pulled += bedges[0] + bedges[1] + bedges[2];
+    for (int k = 0; k < kBins; k++) st->edges_pulled += bedges[k];
     add_bins(st, be, bedges);
     if (cnt == 0) {  // nothing affected: the L-inf change of this iteration is 0
       dR = 0.0;
-      conv = dR <= p.tol;
+      conv = true;
       it++;
       break;
     }
     a.next = next;
-    a.dR = &g->ctl->dR[slot];
-    DFPR_TRY(pull_all<MODE>(g, a, g->worklist, be, bedges, s));
+    DFPR_TRY(pull_all<MODE>(g, a, g->worklist, be, bedges, s, st));
     DFPR_TRY(g->pool.start(&tok));
-    k_commit_expand<<<grid_for(cnt, 256, 1u << 16), 256, 0, s>>>(g->worklist, cnt, r_out, g->contrib, g->out.off,
-                                                                 g->out.idx, cur, next, g->xflag, g->big_list,
-                                                                 &g->ctl->big_count);
+    k_commit_expand<<<grid_for(cnt, 256, 2048), 256, 0, s>>>(g->worklist, cnt, r_out, g->contrib, g->out.off,
+                                                             g->out.idx, cur, next, g->xflag, g->big_list,
+                                                             &g->ctl->big_count);
     DFPR_HIP(hipGetLastError());
     DFPR_TRY(mark_big(g, next, s));
     DFPR_TRY(g->pool.stop(kTCommit, tok));
     std::swap(cur, next);
-    k_iter_reset<<<1, 1, 0, s>>>(g->ctl, slot ^ 1);
     DFPR_TRY(bin_vertices(g, cur, g->worklist, g->ever, s));
-    DFPR_TRY(readback(g, s));
-    dR = bits_to_double(g->ctl_host->dR[slot]);
+    DFPR_TRY(finish_and_read(g, s));
+    dR = bits_to_double(g->ctl_host->dR);
     if (dR <= p.tol) {
       conv = true;
       it++;
@@ -595,11 +789,10 @@ static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_pre
   }
   // leave both flag arrays clear for the next batch
   k_fill_u8<<<gi, 256, 0, s>>>(cur, n, 0);
-  k_count_clear_ever<<<gi, 256, 0, s>>>(g->ever, n, &g->ctl->ever_count);
+  k_count_clear_ever<<<gi, 256, 0, s>>>(g->ever, n, &g->ctl->acc_slots[0][0]);
   DFPR_HIP(hipGetLastError());
-  DFPR_TRY(readback(g, s));
-  // both arrays are zero again; which one is called "current" does not matter
-  g->flag_cur = cur;
+  DFPR_TRY(finish_and_read(g, s));
+  g->flag_cur = cur;  // both arrays are zero again
   g->flag_next = next;
   st->iterations = it;
   st->converged = conv ? 1 : 0;
@@ -630,10 +823,7 @@ int update_ranks(dfpr_graph* g, dfpr_mode mode, const dfpr_params& p, const doub
     int cnt[kTNum] = {0};
     DFPR_TRY(ep.collect(ms, cnt));
     st.ms_total = ms[kTTotal];
-    for (int k = 0; k < 3; k++) {
-      st.ms_pull[k] = ms[kTPull0 + k];
-      st.pull_launches[k] = cnt[kTPull0 + k];
-    }
+    st.ms_pull = ms[kTPull0];
     st.ms_commit = ms[kTCommit];
     st.ms_bin = ms[kTBin];
     st.ms_mark = ms[kTMark];

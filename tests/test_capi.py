@@ -47,7 +47,7 @@ def test_invalid_arguments_rejected_before_device_work(lib):
     assert b"invalid" in lib.dfpr_last_error()
     st = _capi.Stats()
     assert lib.dfpr_update_ranks(None, 3, None, None, None, None, ctypes.byref(st)) == _capi.DFPR_EINVAL
-    assert lib.dfpr_set_tuning(None, 4, 8) == _capi.DFPR_EINVAL
+    assert lib.dfpr_set_tuning(None, (ctypes.c_int32 * 5)(4, 8, 16, 32, 64)) == _capi.DFPR_EINVAL
     assert lib.dfpr_apply_batch(None, -1, None, None, 0, None, None, 0, None, None) == _capi.DFPR_EINVAL
     assert lib.dfpr_graph_destroy(None) == _capi.DFPR_OK
     assert lib.dfpr_version().startswith(b"dfpr")
@@ -57,4 +57,4 @@ def test_struct_layouts_match_header():
     # field counts and sizes of the ABI structs as declared in include/dfpr.h
     assert ctypes.sizeof(_capi.Params) == 4 * 8 + 2 * 4
     assert ctypes.sizeof(_capi.BatchInfo) == 6 * 8 + 4 * 8
-    assert ctypes.sizeof(_capi.Stats) == 4 + 4 + 8 + 3 * 8 + 6 * 8 + 8 + 3 * 8 + 3 * 4 + 4 + 3 * 8
+    assert ctypes.sizeof(_capi.Stats) == 4 + 4 + 8 + 3 * 8 + 12 * 8 + 8 + 8 + 4 + 4 + 3 * 8

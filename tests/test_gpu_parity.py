@@ -119,7 +119,7 @@ def test_ranks_bitexact_lane_bin(mode):
     ranks, iteration counts and frontier statistics are identical."""
     p, r0 = _setup(13, 1e-3, seed=21)
     maxdeg = int(np.diff(p.og.in_off).max())
-    p.g.set_tuning(maxdeg, maxdeg)
+    p.g.set_tuning([maxdeg] * 5)
     r, st, ref = p.rank(mode, r0)
     assert np.array_equal(r, ref.ranks)
     assert st["iterations"] == ref.iterations
@@ -128,14 +128,16 @@ def test_ranks_bitexact_lane_bin(mode):
     assert st["ever_affected"] == ref.ever_affected
 
 
+@pytest.mark.parametrize("bounds", [[1, 2, 3, 4, 5], [1, 1, 1, 2, 3], [2, 4, 8, 16, 32]])
 @pytest.mark.parametrize("mode", ["static", "dfp", "df"])
-def test_chunk_and_wave_bins(mode):
-    """Tiny thresholds push most vertices into the wavefront and chunked bins."""
+def test_all_bins(mode, bounds):
+    """Small thresholds push vertices into every bin, the chunked one included."""
     p, r0 = _setup(12, 1e-2, seed=31)
-    p.g.set_tuning(1, 2)
+    p.g.set_tuning(bounds)
+    assert p.g.get_tuning() == bounds
     r, st, ref = p.rank(mode, r0)
     assert np.abs(r - ref.ranks).max() <= LINF
-    assert st["bin_vertices"][2] > 0 and st["bin_vertices"][1] > 0
+    assert st["bin_vertices"][5] > 0 and st["bin_vertices"][3] > 0
 
 
 @pytest.mark.parametrize("mode", ["static", "df", "dfp"])
@@ -205,7 +207,7 @@ def test_errors_leave_graph_unchanged():
         p.g.update_ranks("dfp", rp, alpha=1.5)
     assert e.value.code == -1
     with pytest.raises(dfpr.DfprError):
-        p.g.set_tuning(10, 5)
+        p.g.set_tuning([10, 5, 20, 30, 40])
     # the pending marks survived the failed calls: DF-P still matches the oracle
     r, st, ref = p.rank("dfp", r0)
     assert np.abs(r - ref.ranks).max() <= LINF

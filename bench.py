@@ -103,6 +103,8 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (R0 from GPU Static)")
     ap.add_argument("--static-runs", type=int, default=3)
+    ap.add_argument("--calib", action="store_true",
+                    help="finish with three 1 GiB device copies (counter calibration under a profiler)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -266,6 +268,13 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(res))
+    if args.calib:
+        a = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log("calibration: 3 copies of 1 GiB done")
 
 
 if __name__ == "__main__":

@@ -177,7 +177,8 @@ struct dfpr_graph {
   int64_t* scan_tmp = nullptr;       // block sums for scans over n
   size_t scan_tmp_n = 0;
   int64_t* bin_blk = nullptr;        // per-block bin counts (kBins * ceil(n/2048) + 1)
-  int64_t* chunk_pre = nullptr;      // n+1: chunk prefix of the workgroup bin
+  int64_t* chunk_pre = nullptr;      // n+1: chunk prefix of the chunked bin (frontier worklist)
+  int64_t* all_chunk_pre = nullptr;  // n+1: the same for the all-vertex bins
   double* partial = nullptr;         // partial sums of pull chunks
   int64_t partial_n = 0;
   int32_t* big_list = nullptr;       // n: vertices with long out-rows to mark

@@ -336,6 +336,7 @@ static int alloc_rank_scratch(dfpr_graph* g) {
   DFPR_TRY(dalloc(&g->arrive, n));
   DFPR_HIP(hipMemset(g->arrive, 0, n * sizeof(int32_t)));
   DFPR_TRY(dalloc(&g->chunk_pre, n + 1));
+  DFPR_TRY(dalloc(&g->all_chunk_pre, n + 1));
   DFPR_TRY(dalloc(&g->big_list, n));
   DFPR_TRY(dalloc(&g->big_pre, n + 1));
   g->partial_n = g->cap / kPullChunk + (int64_t)n + 1;
@@ -391,6 +392,7 @@ int graph_destroy(dfpr_graph* g) {
   dfree(g->scan_tmp);
   dfree(g->bin_blk);
   dfree(g->chunk_pre);
+  dfree(g->all_chunk_pre);
   dfree(g->big_list);
   dfree(g->big_pre);
   dfree(g->partial);

@@ -36,8 +36,9 @@ struct PullArgs {
   uint8_t* next;   // DF/DF-P: affected in the next iteration
   uint8_t* xflag;  // DF/DF-P: expands
   unsigned long long* dR_slots;
-  double* partial;   // bin 5: per-chunk partial sums
-  int32_t* arrive;   // bin 5: chunks finished per vertex
+  double* partial;           // bin 5: per-chunk partial sums
+  int32_t* arrive;           // bin 5: chunks finished per vertex
+  const int64_t* chunk_pre;  // bin 5: first chunk of each vertex (exclusive scan)
   double alpha, C0, tf, tp;
 };
 
@@ -175,42 +176,60 @@ __device__ __forceinline__ void pull_block(const PullArgs& a, const int32_t* __r
   }
 }
 
-// ---- bin 5: rows split in kPullChunk-edge chunks dealt round-robin to the
-// bin's workgroups.  Each chunk's sum goes to `partial`; the workgroup that
-// finishes a vertex's last chunk (arrival counter) adds the partials in chunk
-// order and computes the rank.
+// ---- bin 5: rows split in kPullChunk-edge chunks.  chunk_pre[j] is the
+// first chunk of the bin's j-th vertex (exclusive scan of the chunk counts);
+// workgroup lb takes the contiguous chunk range [lb*T/nb, (lb+1)*T/nb).  Each
+// chunk's sum goes to `partial`; the workgroup that finishes a vertex's last
+// chunk (arrival counter) adds the partials in chunk order and computes the
+// rank.
+__device__ __forceinline__ int64_t upper_bound_i64(const int64_t* a, int64_t lo, int64_t hi, int64_t x) {
+  while (lo < hi) {
+    int64_t mid = lo + ((hi - lo) >> 1);
+    if (a[mid] <= x) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
 template <int MODE>
 __device__ __forceinline__ void pull_chunks(const PullArgs& a, const int32_t* __restrict__ wl, int64_t lo, int64_t hi,
                                             int lb, int nb, double& mx) {
   __shared__ double sh[256 / kWave];
   __shared__ int last;
-  int64_t base = 0;
-  for (int64_t j = 0; j < hi - lo; j++) {
-    const int32_t v = wl[lo + j];
-    const int32_t s = a.in_off[v], e = a.in_off[v + 1];
-    const int64_t nch = ((int64_t)(e - s) + kPullChunk - 1) / kPullChunk;
-    int64_t q = base + ((lb - base % nb) % nb + nb) % nb;
-    for (; q < base + nch; q += nb) {
-      const int32_t cs = s + (int32_t)((q - base) * kPullChunk);
-      const int32_t ce = min(cs + kPullChunk, e);
-      const double part = block_row_sum(a, cs, ce, sh);
-      if (threadIdx.x == 0) {
-        a.partial[q] = part;
-        __threadfence();
-        last = atomicAdd(&a.arrive[j], 1) == (int)(nch - 1);
-      }
-      __syncthreads();
-      if (threadIdx.x == 0 && last) {
-        __threadfence();
-        double c = 0.0;
-        for (int64_t t = base; t < base + nch; t++)
-          c += __hip_atomic_load(&a.partial[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        a.arrive[j] = 0;
-        mx = fmax(mx, vertex_finish<MODE>(a, v, c));
-      }
-      __syncthreads();
+  const int64_t nv = hi - lo;
+  const int64_t* pre = a.chunk_pre;
+  const int64_t T = pre[nv];
+  const int64_t q0 = (int64_t)lb * T / nb, q1 = (int64_t)(lb + 1) * T / nb;
+  if (q0 >= q1) return;
+  int64_t j = upper_bound_i64(pre, 0, nv + 1, q0) - 1;
+  int64_t cj = pre[j], cj1 = pre[j + 1];
+  int32_t v = wl[lo + j];
+  int32_t s = a.in_off[v], e = a.in_off[v + 1];
+  for (int64_t q = q0; q < q1; q++) {
+    while (q >= cj1) {
+      j++;
+      cj = cj1;
+      cj1 = pre[j + 1];
+      v = wl[lo + j];
+      s = a.in_off[v];
+      e = a.in_off[v + 1];
     }
-    base += nch;
+    const int32_t cs = s + (int32_t)((q - cj) * kPullChunk);
+    const int32_t ce = min(cs + kPullChunk, e);
+    const double part = block_row_sum(a, cs, ce, sh);
+    if (threadIdx.x == 0) {
+      a.partial[q] = part;
+      __threadfence();
+      last = atomicAdd(&a.arrive[j], 1) == (int)(cj1 - cj - 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && last) {
+      __threadfence();
+      double c = 0.0;
+      for (int64_t t = cj; t < cj1; t++) c += __hip_atomic_load(&a.partial[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      a.arrive[j] = 0;
+      mx = fmax(mx, vertex_finish<MODE>(a, v, c));
+    }
+    __syncthreads();
   }
 }
 
@@ -352,14 +371,6 @@ __global__ void __launch_bounds__(1024) k_big_scan(const int32_t* big_list, cons
     run += ((int64_t)(out_off[v + 1] - out_off[v]) + kMarkChunk - 1) / kMarkChunk;
   }
   if (threadIdx.x == 0) big_pre[nb] = tot;
-}
-
-__device__ __forceinline__ int64_t upper_bound_i64(const int64_t* a, int64_t lo, int64_t hi, int64_t x) {
-  while (lo < hi) {
-    int64_t mid = lo + ((hi - lo) >> 1);
-    if (a[mid] <= x) lo = mid + 1; else hi = mid;
-  }
-  return lo;
 }
 
 __global__ void __launch_bounds__(256) k_big_mark(const int32_t* big_list, const int64_t* big_count,
@@ -636,13 +647,33 @@ static bool make_layout(const int64_t* be, const int64_t* bedges, PullLayout* L)
   return L->blk[kBins] > 0;
 }
 
+struct LoadChunks {
+  const int32_t* wl;
+  const int32_t* in_off;
+  int64_t lo;
+  __device__ int64_t operator()(int64_t i) const {
+    const int32_t v = wl[lo + i];
+    return ((int64_t)(in_off[v + 1] - in_off[v]) + kPullChunk - 1) / kPullChunk;
+  }
+};
+struct StoreChunk {
+  int64_t* a;
+  __device__ void operator()(int64_t i, int64_t v) const { a[i] = v; }
+};
+
+// chunk_ready: chunk_pre already holds the scan for this worklist (cached
+// all-vertex bins of Static/ND).
 template <int MODE>
-static int pull_all(dfpr_graph* g, const PullArgs& a, const int32_t* wl, const int64_t* be, const int64_t* bedges,
-                    hipStream_t s, dfpr_stats* st) {
+static int pull_all(dfpr_graph* g, PullArgs a, const int32_t* wl, const int64_t* be, const int64_t* bedges,
+                    int64_t* chunk_pre, bool chunk_ready, hipStream_t s, dfpr_stats* st) {
   PullLayout L;
   if (!make_layout(be, bedges, &L)) return DFPR_OK;
   size_t tok;
   DFPR_TRY(g->pool.start(&tok));
+  const int64_t n5 = L.hi[kBins - 1] - L.lo[kBins - 1];
+  if (n5 > 0 && !chunk_ready)
+    DFPR_TRY(scan_generic(LoadChunks{wl, g->in.off, L.lo[kBins - 1]}, StoreChunk{chunk_pre}, n5, g->scan_tmp, s));
+  a.chunk_pre = chunk_pre;
   k_pull<MODE><<<(unsigned)L.blk[kBins], 256, 0, s>>>(a, wl, L);
   DFPR_HIP(hipGetLastError());
   DFPR_TRY(g->pool.stop(kTPull0, tok));
@@ -699,7 +730,7 @@ static int run_sync(dfpr_graph* g, bool cold, const dfpr_params& p, const double
     a.R = Ra;
     a.Rw = Rb;
     a.cw = cb;
-    DFPR_TRY(pull_all<kSync>(g, a, g->all_bins, g->all_bin_end, g->all_bin_edges, s, st));
+    DFPR_TRY(pull_all<kSync>(g, a, g->all_bins, g->all_bin_end, g->all_bin_edges, g->all_chunk_pre, it > 0, s, st));
     DFPR_TRY(finish_and_read(g, s));
     dR = bits_to_double(g->ctl_host->dR);
     st->vertex_updates += n;
@@ -769,7 +800,7 @@ static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_pre
       break;
     }
     a.next = next;
-    DFPR_TRY(pull_all<MODE>(g, a, g->worklist, be, bedges, s, st));
+    DFPR_TRY(pull_all<MODE>(g, a, g->worklist, be, bedges, g->chunk_pre, false, s, st));
     DFPR_TRY(g->pool.start(&tok));
     k_commit_expand<<<grid_for(cnt, 256, 2048), 256, 0, s>>>(g->worklist, cnt, r_out, g->contrib, g->out.off,
                                                              g->out.idx, cur, next, g->xflag, g->big_list,

@@ -112,10 +112,18 @@ void dfpr_params_default(dfpr_params* p);
  * handle owns all its device memory (both CSRs, their rebuild buffers and the
  * rank scratch), allocated here so that later updates allocate nothing unless a
  * batch outgrows the edge capacity.  edge_capacity (0 = automatic) reserves room
- * for that many edges.  Errors: EINVAL (n <= 0, m < 0, null arrays with m > 0,
+ * for that many edges.  flags: DFPR_CREATE_* bits.  Errors: EINVAL (n <= 0, m < 0, null arrays with m > 0,
  * n or m beyond int32), ERANGE (an id outside [0,n)), ENOMEM, EHIP. */
 int dfpr_graph_create(int32_t n, int64_t m, const int32_t* src, const int32_t* dst,
-                      dfpr_where where, int64_t edge_capacity, void* stream, dfpr_graph** out);
+                      dfpr_where where, int64_t edge_capacity, int32_t flags, void* stream,
+                      dfpr_graph** out);
+
+/* create flags.  By default the library numbers vertices internally by
+ * decreasing degree, so that the rank contributions of the high-degree
+ * vertices, which most edges read, sit together in cache; ids at the ABI are
+ * always the caller's.  KEEP_IDS keeps the caller's numbering inside too
+ * (then the one-lane bin sums in the caller's ascending source order). */
+#define DFPR_CREATE_KEEP_IDS 1
 
 int dfpr_graph_destroy(dfpr_graph* g);
 

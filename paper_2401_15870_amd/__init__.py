@@ -74,13 +74,16 @@ class Graph:
         self.n = n
 
     @classmethod
-    def from_coo(cls, n, src, dst, edge_capacity=0, stream=None):
+    def from_coo(cls, n, src, dst, edge_capacity=0, keep_ids=False, stream=None):
+        """keep_ids: keep the caller's vertex numbering inside the library
+        (default: internal numbering by decreasing degree, invisible outside)."""
         ps, ms, ws, ks = _ids(src)
         pd, md, wd, kd = _ids(dst)
         if ms != md or ws != wd:
             raise ValueError("src and dst must have the same length and location")
         h = ctypes.c_void_p()
-        _check(lib().dfpr_graph_create(int(n), int(ms), ps, pd, ws, int(edge_capacity), _stream_ptr(stream),
+        flags = _capi.CREATE_KEEP_IDS if keep_ids else 0
+        _check(lib().dfpr_graph_create(int(n), int(ms), ps, pd, ws, int(edge_capacity), flags, _stream_ptr(stream),
                                        ctypes.byref(h)))
         return cls(h, int(n))
 

@@ -11,6 +11,7 @@ DFPR_OK, DFPR_EINVAL, DFPR_ERANGE, DFPR_ENOMEM, DFPR_EHIP, DFPR_ESTATE = 0, -1, 
 STATIC, ND, DF, DFP = 0, 1, 2, 3
 HOST, DEVICE = 0, 1
 FLAG_TIMING = 1
+CREATE_KEEP_IDS = 1
 
 # Every exported function declared in include/dfpr.h.
 EXPORTS = ("dfpr_params_default", "dfpr_graph_create", "dfpr_graph_destroy", "dfpr_graph_size",
@@ -62,7 +63,7 @@ def declare(lib):
     i32, i64 = ctypes.c_int32, ctypes.c_int64
     lib.dfpr_params_default.argtypes = [ctypes.POINTER(Params)]
     lib.dfpr_params_default.restype = None
-    lib.dfpr_graph_create.argtypes = [i32, i64, P, P, ctypes.c_int, i64, P, ctypes.POINTER(P)]
+    lib.dfpr_graph_create.argtypes = [i32, i64, P, P, ctypes.c_int, i64, i32, P, ctypes.POINTER(P)]
     lib.dfpr_graph_create.restype = ctypes.c_int
     lib.dfpr_graph_destroy.argtypes = [P]
     lib.dfpr_graph_destroy.restype = ctypes.c_int

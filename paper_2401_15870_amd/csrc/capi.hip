@@ -85,7 +85,7 @@ const char* dfpr_last_error(void) { return last_error(); }
 const char* dfpr_version(void) { return "dfpr 0.1 (gfx950)"; }
 
 int dfpr_graph_create(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, dfpr_where where,
-                      int64_t edge_capacity, void* stream, dfpr_graph** out) {
+                      int64_t edge_capacity, int32_t flags, void* stream, dfpr_graph** out) {
   clear_error();
   if (!out) {
     set_error("out is null");
@@ -93,12 +93,12 @@ int dfpr_graph_create(int32_t n, int64_t m, const int32_t* src, const int32_t* d
   }
   *out = nullptr;
   if (n <= 0 || m < 0 || (m > 0 && (!src || !dst)) || (where != DFPR_HOST && where != DFPR_DEVICE) ||
-      edge_capacity < 0) {
+      edge_capacity < 0 || (flags & ~DFPR_CREATE_KEEP_IDS) != 0) {
     set_error("invalid arguments: n=%d m=%lld", n, (long long)m);
     return DFPR_EINVAL;
   }
   try {
-    return graph_create(n, m, src, dst, where, edge_capacity, (hipStream_t)stream, out);
+    return graph_create(n, m, src, dst, where, edge_capacity, flags, (hipStream_t)stream, out);
   } catch (const std::bad_alloc&) {
     set_error("host allocation failed");
     return DFPR_ENOMEM;

@@ -153,6 +153,9 @@ struct dfpr_graph {
   int64_t m = 0;
   int64_t cap = 0;   // edge capacity of each index array
   int id_bits = 1;   // bits per vertex id in packed sort keys
+  int32_t* perm = nullptr;  // n: caller id -> internal id (null: identity)
+  int32_t* inv = nullptr;   // n: internal id -> caller id
+  double* rint = nullptr;   // n: ranks in internal order (when relabelled)
   dfpr::Csr out, in;        // current canonical CSRs
   dfpr::Csr out2, in2;      // rebuild targets (swapped in after a batch)
   // rank scratch (n entries each)
@@ -179,6 +182,7 @@ struct dfpr_graph {
   int64_t* bin_blk = nullptr;        // per-block bin counts (kBins * ceil(n/2048) + 1)
   int64_t* chunk_pre = nullptr;      // n+1: chunk prefix of the chunked bin (frontier worklist)
   int64_t* all_chunk_pre = nullptr;  // n+1: the same for the all-vertex bins
+  int64_t* piece_pre = nullptr;      // n/64+2: CSR rebuild work pieces per 64-row group
   double* partial = nullptr;         // partial sums of pull chunks
   int64_t partial_n = 0;
   int32_t* big_list = nullptr;       // n: vertices with long out-rows to mark
@@ -214,7 +218,7 @@ int compact_keys(const uint64_t* in, const uint8_t* keep, uint64_t* out, int64_t
 
 // ---- graph (graph.hip)
 int graph_create(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, dfpr_where where,
-                 int64_t edge_capacity, hipStream_t s, dfpr_graph** out);
+                 int64_t edge_capacity, int32_t flags, hipStream_t s, dfpr_graph** out);
 int graph_destroy(dfpr_graph* g);
 int graph_export(const dfpr_graph* g, int in_csr, int32_t* off, int32_t* idx, dfpr_where where,
                  hipStream_t s);

@@ -65,19 +65,46 @@ static void dfree(T*& p) {
 // ------------------------------------------------------------------ kernels
 constexpr uint64_t kBadKey = ~0ull;
 
+// ---- internal numbering by decreasing degree (ties by caller id)
+__global__ void k_validate_count(const int32_t* src, const int32_t* dst, int64_t m, int32_t n, int32_t* deg,
+                                 int64_t* err) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t u = src[i], v = dst[i];
+    if (u < 0 || u >= n || v < 0 || v >= n) {
+      atomicOr((unsigned long long*)err, 1ull);
+    } else if (deg) {
+      atomicAdd(&deg[u], 1);
+      atomicAdd(&deg[v], 1);
+    }
+  }
+}
+__global__ void k_degree_keys(const int32_t* deg, int32_t n, int b, uint64_t* keys) {
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+    keys[v] = ((uint64_t)(0x7FFFFFFF - deg[v]) << b) | (uint64_t)v;
+}
+__global__ void k_perm_from_sorted(const uint64_t* keys, int32_t n, int b, int32_t* perm, int32_t* inv) {
+  const uint64_t mask = (1ull << b) - 1;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t v = (int32_t)(keys[i] & mask);
+    inv[i] = v;
+    perm[v] = (int32_t)i;
+  }
+}
+
+// Edge keys (row << b | col) in internal ids plus one self-loop per vertex;
+// ids were validated by k_validate_count.
 __global__ void k_make_graph_keys(const int32_t* src, const int32_t* dst, int64_t m, int32_t n, int b,
-                                  uint64_t* keys, int64_t* err) {
+                                  const int32_t* perm, uint64_t* keys) {
   const int64_t total = m + n;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
     uint64_t k;
     if (i < m) {
-      const int32_t u = src[i], v = dst[i];
-      if (u < 0 || u >= n || v < 0 || v >= n) {
-        atomicOr((unsigned long long*)err, 1ull);
-        k = kBadKey;
-      } else {
-        k = ((uint64_t)u << b) | (uint64_t)v;
+      int32_t u = src[i], v = dst[i];
+      if (perm) {
+        u = perm[u];
+        v = perm[v];
       }
+      k = ((uint64_t)u << b) | (uint64_t)v;
     } else {
       const uint64_t v = (uint64_t)(i - m);
       k = (v << b) | v;  // the self-loop of every vertex
@@ -104,6 +131,15 @@ __global__ void k_csr_from_sorted(const uint64_t* keys, int64_t m, int b, int32_
   if (blockIdx.x == 0 && threadIdx.x == 0) off[n] = (int32_t)m;
 }
 
+// Internal CSR -> (caller row << b | caller col) keys, one thread per row.
+__global__ void k_external_keys(const int32_t* off, const int32_t* idx, int32_t n, const int32_t* inv, int b,
+                                uint64_t* keys) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t r = (uint64_t)inv[i] << b;
+    for (int32_t p = off[i]; p < off[i + 1]; p++) keys[p] = r | (uint64_t)inv[idx[p]];
+  }
+}
+
 __global__ void k_transpose_keys(const uint64_t* in, int64_t m, int b, uint64_t* out) {
   const uint64_t mask = (1ull << b) - 1;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
@@ -114,17 +150,22 @@ __global__ void k_transpose_keys(const uint64_t* in, int64_t m, int b, uint64_t*
 
 // Batch keys; out-of-range ids raise err and produce kBadKey.
 __global__ void k_make_batch_keys(const int32_t* del_src, const int32_t* del_dst, int64_t nd, const int32_t* ins_src,
-                                  const int32_t* ins_dst, int64_t ni, int32_t n, int b, uint64_t* keys, int64_t* err) {
+                                  const int32_t* ins_dst, int64_t ni, int32_t n, int b, const int32_t* perm,
+                                  uint64_t* keys, int64_t* err) {
   const int64_t total = nd + ni;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
     const bool ins = i >= nd;
-    const int32_t u = ins ? ins_src[i - nd] : del_src[i];
-    const int32_t v = ins ? ins_dst[i - nd] : del_dst[i];
+    int32_t u = ins ? ins_src[i - nd] : del_src[i];
+    int32_t v = ins ? ins_dst[i - nd] : del_dst[i];
     uint64_t k;
     if (u < 0 || u >= n || v < 0 || v >= n) {
       atomicOr((unsigned long long*)err, 1ull);
       k = kBadKey;
     } else {
+      if (perm) {
+        u = perm[u];
+        v = perm[v];
+      }
       k = ((uint64_t)u << (b + 1)) | ((uint64_t)v << 1) | (ins ? 1ull : 0ull);
     }
     keys[i] = k;
@@ -212,88 +253,153 @@ struct StoreI64b {
   __device__ void operator()(int64_t i, int64_t v) const { a[i] = v; }
 };
 
-// Rebuild one CSR.  Each wavefront owns 64 consecutive rows.  Untouched rows
-// keep their content and only shift, so a group without touched rows is one
-// contiguous copy.  A touched row is rebuilt by placing every element at its
-// merge position: an old element x lands at j - #del(<x) + #ins(<x), an
-// inserted y at k + #old(<y) - #del(<y), where the counts come from binary
-// searches over the row's sorted effective entries (delpre = prefix count of
-// deletions in that list).
+// Rebuild one CSR.  Rows are taken in groups of 64 (one per lane); a group's
+// old edges are cut into pieces of at most kPiece edges (piece_pre = prefix of
+// the piece counts per group), and each wavefront takes one piece, so a long
+// row is spread over many wavefronts.  Untouched rows keep their content and
+// only shift, so a piece of a group without touched rows is one contiguous
+// copy.  In a touched row an old element x lands at j - #del(<x) + #ins(<x)
+// (counts by binary search over the row's sorted effective entries, delpre =
+// prefix count of deletions in that list); deleted elements are dropped.
+// Insertions are placed by k_place_inserts.
+constexpr int kPiece = 8192;
+
+struct LoadPieces {
+  const int32_t* ooff;
+  int32_t n;
+  __device__ int64_t operator()(int64_t g) const {
+    const int32_t r0 = (int32_t)(g * kWave);
+    const int32_t r1 = (int32_t)min((int64_t)r0 + kWave, (int64_t)n);
+    const int64_t len = (int64_t)ooff[r1] - ooff[r0];
+    return len > kPiece ? (len + kPiece - 1) / kPiece : 1;
+  }
+};
+struct StorePieces {
+  int64_t* a;
+  __device__ void operator()(int64_t i, int64_t v) const { a[i] = v; }
+};
+
+__device__ __forceinline__ int64_t upper_bound_pre(const int64_t* a, int64_t lo, int64_t hi, int64_t x) {
+  while (lo < hi) {
+    int64_t mid = lo + ((hi - lo) >> 1);
+    if (a[mid] <= x) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+// largest lane j with st[j] <= e (st non-decreasing across lanes, st[0] <= e)
+__device__ __forceinline__ int lane_seg(int32_t st, int32_t e) {
+  int lo = 0, hi = kWave;
+#pragma unroll
+  for (int i = 0; i < 6; i++) {
+    const int mid = (lo + hi) >> 1;
+    if (__shfl(st, mid, kWave) <= e) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
 __global__ void __launch_bounds__(256) k_rebuild(const int32_t* __restrict__ ooff, const int32_t* __restrict__ oidx,
-                                                 const int32_t* __restrict__ noff, int32_t* __restrict__ nidx, const uint8_t* touched, const uint64_t* eff,
-                                                 const int64_t* delpre, const int64_t* count, int b, int32_t n,
+                                                 const int32_t* __restrict__ noff, int32_t* __restrict__ nidx,
+                                                 const uint8_t* touched, const uint64_t* eff, const int64_t* delpre,
+                                                 const int64_t* count, int b, int32_t n, const int64_t* piece_pre,
                                                  int64_t* err) {
   const int lane = lane_id();
   const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
   const int64_t groups = ((int64_t)n + kWave - 1) / kWave;
+  const int64_t total = piece_pre[groups];
   const int64_t T = *count;
-  for (int64_t g = blockIdx.x * (int64_t)(blockDim.x / kWave) + threadIdx.x / kWave; g < groups; g += waves) {
+  for (int64_t q = blockIdx.x * (int64_t)(blockDim.x / kWave) + threadIdx.x / kWave; q < total; q += waves) {
+    const int64_t g = upper_bound_pre(piece_pre, 0, groups + 1, q) - 1;
+    const int64_t k = q - piece_pre[g];
     const int32_t r0 = (int32_t)(g * kWave);
-    const int32_t rend = (int32_t)std::min<int64_t>((int64_t)r0 + kWave, n);
-    const bool t = (r0 + lane < rend) ? touched[r0 + lane] != 0 : false;
+    const int32_t rend = (int32_t)min((int64_t)r0 + kWave, (int64_t)n);
+    const int32_t r = r0 + lane;
+    const bool valid = r < rend;
+    const bool t = valid ? touched[r] != 0 : false;
     const uint64_t any = __ballot(t);
+    const int32_t s0 = ooff[r0], s1 = ooff[rend];
+    const int32_t a = s0 + (int32_t)(k * kPiece);
+    const int32_t bnd = (int32_t)min((int64_t)a + kPiece, (int64_t)s1);
     if (!any) {
-      const int32_t s0 = ooff[r0], s1 = ooff[rend];
       const int64_t shift = (int64_t)noff[r0] - s0;
       if ((int64_t)s1 + shift != (int64_t)noff[rend]) {  // offsets disagree: refuse to write
         if (lane == 0) atomicOr((unsigned long long*)err, 2ull);
         continue;
       }
-      int32_t p = s0 + lane;
-      for (; p + 3 * kWave < s1; p += 4 * kWave) {
+      int32_t p = a + lane;
+      for (; p + 3 * kWave < bnd; p += 4 * kWave) {
         const int32_t x0 = oidx[p], x1 = oidx[p + kWave], x2 = oidx[p + 2 * kWave], x3 = oidx[p + 3 * kWave];
         nidx[p + shift] = x0;
         nidx[p + kWave + shift] = x1;
         nidx[p + 2 * kWave + shift] = x2;
         nidx[p + 3 * kWave + shift] = x3;
       }
-      for (; p < s1; p += kWave) nidx[p + shift] = oidx[p];
+      for (; p < bnd; p += kWave) nidx[p + shift] = oidx[p];
       continue;
     }
-    for (int32_t r = r0; r < rend; r++) {
-      const int32_t os = ooff[r], oe = ooff[r + 1];
-      const int32_t base = noff[r], lim = noff[r + 1];
-      if (!((any >> (r - r0)) & 1ull)) {
-        if (lim - base != oe - os) {
-          if (lane == 0) atomicOr((unsigned long long*)err, 2ull);
-          continue;
-        }
-        for (int32_t p = os + lane; p < oe; p += kWave) nidx[base + (p - os)] = oidx[p];
+    // per-lane row data of the group (lane l holds row r0 + l)
+    const int32_t os = valid ? ooff[r] : INT32_MAX;
+    const int32_t base = valid ? noff[r] : 0;
+    const int32_t lim = valid ? noff[r + 1] : 0;
+    int64_t lo = 0, hi = 0, dlo = 0;
+    if (t) {
+      const uint64_t rk = (uint64_t)r << (b + 1);
+      lo = lower_bound_u64(eff, 0, T, rk);
+      hi = lower_bound_u64(eff, lo, T, rk + (1ull << (b + 1)));
+      dlo = delpre[lo];
+    }
+    for (int32_t p0 = a; p0 < bnd; p0 += kWave) {
+      const int32_t p = p0 + lane;
+      const bool ok = p < bnd;
+      const int j = lane_seg(os, ok ? p : a);
+      const int32_t r_os = __shfl(os, j, kWave), r_base = __shfl(base, j, kWave), r_lim = __shfl(lim, j, kWave);
+      const bool r_t = __shfl((int)t, j, kWave) != 0;
+      const int64_t r_lo = __shfl(lo, j, kWave), r_hi = __shfl(hi, j, kWave), r_dlo = __shfl(dlo, j, kWave);
+      if (!ok) continue;
+      const int32_t x = oidx[p];
+      const int32_t jj = p - r_os;
+      int64_t pos;
+      if (!r_t) {
+        pos = (int64_t)r_base + jj;
+      } else {
+        const uint64_t xk = ((uint64_t)(r0 + j) << (b + 1)) | ((uint64_t)x << 1);
+        const int64_t qq = lower_bound_u64(eff, r_lo, r_hi, xk);
+        if (qq < r_hi && eff[qq] == xk) continue;  // deleted
+        const int64_t dels = delpre[qq] - r_dlo;
+        pos = (int64_t)r_base + jj - dels + ((qq - r_lo) - dels);
+      }
+      if (pos < r_base || pos >= r_lim) {
+        atomicOr((unsigned long long*)err, 2ull);
         continue;
       }
-      const uint64_t rk = (uint64_t)r << (b + 1);
-      const int64_t lo = lower_bound_u64(eff, 0, T, rk);
-      const int64_t hi = lower_bound_u64(eff, lo, T, rk + (1ull << (b + 1)));
-      const int64_t dlo = delpre[lo];
-      for (int32_t j = lane; j < oe - os; j += kWave) {
-        const int32_t x = oidx[os + j];
-        const uint64_t xk = rk | ((uint64_t)x << 1);
-        const int64_t q = lower_bound_u64(eff, lo, hi, xk);
-        if (q < hi && eff[q] == xk) continue;  // deleted
-        const int64_t dels = delpre[q] - dlo;
-        const int64_t inss = (q - lo) - dels;
-        const int64_t pos = base + j - dels + inss;
-        if (pos < base || pos >= lim) {
-          atomicOr((unsigned long long*)err, 2ull);
-          continue;
-        }
-        nidx[pos] = x;
-      }
-      for (int64_t e = lo + lane; e < hi; e += kWave) {
-        const uint64_t k = eff[e];
-        if (!(k & 1ull)) continue;
-        const int32_t y = (int32_t)((k >> 1) & ((1ull << b) - 1));
-        const int64_t dels = delpre[e] - dlo;
-        const int64_t kins = (e - lo) - dels;
-        const int32_t oless = lower_bound_i32(oidx, os, oe, y) - os;
-        const int64_t pos = base + kins + oless - dels;
-        if (pos < base || pos >= lim) {
-          atomicOr((unsigned long long*)err, 2ull);
-          continue;
-        }
-        nidx[pos] = y;
-      }
+      nidx[pos] = x;
     }
+  }
+}
+
+// Insertions: an inserted y of row r lands at k + #old(<y) - #del(<y), k its
+// index among the row's insertions.
+__global__ void k_place_inserts(const int32_t* __restrict__ ooff, const int32_t* __restrict__ oidx,
+                                const int32_t* __restrict__ noff, int32_t* __restrict__ nidx, const uint64_t* eff,
+                                const int64_t* delpre, const int64_t* count, int b, int64_t* err) {
+  const int64_t T = *count;
+  const uint64_t mask = (1ull << b) - 1;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < T; e += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t k = eff[e];
+    if (!(k & 1ull)) continue;
+    const int32_t r = (int32_t)(k >> (b + 1));
+    const int32_t y = (int32_t)((k >> 1) & mask);
+    const int64_t lo = lower_bound_u64(eff, 0, e, (uint64_t)r << (b + 1));
+    const int64_t dels = delpre[e] - delpre[lo];
+    const int64_t kins = (e - lo) - dels;
+    const int32_t os = ooff[r], oe = ooff[r + 1];
+    const int32_t oless = lower_bound_i32(oidx, os, oe, y) - os;
+    const int64_t pos = (int64_t)noff[r] + kins + oless - dels;
+    if (pos < noff[r] || pos >= noff[r + 1]) {
+      atomicOr((unsigned long long*)err, 2ull);
+      continue;
+    }
+    nidx[pos] = y;
   }
 }
 
@@ -336,6 +442,7 @@ static int alloc_rank_scratch(dfpr_graph* g) {
   DFPR_TRY(dalloc(&g->arrive, n));
   DFPR_HIP(hipMemset(g->arrive, 0, n * sizeof(int32_t)));
   DFPR_TRY(dalloc(&g->chunk_pre, n + 1));
+  DFPR_TRY(dalloc(&g->piece_pre, n / kWave + 2));
   DFPR_TRY(dalloc(&g->all_chunk_pre, n + 1));
   DFPR_TRY(dalloc(&g->big_list, n));
   DFPR_TRY(dalloc(&g->big_pre, n + 1));
@@ -392,11 +499,15 @@ int graph_destroy(dfpr_graph* g) {
   dfree(g->scan_tmp);
   dfree(g->bin_blk);
   dfree(g->chunk_pre);
+  dfree(g->piece_pre);
   dfree(g->all_chunk_pre);
   dfree(g->big_list);
   dfree(g->big_pre);
   dfree(g->partial);
   dfree(g->arrive);
+  dfree(g->perm);
+  dfree(g->inv);
+  dfree(g->rint);
   if (g->ctl_host) (void)hipHostFree(g->ctl_host);
   g->ctl_host = nullptr;
   g->keys_a.release();
@@ -438,7 +549,7 @@ static int build_csr_from_keys(uint64_t** ka, uint64_t** kb, int64_t m, int b, i
 }
 
 int graph_create(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, dfpr_where where,
-                 int64_t edge_capacity, hipStream_t s, dfpr_graph** out) {
+                 int64_t edge_capacity, int32_t flags, hipStream_t s, dfpr_graph** out) {
   *out = nullptr;
   const int64_t total = m + n;
   if (total > INT32_MAX) {
@@ -454,6 +565,7 @@ int graph_create(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, d
   g->n = n;
   g->id_bits = bits_for(n);
   const int b = g->id_bits;
+  const bool relabel = (flags & DFPR_CREATE_KEEP_IDS) == 0;
   int rc = DFPR_OK;
   {
     CreateTmp t;
@@ -472,23 +584,37 @@ int graph_create(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, d
       dsrc = t.coo;
       ddst = t.coo + m;
     }
-    if ((rc = dalloc(&t.ka, total)) || (rc = dalloc(&t.kb, total)) || (rc = dalloc(&t.keep, total)) ||
-        (rc = dalloc(&t.pre, total + 1)) || (rc = dalloc(&t.hist, radix_hist_elems(total))) ||
-        (rc = dalloc(&t.tmp, std::max(radix_scan_tmp_elems(total), scan_tmp_elems(total + 1)))) ||
+    const int64_t kmax = std::max<int64_t>(total, n);
+    if ((rc = dalloc(&t.ka, kmax)) || (rc = dalloc(&t.kb, kmax)) || (rc = dalloc(&t.keep, total)) ||
+        (rc = dalloc(&t.pre, total + 1)) || (rc = dalloc(&t.hist, radix_hist_elems(kmax))) ||
+        (rc = dalloc(&t.tmp, std::max(radix_scan_tmp_elems(kmax), scan_tmp_elems(total + 1)))) ||
         (rc = dalloc(&t.cnt, 2)))
       return fail(rc);
+    int32_t* deg = nullptr;
+    if (relabel) {
+      if ((rc = dalloc(&g->perm, n)) || (rc = dalloc(&g->inv, n)) || (rc = dalloc(&g->rint, n))) return fail(rc);
+      deg = reinterpret_cast<int32_t*>(t.kb);  // the second key buffer is free until the sort
+      if (hipMemsetAsync(deg, 0, (size_t)n * sizeof(int32_t), s) != hipSuccess) return fail(DFPR_EHIP);
+    }
     if (hipMemsetAsync(t.cnt, 0, 2 * sizeof(int64_t), s) != hipSuccess) return fail(DFPR_EHIP);
-    k_make_graph_keys<<<grid_for(total, 256, 65536), 256, 0, s>>>(dsrc, ddst, m, n, b, t.ka, t.cnt);
+    if (m > 0) k_validate_count<<<grid_for(m, 256, 65536), 256, 0, s>>>(dsrc, ddst, m, n, deg, t.cnt);
     int64_t err = 0;
     if (hipMemcpyAsync(&err, t.cnt, sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess) {
-      set_error("graph key construction failed");
+      set_error("edge validation failed");
       return fail(DFPR_EHIP);
     }
     if (err) {
       set_error("vertex id outside [0, %d)", n);
       return fail(DFPR_ERANGE);
     }
+    if (relabel) {
+      // order vertices by decreasing degree: sort (2^31-1-deg, id) keys
+      k_degree_keys<<<grid_for(n, 256, 65536), 256, 0, s>>>(deg, n, b, t.ka);
+      if ((rc = radix_sort(&t.ka, &t.kb, n, 31 + b, t.hist, t.tmp, s))) return fail(rc);
+      k_perm_from_sorted<<<grid_for(n, 256, 65536), 256, 0, s>>>(t.ka, n, b, g->perm, g->inv);
+    }
+    k_make_graph_keys<<<grid_for(total, 256, 65536), 256, 0, s>>>(dsrc, ddst, m, n, b, g->perm, t.ka);
     if ((rc = radix_sort(&t.ka, &t.kb, total, 2 * b, t.hist, t.tmp, s))) return fail(rc);
     k_mark_unique<<<grid_for(total, 256, 65536), 256, 0, s>>>(t.ka, total, t.keep);
     if ((rc = compact_keys(t.ka, t.keep, t.kb, total, t.cnt + 1, t.pre, t.tmp, s))) return fail(rc);
@@ -524,9 +650,40 @@ int graph_create(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, d
 int graph_export(const dfpr_graph* g, int in_csr, int32_t* off, int32_t* idx, dfpr_where where, hipStream_t s) {
   const Csr& c = in_csr ? g->in : g->out;
   const hipMemcpyKind kind = where == DFPR_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
-  DFPR_HIP(hipMemcpyAsync(off, c.off, ((size_t)g->n + 1) * sizeof(int32_t), kind, s));
-  if (g->m > 0) DFPR_HIP(hipMemcpyAsync(idx, c.idx, (size_t)g->m * sizeof(int32_t), kind, s));
+  if (!g->perm) {
+    DFPR_HIP(hipMemcpyAsync(off, c.off, ((size_t)g->n + 1) * sizeof(int32_t), kind, s));
+    if (g->m > 0) DFPR_HIP(hipMemcpyAsync(idx, c.idx, (size_t)g->m * sizeof(int32_t), kind, s));
+    DFPR_HIP(hipStreamSynchronize(s));
+    return DFPR_OK;
+  }
+  // caller numbering: map both ends of every edge back and sort again
+  const int32_t n = g->n;
+  const int64_t m = g->m;
+  const int b = g->id_bits;
+  CreateTmp t;
+  Csr outc;
+  int rc;
+  if ((rc = dalloc(&t.ka, m)) || (rc = dalloc(&t.kb, m)) || (rc = dalloc(&t.hist, radix_hist_elems(m))) ||
+      (rc = dalloc(&t.tmp, radix_scan_tmp_elems(m))))
+    return rc;
+  int32_t* doff = off;
+  int32_t* didx = idx;
+  if (where == DFPR_HOST) {
+    if ((rc = dalloc(&t.coo, (size_t)(n + 1 + m)))) return rc;
+    doff = t.coo;
+    didx = t.coo + n + 1;
+  }
+  k_external_keys<<<grid_for(n, 256, 65536), 256, 0, s>>>(c.off, c.idx, n, g->inv, b, t.ka);
+  DFPR_HIP(hipGetLastError());
+  outc.off = doff;
+  outc.idx = didx;
+  DFPR_TRY(build_csr_from_keys(&t.ka, &t.kb, m, b, n, &outc, t.hist, t.tmp, s));
+  if (where == DFPR_HOST) {
+    DFPR_HIP(hipMemcpyAsync(off, doff, ((size_t)n + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    if (m > 0) DFPR_HIP(hipMemcpyAsync(idx, didx, (size_t)m * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  }
   DFPR_HIP(hipStreamSynchronize(s));
+  outc.off = outc.idx = nullptr;
   return DFPR_OK;
 }
 
@@ -550,6 +707,21 @@ static int grow_capacity(dfpr_graph* g, int64_t want, hipStream_t s) {
     DFPR_TRY(dalloc(&g->partial, (size_t)pn));
     g->partial_n = pn;
   }
+  return DFPR_OK;
+}
+
+// One CSR: pieces of the old edges, then the insertions.
+static int rebuild_csr(dfpr_graph* g, const Csr& o, const Csr& nw, const uint8_t* touched, const uint64_t* eff,
+                       const int64_t* delpre, const int64_t* cnt, int64_t nk, int64_t* err, hipStream_t s) {
+  const int32_t n = g->n;
+  const int64_t groups = ((int64_t)n + kWave - 1) / kWave;
+  DFPR_TRY(scan_generic(LoadPieces{o.off, n}, StorePieces{g->piece_pre}, groups, g->scan_tmp, s));
+  const int64_t est = groups + g->m / kPiece + 1;  // upper bound on the piece count
+  k_rebuild<<<grid_for(est, 4, 1u << 16), 256, 0, s>>>(o.off, o.idx, nw.off, nw.idx, touched, eff, delpre, cnt,
+                                                       g->id_bits, n, g->piece_pre, err);
+  k_place_inserts<<<grid_for(nk, 256, 4096), 256, 0, s>>>(o.off, o.idx, nw.off, nw.idx, eff, delpre, cnt, g->id_bits,
+                                                          err);
+  DFPR_HIP(hipGetLastError());
   return DFPR_OK;
 }
 
@@ -613,7 +785,8 @@ int graph_apply(dfpr_graph* g, int64_t nd, const int32_t* del_src, const int32_t
   DFPR_TRY(ep.start(&t_total));
   // ---- keys + validation (validation before mutation: one sync)
   DFPR_HIP(hipMemsetAsync(counters, 0, 6 * sizeof(int64_t), s));
-  k_make_batch_keys<<<grid_for(nk, 256, 65536), 256, 0, s>>>(ds, dd, nd, is, id, ni, n, b, ka, counters + 4);
+  k_make_batch_keys<<<grid_for(nk, 256, 65536), 256, 0, s>>>(ds, dd, nd, is, id, ni, n, b, g->perm, ka,
+                                                              counters + 4);
   DFPR_HIP(hipGetLastError());
   DFPR_HIP(hipMemcpyAsync(g->ctl_host->n_apply, counters, 6 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
   DFPR_HIP(hipStreamSynchronize(s));
@@ -638,11 +811,8 @@ int graph_apply(dfpr_graph* g, int64_t nd, const int32_t* del_src, const int32_t
 
   // ---- out-CSR
   DFPR_TRY(scan_row_offsets(g->out.off, g->delta_out, g->out2.off, n, g->scan_tmp, s));
-  const unsigned rb_grid = grid_for(((int64_t)n + kWave - 1) / kWave, 4, 1u << 16);
   DFPR_TRY(ep.start(&tok));
-  k_rebuild<<<rb_grid, 256, 0, s>>>(g->out.off, g->out.idx, g->out2.off, g->out2.idx, g->touched_out, eff_out,
-                                    pre_out, cnt, b, n, counters + 4);
-  DFPR_HIP(hipGetLastError());
+  DFPR_TRY(rebuild_csr(g, g->out, g->out2, g->touched_out, eff_out, pre_out, cnt, nk, counters + 4, s));
   DFPR_TRY(ep.stop(kTRebuildOut, tok));
 
   // ---- in-CSR: the same entries ordered by (v, u)
@@ -655,9 +825,7 @@ int graph_apply(dfpr_graph* g, int64_t nd, const int32_t* del_src, const int32_t
   DFPR_TRY(scan_generic(LoadIsDel{eff_in, cnt}, StoreI64b{pre_in}, nk, tmp, s));
   DFPR_TRY(scan_row_offsets(g->in.off, g->delta_in, g->in2.off, n, g->scan_tmp, s));
   DFPR_TRY(ep.start(&tok));
-  k_rebuild<<<rb_grid, 256, 0, s>>>(g->in.off, g->in.idx, g->in2.off, g->in2.idx, g->touched_in, eff_in, pre_in, cnt,
-                                    b, n, counters + 4);
-  DFPR_HIP(hipGetLastError());
+  DFPR_TRY(rebuild_csr(g, g->in, g->in2, g->touched_in, eff_in, pre_in, cnt, nk, counters + 4, s));
   DFPR_TRY(ep.stop(kTRebuildIn, tok));
   k_clear_rows<<<grid_for(nk, 256, 65536), 256, 0, s>>>(eff_out, cnt, b, g->delta_out, g->delta_in, g->touched_out,
                                                         g->touched_in);

@@ -566,6 +566,19 @@ __global__ void k_init_prev(const double* r_prev, double* R, double* contrib, co
     contrib[v] = r / (double)(out_off[v + 1] - out_off[v]);
   }
 }
+// Caller order <-> internal order of the rank vector.
+__global__ void k_gather_ranks(const double* r_ext, const int32_t* __restrict__ inv, double* R, double* contrib,
+                               const int32_t* __restrict__ out_off, int32_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double r = r_ext[inv[i]];
+    R[i] = r;
+    contrib[i] = r / (double)(out_off[i + 1] - out_off[i]);
+  }
+}
+__global__ void k_scatter_ranks(const double* R, const int32_t* __restrict__ inv, double* r_ext, int32_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    r_ext[inv[i]] = R[i];
+}
 __global__ void __launch_bounds__(256) k_count_clear_ever(uint8_t* ever, int32_t n, unsigned long long* acc) {
   int64_t c = 0;
   for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
@@ -715,12 +728,15 @@ static int run_sync(dfpr_graph* g, bool cold, const dfpr_params& p, const double
     g->all_bins_valid = true;
   }
   const unsigned gi = grid_for(n, 256, 2048);
+  double* R0 = g->perm ? g->rint : r_out;  // ranks in internal order
   if (cold)
-    k_init_static<<<gi, 256, 0, s>>>(r_out, g->contrib, g->out.off, n);
+    k_init_static<<<gi, 256, 0, s>>>(R0, g->contrib, g->out.off, n);
+  else if (g->perm)
+    k_gather_ranks<<<gi, 256, 0, s>>>(r_prev, g->inv, R0, g->contrib, g->out.off, n);
   else
     k_init_prev<<<gi, 256, 0, s>>>(r_prev, r_out, g->contrib, g->out.off, n, r_prev != r_out);
   DFPR_HIP(hipGetLastError());
-  double *Ra = r_out, *Rb = g->rn, *ca = g->contrib, *cb = g->contrib2;
+  double *Ra = R0, *Rb = g->rn, *ca = g->contrib, *cb = g->contrib2;
   PullArgs a = make_args(g, p);
   int it = 0;
   double dR = 0.0;
@@ -744,7 +760,10 @@ static int run_sync(dfpr_graph* g, bool cold, const dfpr_params& p, const double
       break;
     }
   }
-  if (Ra != r_out) DFPR_HIP(hipMemcpyAsync(r_out, Ra, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (g->perm)
+    k_scatter_ranks<<<gi, 256, 0, s>>>(Ra, g->inv, r_out, n);
+  else if (Ra != r_out)
+    DFPR_HIP(hipMemcpyAsync(r_out, Ra, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
   // ranks now come from a full solve: pending batch marks are void
   if (g->pending_any) {
     k_fill_u8<<<gi, 256, 0, s>>>(g->pend_src, n, 0);
@@ -765,7 +784,11 @@ static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_pre
   const int32_t n = g->n;
   const unsigned gi = grid_for(n, 256, 2048);
   k_reset_ctl<<<64, 256, 0, s>>>(g->ctl);
-  k_init_prev<<<gi, 256, 0, s>>>(r_prev, r_out, g->contrib, g->out.off, n, r_prev != r_out);
+  double* R = g->perm ? g->rint : r_out;  // ranks in internal order
+  if (g->perm)
+    k_gather_ranks<<<gi, 256, 0, s>>>(r_prev, g->inv, R, g->contrib, g->out.off, n);
+  else
+    k_init_prev<<<gi, 256, 0, s>>>(r_prev, r_out, g->contrib, g->out.off, n, r_prev != r_out);
   // initial marking: out(u) of pending sources (+ deletion targets already in flag_cur)
   size_t tok;
   DFPR_TRY(g->pool.start(&tok));
@@ -780,7 +803,7 @@ static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_pre
   uint8_t *cur = g->flag_cur, *next = g->flag_next;
   PullArgs a = make_args(g, p);
   a.contrib = g->contrib;
-  a.R = r_out;
+  a.R = R;
   a.xflag = g->xflag;
   int it = 0;
   double dR = 0.0;
@@ -802,7 +825,7 @@ static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_pre
     a.next = next;
     DFPR_TRY(pull_all<MODE>(g, a, g->worklist, be, bedges, g->chunk_pre, false, s, st));
     DFPR_TRY(g->pool.start(&tok));
-    k_commit_expand<<<grid_for(cnt, 256, 2048), 256, 0, s>>>(g->worklist, cnt, r_out, g->contrib, g->out.off,
+    k_commit_expand<<<grid_for(cnt, 256, 2048), 256, 0, s>>>(g->worklist, cnt, R, g->contrib, g->out.off,
                                                              g->out.idx, cur, next, g->xflag, g->big_list,
                                                              &g->ctl->big_count);
     DFPR_HIP(hipGetLastError());
@@ -818,6 +841,7 @@ static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_pre
       break;
     }
   }
+  if (g->perm) k_scatter_ranks<<<gi, 256, 0, s>>>(R, g->inv, r_out, n);
   // leave both flag arrays clear for the next batch
   k_fill_u8<<<gi, 256, 0, s>>>(cur, n, 0);
   k_count_clear_ever<<<gi, 256, 0, s>>>(g->ever, n, &g->ctl->acc_slots[0][0]);

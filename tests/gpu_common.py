@@ -41,6 +41,7 @@ class Pair:
         self.dfpr = dfpr()
         self.og = O.graph(n, src, dst)
         self.g = self.dfpr.Graph.from_coo(n, src, dst, **kw)
+        self.kw = kw
         self.og_prev = None
         self.batch = None
         self.n = n

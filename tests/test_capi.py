@@ -41,9 +41,10 @@ def test_params_default(lib):
 
 def test_invalid_arguments_rejected_before_device_work(lib):
     h = ctypes.c_void_p()
-    assert lib.dfpr_graph_create(0, 0, None, None, 0, 0, None, ctypes.byref(h)) == _capi.DFPR_EINVAL
-    assert lib.dfpr_graph_create(5, 3, None, None, 0, 0, None, ctypes.byref(h)) == _capi.DFPR_EINVAL
-    assert lib.dfpr_graph_create(5, -1, None, None, 0, 0, None, ctypes.byref(h)) == _capi.DFPR_EINVAL
+    assert lib.dfpr_graph_create(0, 0, None, None, 0, 0, 0, None, ctypes.byref(h)) == _capi.DFPR_EINVAL
+    assert lib.dfpr_graph_create(5, 3, None, None, 0, 0, 0, None, ctypes.byref(h)) == _capi.DFPR_EINVAL
+    assert lib.dfpr_graph_create(5, -1, None, None, 0, 0, 0, None, ctypes.byref(h)) == _capi.DFPR_EINVAL
+    assert lib.dfpr_graph_create(5, 0, None, None, 0, 0, 8, None, ctypes.byref(h)) == _capi.DFPR_EINVAL
     assert b"invalid" in lib.dfpr_last_error()
     st = _capi.Stats()
     assert lib.dfpr_update_ranks(None, 3, None, None, None, None, ctypes.byref(st)) == _capi.DFPR_EINVAL

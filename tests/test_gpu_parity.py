@@ -16,8 +16,9 @@ def _print(*a):
 
 
 # ------------------------------------------------------------------ graph store
+@pytest.mark.parametrize("keep_ids", [False, True])
 @pytest.mark.parametrize("case", ["single_vertex", "no_edges", "dups_and_selfs", "rmat10", "rmat14", "hub"])
-def test_create_csr_bitexact(case):
+def test_create_csr_bitexact(case, keep_ids):
     torch_cuda()
     _print("create", case)
     if case == "single_vertex":
@@ -36,7 +37,7 @@ def test_create_csr_bitexact(case):
         n, s, d = rmat(14, seed=3)
     else:
         n, s, d = hub_graph(30000, 9000, 12000, 60000, seed=4)
-    p = Pair(n, s, d)
+    p = Pair(n, s, d, keep_ids=keep_ids)
     assert p.g.m == p.og.m
     assert_csr_equal(p.g, p.og)
 
@@ -49,7 +50,7 @@ def test_apply_messy_batches_chained():
     for trial in range(12):
         n = int(rng.integers(2, 400))
         s, d = W.random_digraph(n, float(rng.uniform(0.002, 0.05)), seed=trial)
-        p = Pair(n, s, d)
+        p = Pair(n, s, d, keep_ids=bool(trial % 2))
         for step in range(4):
             ds, dd, is_, id_ = W.random_edit_batch(n, p.og.esrc, p.og.edst, int(rng.integers(0, 60)),
                                                    int(rng.integers(0, 60)), seed=trial * 10 + step)
@@ -89,19 +90,20 @@ def test_apply_hub_rows():
 
 
 # ------------------------------------------------------------------ ranks
-def _setup(scale=12, frac=1e-3, seed=1, ef=16):
+def _setup(scale=12, frac=1e-3, seed=1, ef=16, keep_ids=False):
     n, s, d = rmat(scale, ef=ef, seed=seed)
-    p = Pair(n, s, d)
+    p = Pair(n, s, d, keep_ids=keep_ids)
     r0 = O.rank("static", p.og).ranks
     ds, dd, is_, id_ = W.batch_8020(n, s, d, frac, seed=seed + 100)
     p.apply(ds, dd, is_, id_)
     return p, r0
 
 
+@pytest.mark.parametrize("keep_ids", [False, True])
 @pytest.mark.parametrize("mode", ["static", "nd", "df", "dfp"])
 @pytest.mark.parametrize("scale,frac", [(10, 1e-2), (14, 1e-3)])
-def test_ranks_parity(mode, scale, frac):
-    p, r0 = _setup(scale, frac, seed=scale)
+def test_ranks_parity(mode, scale, frac, keep_ids):
+    p, r0 = _setup(scale, frac, seed=scale, keep_ids=keep_ids)
     _print("ranks", mode, scale, frac)
     r, st, ref = p.rank(mode, r0)
     err = float(np.abs(r - ref.ranks).max())
@@ -117,7 +119,7 @@ def test_ranks_parity(mode, scale, frac):
 def test_ranks_bitexact_lane_bin(mode):
     """With every vertex in the one-lane bin the sums run in the oracle's order:
     ranks, iteration counts and frontier statistics are identical."""
-    p, r0 = _setup(13, 1e-3, seed=21)
+    p, r0 = _setup(13, 1e-3, seed=21, keep_ids=True)
     maxdeg = int(np.diff(p.og.in_off).max())
     p.g.set_tuning([maxdeg] * 5)
     r, st, ref = p.rank(mode, r0)

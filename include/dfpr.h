@@ -54,9 +54,13 @@ typedef enum { DFPR_HOST = 0, DFPR_DEVICE = 1 } dfpr_where;
  * of the rank change (> 0).  frontier_tol (tau_f): a processed vertex marks its
  * out-neighbours when its relative change exceeds it.  prune_tol (tau_p): DF-P
  * unmarks a processed vertex whose relative change is at most this.
+ * dense_switch (>= 0): DF/DF-P iterations whose affected vertices hold more than
+ * this share of |E| in-edges run in the dense form (every vertex checks its
+ * in-neighbours' expand flags instead of being marked); 0 = always dense, above
+ * 1 = never.  Both forms give identical results; only speed differs.
  * max_iters >= 1.  flags: DFPR_FLAG_* bits. */
 typedef struct {
-  double alpha, tol, frontier_tol, prune_tol;
+  double alpha, tol, frontier_tol, prune_tol, dense_switch;
   int32_t max_iters;
   int32_t flags;
 } dfpr_params;
@@ -98,12 +102,19 @@ typedef struct {
   double ms_commit;                /* commit + expansion kernels                        */
   double ms_bin;                   /* affected-set binning (compaction) kernels         */
   double ms_mark;                  /* initial marking kernels                           */
+  /* Algorithmic bytes of all pull launches (every gather counted): frontier
+   * pull 30 B per processed vertex + 12 B per pulled edge; Static/ND 36 B per
+   * vertex + 12 B per edge; dense DF/DF-P pull 31 B per vertex + 5 B per edge
+   * (index + expand flag) + 8 B per pulled edge. */
+  double pull_bytes;
+  int32_t dense_iterations;        /* iterations run in dense (all-vertex) mode         */
+  int32_t reserved2;
 } dfpr_stats;
 
 typedef struct dfpr_graph dfpr_graph;
 
 /* Paper defaults: alpha 0.85, tol 1e-10, tau_f = tau_p = 1e-6, 500 iterations
- * (Section 5.1.2; Sections 4.2-4.3). */
+ * (Section 5.1.2; Sections 4.2-4.3); dense_switch 0.4. */
 void dfpr_params_default(dfpr_params* p);
 
 /* Create a graph on the current HIP device from a COO edge list of m pairs.

@@ -21,7 +21,8 @@ EXPORTS = ("dfpr_params_default", "dfpr_graph_create", "dfpr_graph_destroy", "df
 
 class Params(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_double), ("tol", ctypes.c_double), ("frontier_tol", ctypes.c_double),
-                ("prune_tol", ctypes.c_double), ("max_iters", ctypes.c_int32), ("flags", ctypes.c_int32)]
+                ("prune_tol", ctypes.c_double), ("dense_switch", ctypes.c_double), ("max_iters", ctypes.c_int32),
+                ("flags", ctypes.c_int32)]
 
 
 class BatchInfo(ctypes.Structure):
@@ -47,7 +48,8 @@ class Stats(ctypes.Structure):
                 ("edges_pulled", ctypes.c_int64), ("bin_vertices", ctypes.c_int64 * BINS),
                 ("bin_edges", ctypes.c_int64 * BINS), ("ms_total", ctypes.c_double), ("ms_pull", ctypes.c_double),
                 ("pull_launches", ctypes.c_int32), ("reserved", ctypes.c_int32), ("ms_commit", ctypes.c_double),
-                ("ms_bin", ctypes.c_double), ("ms_mark", ctypes.c_double)]
+                ("ms_bin", ctypes.c_double), ("ms_mark", ctypes.c_double), ("pull_bytes", ctypes.c_double),
+                ("dense_iterations", ctypes.c_int32), ("reserved2", ctypes.c_int32)]
 
     def as_dict(self):
         out = {}
@@ -55,6 +57,7 @@ class Stats(ctypes.Structure):
             v = getattr(self, k)
             out[k] = list(v) if hasattr(v, "__len__") else v
         out.pop("reserved", None)
+        out.pop("reserved2", None)
         return out
 
 

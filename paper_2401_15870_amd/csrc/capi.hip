@@ -55,8 +55,8 @@ int check_params(const dfpr_params& p) {
     set_error("alpha must lie in (0,1), got %g", p.alpha);
     return DFPR_EINVAL;
   }
-  if (!(p.tol > 0.0) || std::isnan(p.frontier_tol) || std::isnan(p.prune_tol)) {
-    set_error("tol must be > 0 and tolerances must not be NaN");
+  if (!(p.tol > 0.0) || std::isnan(p.frontier_tol) || std::isnan(p.prune_tol) || !(p.dense_switch >= 0.0)) {
+    set_error("tol must be > 0, dense_switch >= 0 and tolerances must not be NaN");
     return DFPR_EINVAL;
   }
   if (p.max_iters < 1) {
@@ -76,6 +76,7 @@ void dfpr_params_default(dfpr_params* p) {
   p->tol = 1e-10;
   p->frontier_tol = 1e-6;
   p->prune_tol = 1e-6;
+  p->dense_switch = 0.4;
   p->max_iters = 500;
   p->flags = 0;
 }

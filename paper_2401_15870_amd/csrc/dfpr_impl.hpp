@@ -121,7 +121,14 @@ struct Csr {
 constexpr int kSlots = 64;
 constexpr int kSlotStride = 16;  // 16 x 8 bytes = 128 bytes between slots
 constexpr int kBins = DFPR_BINS;
-enum AccRow : int { kAccEdges0 = 0, kAccEver = kBins, kAccRows = kBins + 1 };
+enum AccRow : int {
+  kAccEdges0 = 0,          // per-bin in-degree sums of a binning pass (kBins rows)
+  kAccEver = kBins,        // vertices processed at least once
+  kAccCnt = kBins + 1,     // dense pull: affected vertices
+  kAccAffEdges = kBins + 2,// dense pull: summed in-degree of the affected vertices
+  kAccXEdges = kBins + 3,  // dense pull: summed out-degree of the expanding vertices
+  kAccRows = kBins + 4
+};
 
 // Per-update control block in device memory.  The compact head is read back
 // once per iteration; the slot arrays are the spread accumulators.
@@ -132,6 +139,9 @@ struct IterCtl {
   int64_t n_apply[6];        // apply: eff ins, eff del, self dels, eff count, error flag, m_new
   int64_t big_count;         // entries in the long out-row list
   int64_t ever_count;        // vertices processed at least once in this update
+  int64_t dense_cnt;         // dense pull: affected vertices of the last iteration
+  int64_t dense_edges;       // dense pull: their summed in-degree
+  int64_t dense_xedges;      // dense pull: summed out-degree of its expanding vertices
   int64_t pad[2];
   unsigned long long dR_slots[kSlots * kSlotStride];
   unsigned long long acc_slots[kAccRows][kSlots * kSlotStride];
@@ -166,6 +176,7 @@ struct dfpr_graph {
                                  // pending targets of effective deletions
   uint8_t* flag_next = nullptr;  // affected in the next iteration
   uint8_t* xflag = nullptr;      // expands in this iteration
+  uint8_t* xflag2 = nullptr;     // dense mode: expand flags of the previous iteration
   uint8_t* ever = nullptr;       // processed at least once in this update
   uint8_t* pend_src = nullptr;   // pending sources of effective changes
   uint8_t* touched_out = nullptr, *touched_in = nullptr;  // rows changed by the batch
@@ -175,6 +186,7 @@ struct dfpr_graph {
   int64_t all_bin_end[DFPR_BINS] = {0};
   int64_t all_bin_edges[DFPR_BINS] = {0};
   bool all_bins_valid = false;
+  bool all_chunks_valid = false;  // all_chunk_pre matches all_bins
   dfpr::IterCtl* ctl = nullptr;      // device
   dfpr::IterCtl* ctl_host = nullptr; // pinned host mirror
   int64_t* scan_tmp = nullptr;       // block sums for scans over n
@@ -192,6 +204,7 @@ struct dfpr_graph {
   bool pending_any = false;  // an apply happened since the last DF/DF-P update
   int32_t bounds[5] = {4, 16, 64, 512, 4096};  // in-degree bin limits (dfpr_set_tuning)
   int32_t* arrive = nullptr;  // n: per-vertex chunk arrival counters of bin 5
+  int32_t* partial_x = nullptr;  // per-chunk "an in-neighbour expanded" flags (dense mode)
   bool timing = false;        // record HIP-event timings of every call
   dfpr::EventPool pool;
 };

@@ -428,6 +428,7 @@ static int alloc_rank_scratch(dfpr_graph* g) {
   DFPR_TRY(dalloc(&g->flag_cur, n));
   DFPR_TRY(dalloc(&g->flag_next, n));
   DFPR_TRY(dalloc(&g->xflag, n));
+  DFPR_TRY(dalloc(&g->xflag2, n));
   DFPR_TRY(dalloc(&g->ever, n));
   DFPR_TRY(dalloc(&g->pend_src, n));
   DFPR_TRY(dalloc(&g->touched_out, n));
@@ -448,12 +449,14 @@ static int alloc_rank_scratch(dfpr_graph* g) {
   DFPR_TRY(dalloc(&g->big_pre, n + 1));
   g->partial_n = g->cap / kPullChunk + (int64_t)n + 1;
   DFPR_TRY(dalloc(&g->partial, (size_t)g->partial_n));
+  DFPR_TRY(dalloc(&g->partial_x, (size_t)g->partial_n));
   g->scan_tmp_n = scan_tmp_elems((int64_t)n + 1);
   DFPR_TRY(dalloc(&g->scan_tmp, g->scan_tmp_n));
   DFPR_HIP(hipHostMalloc((void**)&g->ctl_host, sizeof(IterCtl), hipHostMallocDefault));
   DFPR_HIP(hipMemset(g->flag_cur, 0, n));
   DFPR_HIP(hipMemset(g->flag_next, 0, n));
   DFPR_HIP(hipMemset(g->xflag, 0, n));
+  DFPR_HIP(hipMemset(g->xflag2, 0, n));
   DFPR_HIP(hipMemset(g->ever, 0, n));
   DFPR_HIP(hipMemset(g->pend_src, 0, n));
   DFPR_HIP(hipMemset(g->touched_out, 0, n));
@@ -487,6 +490,7 @@ int graph_destroy(dfpr_graph* g) {
   dfree(g->flag_cur);
   dfree(g->flag_next);
   dfree(g->xflag);
+  dfree(g->xflag2);
   dfree(g->ever);
   dfree(g->pend_src);
   dfree(g->touched_out);
@@ -504,6 +508,7 @@ int graph_destroy(dfpr_graph* g) {
   dfree(g->big_list);
   dfree(g->big_pre);
   dfree(g->partial);
+  dfree(g->partial_x);
   dfree(g->arrive);
   dfree(g->perm);
   dfree(g->inv);
@@ -704,7 +709,9 @@ static int grow_capacity(dfpr_graph* g, int64_t want, hipStream_t s) {
   const int64_t pn = cap / kPullChunk + (int64_t)g->n + 1;
   if (pn > g->partial_n) {
     dfree(g->partial);
+    dfree(g->partial_x);
     DFPR_TRY(dalloc(&g->partial, (size_t)pn));
+    DFPR_TRY(dalloc(&g->partial_x, (size_t)pn));
     g->partial_n = pn;
   }
   return DFPR_OK;

@@ -30,13 +30,22 @@ struct PullArgs {
   const int32_t* __restrict__ in_idx;
   const int32_t* __restrict__ out_off;
   const double* __restrict__ contrib;
-  double* R;       // ranks of this iteration (DF/DF-P: written in place)
-  double* Rw;      // Static/ND: ranks of the next iteration
-  double* cw;      // Static/ND: contributions of the next iteration
-  uint8_t* next;   // DF/DF-P: affected in the next iteration
-  uint8_t* xflag;  // DF/DF-P: expands
+  double* R;       // ranks of this iteration (frontier DF/DF-P: written in place)
+  double* Rw;      // Static/ND and dense DF/DF-P: ranks of the next iteration
+  double* cw;      // Static/ND and dense DF/DF-P: contributions of the next iteration
+  uint8_t* next;   // frontier DF/DF-P: affected in the next iteration
+  uint8_t* xflag;  // frontier DF/DF-P: expands
+  // dense DF/DF-P: v is affected iff stay_in[v] or an in-neighbour u has x_in[u]
+  const uint8_t* stay_in;
+  const uint8_t* x_in;
+  uint8_t* stay_out;
+  uint8_t* x_out;
+  uint8_t* ever;
+  int use_x;
   unsigned long long* dR_slots;
+  unsigned long long* acc;   // spread accumulator rows (dense counts)
   double* partial;           // bin 5: per-chunk partial sums
+  int32_t* partial_x;        // bin 5: per-chunk "an in-neighbour expanded" (dense)
   int32_t* arrive;           // bin 5: chunks finished per vertex
   const int64_t* chunk_pre;  // bin 5: first chunk of each vertex (exclusive scan)
   double alpha, C0, tf, tp;
@@ -52,127 +61,254 @@ struct Bounds {
   int32_t b[5];
 };
 
-// Equation 1 (DF, Static, ND) or Equation 2 (DF-P) for vertex v from its
-// in-neighbour sum c; returns |r - R[v]|.  Same operation order as the
-// algorithm states it; the library is built without FMA contraction.
-template <int MODE>
-__device__ __forceinline__ double vertex_finish(const PullArgs& a, int32_t v, double c) {
-  const double d = (double)(a.out_off[v + 1] - a.out_off[v]);
-  const double Rv = a.R[v];
+// What a vertex needs besides its in-neighbour sum.  The self-loop term
+// R[v]/|out(v)| is taken from R[v] instead of gathering contrib[v]: the same
+// correctly rounded quotient.
+struct VCtx {
+  int32_t v, s, e;
+  double Rv, d, selfc;
+};
+__device__ __forceinline__ VCtx load_vertex(const PullArgs& a, int32_t v) {
+  VCtx c;
+  c.v = v;
+  c.s = a.in_off[v];
+  c.e = a.in_off[v + 1];
+  c.d = (double)(a.out_off[v + 1] - a.out_off[v]);
+  c.Rv = a.R[v];
+  c.selfc = c.Rv / c.d;
+  return c;
+}
+__device__ __forceinline__ int32_t ld_idx(const PullArgs& a, int32_t p) {
+  return __builtin_nontemporal_load(&a.in_idx[p]);  // streamed once: keep L2 for the gathers
+}
+__device__ __forceinline__ double gx(const PullArgs& a, int32_t u, const VCtx& c) {
+  return u == c.v ? c.selfc : a.contrib[u];
+}
+
+// Per-thread accumulators of one pull launch.
+struct Acc {
+  double mx = 0.0;                       // L-inf change
+  int64_t cnt = 0, aedges = 0, xedges = 0;  // dense: affected, their in-edges, expander out-edges
+};
+
+// Equation 1 (DF, Static, ND) or Equation 2 (DF-P) for the vertex from its
+// in-neighbour sum c.  Same operation order as the algorithm states it; the
+// library is built without FMA contraction.  DENSE: aff tells whether the
+// vertex is affected; unaffected vertices carry their rank over.
+template <int MODE, bool DENSE>
+__device__ __forceinline__ void vertex_finish(const PullArgs& a, const VCtx& x, double c, bool aff, Acc& acc) {
+  if (DENSE && !aff) {
+    a.Rw[x.v] = x.Rv;
+    a.cw[x.v] = x.selfc;
+    a.stay_out[x.v] = 0;
+    a.x_out[x.v] = 0;
+    return;
+  }
+  const double d = x.d, Rv = x.Rv;
   double r;
   if (MODE == kDFP)
     r = (1.0 / (1.0 - a.alpha / d)) * (a.C0 + a.alpha * (c - Rv / d));
   else
     r = a.C0 + a.alpha * c;
   const double dr = fabs(r - Rv);
+  acc.mx = fmax(acc.mx, dr);
   if (MODE == kSync) {
-    a.Rw[v] = r;
-    a.cw[v] = r / d;
-  } else {
-    a.R[v] = r;
-    const double rel = dr / fmax(r, Rv);
-    if (!(MODE == kDFP && rel <= a.tp)) a.next[v] = 1;  // prune (DF-P) or keep
-    if (rel > a.tf) a.xflag[v] = 1;                      // expand
+    a.Rw[x.v] = r;
+    a.cw[x.v] = r / d;
+    return;
   }
-  return dr;
+  const double rel = dr / fmax(r, Rv);
+  const bool stay = !(MODE == kDFP && rel <= a.tp);  // prune (DF-P) or keep
+  const bool expand = rel > a.tf;
+  if (DENSE) {
+    a.Rw[x.v] = r;
+    a.cw[x.v] = r / d;
+    a.stay_out[x.v] = stay;
+    a.x_out[x.v] = expand;
+    a.ever[x.v] = 1;
+    acc.cnt++;
+    acc.aedges += x.e - x.s;
+    if (expand) acc.xedges += (int64_t)d;
+  } else {
+    a.R[x.v] = r;
+    if (stay) a.next[x.v] = 1;
+    if (expand) a.xflag[x.v] = 1;
+  }
 }
 
-// Workgroup max of non-negative doubles into one of kSlots spread slots (the
-// bit pattern of a non-negative IEEE double orders like the value).
-__device__ __forceinline__ void block_max_to_slots(double x, unsigned long long* slots) {
-  __shared__ double sh[1024 / kWave];
-  x = wave_max(x);
-  if (lane_id() == 0) sh[threadIdx.x / kWave] = x;
+// Workgroup reduction of the accumulators into spread slots (the bit pattern
+// of a non-negative IEEE double orders like the value).
+template <bool DENSE>
+__device__ __forceinline__ void block_acc_to_slots(Acc acc, const PullArgs& a) {
+  __shared__ double shm[1024 / kWave];
+  __shared__ int64_t shc[3][1024 / kWave];
+  const int w = threadIdx.x / kWave;
+  const double m = wave_max(acc.mx);
+  int64_t c0 = 0, c1 = 0, c2 = 0;
+  if (DENSE) {
+    c0 = wave_sum_i64(acc.cnt);
+    c1 = wave_sum_i64(acc.aedges);
+    c2 = wave_sum_i64(acc.xedges);
+  }
+  if (lane_id() == 0) {
+    shm[w] = m;
+    shc[0][w] = c0;
+    shc[1][w] = c1;
+    shc[2][w] = c2;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
-    double m = 0.0;
-    for (int w = 0; w < (int)(blockDim.x / kWave); w++) m = fmax(m, sh[w]);
-    if (m > 0.0) atomicMax(&slots[(blockIdx.x % kSlots) * kSlotStride], (unsigned long long)__double_as_longlong(m));
+    double mm = 0.0;
+    int64_t t0 = 0, t1 = 0, t2 = 0;
+    for (int i = 0; i < (int)(blockDim.x / kWave); i++) {
+      mm = fmax(mm, shm[i]);
+      t0 += shc[0][i];
+      t1 += shc[1][i];
+      t2 += shc[2][i];
+    }
+    const int slot = (blockIdx.x % kSlots) * kSlotStride;
+    if (mm > 0.0) atomicMax(&a.dR_slots[slot], (unsigned long long)__double_as_longlong(mm));
+    if (DENSE) {
+      constexpr int kRow = kSlots * kSlotStride;
+      if (t0) atomicAdd(&a.acc[kAccCnt * kRow + slot], (unsigned long long)t0);
+      if (t1) atomicAdd(&a.acc[kAccAffEdges * kRow + slot], (unsigned long long)t1);
+      if (t2) atomicAdd(&a.acc[kAccXEdges * kRow + slot], (unsigned long long)t2);
+    }
   }
 }
 
 // ---- bins 0-3: groups of G lanes per vertex.  G = 1 folds in ascending
 // source order (the order of the algorithm's sum); G > 1 lanes take strided
 // edges and combine with a butterfly.  Up to four gathers in flight per lane.
-template <int MODE, int G>
+// DENSE: a vertex not kept by its own flag first checks its in-neighbours'
+// expand flags (same strided sweep), and gathers contributions only if it is
+// affected.
+template <int MODE, int G, bool DENSE>
 __device__ __forceinline__ void pull_groups(const PullArgs& a, const int32_t* __restrict__ wl, int64_t lo, int64_t hi,
-                                            int lb, int nb, double& mx) {
+                                            int lb, int nb, Acc& acc) {
   constexpr int kGroups = 256 / G;
   const int gl = threadIdx.x % G;
   for (int64_t k = lo + (int64_t)lb * kGroups + threadIdx.x / G; k < hi; k += (int64_t)nb * kGroups) {
-    const int32_t v = wl[k];
-    const int32_t s = a.in_off[v], e = a.in_off[v + 1];
-    double c = 0.0;
-    if (G == 1) {
-      int32_t p = s;
-      for (; p + 4 <= e; p += 4) {
-        const int32_t u0 = a.in_idx[p], u1 = a.in_idx[p + 1], u2 = a.in_idx[p + 2], u3 = a.in_idx[p + 3];
-        const double x0 = a.contrib[u0], x1 = a.contrib[u1], x2 = a.contrib[u2], x3 = a.contrib[u3];
-        c = c + x0;
-        c = c + x1;
-        c = c + x2;
-        c = c + x3;
-      }
-      const int32_t r = e - p;  // 0..3 left
-      const int32_t u0 = r > 0 ? a.in_idx[p] : 0;
-      const int32_t u1 = r > 1 ? a.in_idx[p + 1] : 0;
-      const int32_t u2 = r > 2 ? a.in_idx[p + 2] : 0;
-      const double x0 = r > 0 ? a.contrib[u0] : 0.0;
-      const double x1 = r > 1 ? a.contrib[u1] : 0.0;
-      const double x2 = r > 2 ? a.contrib[u2] : 0.0;
-      if (r > 0) c = c + x0;
-      if (r > 1) c = c + x1;
-      if (r > 2) c = c + x2;
-    } else {
-      int32_t p = s + gl;
-      for (; p + 3 * G < e; p += 4 * G) {
-        const int32_t u0 = a.in_idx[p], u1 = a.in_idx[p + G], u2 = a.in_idx[p + 2 * G], u3 = a.in_idx[p + 3 * G];
-        const double x0 = a.contrib[u0], x1 = a.contrib[u1], x2 = a.contrib[u2], x3 = a.contrib[u3];
-        c += x0;
-        c += x1;
-        c += x2;
-        c += x3;
-      }
-      for (; p < e; p += G) c += a.contrib[a.in_idx[p]];
+    const VCtx x = load_vertex(a, wl[k]);
+    bool aff = true;
+    if (DENSE) {
+      aff = a.stay_in[x.v] != 0;
+      if (!aff && a.use_x) {
+        int any = 0;
+        int32_t p = x.s + gl;
+        for (; p + 3 * G < x.e; p += 4 * G) {
+          const int32_t u0 = ld_idx(a, p), u1 = ld_idx(a, p + G), u2 = ld_idx(a, p + 2 * G), u3 = ld_idx(a, p + 3 * G);
+          any |= a.x_in[u0] | a.x_in[u1] | a.x_in[u2] | a.x_in[u3];
+        }
+        for (; p < x.e; p += G) any |= a.x_in[ld_idx(a, p)];
 #pragma unroll
-      for (int o = G / 2; o >= 1; o >>= 1) c += __shfl_xor(c, o, kWave);
+        for (int o = G / 2; o >= 1; o >>= 1) any |= __shfl_xor(any, o, kWave);
+        aff = any != 0;
+      }
     }
-    if (gl == 0) mx = fmax(mx, vertex_finish<MODE>(a, v, c));
+    double c = 0.0;
+    if (aff) {
+      if (G == 1) {
+        int32_t p = x.s;
+        for (; p + 4 <= x.e; p += 4) {
+          const int32_t u0 = ld_idx(a, p), u1 = ld_idx(a, p + 1), u2 = ld_idx(a, p + 2), u3 = ld_idx(a, p + 3);
+          const double x0 = gx(a, u0, x), x1 = gx(a, u1, x), x2 = gx(a, u2, x), x3 = gx(a, u3, x);
+          c = c + x0;
+          c = c + x1;
+          c = c + x2;
+          c = c + x3;
+        }
+        const int32_t r = x.e - p;  // 0..3 left
+        const int32_t u0 = r > 0 ? ld_idx(a, p) : x.v;
+        const int32_t u1 = r > 1 ? ld_idx(a, p + 1) : x.v;
+        const int32_t u2 = r > 2 ? ld_idx(a, p + 2) : x.v;
+        const double x0 = gx(a, u0, x), x1 = gx(a, u1, x), x2 = gx(a, u2, x);
+        if (r > 0) c = c + x0;
+        if (r > 1) c = c + x1;
+        if (r > 2) c = c + x2;
+      } else {
+        int32_t p = x.s + gl;
+        for (; p + 3 * G < x.e; p += 4 * G) {
+          const int32_t u0 = ld_idx(a, p), u1 = ld_idx(a, p + G), u2 = ld_idx(a, p + 2 * G), u3 = ld_idx(a, p + 3 * G);
+          const double x0 = gx(a, u0, x), x1 = gx(a, u1, x), x2 = gx(a, u2, x), x3 = gx(a, u3, x);
+          c += x0;
+          c += x1;
+          c += x2;
+          c += x3;
+        }
+        for (; p < x.e; p += G) c += gx(a, ld_idx(a, p), x);
+#pragma unroll
+        for (int o = G / 2; o >= 1; o >>= 1) c += __shfl_xor(c, o, kWave);
+      }
+    }
+    if (gl == 0) vertex_finish<MODE, DENSE>(a, x, c, aff, acc);
   }
 }
 
-// Strided sum of contrib over in_idx[s, e) by the 256 threads of a workgroup,
-// combined in a fixed order; valid in thread 0.
-__device__ __forceinline__ double block_row_sum(const PullArgs& a, int32_t s, int32_t e, double* sh) {
+// Strided sum (and expand-flag OR when want_x) over in_idx[s, e) by the 256
+// threads of a workgroup, combined in a fixed order; valid in thread 0.
+__device__ __forceinline__ double block_row_sum(const PullArgs& a, const VCtx& x, int32_t s, int32_t e, bool want_sum,
+                                                bool want_x, int* any_out, double* sh, int* shx) {
   double part = 0.0;
+  int any = 0;
   int32_t p = s + (int32_t)threadIdx.x;
   for (; p + 3 * 256 < e; p += 4 * 256) {
-    const int32_t u0 = a.in_idx[p], u1 = a.in_idx[p + 256], u2 = a.in_idx[p + 512], u3 = a.in_idx[p + 768];
-    const double x0 = a.contrib[u0], x1 = a.contrib[u1], x2 = a.contrib[u2], x3 = a.contrib[u3];
-    part += x0;
-    part += x1;
-    part += x2;
-    part += x3;
+    const int32_t u0 = ld_idx(a, p), u1 = ld_idx(a, p + 256), u2 = ld_idx(a, p + 512), u3 = ld_idx(a, p + 768);
+    if (want_x) any |= a.x_in[u0] | a.x_in[u1] | a.x_in[u2] | a.x_in[u3];
+    if (want_sum) {
+      const double x0 = gx(a, u0, x), x1 = gx(a, u1, x), x2 = gx(a, u2, x), x3 = gx(a, u3, x);
+      part += x0;
+      part += x1;
+      part += x2;
+      part += x3;
+    }
   }
-  for (; p < e; p += 256) part += a.contrib[a.in_idx[p]];
+  for (; p < e; p += 256) {
+    const int32_t u = ld_idx(a, p);
+    if (want_x) any |= a.x_in[u];
+    if (want_sum) part += gx(a, u, x);
+  }
   part = wave_sum(part);
-  if (lane_id() == 0) sh[threadIdx.x / kWave] = part;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) any |= __shfl_xor(any, o, kWave);
+  if (lane_id() == 0) {
+    sh[threadIdx.x / kWave] = part;
+    shx[threadIdx.x / kWave] = any;
+  }
   __syncthreads();
   double c = 0.0;
-  if (threadIdx.x == 0) c = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+  if (threadIdx.x == 0) {
+    c = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+    *any_out = shx[0] | shx[1] | shx[2] | shx[3];
+  }
   __syncthreads();
   return c;
 }
 
 // ---- bin 4: one workgroup per vertex
-template <int MODE>
+template <int MODE, bool DENSE>
 __device__ __forceinline__ void pull_block(const PullArgs& a, const int32_t* __restrict__ wl, int64_t lo, int64_t hi,
-                                           int lb, int nb, double& mx) {
+                                           int lb, int nb, Acc& acc) {
   __shared__ double sh[256 / kWave];
+  __shared__ int shx[256 / kWave];
+  __shared__ int aff_sh;
   for (int64_t k = lo + lb; k < hi; k += nb) {
-    const int32_t v = wl[k];
-    const double c = block_row_sum(a, a.in_off[v], a.in_off[v + 1], sh);
-    if (threadIdx.x == 0) mx = fmax(mx, vertex_finish<MODE>(a, v, c));
+    const VCtx x = load_vertex(a, wl[k]);
+    bool aff = true;
+    if (DENSE) {
+      aff = a.stay_in[x.v] != 0;
+      if (!aff && a.use_x) {
+        int any = 0;
+        block_row_sum(a, x, x.s, x.e, false, true, &any, sh, shx);
+        if (threadIdx.x == 0) aff_sh = any;
+        __syncthreads();
+        aff = aff_sh != 0;
+        __syncthreads();
+      }
+    }
+    int dummy;
+    const double c = aff ? block_row_sum(a, x, x.s, x.e, true, false, &dummy, sh, shx) : 0.0;
+    if (threadIdx.x == 0) vertex_finish<MODE, DENSE>(a, x, c, aff, acc);
   }
 }
 
@@ -181,7 +317,7 @@ __device__ __forceinline__ void pull_block(const PullArgs& a, const int32_t* __r
 // workgroup lb takes the contiguous chunk range [lb*T/nb, (lb+1)*T/nb).  Each
 // chunk's sum goes to `partial`; the workgroup that finishes a vertex's last
 // chunk (arrival counter) adds the partials in chunk order and computes the
-// rank.
+// rank.  DENSE: each chunk also reports whether an in-neighbour expanded.
 __device__ __forceinline__ int64_t upper_bound_i64(const int64_t* a, int64_t lo, int64_t hi, int64_t x) {
   while (lo < hi) {
     int64_t mid = lo + ((hi - lo) >> 1);
@@ -190,10 +326,11 @@ __device__ __forceinline__ int64_t upper_bound_i64(const int64_t* a, int64_t lo,
   return lo;
 }
 
-template <int MODE>
+template <int MODE, bool DENSE>
 __device__ __forceinline__ void pull_chunks(const PullArgs& a, const int32_t* __restrict__ wl, int64_t lo, int64_t hi,
-                                            int lb, int nb, double& mx) {
+                                            int lb, int nb, Acc& acc) {
   __shared__ double sh[256 / kWave];
+  __shared__ int shx[256 / kWave];
   __shared__ int last;
   const int64_t nv = hi - lo;
   const int64_t* pre = a.chunk_pre;
@@ -202,22 +339,22 @@ __device__ __forceinline__ void pull_chunks(const PullArgs& a, const int32_t* __
   if (q0 >= q1) return;
   int64_t j = upper_bound_i64(pre, 0, nv + 1, q0) - 1;
   int64_t cj = pre[j], cj1 = pre[j + 1];
-  int32_t v = wl[lo + j];
-  int32_t s = a.in_off[v], e = a.in_off[v + 1];
+  VCtx x = load_vertex(a, wl[lo + j]);
   for (int64_t q = q0; q < q1; q++) {
     while (q >= cj1) {
       j++;
       cj = cj1;
       cj1 = pre[j + 1];
-      v = wl[lo + j];
-      s = a.in_off[v];
-      e = a.in_off[v + 1];
+      x = load_vertex(a, wl[lo + j]);
     }
-    const int32_t cs = s + (int32_t)((q - cj) * kPullChunk);
-    const int32_t ce = min(cs + kPullChunk, e);
-    const double part = block_row_sum(a, cs, ce, sh);
+    const bool want_x = DENSE && a.use_x && !a.stay_in[x.v];
+    const int32_t cs = x.s + (int32_t)((q - cj) * kPullChunk);
+    const int32_t ce = min(cs + kPullChunk, x.e);
+    int any = 0;
+    const double part = block_row_sum(a, x, cs, ce, true, want_x, &any, sh, shx);
     if (threadIdx.x == 0) {
       a.partial[q] = part;
+      if (DENSE) a.partial_x[q] = any;
       __threadfence();
       last = atomicAdd(&a.arrive[j], 1) == (int)(cj1 - cj - 1);
     }
@@ -225,30 +362,35 @@ __device__ __forceinline__ void pull_chunks(const PullArgs& a, const int32_t* __
     if (threadIdx.x == 0 && last) {
       __threadfence();
       double c = 0.0;
-      for (int64_t t = cj; t < cj1; t++) c += __hip_atomic_load(&a.partial[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      int anyx = 0;
+      for (int64_t t = cj; t < cj1; t++) {
+        c += __hip_atomic_load(&a.partial[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (DENSE) anyx |= __hip_atomic_load(&a.partial_x[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
       a.arrive[j] = 0;
-      mx = fmax(mx, vertex_finish<MODE>(a, v, c));
+      const bool aff = !DENSE || a.stay_in[x.v] || (a.use_x && anyx);
+      vertex_finish<MODE, DENSE>(a, x, aff ? c : 0.0, aff, acc);
     }
     __syncthreads();
   }
 }
 
-template <int MODE>
+template <int MODE, bool DENSE>
 __global__ void __launch_bounds__(256) k_pull(PullArgs a, const int32_t* __restrict__ wl, PullLayout L) {
   const int b = blockIdx.x;
   int k = 0;
   while (k < kBins - 1 && b >= L.blk[k + 1]) k++;
   const int lb = b - L.blk[k], nb = L.blk[k + 1] - L.blk[k];
-  double mx = 0.0;
+  Acc acc;
   switch (k) {
-    case 0: pull_groups<MODE, 1>(a, wl, L.lo[0], L.hi[0], lb, nb, mx); break;
-    case 1: pull_groups<MODE, 4>(a, wl, L.lo[1], L.hi[1], lb, nb, mx); break;
-    case 2: pull_groups<MODE, 16>(a, wl, L.lo[2], L.hi[2], lb, nb, mx); break;
-    case 3: pull_groups<MODE, 64>(a, wl, L.lo[3], L.hi[3], lb, nb, mx); break;
-    case 4: pull_block<MODE>(a, wl, L.lo[4], L.hi[4], lb, nb, mx); break;
-    default: pull_chunks<MODE>(a, wl, L.lo[5], L.hi[5], lb, nb, mx); break;
+    case 0: pull_groups<MODE, 1, DENSE>(a, wl, L.lo[0], L.hi[0], lb, nb, acc); break;
+    case 1: pull_groups<MODE, 4, DENSE>(a, wl, L.lo[1], L.hi[1], lb, nb, acc); break;
+    case 2: pull_groups<MODE, 16, DENSE>(a, wl, L.lo[2], L.hi[2], lb, nb, acc); break;
+    case 3: pull_groups<MODE, 64, DENSE>(a, wl, L.lo[3], L.hi[3], lb, nb, acc); break;
+    case 4: pull_block<MODE, DENSE>(a, wl, L.lo[4], L.hi[4], lb, nb, acc); break;
+    default: pull_chunks<MODE, DENSE>(a, wl, L.lo[5], L.hi[5], lb, nb, acc); break;
   }
-  block_max_to_slots(mx, a.dR_slots);
+  block_acc_to_slots<DENSE>(acc, a);
 }
 
 // ---- marking of out-rows, balanced over the wave: every lane that wants its
@@ -538,6 +680,9 @@ __global__ void __launch_bounds__(kSlots) k_iter_finish(IterCtl* c) {
     c->dR = m;
     for (int b = 0; b < kBins; b++) c->bin_edges[b] = r[kAccEdges0 + b];
     c->ever_count = r[kAccEver];
+    c->dense_cnt = r[kAccCnt];
+    c->dense_edges = r[kAccAffEdges];
+    c->dense_xedges = r[kAccXEdges];
     c->big_count = 0;
   }
 }
@@ -676,7 +821,7 @@ struct StoreChunk {
 
 // chunk_ready: chunk_pre already holds the scan for this worklist (cached
 // all-vertex bins of Static/ND).
-template <int MODE>
+template <int MODE, bool DENSE = false>
 static int pull_all(dfpr_graph* g, PullArgs a, const int32_t* wl, const int64_t* be, const int64_t* bedges,
                     int64_t* chunk_pre, bool chunk_ready, hipStream_t s, dfpr_stats* st) {
   PullLayout L;
@@ -687,7 +832,7 @@ static int pull_all(dfpr_graph* g, PullArgs a, const int32_t* wl, const int64_t*
   if (n5 > 0 && !chunk_ready)
     DFPR_TRY(scan_generic(LoadChunks{wl, g->in.off, L.lo[kBins - 1]}, StoreChunk{chunk_pre}, n5, g->scan_tmp, s));
   a.chunk_pre = chunk_pre;
-  k_pull<MODE><<<(unsigned)L.blk[kBins], 256, 0, s>>>(a, wl, L);
+  k_pull<MODE, DENSE><<<(unsigned)L.blk[kBins], 256, 0, s>>>(a, wl, L);
   DFPR_HIP(hipGetLastError());
   DFPR_TRY(g->pool.stop(kTPull0, tok));
   st->pull_launches++;
@@ -707,7 +852,9 @@ static PullArgs make_args(dfpr_graph* g, const dfpr_params& p) {
   a.in_idx = g->in.idx;
   a.out_off = g->out.off;
   a.dR_slots = g->ctl->dR_slots;
+  a.acc = &g->ctl->acc_slots[0][0];
   a.partial = g->partial;
+  a.partial_x = g->partial_x;
   a.arrive = g->arrive;
   a.alpha = p.alpha;
   a.C0 = (1.0 - p.alpha) / (double)g->n;
@@ -726,6 +873,7 @@ static int run_sync(dfpr_graph* g, bool cold, const dfpr_params& p, const double
     std::copy(g->ctl_host->bin_end, g->ctl_host->bin_end + kBins, g->all_bin_end);
     std::copy(g->ctl_host->bin_edges, g->ctl_host->bin_edges + kBins, g->all_bin_edges);
     g->all_bins_valid = true;
+    g->all_chunks_valid = false;
   }
   const unsigned gi = grid_for(n, 256, 2048);
   double* R0 = g->perm ? g->rint : r_out;  // ranks in internal order
@@ -746,11 +894,14 @@ static int run_sync(dfpr_graph* g, bool cold, const dfpr_params& p, const double
     a.R = Ra;
     a.Rw = Rb;
     a.cw = cb;
-    DFPR_TRY(pull_all<kSync>(g, a, g->all_bins, g->all_bin_end, g->all_bin_edges, g->all_chunk_pre, it > 0, s, st));
+    DFPR_TRY(pull_all<kSync>(g, a, g->all_bins, g->all_bin_end, g->all_bin_edges, g->all_chunk_pre,
+                             g->all_chunks_valid, s, st));
+    g->all_chunks_valid = true;
     DFPR_TRY(finish_and_read(g, s));
     dR = bits_to_double(g->ctl_host->dR);
     st->vertex_updates += n;
     st->edges_pulled += g->m;
+    st->pull_bytes += 36.0 * n + 12.0 * (double)g->m;
     add_bins(st, g->all_bin_end, g->all_bin_edges);
     std::swap(Ra, Rb);
     std::swap(ca, cb);
@@ -778,17 +929,31 @@ static int run_sync(dfpr_graph* g, bool cold, const dfpr_params& p, const double
   return DFPR_OK;
 }
 
+// DF / DF-P.  Each iteration runs in one of two forms with the same result:
+//  frontier: pull over the binned worklist of affected vertices (ranks in
+//    place), commit their contributions and push-mark the out-rows of the
+//    expanding vertices into the next flags, then bin those flags;
+//  dense: pull over every vertex; a vertex is affected iff its own keep flag
+//    is set or an in-neighbour expanded (read from the in-neighbours' expand
+//    flags, so no marks are written); ranks and contributions ping-pong.
+// The affected sets, the per-vertex sums (same bins, same order) and so the
+// ranks are identical; dense is chosen while the frontier's in-edges exceed
+// dense_switch * |E|, where scanning everything beats scattered marking.
 template <int MODE>
 static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_prev, double* r_out, hipStream_t s,
                         dfpr_stats* st) {
   const int32_t n = g->n;
+  const int64_t m = g->m;
   const unsigned gi = grid_for(n, 256, 2048);
   k_reset_ctl<<<64, 256, 0, s>>>(g->ctl);
-  double* R = g->perm ? g->rint : r_out;  // ranks in internal order
+  double* Ra = g->perm ? g->rint : r_out;  // current ranks, internal order
+  double* Rb = g->rn;
+  double* ca = g->contrib;
+  double* cb = g->contrib2;
   if (g->perm)
-    k_gather_ranks<<<gi, 256, 0, s>>>(r_prev, g->inv, R, g->contrib, g->out.off, n);
+    k_gather_ranks<<<gi, 256, 0, s>>>(r_prev, g->inv, Ra, ca, g->out.off, n);
   else
-    k_init_prev<<<gi, 256, 0, s>>>(r_prev, r_out, g->contrib, g->out.off, n, r_prev != r_out);
+    k_init_prev<<<gi, 256, 0, s>>>(r_prev, r_out, ca, g->out.off, n, r_prev != r_out);
   // initial marking: out(u) of pending sources (+ deletion targets already in flag_cur)
   size_t tok;
   DFPR_TRY(g->pool.start(&tok));
@@ -800,21 +965,90 @@ static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_pre
   g->pending_any = false;
   DFPR_TRY(bin_vertices(g, g->flag_cur, g->worklist, g->ever, s));
   DFPR_TRY(finish_and_read(g, s));
-  uint8_t *cur = g->flag_cur, *next = g->flag_next;
+  uint8_t *cur = g->flag_cur, *next = g->flag_next, *xa = g->xflag, *xb = g->xflag2;
+  const double switch_edges = p.dense_switch * (double)m;
+  bool need_bins = false;  // dense -> frontier: the frontier must be marked and binned first
+  bool dense = false, use_x = false;
+  int64_t front_edges = 0, front_cnt = 0;
+  {
+    const int64_t* h = g->ctl_host->bin_edges;
+    for (int k = 0; k < kBins; k++) front_edges += h[k];
+    front_cnt = g->ctl_host->bin_end[kBins - 1];
+  }
   PullArgs a = make_args(g, p);
-  a.contrib = g->contrib;
-  a.R = R;
-  a.xflag = g->xflag;
   int it = 0;
   double dR = 0.0;
   bool conv = false;
   for (it = 0; it < p.max_iters; it++) {
+    if (!dense && front_edges > switch_edges && MODE != kSync) {
+      dense = true;  // the complete frontier is in `cur`; no expand flags to read
+      use_x = false;
+    }
+    if (dense) {
+      if (!g->all_bins_valid) {
+        DFPR_TRY(bin_vertices(g, nullptr, g->all_bins, nullptr, s));
+        DFPR_TRY(finish_and_read(g, s));
+        std::copy(g->ctl_host->bin_end, g->ctl_host->bin_end + kBins, g->all_bin_end);
+        std::copy(g->ctl_host->bin_edges, g->ctl_host->bin_edges + kBins, g->all_bin_edges);
+        g->all_bins_valid = true;
+        g->all_chunks_valid = false;
+      }
+      a.contrib = ca;
+      a.R = Ra;
+      a.Rw = Rb;
+      a.cw = cb;
+      a.stay_in = cur;
+      a.x_in = xa;
+      a.stay_out = next;
+      a.x_out = xb;
+      a.ever = g->ever;
+      a.use_x = use_x ? 1 : 0;
+      DFPR_TRY((pull_all<MODE, true>(g, a, g->all_bins, g->all_bin_end, g->all_bin_edges, g->all_chunk_pre,
+                                     g->all_chunks_valid, s, st)));
+      g->all_chunks_valid = true;
+      DFPR_TRY(finish_and_read(g, s));
+      const IterCtl* h = g->ctl_host;
+      dR = bits_to_double(h->dR);
+      st->vertex_updates += h->dense_cnt;
+      st->edges_pulled += h->dense_edges;
+      st->pull_bytes += 31.0 * n + 5.0 * (double)m + 8.0 * (double)h->dense_edges;
+      st->dense_iterations++;
+      std::swap(Ra, Rb);
+      std::swap(ca, cb);
+      std::swap(cur, next);  // cur = keep flags of the next iteration
+      std::swap(xa, xb);     // xa = expand flags of this iteration
+      use_x = true;
+      front_edges = h->dense_edges;  // next frontier about as large as this one
+      if (dR <= p.tol) {
+        conv = true;
+        it++;
+        break;
+      }
+      if (front_edges <= switch_edges / 2) {
+        // back to the frontier form: mark out(v) of this iteration's expanders
+        // into the keep flags (clears xa), then bin
+        k_mark_pending<<<gi, 256, 0, s>>>(xa, n, g->out.off, g->out.idx, cur, g->big_list, &g->ctl->big_count);
+        DFPR_HIP(hipGetLastError());
+        DFPR_TRY(mark_big(g, cur, s));
+        k_fill_u8<<<gi, 256, 0, s>>>(next, n, 0);
+        DFPR_TRY(bin_vertices(g, cur, g->worklist, g->ever, s));
+        DFPR_TRY(finish_and_read(g, s));
+        dense = false;
+        need_bins = false;
+        front_edges = 0;
+        for (int k = 0; k < kBins; k++) front_edges += g->ctl_host->bin_edges[k];
+        front_cnt = g->ctl_host->bin_end[kBins - 1];
+      }
+      continue;
+    }
+    (void)need_bins;
     int64_t be[kBins], bedges[kBins];
     std::copy(g->ctl_host->bin_end, g->ctl_host->bin_end + kBins, be);
     std::copy(g->ctl_host->bin_edges, g->ctl_host->bin_edges + kBins, bedges);
-    const int64_t cnt = be[kBins - 1];
+    const int64_t cnt = front_cnt;
     st->vertex_updates += cnt;
-    for (int k = 0; k < kBins; k++) st->edges_pulled += bedges[k];
+    st->edges_pulled += front_edges;
+    st->pull_bytes += 30.0 * cnt + 12.0 * (double)front_edges;
     add_bins(st, be, bedges);
     if (cnt == 0) {  // nothing affected: the L-inf change of this iteration is 0
       dR = 0.0;
@@ -822,12 +1056,14 @@ static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_pre
       it++;
       break;
     }
+    a.contrib = ca;
+    a.R = Ra;
     a.next = next;
+    a.xflag = xa;
     DFPR_TRY(pull_all<MODE>(g, a, g->worklist, be, bedges, g->chunk_pre, false, s, st));
     DFPR_TRY(g->pool.start(&tok));
-    k_commit_expand<<<grid_for(cnt, 256, 2048), 256, 0, s>>>(g->worklist, cnt, R, g->contrib, g->out.off,
-                                                             g->out.idx, cur, next, g->xflag, g->big_list,
-                                                             &g->ctl->big_count);
+    k_commit_expand<<<grid_for(cnt, 256, 2048), 256, 0, s>>>(g->worklist, cnt, Ra, ca, g->out.off, g->out.idx, cur,
+                                                             next, xa, g->big_list, &g->ctl->big_count);
     DFPR_HIP(hipGetLastError());
     DFPR_TRY(mark_big(g, next, s));
     DFPR_TRY(g->pool.stop(kTCommit, tok));
@@ -835,20 +1071,33 @@ static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_pre
     DFPR_TRY(bin_vertices(g, cur, g->worklist, g->ever, s));
     DFPR_TRY(finish_and_read(g, s));
     dR = bits_to_double(g->ctl_host->dR);
+    front_edges = 0;
+    for (int k = 0; k < kBins; k++) front_edges += g->ctl_host->bin_edges[k];
+    front_cnt = g->ctl_host->bin_end[kBins - 1];
     if (dR <= p.tol) {
       conv = true;
       it++;
       break;
     }
   }
-  if (g->perm) k_scatter_ranks<<<gi, 256, 0, s>>>(R, g->inv, r_out, n);
-  // leave both flag arrays clear for the next batch
+  if (g->perm)
+    k_scatter_ranks<<<gi, 256, 0, s>>>(Ra, g->inv, r_out, n);
+  else if (Ra != r_out)
+    DFPR_HIP(hipMemcpyAsync(r_out, Ra, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  // leave every flag array clear for the next batch
   k_fill_u8<<<gi, 256, 0, s>>>(cur, n, 0);
+  if (st->dense_iterations) {
+    k_fill_u8<<<gi, 256, 0, s>>>(next, n, 0);
+    k_fill_u8<<<gi, 256, 0, s>>>(xa, n, 0);
+    k_fill_u8<<<gi, 256, 0, s>>>(xb, n, 0);
+  }
   k_count_clear_ever<<<gi, 256, 0, s>>>(g->ever, n, &g->ctl->acc_slots[0][0]);
   DFPR_HIP(hipGetLastError());
   DFPR_TRY(finish_and_read(g, s));
-  g->flag_cur = cur;  // both arrays are zero again
+  g->flag_cur = cur;
   g->flag_next = next;
+  g->xflag = xa;
+  g->xflag2 = xb;
   st->iterations = it;
   st->converged = conv ? 1 : 0;
   st->last_delta = dR;

@@ -115,6 +115,30 @@ def test_ranks_parity(mode, scale, frac, keep_ids):
     assert (r >= (1 - 0.85) / p.n).all()
 
 
+@pytest.mark.parametrize("frac", [1e-3, 1e-1])
+@pytest.mark.parametrize("mode", ["df", "dfp"])
+def test_dense_and_frontier_forms_agree(mode, frac):
+    """The dense form (every vertex reads its in-neighbours' expand flags) and the
+    frontier form (marks pushed to out-neighbours) give bit-identical ranks and
+    frontier statistics, and both match the oracle; the default switches between
+    them as the frontier grows and shrinks."""
+    torch = torch_cuda()
+    p, r0 = _setup(13, frac, seed=91)
+    outs = {}
+    for sw in (0.0, 0.4, 2.0):
+        p2 = Pair(p.n, p.og_prev.esrc, p.og_prev.edst)
+        p2.apply(p.batch.dm_src, p.batch.dm_dst, p.batch.dp_src, p.batch.dp_dst)
+        r, st, ref = p2.rank(mode, r0, dense_switch=sw)
+        outs[sw] = (r, st)
+        assert np.abs(r - ref.ranks).max() <= LINF
+        assert abs(st["iterations"] - ref.iterations) <= 1
+    for key in ("iterations", "ever_affected", "vertex_updates", "edges_pulled"):
+        assert outs[0.0][1][key] == outs[0.4][1][key] == outs[2.0][1][key], key
+    assert outs[0.0][1]["dense_iterations"] == outs[0.0][1]["iterations"]
+    assert outs[2.0][1]["dense_iterations"] == 0
+    assert np.array_equal(outs[0.0][0], outs[2.0][0]) and np.array_equal(outs[0.4][0], outs[2.0][0])
+
+
 @pytest.mark.parametrize("mode", ["static", "nd", "df", "dfp"])
 def test_ranks_bitexact_lane_bin(mode):
     """With every vertex in the one-lane bin the sums run in the oracle's order:

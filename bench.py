@@ -103,6 +103,7 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (R0 from GPU Static)")
     ap.add_argument("--static-runs", type=int, default=3)
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--calib", action="store_true",
                     help="finish with three 1 GiB device copies (counter calibration under a profiler)")
     args = ap.parse_args()
@@ -132,6 +133,10 @@ def main():
     torch.cuda.synchronize()
     log(f"create: m={m0} {time.time() - t0:.2f}s")
     dev_batches = [tuple(torch.from_numpy(a).to(dev) for a in b) for b in batches]
+    if not args.no_autotune:
+        t0 = time.time()
+        bounds, tune_ms = g.autotune()
+        log(f"autotune: bounds {bounds} pull {tune_ms:.3f} ms ({time.time() - t0:.1f}s)")
 
     # ---- GPU Static (cold, from 1/N) on G0: the comparison baseline
     r_static = torch.empty(n, dtype=torch.float64, device=dev)
@@ -251,7 +256,7 @@ def main():
                                f"{args.edge_factor:g}, self-loops; chained 80/20 batches of "
                                f"{args.frac:g}*|E|; apply + {args.mode.upper()} update per step",
                    "n": n, "m": int(m0), "batch_edges": int(len(batches[0][0]) + len(batches[0][2])),
-                   "mode": args.mode, "parallelism": "1 GPU"},
+                   "mode": args.mode, "parallelism": "1 GPU", "bin_bounds": g.get_tuning()},
         "p50_ms": pct(step_ms, 50),
         "p99_ms": pct(step_ms, 99),
         "apply_p50_ms": pct(apply_ms, 50),

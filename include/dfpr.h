@@ -181,6 +181,14 @@ int dfpr_update_ranks(dfpr_graph* g, dfpr_mode mode, const dfpr_params* p, const
 int dfpr_set_tuning(dfpr_graph* g, const int32_t bounds[5]);
 int dfpr_get_tuning(const dfpr_graph* g, int32_t bounds[5]);
 
+/* Autotuner: choose the in-degree thresholds of the pull kernel for this
+ * graph by timing a few Static iterations (HIP events) for each candidate, one
+ * threshold at a time (coordinate descent from the current setting).  The
+ * best setting is installed and written to bounds_out (nullable); ms_out
+ * (nullable) receives the best average pull time.  Uses temporary device
+ * memory for one rank vector; pending batch marks are left untouched. */
+int dfpr_autotune(dfpr_graph* g, void* stream, int32_t bounds_out[5], double* ms_out);
+
 /* Turn HIP-event timing of every apply and update on this graph on (1) or
  * off (0).  Events are recorded between kernels and read after the call's
  * final synchronisation, so timing adds no host round trips. */

@@ -165,6 +165,13 @@ class Graph:
         _check(lib().dfpr_get_tuning(self._h, arr))
         return list(arr)
 
+    def autotune(self, stream=None):
+        """Time candidate bin thresholds on this graph and install the best; returns (bounds, ms)."""
+        arr = (ctypes.c_int32 * 5)()
+        ms = ctypes.c_double()
+        _check(lib().dfpr_autotune(self._h, _stream_ptr(stream), arr, ctypes.byref(ms)))
+        return list(arr), ms.value
+
     def set_timing(self, on=True):
         _check(lib().dfpr_set_timing(self._h, 1 if on else 0))
 

@@ -16,7 +16,7 @@ CREATE_KEEP_IDS = 1
 # Every exported function declared in include/dfpr.h.
 EXPORTS = ("dfpr_params_default", "dfpr_graph_create", "dfpr_graph_destroy", "dfpr_graph_size",
            "dfpr_graph_export", "dfpr_apply_batch", "dfpr_update_ranks", "dfpr_set_tuning",
-           "dfpr_get_tuning", "dfpr_set_timing", "dfpr_last_error", "dfpr_version")
+           "dfpr_get_tuning", "dfpr_autotune", "dfpr_set_timing", "dfpr_last_error", "dfpr_version")
 
 
 class Params(ctypes.Structure):
@@ -82,6 +82,8 @@ def declare(lib):
     lib.dfpr_set_tuning.restype = ctypes.c_int
     lib.dfpr_get_tuning.argtypes = [P, ctypes.POINTER(i32)]
     lib.dfpr_get_tuning.restype = ctypes.c_int
+    lib.dfpr_autotune.argtypes = [P, P, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]
+    lib.dfpr_autotune.restype = ctypes.c_int
     lib.dfpr_set_timing.argtypes = [P, ctypes.c_int]
     lib.dfpr_set_timing.restype = ctypes.c_int
     lib.dfpr_last_error.argtypes = []

@@ -192,6 +192,11 @@ int dfpr_set_tuning(dfpr_graph* g, const int32_t bounds[5]) {
   });
 }
 
+int dfpr_autotune(dfpr_graph* g, void* stream, int32_t bounds_out[5], double* ms_out) {
+  clear_error();
+  return guarded(g, [&] { return autotune(g, (hipStream_t)stream, bounds_out, ms_out); });
+}
+
 int dfpr_set_timing(dfpr_graph* g, int on) {
   clear_error();
   return guarded(g, [&] {

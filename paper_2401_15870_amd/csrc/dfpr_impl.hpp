@@ -202,7 +202,7 @@ struct dfpr_graph {
   // growable batch scratch
   dfpr::DevBuf keys_a, keys_b, keys_c, sort_hist, eff_pre, batch_in, keys_in;
   bool pending_any = false;  // an apply happened since the last DF/DF-P update
-  int32_t bounds[5] = {4, 16, 64, 512, 4096};  // in-degree bin limits (dfpr_set_tuning)
+  int32_t bounds[5] = {4, 16, 128, 2048, 32768};  // in-degree bin limits (dfpr_set_tuning)
   int32_t* arrive = nullptr;  // n: per-vertex chunk arrival counters of bin 5
   int32_t* partial_x = nullptr;  // per-chunk "an in-neighbour expanded" flags (dense mode)
   bool timing = false;        // record HIP-event timings of every call
@@ -242,6 +242,7 @@ int graph_apply(dfpr_graph* g, int64_t n_del, const int32_t* del_src, const int3
 // ---- ranks (rank.hip)
 int update_ranks(dfpr_graph* g, dfpr_mode mode, const dfpr_params& p, const double* r_prev,
                  double* r_out, hipStream_t s, dfpr_stats* st);
+int autotune(dfpr_graph* g, hipStream_t s, int32_t* bounds_out, double* ms_out);
 
 inline int bits_for(int64_t n) {
   int b = 1;

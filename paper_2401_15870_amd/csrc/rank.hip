@@ -1136,4 +1136,81 @@ int update_ranks(dfpr_graph* g, dfpr_mode mode, const dfpr_params& p, const doub
   return DFPR_OK;
 }
 
+// ---- autotuner: coordinate descent over the five bin thresholds, each
+// candidate timed on Static iterations (pull kernel only, HIP events).
+static int time_pull(dfpr_graph* g, double* r, hipStream_t s, double* ms) {
+  dfpr_params p;
+  p.alpha = 0.85;
+  p.tol = 1e-300;  // run the full iteration count
+  p.frontier_tol = p.prune_tol = 1e-6;
+  p.dense_switch = 0.4;
+  p.max_iters = 4;
+  p.flags = DFPR_FLAG_TIMING;
+  // pending marks must survive: run_sync clears them only if pending_any
+  const bool pend = g->pending_any;
+  g->pending_any = false;
+  dfpr_stats st{};
+  int rc = update_ranks(g, DFPR_STATIC, p, nullptr, r, s, &st);
+  g->pending_any = pend;
+  if (rc != DFPR_OK) return rc;
+  *ms = st.pull_launches ? st.ms_pull / st.pull_launches : 0.0;
+  return DFPR_OK;
+}
+
+int autotune(dfpr_graph* g, hipStream_t s, int32_t* bounds_out, double* ms_out) {
+  double* r = nullptr;
+  if (hipMalloc((void**)&r, (size_t)g->n * sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("autotune: device allocation failed");
+    return DFPR_ENOMEM;
+  }
+  static const int32_t cand[5][6] = {{2, 4, 8, 16, 0, 0},
+                                     {8, 16, 32, 64, 0, 0},
+                                     {32, 64, 128, 256, 512, 0},
+                                     {256, 512, 1024, 2048, 4096, 8192},
+                                     {4096, 8192, 16384, 32768, 131072, 1 << 20}};
+  int32_t best[5];
+  std::copy(g->bounds, g->bounds + 5, best);
+  double best_ms = 0.0;
+  int rc = DFPR_OK;
+  auto eval = [&](const int32_t* b, double* ms) {
+    const int32_t keep[5] = {g->bounds[0], g->bounds[1], g->bounds[2], g->bounds[3], g->bounds[4]};
+    std::copy(b, b + 5, g->bounds);
+    g->all_bins_valid = false;
+    int e = time_pull(g, r, s, ms);  // first call rebuilds the bins
+    if (e == DFPR_OK) e = time_pull(g, r, s, ms);
+    std::copy(keep, keep + 5, g->bounds);
+    g->all_bins_valid = false;
+    return e;
+  };
+  rc = eval(best, &best_ms);
+  for (int pass = 0; pass < 2 && rc == DFPR_OK; pass++) {
+    for (int k = 4; k >= 0 && rc == DFPR_OK; k--) {
+      for (int c = 0; c < 6 && rc == DFPR_OK; c++) {
+        const int32_t v = cand[k][c];
+        if (v == 0 || v == best[k]) continue;
+        int32_t b[5];
+        std::copy(best, best + 5, b);
+        b[k] = v;
+        bool ok = b[0] >= 1;
+        for (int i = 1; i < 5; i++) ok = ok && b[i] >= b[i - 1];
+        if (!ok) continue;
+        double ms = 0.0;
+        rc = eval(b, &ms);
+        if (rc == DFPR_OK && ms < best_ms) {
+          best_ms = ms;
+          std::copy(b, b + 5, best);
+        }
+      }
+    }
+  }
+  (void)hipFree(r);
+  if (rc != DFPR_OK) return rc;
+  std::copy(best, best + 5, g->bounds);
+  g->all_bins_valid = false;
+  if (bounds_out) std::copy(best, best + 5, bounds_out);
+  if (ms_out) *ms_out = best_ms;
+  return DFPR_OK;
+}
+
 }  // namespace dfpr

@@ -161,9 +161,12 @@ def test_all_bins(mode, bounds):
     p, r0 = _setup(12, 1e-2, seed=31)
     p.g.set_tuning(bounds)
     assert p.g.get_tuning() == bounds
-    r, st, ref = p.rank(mode, r0)
+    r, st, ref = p.rank(mode, r0, dense_switch=2.0)  # frontier form: the worklist bins are used
     assert np.abs(r - ref.ranks).max() <= LINF
     assert st["bin_vertices"][5] > 0 and st["bin_vertices"][3] > 0
+    if mode != "static":
+        r2, st2, _ = p.rank(mode, r0, dense_switch=0.0)  # dense form over the all-vertex bins
+        assert np.array_equal(r, r2) and st2["dense_iterations"] == st2["iterations"]
 
 
 @pytest.mark.parametrize("mode", ["static", "df", "dfp"])
@@ -178,6 +181,16 @@ def test_hub_graph_ranks(mode):
     assert np.abs(r - ref.ranks).max() <= LINF
     if mode != "static":
         assert st["ever_affected"] == ref.ever_affected
+
+
+def test_autotune_keeps_parity():
+    p, r0 = _setup(13, 1e-3, seed=97)
+    bounds, ms = p.g.autotune()
+    assert bounds == p.g.get_tuning() and ms > 0
+    assert bounds[0] >= 1 and all(bounds[i] <= bounds[i + 1] for i in range(4))
+    r, st, ref = p.rank("dfp", r0)  # the pending marks of the batch survived tuning
+    assert np.abs(r - ref.ranks).max() <= LINF
+    assert st["ever_affected"] == ref.ever_affected
 
 
 def test_empty_and_noop_batches():

@@ -194,6 +194,63 @@ int dfpr_autotune(dfpr_graph* g, void* stream, int32_t bounds_out[5], double* ms
  * final synchronisation, so timing adds no host round trips. */
 int dfpr_set_timing(dfpr_graph* g, int on);
 
+/* ---- Batched form: many independent graphs updated together.
+ *
+ * Graphs that each need the same update (apply a batch, then Static / ND / DF /
+ * DF-P) are held as one batch handle: the disjoint union of the member graphs
+ * in one device arena, member k owning the vertex range [base_k, base_k + n_k).
+ * Every step of the update runs once over the whole arena, so small graphs
+ * share launches instead of each paying its own.  Each member follows
+ * Algorithm 1 on its own: its constant term is (1 - alpha)/n_k (Equation 1 with
+ * |V| = n_k), its Static start is 1/n_k, and its L-inf change, iteration count
+ * and convergence are its own; a member that has converged drops out of the
+ * later iterations of the call, so its result is the one its plain-handle
+ * update would give.  With the default thresholds and the same create flags the
+ * results are bit-identical to per-graph plain handles.  Rank vectors of a
+ * batch handle have one entry per arena vertex; member k's ranks sit at
+ * [base_k, base_k + n_k) in its own vertex order.
+ *
+ * On a batch handle, dfpr_apply_batch is refused (EINVAL: its ids could join
+ * members); dfpr_update_ranks works and reports totals only; dfpr_graph_size,
+ * dfpr_graph_export and the tuning calls see the arena. */
+
+/* Create a batch handle from `count` >= 1 member edge lists.  Member k has
+ * n[k] >= 1 vertices and m[k] >= 0 pairs src[k][i] -> dst[k][i] with ids in
+ * [0, n[k]) (all arrays in `where` memory; the pointer arrays themselves on
+ * the host).  Each member is made canonical like dfpr_graph_create.  flags as
+ * for dfpr_graph_create.  Errors: EINVAL (count < 1, n[k] < 1, m[k] < 0, null
+ * arrays with m[k] > 0, arena beyond int32), ERANGE (an id outside its member),
+ * ENOMEM, EHIP. */
+int dfpr_batch_create(int32_t count, const int32_t* n, const int64_t* m, const int32_t* const* src,
+                      const int32_t* const* dst, dfpr_where where, int32_t flags, void* stream,
+                      dfpr_graph** out);
+
+/* Number of members (1 for a plain handle). */
+int dfpr_batch_count(const dfpr_graph* g, int32_t* count);
+
+/* Vertex range of member k in the arena: base and n. */
+int dfpr_batch_member(const dfpr_graph* g, int32_t k, int32_t* base, int32_t* n);
+
+/* Apply one batch update to every member (Section 3.2, per member as in
+ * dfpr_apply_batch).  Per member k: n_del[k] deletions del_src[k][i] ->
+ * del_dst[k][i] and n_ins[k] insertions, ids member-local.  info (nullable)
+ * receives `count` entries; their ms_* fields time the whole call.  Errors:
+ * EINVAL, ERANGE (no member changed), ENOMEM, EHIP. */
+int dfpr_apply_batch_many(dfpr_graph* g, const int64_t* n_del, const int32_t* const* del_src,
+                          const int32_t* const* del_dst, const int64_t* n_ins, const int32_t* const* ins_src,
+                          const int32_t* const* ins_dst, dfpr_where where, void* stream, dfpr_batch_info* info);
+
+/* Update the ranks of every member (Algorithm 1; Equations 1 and 2 per
+ * member).  r_prev / r_out: device arrays over the arena (see above), may
+ * alias.  total (nullable): iterations = the most any member ran, converged =
+ * all members converged, last_delta = the largest member last change,
+ * ever_affected and the work counters summed, timings of the whole call.
+ * per_graph (nullable, `count` entries): iterations, converged, last_delta and
+ * ever_affected of each member; its other fields are 0.  Errors as for
+ * dfpr_update_ranks. */
+int dfpr_update_ranks_many(dfpr_graph* g, dfpr_mode mode, const dfpr_params* p, const double* r_prev,
+                           double* r_out, void* stream, dfpr_stats* total, dfpr_stats* per_graph);
+
 /* Thread-local message for the last failing call on this thread ("" if none). */
 const char* dfpr_last_error(void);
 

@@ -176,5 +176,101 @@ class Graph:
         _check(lib().dfpr_set_timing(self._h, 1 if on else 0))
 
 
+def _ptr_array(items):
+    """(void* array, where, keepalive) for a list of int32 id arrays (numpy or torch)."""
+    parts = [_ids(a) for a in items]
+    wheres = {w for _, k, w, _ in parts if k}
+    if len(wheres) > 1:
+        raise ValueError("all member arrays must live in the same memory")
+    arr = (ctypes.c_void_p * max(len(parts), 1))(*[p for p, _, _, _ in parts])
+    return arr, [k for _, k, _, _ in parts], (wheres.pop() if wheres else _capi.HOST), parts
+
+
+class BatchGraph(Graph):
+    """Many independent graphs in one device arena, updated together.
+
+    Member k owns arena vertices [base_k, base_k + n_k); rank vectors span the
+    arena.  Each member converges on its own (per-member constant term,
+    L-inf change, iteration count)."""
+
+    def __init__(self, handle, n, bases, sizes):
+        super().__init__(handle, n)
+        self.bases = bases
+        self.sizes = sizes
+
+    @property
+    def count(self) -> int:
+        return len(self.sizes)
+
+    @classmethod
+    def from_coo(cls, graphs, keep_ids=False, stream=None):
+        """graphs: list of (n_k, src_k, dst_k) with member-local ids."""
+        count = len(graphs)
+        ns = (ctypes.c_int32 * count)(*[int(g[0]) for g in graphs])
+        srcs, ms, w1, k1 = _ptr_array([g[1] for g in graphs])
+        dsts, md, w2, k2 = _ptr_array([g[2] for g in graphs])
+        if ms != md:
+            raise ValueError("src and dst must have the same length per member")
+        if any(ms) and w1 != w2:
+            raise ValueError("src and dst must live in the same memory")
+        mm = (ctypes.c_int64 * count)(*ms)
+        h = ctypes.c_void_p()
+        flags = _capi.CREATE_KEEP_IDS if keep_ids else 0
+        _check(lib().dfpr_batch_create(count, ns, mm, srcs, dsts, w1, flags, _stream_ptr(stream), ctypes.byref(h)))
+        bases, sizes = [], []
+        for k in range(count):
+            b, n = ctypes.c_int32(), ctypes.c_int32()
+            _check(lib().dfpr_batch_member(h, k, ctypes.byref(b), ctypes.byref(n)))
+            bases.append(b.value)
+            sizes.append(n.value)
+        return cls(h, sum(sizes), bases, sizes)
+
+    def member(self, r, k):
+        """Member k's slice of an arena rank vector."""
+        return r[self.bases[k]: self.bases[k] + self.sizes[k]]
+
+    def apply_batch_many(self, batches, stream=None):
+        """batches: list (one per member) of (del_src, del_dst, ins_src, ins_dst), member-local ids."""
+        if len(batches) != self.count:
+            raise ValueError("one batch per member")
+        ds, nds, wa, ka = _ptr_array([b[0] for b in batches])
+        dd, ndd, wb, kb = _ptr_array([b[1] for b in batches])
+        is_, nis, wc, kc = _ptr_array([b[2] for b in batches])
+        id_, nid, wd, kd = _ptr_array([b[3] for b in batches])
+        if nds != ndd or nis != nid:
+            raise ValueError("src/dst length mismatch")
+        wheres = {w for w, cnt in ((wa, sum(nds)), (wc, sum(nis))) if cnt}
+        if len(wheres) > 1:
+            raise ValueError("deletions and insertions must live in the same memory")
+        where = wheres.pop() if wheres else _capi.HOST
+        info = (BatchInfo * self.count)()
+        _check(lib().dfpr_apply_batch_many(self._h, (ctypes.c_int64 * self.count)(*nds), ds, dd,
+                                           (ctypes.c_int64 * self.count)(*nis), is_, id_, where,
+                                           _stream_ptr(stream), info))
+        return [x.as_dict() for x in info]
+
+    def update_ranks_many(self, mode, r_prev=None, out=None, stream=None, timing=False, **kw):
+        """Update every member; returns (arena ranks, total stats, per-member stats)."""
+        import torch
+        m = MODES[mode] if isinstance(mode, str) else int(mode)
+        p = default_params()
+        for k, v in kw.items():
+            setattr(p, k, v)
+        if timing:
+            p.flags |= _capi.FLAG_TIMING
+        if out is None:
+            out = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        for t in (out, r_prev):
+            if t is not None and (t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous()
+                                  or t.numel() != self.n):
+                raise ValueError("rank vectors must be contiguous float64 CUDA tensors over the arena")
+        st = Stats()
+        per = (Stats * self.count)()
+        rp = ctypes.c_void_p(r_prev.data_ptr()) if r_prev is not None else None
+        _check(lib().dfpr_update_ranks_many(self._h, m, ctypes.byref(p), rp, ctypes.c_void_p(out.data_ptr()),
+                                            _stream_ptr(stream), ctypes.byref(st), per))
+        return out, st.as_dict(), [x.as_dict() for x in per]
+
+
 def version() -> str:
     return lib().dfpr_version().decode()

@@ -16,7 +16,9 @@ CREATE_KEEP_IDS = 1
 # Every exported function declared in include/dfpr.h.
 EXPORTS = ("dfpr_params_default", "dfpr_graph_create", "dfpr_graph_destroy", "dfpr_graph_size",
            "dfpr_graph_export", "dfpr_apply_batch", "dfpr_update_ranks", "dfpr_set_tuning",
-           "dfpr_get_tuning", "dfpr_autotune", "dfpr_set_timing", "dfpr_last_error", "dfpr_version")
+           "dfpr_get_tuning", "dfpr_autotune", "dfpr_set_timing", "dfpr_batch_create", "dfpr_batch_count",
+           "dfpr_batch_member", "dfpr_apply_batch_many", "dfpr_update_ranks_many", "dfpr_last_error",
+           "dfpr_version")
 
 
 class Params(ctypes.Structure):
@@ -86,6 +88,20 @@ def declare(lib):
     lib.dfpr_autotune.restype = ctypes.c_int
     lib.dfpr_set_timing.argtypes = [P, ctypes.c_int]
     lib.dfpr_set_timing.restype = ctypes.c_int
+    PP = ctypes.POINTER(P)
+    lib.dfpr_batch_create.argtypes = [i32, ctypes.POINTER(i32), ctypes.POINTER(i64), PP, PP, ctypes.c_int, i32, P,
+                                      ctypes.POINTER(P)]
+    lib.dfpr_batch_create.restype = ctypes.c_int
+    lib.dfpr_batch_count.argtypes = [P, ctypes.POINTER(i32)]
+    lib.dfpr_batch_count.restype = ctypes.c_int
+    lib.dfpr_batch_member.argtypes = [P, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.dfpr_batch_member.restype = ctypes.c_int
+    lib.dfpr_apply_batch_many.argtypes = [P, ctypes.POINTER(i64), PP, PP, ctypes.POINTER(i64), PP, PP, ctypes.c_int,
+                                          P, ctypes.POINTER(BatchInfo)]
+    lib.dfpr_apply_batch_many.restype = ctypes.c_int
+    lib.dfpr_update_ranks_many.argtypes = [P, ctypes.c_int, ctypes.POINTER(Params), P, P, P, ctypes.POINTER(Stats),
+                                           ctypes.POINTER(Stats)]
+    lib.dfpr_update_ranks_many.restype = ctypes.c_int
     lib.dfpr_last_error.argtypes = []
     lib.dfpr_last_error.restype = ctypes.c_char_p
     lib.dfpr_version.argtypes = []

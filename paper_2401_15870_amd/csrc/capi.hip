@@ -150,6 +150,10 @@ int dfpr_apply_batch(dfpr_graph* g, int64_t n_del, const int32_t* del_src, const
     return DFPR_EINVAL;
   }
   return guarded(g, [&] {
+    if (g->ngraphs > 1) {
+      set_error("batch handle: use dfpr_apply_batch_many");
+      return (int)DFPR_EINVAL;
+    }
     return graph_apply(g, n_del, del_src, del_dst, n_ins, ins_src, ins_dst, where, (hipStream_t)stream, info);
   });
 }
@@ -169,6 +173,101 @@ int dfpr_update_ranks(dfpr_graph* g, dfpr_mode mode, const dfpr_params* p, const
     return DFPR_EINVAL;
   }
   return guarded(g, [&] { return update_ranks(g, mode, prm, r_prev, r_out, (hipStream_t)stream, st); });
+}
+
+int dfpr_batch_create(int32_t count, const int32_t* n, const int64_t* m, const int32_t* const* src,
+                      const int32_t* const* dst, dfpr_where where, int32_t flags, void* stream, dfpr_graph** out) {
+  clear_error();
+  if (!out) {
+    set_error("out is null");
+    return DFPR_EINVAL;
+  }
+  *out = nullptr;
+  if (count < 1 || !n || !m || !src || !dst || (where != DFPR_HOST && where != DFPR_DEVICE) ||
+      (flags & ~DFPR_CREATE_KEEP_IDS) != 0) {
+    set_error("invalid batch arguments: count=%d", count);
+    return DFPR_EINVAL;
+  }
+  for (int32_t k = 0; k < count; k++) {
+    if (n[k] < 1 || m[k] < 0 || (m[k] > 0 && (!src[k] || !dst[k]))) {
+      set_error("member %d: invalid n=%d m=%lld or null arrays", k, n[k], (long long)m[k]);
+      return DFPR_EINVAL;
+    }
+  }
+  try {
+    return batch_create(count, n, m, src, dst, where, flags, (hipStream_t)stream, out);
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return DFPR_ENOMEM;
+  }
+}
+
+int dfpr_batch_count(const dfpr_graph* g, int32_t* count) {
+  clear_error();
+  if (!g || !count) {
+    set_error("null argument");
+    return DFPR_EINVAL;
+  }
+  *count = g->ngraphs;
+  return DFPR_OK;
+}
+
+int dfpr_batch_member(const dfpr_graph* g, int32_t k, int32_t* base, int32_t* n) {
+  clear_error();
+  if (!g || !base || !n || k < 0 || k >= g->ngraphs) {
+    set_error("null argument or member index out of range");
+    return DFPR_EINVAL;
+  }
+  *base = (int32_t)g->vbase[k];
+  *n = (int32_t)(g->vbase[k + 1] - g->vbase[k]);
+  return DFPR_OK;
+}
+
+int dfpr_apply_batch_many(dfpr_graph* g, const int64_t* n_del, const int32_t* const* del_src,
+                          const int32_t* const* del_dst, const int64_t* n_ins, const int32_t* const* ins_src,
+                          const int32_t* const* ins_dst, dfpr_where where, void* stream, dfpr_batch_info* info) {
+  clear_error();
+  if (!n_del || !n_ins || (where != DFPR_HOST && where != DFPR_DEVICE)) {
+    set_error("invalid batch arguments");
+    return DFPR_EINVAL;
+  }
+  return guarded(g, [&] {
+    for (int32_t k = 0; k < g->ngraphs; k++) {
+      if (n_del[k] < 0 || n_ins[k] < 0 || (n_del[k] > 0 && (!del_src || !del_dst || !del_src[k] || !del_dst[k])) ||
+          (n_ins[k] > 0 && (!ins_src || !ins_dst || !ins_src[k] || !ins_dst[k]))) {
+        set_error("member %d: invalid batch counts or null arrays", k);
+        return (int)DFPR_EINVAL;
+      }
+    }
+    return batch_apply(g, n_del, del_src, del_dst, n_ins, ins_src, ins_dst, where, (hipStream_t)stream, info);
+  });
+}
+
+int dfpr_update_ranks_many(dfpr_graph* g, dfpr_mode mode, const dfpr_params* p, const double* r_prev,
+                           double* r_out, void* stream, dfpr_stats* total, dfpr_stats* per_graph) {
+  clear_error();
+  dfpr_params prm;
+  if (p) prm = *p; else dfpr_params_default(&prm);
+  if (mode < DFPR_STATIC || mode > DFPR_DFP) {
+    set_error("unknown mode %d", (int)mode);
+    return DFPR_EINVAL;
+  }
+  if (check_params(prm) != DFPR_OK) return DFPR_EINVAL;
+  if (!r_out || (mode != DFPR_STATIC && !r_prev)) {
+    set_error("rank arrays must not be null");
+    return DFPR_EINVAL;
+  }
+  return guarded(g, [&] {
+    const int rc = update_ranks(g, mode, prm, r_prev, r_out, (hipStream_t)stream, total, per_graph);
+    if (rc == DFPR_OK && per_graph && g->ngraphs == 1 && total) {
+      per_graph[0] = dfpr_stats{};
+      per_graph[0].iterations = total->iterations;
+      per_graph[0].converged = total->converged;
+      per_graph[0].last_delta = total->last_delta;
+      per_graph[0].ever_affected = total->ever_affected;
+    }
+    return rc;
+  });
 }
 
 int dfpr_set_tuning(dfpr_graph* g, const int32_t bounds[5]) {

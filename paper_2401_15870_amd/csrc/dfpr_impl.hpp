@@ -142,8 +142,8 @@ struct IterCtl {
   int64_t dense_cnt;         // dense pull: affected vertices of the last iteration
   int64_t dense_edges;       // dense pull: their summed in-degree
   int64_t dense_xedges;      // dense pull: summed out-degree of its expanding vertices
+  int64_t active;            // member graphs not yet converged (1/0 for a plain graph)
   int64_t pad[2];
-  unsigned long long dR_slots[kSlots * kSlotStride];
   unsigned long long acc_slots[kAccRows][kSlots * kSlotStride];
 };
 constexpr size_t kCtlHead = offsetof(IterCtl, pad);
@@ -152,6 +152,7 @@ constexpr size_t kCtlHead = offsetof(IterCtl, pad);
 constexpr int kPullChunk = 4096;   // in-edges per workgroup work item (bin 5)
 constexpr int kMarkChunk = 4096;   // out-edges per workgroup work item
 constexpr int kBigRow = 4096;      // out-rows longer than this go to the chunked marking
+constexpr int kGSub = 8;           // spread slots per member graph for its L-inf reduction
 
 }  // namespace dfpr
 
@@ -163,6 +164,20 @@ struct dfpr_graph {
   int64_t m = 0;
   int64_t cap = 0;   // edge capacity of each index array
   int id_bits = 1;   // bits per vertex id in packed sort keys
+  // members of a batch (disjoint union; member k owns vertices [vbase[k], vbase[k+1]))
+  int32_t ngraphs = 1;
+  std::vector<int64_t> vbase;        // host, ngraphs + 1
+  int32_t* gidv = nullptr;           // n: member of each vertex (null for a plain graph)
+  int64_t* vbase_d = nullptr;        // device copy of vbase (batches)
+  int32_t* nk = nullptr;             // ngraphs: vertex count of each member
+  uint8_t* done = nullptr;           // ngraphs: member converged in this update
+  int gsub = 1;                      // spread L-inf slots per member (kSlots for a plain graph)
+  unsigned long long* gslots = nullptr;  // ngraphs * gsub spread L-inf slots (kSlotStride apart)
+  double* g_dr = nullptr;            // ngraphs: last L-inf change
+  int32_t* g_iters = nullptr;        // ngraphs: iterations run
+  int64_t* g_ever = nullptr;         // ngraphs: vertices processed at least once
+  int64_t* g_eff = nullptr;          // 4 * ngraphs: eff. ins/del pairs, edges after, ignored self dels
+  void* g_host = nullptr;            // pinned mirror of g_dr, g_iters, g_ever, g_eff, done
   int32_t* perm = nullptr;  // n: caller id -> internal id (null: identity)
   int32_t* inv = nullptr;   // n: internal id -> caller id
   double* rint = nullptr;   // n: ranks in internal order (when relabelled)
@@ -231,7 +246,13 @@ int compact_keys(const uint64_t* in, const uint8_t* keep, uint64_t* out, int64_t
 
 // ---- graph (graph.hip)
 int graph_create(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, dfpr_where where,
-                 int64_t edge_capacity, int32_t flags, hipStream_t s, dfpr_graph** out);
+                 int64_t edge_capacity, int32_t flags, hipStream_t s, dfpr_graph** out,
+                 const std::vector<int64_t>* members = nullptr);
+int batch_create(int32_t count, const int32_t* n, const int64_t* m, const int32_t* const* src,
+                 const int32_t* const* dst, dfpr_where where, int32_t flags, hipStream_t s, dfpr_graph** out);
+int batch_apply(dfpr_graph* g, const int64_t* n_del, const int32_t* const* del_src, const int32_t* const* del_dst,
+                const int64_t* n_ins, const int32_t* const* ins_src, const int32_t* const* ins_dst, dfpr_where where,
+                hipStream_t s, dfpr_batch_info* info);
 int graph_destroy(dfpr_graph* g);
 int graph_export(const dfpr_graph* g, int in_csr, int32_t* off, int32_t* idx, dfpr_where where,
                  hipStream_t s);
@@ -241,7 +262,7 @@ int graph_apply(dfpr_graph* g, int64_t n_del, const int32_t* del_src, const int3
 
 // ---- ranks (rank.hip)
 int update_ranks(dfpr_graph* g, dfpr_mode mode, const dfpr_params& p, const double* r_prev,
-                 double* r_out, hipStream_t s, dfpr_stats* st);
+                 double* r_out, hipStream_t s, dfpr_stats* st, dfpr_stats* per_member = nullptr);
 int autotune(dfpr_graph* g, hipStream_t s, int32_t* bounds_out, double* ms_out);
 
 inline int bits_for(int64_t n) {

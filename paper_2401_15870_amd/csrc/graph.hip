@@ -78,9 +78,70 @@ __global__ void k_validate_count(const int32_t* src, const int32_t* dst, int64_t
     }
   }
 }
-__global__ void k_degree_keys(const int32_t* deg, int32_t n, int b, uint64_t* keys) {
-  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
-    keys[v] = ((uint64_t)(0x7FFFFFFF - deg[v]) << b) | (uint64_t)v;
+// Sort key of the internal numbering: member, then decreasing degree (capped
+// at 2^24-1), then caller id; members keep their contiguous vertex ranges.
+__global__ void k_degree_keys(const int32_t* deg, const int32_t* gidv, int32_t n, int b, uint64_t* keys) {
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t d = (uint64_t)min(deg[v], 0xFFFFFF);
+    const uint64_t gk = gidv ? (uint64_t)gidv[v] : 0ull;
+    keys[v] = (gk << (24 + b)) | ((0xFFFFFFull - d) << b) | (uint64_t)v;
+  }
+}
+// Member of every vertex from the member vertex bases (binary search).
+__global__ void k_member_ids(const int64_t* vbase, int32_t count, int32_t n, int32_t* gidv) {
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    int32_t lo = 0, hi = count;  // largest k with vbase[k] <= v
+    while (hi - lo > 1) {
+      const int32_t mid = (lo + hi) >> 1;
+      if (vbase[mid] <= v) lo = mid; else hi = mid;
+    }
+    gidv[v] = lo;
+  }
+}
+// Per-member effective insertion / deletion counts of a batch (keys sorted by
+// row, so a wavefront is nearly always inside one member).
+__global__ void k_member_eff(const uint64_t* eff, const int64_t* count, int b, const int32_t* gidv, int64_t* g_eff) {
+  const int64_t T = *count;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t base = blockIdx.x * (int64_t)blockDim.x + (threadIdx.x & ~(kWave - 1)); base < T; base += stride) {
+    const int64_t i = base + lane_id();
+    const bool ok = i < T;
+    const uint64_t k = ok ? eff[i] : 0ull;
+    const int32_t gk = ok ? gidv[(int32_t)(k >> (b + 1))] : -1;
+    const int is_ins = ok ? (int)(k & 1ull) : 0;
+    const int32_t g0 = __shfl(gk, 0, kWave);
+    const bool same = __ballot(ok && gk != g0) == 0ull;
+    if (same) {
+      const int64_t ni = wave_sum_i64(is_ins), nd = wave_sum_i64(ok ? 1 - is_ins : 0);
+      if (lane_id() == 0 && g0 >= 0) {
+        if (ni) atomicAdd((unsigned long long*)&g_eff[2 * g0], (unsigned long long)ni);
+        if (nd) atomicAdd((unsigned long long*)&g_eff[2 * g0 + 1], (unsigned long long)nd);
+      }
+    } else if (ok) {
+      atomicAdd((unsigned long long*)&g_eff[2 * gk + (is_ins ? 0 : 1)], 1ull);
+    }
+  }
+}
+// Edge count of every member after a batch (its rows of the union out-CSR).
+__global__ void k_member_m(const int32_t* out_off, const int64_t* vbase, int32_t G, int64_t* m_out) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < G; k += (int64_t)gridDim.x * blockDim.x)
+    m_out[k] = (int64_t)out_off[vbase[k + 1]] - out_off[vbase[k]];
+}
+// Member-local batch ids -> union ids, with validation against the member size.
+__global__ void k_offset_ids(const int32_t* a, const int32_t* b, int64_t cnt, int32_t nmem, int64_t base, int32_t* oa,
+                             int32_t* ob, int64_t* err) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t u = a[i], v = b[i];
+    if (u < 0 || u >= nmem || v < 0 || v >= nmem) {
+      atomicOr((unsigned long long*)err, 1ull);
+      oa[i] = 0;
+      ob[i] = 0;
+    } else {
+      oa[i] = (int32_t)(u + base);
+      ob[i] = (int32_t)(v + base);
+    }
+  }
+
 }
 __global__ void k_perm_from_sorted(const uint64_t* keys, int32_t n, int b, int32_t* perm, int32_t* inv) {
   const uint64_t mask = (1ull << b) - 1;
@@ -180,7 +241,8 @@ __global__ void k_make_batch_keys(const int32_t* del_src, const int32_t* del_dst
 // Effective pairs set row deltas, touched rows and the pending marks.
 __global__ void k_classify(const uint64_t* keys, int64_t nk, int b, const int32_t* ooff, const int32_t* oidx,
                            uint8_t* keep, int32_t* delta_out, int32_t* delta_in, uint8_t* touched_out,
-                           uint8_t* touched_in, uint8_t* pend_src, uint8_t* pend_tgt, int64_t* counters) {
+                           uint8_t* touched_in, uint8_t* pend_src, uint8_t* pend_tgt, int64_t* counters,
+                           const int32_t* gidv, int64_t* g_self) {
   const uint64_t mask = (1ull << b) - 1;
   int64_t n_ins = 0, n_del = 0, n_self = 0;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nk; i += (int64_t)gridDim.x * blockDim.x) {
@@ -195,7 +257,10 @@ __global__ void k_classify(const uint64_t* keys, int64_t nk, int b, const int32_
       const int32_t u = (int32_t)(pair >> b);
       const int32_t v = (int32_t)(pair & mask);
       if (u == v) {
-        if (has_del) n_self++;
+        if (has_del) {
+          n_self++;
+          if (gidv) atomicAdd((unsigned long long*)&g_self[gidv[u]], 1ull);  // batch: per member
+        }
       } else {
         const int32_t s = ooff[u], e = ooff[u + 1];
         const int32_t p = lower_bound_i32(oidx, s, e, v);
@@ -453,6 +518,23 @@ static int alloc_rank_scratch(dfpr_graph* g) {
   g->scan_tmp_n = scan_tmp_elems((int64_t)n + 1);
   DFPR_TRY(dalloc(&g->scan_tmp, g->scan_tmp_n));
   DFPR_HIP(hipHostMalloc((void**)&g->ctl_host, sizeof(IterCtl), hipHostMallocDefault));
+  const size_t G = (size_t)g->ngraphs;
+  DFPR_TRY(dalloc(&g->nk, G));
+  DFPR_TRY(dalloc(&g->done, G));
+  g->gsub = G == 1 ? kSlots : kGSub;
+  DFPR_TRY(dalloc(&g->gslots, G * g->gsub * kSlotStride));
+  DFPR_TRY(dalloc(&g->g_dr, G));
+  DFPR_TRY(dalloc(&g->g_iters, G));
+  DFPR_TRY(dalloc(&g->g_ever, G));
+  DFPR_TRY(dalloc(&g->g_eff, 4 * G));  // ins/del pairs, edges after, ignored self-loop deletions
+  DFPR_HIP(hipHostMalloc(&g->g_host, G * (8 + 4 + 8 + 16 + 1) + 64, hipHostMallocDefault));
+  DFPR_HIP(hipMemset(g->gslots, 0, G * g->gsub * kSlotStride * sizeof(unsigned long long)));
+  DFPR_HIP(hipMemset(g->done, 0, G));
+  {
+    std::vector<int32_t> nkh(G);
+    for (size_t k = 0; k < G; k++) nkh[k] = (int32_t)(g->vbase[k + 1] - g->vbase[k]);
+    DFPR_HIP(hipMemcpy(g->nk, nkh.data(), G * sizeof(int32_t), hipMemcpyHostToDevice));
+  }
   DFPR_HIP(hipMemset(g->flag_cur, 0, n));
   DFPR_HIP(hipMemset(g->flag_next, 0, n));
   DFPR_HIP(hipMemset(g->xflag, 0, n));
@@ -515,6 +597,17 @@ int graph_destroy(dfpr_graph* g) {
   dfree(g->rint);
   if (g->ctl_host) (void)hipHostFree(g->ctl_host);
   g->ctl_host = nullptr;
+  dfree(g->gidv);
+  dfree(g->vbase_d);
+  dfree(g->nk);
+  dfree(g->done);
+  dfree(g->gslots);
+  dfree(g->g_dr);
+  dfree(g->g_iters);
+  dfree(g->g_ever);
+  dfree(g->g_eff);
+  if (g->g_host) (void)hipHostFree(g->g_host);
+  g->g_host = nullptr;
   g->keys_a.release();
   g->keys_b.release();
   g->keys_c.release();
@@ -554,7 +647,8 @@ static int build_csr_from_keys(uint64_t** ka, uint64_t** kb, int64_t m, int b, i
 }
 
 int graph_create(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, dfpr_where where,
-                 int64_t edge_capacity, int32_t flags, hipStream_t s, dfpr_graph** out) {
+                 int64_t edge_capacity, int32_t flags, hipStream_t s, dfpr_graph** out,
+                 const std::vector<int64_t>* members) {
   *out = nullptr;
   const int64_t total = m + n;
   if (total > INT32_MAX) {
@@ -569,7 +663,20 @@ int graph_create(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, d
   DFPR_HIP(hipGetDevice(&g->device));
   g->n = n;
   g->id_bits = bits_for(n);
+  if (members) {
+    g->vbase = *members;
+    g->ngraphs = (int32_t)members->size() - 1;
+  } else {
+    g->vbase = {0, (int64_t)n};
+    g->ngraphs = 1;
+  }
   const int b = g->id_bits;
+  const int gbits = g->ngraphs > 1 ? bits_for(g->ngraphs) : 0;
+  if (gbits + 24 + b > 64) {
+    delete g;
+    set_error("too many member graphs for the sort key");
+    return DFPR_EINVAL;
+  }
   const bool relabel = (flags & DFPR_CREATE_KEEP_IDS) == 0;
   int rc = DFPR_OK;
   {
@@ -613,10 +720,17 @@ int graph_create(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, d
       set_error("vertex id outside [0, %d)", n);
       return fail(DFPR_ERANGE);
     }
+    if (g->ngraphs > 1) {
+      if ((rc = dalloc(&g->gidv, n)) || (rc = dalloc(&g->vbase_d, g->vbase.size()))) return fail(rc);
+      if (hipMemcpy(g->vbase_d, g->vbase.data(), g->vbase.size() * sizeof(int64_t), hipMemcpyHostToDevice) !=
+          hipSuccess)
+        return fail(DFPR_EHIP);
+      k_member_ids<<<grid_for(n, 256, 65536), 256, 0, s>>>(g->vbase_d, g->ngraphs, n, g->gidv);
+    }
     if (relabel) {
-      // order vertices by decreasing degree: sort (2^31-1-deg, id) keys
-      k_degree_keys<<<grid_for(n, 256, 65536), 256, 0, s>>>(deg, n, b, t.ka);
-      if ((rc = radix_sort(&t.ka, &t.kb, n, 31 + b, t.hist, t.tmp, s))) return fail(rc);
+      // order vertices by member, then decreasing degree (ties by id)
+      k_degree_keys<<<grid_for(n, 256, 65536), 256, 0, s>>>(deg, g->gidv, n, b, t.ka);
+      if ((rc = radix_sort(&t.ka, &t.kb, n, gbits + 24 + b, t.hist, t.tmp, s))) return fail(rc);
       k_perm_from_sorted<<<grid_for(n, 256, 65536), 256, 0, s>>>(t.ka, n, b, g->perm, g->inv);
     }
     k_make_graph_keys<<<grid_for(total, 256, 65536), 256, 0, s>>>(dsrc, ddst, m, n, b, g->perm, t.ka);
@@ -806,14 +920,20 @@ int graph_apply(dfpr_graph* g, int64_t nd, const int32_t* del_src, const int32_t
   DFPR_TRY(ep.start(&tok));
   DFPR_TRY(radix_sort(&ka, &kb, nk, 2 * b + 1, hist, tmp, s));
   DFPR_TRY(ep.stop(kTSort, tok));
+  int64_t* g_self = g->ngraphs > 1 ? g->g_eff + 3 * (size_t)g->ngraphs : nullptr;
+  if (g_self) DFPR_HIP(hipMemsetAsync(g_self, 0, (size_t)g->ngraphs * sizeof(int64_t), s));
   k_classify<<<grid_for(nk, 256, 65536), 256, 0, s>>>(ka, nk, b, g->out.off, g->out.idx, keep, g->delta_out,
                                                        g->delta_in, g->touched_out, g->touched_in, g->pend_src,
-                                                       g->flag_cur, counters);
+                                                       g->flag_cur, counters, g->gidv, g_self);
   DFPR_HIP(hipGetLastError());
   // effective entries, sorted by (u, v): count lands in counters[3]
   DFPR_TRY(compact_keys(ka, keep, kb, nk, counters + 3, pre_out, tmp, s));
   uint64_t* eff_out = kb;
   const int64_t* cnt = counters + 3;
+  if (g->ngraphs > 1) {
+    DFPR_HIP(hipMemsetAsync(g->g_eff, 0, 2 * (size_t)g->ngraphs * sizeof(int64_t), s));
+    k_member_eff<<<grid_for(nk, 256, 4096), 256, 0, s>>>(eff_out, cnt, b, g->gidv, g->g_eff);
+  }
   DFPR_TRY(scan_generic(LoadIsDel{eff_out, cnt}, StoreI64b{pre_out}, nk, tmp, s));
 
   // ---- out-CSR
@@ -868,6 +988,152 @@ int graph_apply(dfpr_graph* g, int64_t nd, const int32_t* del_src, const int32_t
       info->ms_sort = ms[kTSort];
       info->ms_rebuild[0] = ms[kTRebuildOut];
       info->ms_rebuild[1] = ms[kTRebuildIn];
+    }
+  }
+  return DFPR_OK;
+}
+
+}  // namespace dfpr
+
+namespace dfpr {
+
+// ---- batches of graphs: one disjoint union, member ids local to each member
+int batch_create(int32_t count, const int32_t* n, const int64_t* m, const int32_t* const* src,
+                 const int32_t* const* dst, dfpr_where where, int32_t flags, hipStream_t s, dfpr_graph** out) {
+  std::vector<int64_t> vb(count + 1, 0);
+  int64_t mt = 0;
+  for (int32_t k = 0; k < count; k++) {
+    vb[k + 1] = vb[k] + n[k];
+    mt += m[k];
+  }
+  if (vb[count] > INT32_MAX || mt + vb[count] > INT32_MAX) {
+    set_error("batch too large for int32 ids and offsets");
+    return DFPR_EINVAL;
+  }
+  int32_t* coo = nullptr;
+  int64_t* err = nullptr;
+  int rc;
+  if ((rc = dalloc(&coo, (size_t)(2 * mt))) || (rc = dalloc(&err, 1))) {
+    dfree(coo);
+    return rc;
+  }
+  DFPR_HIP(hipMemsetAsync(err, 0, sizeof(int64_t), s));
+  // member arrays -> union arrays (device), ids shifted by the member base
+  int32_t* tmp = nullptr;
+  int64_t off = 0;
+  for (int32_t k = 0; k < count && rc == DFPR_OK; k++) {
+    if (m[k] == 0) continue;
+    const int32_t *ps = src[k], *pd = dst[k];
+    if (where == DFPR_HOST) {
+      dfree(tmp);
+      if ((rc = dalloc(&tmp, (size_t)(2 * m[k])))) break;
+      if (hipMemcpyAsync(tmp, src[k], m[k] * sizeof(int32_t), hipMemcpyHostToDevice, s) != hipSuccess ||
+          hipMemcpyAsync(tmp + m[k], dst[k], m[k] * sizeof(int32_t), hipMemcpyHostToDevice, s) != hipSuccess) {
+        rc = DFPR_EHIP;
+        break;
+      }
+      ps = tmp;
+      pd = tmp + m[k];
+    }
+    k_offset_ids<<<grid_for(m[k], 256, 65536), 256, 0, s>>>(ps, pd, m[k], n[k], vb[k], coo + off, coo + mt + off, err);
+    if (where == DFPR_HOST && hipStreamSynchronize(s) != hipSuccess) rc = DFPR_EHIP;
+    off += m[k];
+  }
+  int64_t herr = 0;
+  if (rc == DFPR_OK && (hipMemcpyAsync(&herr, err, sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                        hipStreamSynchronize(s) != hipSuccess))
+    rc = DFPR_EHIP;
+  dfree(tmp);
+  dfree(err);
+  if (rc == DFPR_OK && herr) {
+    set_error("vertex id outside its member graph");
+    rc = DFPR_ERANGE;
+  }
+  if (rc == DFPR_OK)
+    rc = graph_create((int32_t)vb[count], mt, coo, coo + mt, DFPR_DEVICE, 0, flags, s, out, &vb);
+  dfree(coo);
+  return rc;
+}
+
+int batch_apply(dfpr_graph* g, const int64_t* n_del, const int32_t* const* del_src, const int32_t* const* del_dst,
+                const int64_t* n_ins, const int32_t* const* ins_src, const int32_t* const* ins_dst, dfpr_where where,
+                hipStream_t s, dfpr_batch_info* info) {
+  const int32_t G = g->ngraphs;
+  int64_t nd = 0, ni = 0;
+  for (int32_t k = 0; k < G; k++) {
+    nd += n_del[k];
+    ni += n_ins[k];
+  }
+  const int64_t nk = nd + ni;
+  DFPR_TRY(g->batch_in.ensure((size_t)(2 * nk + 2) * sizeof(int32_t) + 16));
+  int32_t* bi = g->batch_in.as<int32_t>();
+  int32_t *ds = bi, *dd = bi + nd, *is = bi + 2 * nd, *id = bi + 2 * nd + ni;
+  int64_t* err = reinterpret_cast<int64_t*>(bi + 2 * nk + ((2 * nk) & 1));
+  DFPR_HIP(hipMemsetAsync(err, 0, sizeof(int64_t), s));
+  DevBuf stage;
+  int64_t od = 0, oi = 0;
+  for (int32_t k = 0; k < G; k++) {
+    const int32_t nmem = (int32_t)(g->vbase[k + 1] - g->vbase[k]);
+    for (int pass = 0; pass < 2; pass++) {
+      const int64_t c = pass ? n_ins[k] : n_del[k];
+      if (c == 0) continue;
+      const int32_t* a = pass ? ins_src[k] : del_src[k];
+      const int32_t* b = pass ? ins_dst[k] : del_dst[k];
+      if (where == DFPR_HOST) {
+        DFPR_TRY(stage.ensure((size_t)(2 * c) * sizeof(int32_t)));
+        int32_t* st = stage.as<int32_t>();
+        DFPR_HIP(hipMemcpyAsync(st, a, c * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        DFPR_HIP(hipMemcpyAsync(st + c, b, c * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        a = st;
+        b = st + c;
+      }
+      int32_t* oa = pass ? is + oi : ds + od;
+      int32_t* ob = pass ? id + oi : dd + od;
+      k_offset_ids<<<grid_for(c, 256, 65536), 256, 0, s>>>(a, b, c, nmem, g->vbase[k], oa, ob, err);
+      DFPR_HIP(hipGetLastError());
+      if (where == DFPR_HOST) DFPR_HIP(hipStreamSynchronize(s));
+      if (pass) oi += c; else od += c;
+    }
+  }
+  int64_t herr = 0;
+  DFPR_HIP(hipMemcpyAsync(&herr, err, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  DFPR_HIP(hipStreamSynchronize(s));
+  stage.release();
+  if (herr) {
+    set_error("vertex id outside its member graph in batch");
+    return DFPR_ERANGE;
+  }
+  // the union ids live in batch_in; graph_apply reads DEVICE input in place
+  // (and returns early on an empty batch: clear the per-member counts here)
+  if (G > 1) DFPR_HIP(hipMemsetAsync(g->g_eff, 0, 4 * (size_t)G * sizeof(int64_t), s));
+  dfpr_batch_info total{};
+  DFPR_TRY(graph_apply(g, nd, ds, dd, ni, is, id, DFPR_DEVICE, s, &total));
+  if (info) {
+    // per member: effective counts (set by the apply), edges after, ignored self-loop deletions
+    std::vector<int64_t> eff(4 * (size_t)G, 0);
+    if (G > 1) {
+      k_member_m<<<grid_for(G, 256, 64), 256, 0, s>>>(g->out.off, g->vbase_d, G, g->g_eff + 2 * (size_t)G);
+      DFPR_HIP(hipGetLastError());
+      DFPR_HIP(hipMemcpyAsync(eff.data(), g->g_eff, eff.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+      DFPR_HIP(hipStreamSynchronize(s));
+    } else {
+      eff[0] = total.ins_effective;
+      eff[1] = total.del_effective;
+      eff[2] = total.m_after;
+      eff[3] = total.self_loop_dels_ignored;
+    }
+    for (int32_t k = 0; k < G; k++) {
+      info[k] = dfpr_batch_info{};
+      info[k].ins_in = n_ins[k];
+      info[k].del_in = n_del[k];
+      info[k].ins_effective = eff[2 * k];
+      info[k].del_effective = eff[2 * k + 1];
+      info[k].m_after = eff[2 * (size_t)G + k];
+      info[k].self_loop_dels_ignored = eff[3 * (size_t)G + k];
+      info[k].ms_total = total.ms_total;  // timings are of the whole batch
+      info[k].ms_sort = total.ms_sort;
+      info[k].ms_rebuild[0] = total.ms_rebuild[0];
+      info[k].ms_rebuild[1] = total.ms_rebuild[1];
     }
   }
   return DFPR_OK;

@@ -42,7 +42,11 @@ struct PullArgs {
   uint8_t* x_out;
   uint8_t* ever;
   int use_x;
-  unsigned long long* dR_slots;
+  unsigned long long* gslots;  // spread L-inf slots: member g, sub j at (g * gsub + j) * kSlotStride
+  int gsub;
+  const int32_t* gid;          // member of each vertex (null: plain graph)
+  const int32_t* nk;           // vertex count of each member
+  const uint8_t* done;         // member already converged (null: none)
   unsigned long long* acc;   // spread accumulator rows (dense counts)
   double* partial;           // bin 5: per-chunk partial sums
   int32_t* partial_x;        // bin 5: per-chunk "an in-neighbour expanded" (dense)
@@ -65,12 +69,13 @@ struct Bounds {
 // R[v]/|out(v)| is taken from R[v] instead of gathering contrib[v]: the same
 // correctly rounded quotient.
 struct VCtx {
-  int32_t v, s, e;
+  int32_t v, s, e, g;
   double Rv, d, selfc;
 };
 __device__ __forceinline__ VCtx load_vertex(const PullArgs& a, int32_t v) {
   VCtx c;
   c.v = v;
+  c.g = a.gid ? a.gid[v] : 0;
   c.s = a.in_off[v];
   c.e = a.in_off[v + 1];
   c.d = (double)(a.out_off[v + 1] - a.out_off[v]);
@@ -85,11 +90,40 @@ __device__ __forceinline__ double gx(const PullArgs& a, int32_t u, const VCtx& c
   return u == c.v ? c.selfc : a.contrib[u];
 }
 
+// Per-member maxima of one workgroup, in LDS: a small open-addressing table
+// (member -> bit pattern of the max), flushed to the spread slots at the end.
+// A batch's worklist is sorted by vertex and members are vertex ranges, so a
+// workgroup meets few members; when the table is full the update goes
+// straight to the member's slot.
+constexpr int kGTab = 32;
+struct GTab {
+  int key[kGTab];
+  unsigned long long val[kGTab];
+};
+__device__ __forceinline__ void gtab_max(GTab* t, int g, double x, unsigned long long* gslots, int gsub) {
+  if (!(x > 0.0)) return;
+  const unsigned long long bits = (unsigned long long)__double_as_longlong(x);
+  for (int i = 0; i < kGTab; i++) {
+    const int sl = (g + i) & (kGTab - 1);
+    const int cur = atomicCAS(&t->key[sl], -1, g);
+    if (cur == -1 || cur == g) {
+      atomicMax(&t->val[sl], bits);
+      return;
+    }
+  }
+  atomicMax(&gslots[((size_t)g * gsub + blockIdx.x % gsub) * kSlotStride], bits);
+}
+
 // Per-thread accumulators of one pull launch.
 struct Acc {
-  double mx = 0.0;                       // L-inf change
+  double mx = 0.0;                          // L-inf change (plain graph)
   int64_t cnt = 0, aedges = 0, xedges = 0;  // dense: affected, their in-edges, expander out-edges
+  GTab* tab = nullptr;                      // per-member maxima (batch)
 };
+__device__ __forceinline__ void acc_dr(Acc& acc, const PullArgs& a, int g, double dr) {
+  if (acc.tab) gtab_max(acc.tab, g, dr, a.gslots, a.gsub); else acc.mx = fmax(acc.mx, dr);
+}
+__device__ __forceinline__ bool member_done(const PullArgs& a, int g) { return a.done && a.done[g]; }
 
 // Equation 1 (DF, Static, ND) or Equation 2 (DF-P) for the vertex from its
 // in-neighbour sum c.  Same operation order as the algorithm states it; the
@@ -97,21 +131,26 @@ struct Acc {
 // vertex is affected; unaffected vertices carry their rank over.
 template <int MODE, bool DENSE>
 __device__ __forceinline__ void vertex_finish(const PullArgs& a, const VCtx& x, double c, bool aff, Acc& acc) {
-  if (DENSE && !aff) {
-    a.Rw[x.v] = x.Rv;
-    a.cw[x.v] = x.selfc;
-    a.stay_out[x.v] = 0;
-    a.x_out[x.v] = 0;
+  if (!aff) {  // not processed (unaffected, or its member converged): carry over
+    if (DENSE || MODE == kSync) {
+      a.Rw[x.v] = x.Rv;
+      a.cw[x.v] = x.selfc;
+    }
+    if (DENSE) {
+      a.stay_out[x.v] = 0;
+      a.x_out[x.v] = 0;
+    }
     return;
   }
   const double d = x.d, Rv = x.Rv;
+  const double C0 = a.gid ? (1.0 - a.alpha) / (double)a.nk[x.g] : a.C0;  // (1-alpha)/|V| of the member
   double r;
   if (MODE == kDFP)
-    r = (1.0 / (1.0 - a.alpha / d)) * (a.C0 + a.alpha * (c - Rv / d));
+    r = (1.0 / (1.0 - a.alpha / d)) * (C0 + a.alpha * (c - Rv / d));
   else
-    r = a.C0 + a.alpha * c;
+    r = C0 + a.alpha * c;
   const double dr = fabs(r - Rv);
-  acc.mx = fmax(acc.mx, dr);
+  acc_dr(acc, a, x.g, dr);
   if (MODE == kSync) {
     a.Rw[x.v] = r;
     a.cw[x.v] = r / d;
@@ -157,6 +196,11 @@ __device__ __forceinline__ void block_acc_to_slots(Acc acc, const PullArgs& a) {
     shc[2][w] = c2;
   }
   __syncthreads();
+  if (acc.tab) {  // batch: flush the per-member maxima (all threads reached the barrier above)
+    for (int i = threadIdx.x; i < kGTab; i += blockDim.x)
+      if (acc.tab->key[i] >= 0 && acc.tab->val[i])
+        atomicMax(&a.gslots[((size_t)acc.tab->key[i] * a.gsub + blockIdx.x % a.gsub) * kSlotStride], acc.tab->val[i]);
+  }
   if (threadIdx.x == 0) {
     double mm = 0.0;
     int64_t t0 = 0, t1 = 0, t2 = 0;
@@ -167,7 +211,8 @@ __device__ __forceinline__ void block_acc_to_slots(Acc acc, const PullArgs& a) {
       t2 += shc[2][i];
     }
     const int slot = (blockIdx.x % kSlots) * kSlotStride;
-    if (mm > 0.0) atomicMax(&a.dR_slots[slot], (unsigned long long)__double_as_longlong(mm));
+    if (mm > 0.0)
+      atomicMax(&a.gslots[(blockIdx.x % a.gsub) * kSlotStride], (unsigned long long)__double_as_longlong(mm));
     if (DENSE) {
       constexpr int kRow = kSlots * kSlotStride;
       if (t0) atomicAdd(&a.acc[kAccCnt * kRow + slot], (unsigned long long)t0);
@@ -190,8 +235,8 @@ __device__ __forceinline__ void pull_groups(const PullArgs& a, const int32_t* __
   const int gl = threadIdx.x % G;
   for (int64_t k = lo + (int64_t)lb * kGroups + threadIdx.x / G; k < hi; k += (int64_t)nb * kGroups) {
     const VCtx x = load_vertex(a, wl[k]);
-    bool aff = true;
-    if (DENSE) {
+    bool aff = !member_done(a, x.g);
+    if (DENSE && aff) {
       aff = a.stay_in[x.v] != 0;
       if (!aff && a.use_x) {
         int any = 0;
@@ -294,8 +339,8 @@ __device__ __forceinline__ void pull_block(const PullArgs& a, const int32_t* __r
   __shared__ int aff_sh;
   for (int64_t k = lo + lb; k < hi; k += nb) {
     const VCtx x = load_vertex(a, wl[k]);
-    bool aff = true;
-    if (DENSE) {
+    bool aff = !member_done(a, x.g);
+    if (DENSE && aff) {
       aff = a.stay_in[x.v] != 0;
       if (!aff && a.use_x) {
         int any = 0;
@@ -347,7 +392,7 @@ __device__ __forceinline__ void pull_chunks(const PullArgs& a, const int32_t* __
       cj1 = pre[j + 1];
       x = load_vertex(a, wl[lo + j]);
     }
-    const bool want_x = DENSE && a.use_x && !a.stay_in[x.v];
+    const bool want_x = DENSE && a.use_x && !a.stay_in[x.v] && !member_done(a, x.g);
     const int32_t cs = x.s + (int32_t)((q - cj) * kPullChunk);
     const int32_t ce = min(cs + kPullChunk, x.e);
     int any = 0;
@@ -368,7 +413,7 @@ __device__ __forceinline__ void pull_chunks(const PullArgs& a, const int32_t* __
         if (DENSE) anyx |= __hip_atomic_load(&a.partial_x[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
       a.arrive[j] = 0;
-      const bool aff = !DENSE || a.stay_in[x.v] || (a.use_x && anyx);
+      const bool aff = !member_done(a, x.g) && (!DENSE || a.stay_in[x.v] || (a.use_x && anyx));
       vertex_finish<MODE, DENSE>(a, x, aff ? c : 0.0, aff, acc);
     }
     __syncthreads();
@@ -382,6 +427,15 @@ __global__ void __launch_bounds__(256) k_pull(PullArgs a, const int32_t* __restr
   while (k < kBins - 1 && b >= L.blk[k + 1]) k++;
   const int lb = b - L.blk[k], nb = L.blk[k + 1] - L.blk[k];
   Acc acc;
+  __shared__ GTab tab;
+  if (a.gid) {
+    for (int i = threadIdx.x; i < kGTab; i += blockDim.x) {
+      tab.key[i] = -1;
+      tab.val[i] = 0ull;
+    }
+    __syncthreads();
+    acc.tab = &tab;
+  }
   switch (k) {
     case 0: pull_groups<MODE, 1, DENSE>(a, wl, L.lo[0], L.hi[0], lb, nb, acc); break;
     case 1: pull_groups<MODE, 4, DENSE>(a, wl, L.lo[1], L.hi[1], lb, nb, acc); break;
@@ -547,27 +601,40 @@ __device__ __forceinline__ int bin_of(int32_t d, const Bounds& B) {
   return d <= B.b[0] ? 0 : d <= B.b[1] ? 1 : d <= B.b[2] ? 2 : d <= B.b[3] ? 3 : d <= B.b[4] ? 4 : 5;
 }
 
-// Flags of vertices base..base+7 as a bit mask.
-__device__ __forceinline__ unsigned tile_flags(const uint8_t* flags, int64_t base, int32_t n) {
+// Flags of vertices base..base+7 as a bit mask; in a batch, vertices of
+// members that have converged drop out.
+struct MemberMask {
+  const int32_t* gid;   // null: plain graph
+  const uint8_t* done;
+};
+__device__ __forceinline__ unsigned tile_flags(const uint8_t* flags, int64_t base, int32_t n, MemberMask mm) {
   unsigned m = 0;
   if (base + kBinItems <= n) {
-    if (flags == nullptr) return 0xFFu;
-    const uint64_t w = *reinterpret_cast<const uint64_t*>(flags + base);
+    if (flags == nullptr) {
+      m = 0xFFu;
+    } else {
+      const uint64_t w = *reinterpret_cast<const uint64_t*>(flags + base);
 #pragma unroll
-    for (int j = 0; j < kBinItems; j++) m |= ((w >> (8 * j)) & 0xFFull) ? (1u << j) : 0u;
-    return m;
+      for (int j = 0; j < kBinItems; j++) m |= ((w >> (8 * j)) & 0xFFull) ? (1u << j) : 0u;
+    }
+  } else {
+    for (int j = 0; j < kBinItems; j++)
+      if (base + j < n && (flags == nullptr || flags[base + j])) m |= 1u << j;
   }
-  for (int j = 0; j < kBinItems; j++)
-    if (base + j < n && (flags == nullptr || flags[base + j])) m |= 1u << j;
+  if (mm.gid && m) {
+    for (int j = 0; j < kBinItems; j++)
+      if ((m & (1u << j)) && mm.done[mm.gid[base + j]]) m &= ~(1u << j);
+  }
   return m;
 }
 
 __global__ void __launch_bounds__(256) k_bin_count(const uint8_t* flags, const int32_t* __restrict__ in_off, int32_t n,
-                                                   Bounds B, int64_t* blk, int64_t nb, unsigned long long* acc) {
+                                                   MemberMask mm, Bounds B, int64_t* blk, int64_t nb,
+                                                   unsigned long long* acc) {
   __shared__ int64_t sh[256 / kWave + 1];
   __shared__ int64_t she[256 / kWave][kBins];
   const int64_t base = (int64_t)blockIdx.x * kBinTile + (int64_t)threadIdx.x * kBinItems;
-  const unsigned m = tile_flags(flags, base, n);
+  const unsigned m = tile_flags(flags, base, n, mm);
   int64_t p0 = 0, p1 = 0;
   int64_t ed[kBins] = {0, 0, 0, 0, 0, 0};
   if (m) {
@@ -608,11 +675,11 @@ __global__ void __launch_bounds__(256) k_bin_count(const uint8_t* flags, const i
 }
 
 __global__ void __launch_bounds__(256) k_bin_scatter(const uint8_t* flags, const int32_t* __restrict__ in_off,
-                                                     int32_t n, Bounds B, const int64_t* offs, int64_t nb, int32_t* wl,
-                                                     uint8_t* ever, int64_t* bin_end) {
+                                                     int32_t n, MemberMask mm, Bounds B, const int64_t* offs, int64_t nb,
+                                                     int32_t* wl, uint8_t* ever, int64_t* bin_end) {
   __shared__ int64_t sh[256 / kWave + 1];
   const int64_t base = (int64_t)blockIdx.x * kBinTile + (int64_t)threadIdx.x * kBinItems;
-  const unsigned m = tile_flags(flags, base, n);
+  const unsigned m = tile_flags(flags, base, n, mm);
   uint8_t bins[kBinItems];
   int64_t p0 = 0, p1 = 0;
 #pragma unroll
@@ -658,17 +725,74 @@ __global__ void __launch_bounds__(256) k_bin_scatter(const uint8_t* flags, const
 }
 
 // ---- control block
-// Fold the spread slots into the compact head and clear them; also clears the
-// long-row list count for the next marking pass.
+// Per-member convergence after a pull: fold each member's spread slots (and
+// clear them), record its change and iteration count, and retire it once the
+// change is within tolerance (Algorithm 1's stopping rule, applied to every
+// member graph on its own).  head.dR = largest change among the members still
+// running, head.active = members not yet converged.  One workgroup; a wave
+// per member, a lane per slot.
+__global__ void __launch_bounds__(256) k_dr_finish(unsigned long long* gslots, int gsub, int32_t G, uint8_t* done,
+                                                   double* g_dr, int32_t* g_iters, int32_t it, double tol,
+                                                   IterCtl* c) {
+  __shared__ unsigned long long shm[256 / kWave];
+  __shared__ int64_t sha[256 / kWave];
+  const int w = threadIdx.x / kWave, lane = lane_id();
+  unsigned long long mx = 0ull;
+  int64_t active = 0;
+  for (int32_t g = w; g < G; g += 256 / kWave) {
+    unsigned long long m = 0ull;
+    if (lane < gsub) {
+      unsigned long long* sl = &gslots[((size_t)g * gsub + lane) * kSlotStride];
+      m = *sl;
+      *sl = 0ull;
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      const unsigned long long y = __shfl_xor(m, o, kWave);
+      m = y > m ? y : m;
+    }
+    if (lane == 0 && !done[g]) {
+      double d;
+      __builtin_memcpy(&d, &m, sizeof d);
+      g_dr[g] = d;
+      g_iters[g] = it + 1;
+      if (d <= tol) done[g] = 1; else active++;
+      mx = m > mx ? m : mx;
+    }
+  }
+  if (lane == 0) {
+    shm[w] = mx;
+    sha[w] = active;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < 256 / kWave; i++) {
+      mx = shm[i] > mx ? shm[i] : mx;
+      active += sha[i];
+    }
+    c->dR = mx;
+    c->active = active;
+  }
+}
+
+// Reset of the per-member state at the start of an update.
+__global__ void k_member_reset(int32_t G, int gsub, unsigned long long* gslots, uint8_t* done, double* g_dr,
+                               int32_t* g_iters, int64_t* g_ever) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < (int64_t)G * gsub; i += stride)
+    gslots[i * kSlotStride] = 0ull;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < G; i += stride) {
+    done[i] = 0;
+    g_dr[i] = 0.0;
+    g_iters[i] = 0;
+    g_ever[i] = 0;
+  }
+}
+
+// Fold the spread accumulator rows into the compact head and clear them; also
+// clears the long-row list count for the next marking pass.
 __global__ void __launch_bounds__(kSlots) k_iter_finish(IterCtl* c) {
   const int t = threadIdx.x;
-  unsigned long long m = c->dR_slots[t * kSlotStride];
-  c->dR_slots[t * kSlotStride] = 0ull;
-#pragma unroll
-  for (int o = kSlots / 2; o >= 1; o >>= 1) {
-    const unsigned long long y = __shfl_xor(m, o, kSlots);
-    m = y > m ? y : m;
-  }
   int64_t r[kAccRows];
 #pragma unroll
   for (int a = 0; a < kAccRows; a++) {
@@ -677,7 +801,6 @@ __global__ void __launch_bounds__(kSlots) k_iter_finish(IterCtl* c) {
     r[a] = wave_sum_i64(r[a]);
   }
   if (t == 0) {
-    c->dR = m;
     for (int b = 0; b < kBins; b++) c->bin_edges[b] = r[kAccEdges0 + b];
     c->ever_count = r[kAccEver];
     c->dense_cnt = r[kAccCnt];
@@ -696,9 +819,11 @@ __global__ void k_reset_ctl(IterCtl* c) {
 }
 
 // ---- small helpers
-__global__ void k_init_static(double* R, double* contrib, const int32_t* __restrict__ out_off, int32_t n) {
+// Uniform start 1/|V| (of the vertex's member graph in a batch).
+__global__ void k_init_static(double* R, double* contrib, const int32_t* __restrict__ out_off, int32_t n,
+                              const int32_t* gid, const int32_t* nk) {
   for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
-    const double r = 1.0 / (double)n;
+    const double r = 1.0 / (double)(gid ? nk[gid[v]] : n);
     R[v] = r;
     contrib[v] = r / (double)(out_off[v + 1] - out_off[v]);
   }
@@ -737,6 +862,31 @@ __global__ void __launch_bounds__(256) k_count_clear_ever(uint8_t* ever, int32_t
     atomicAdd(&acc[kAccEver * (kSlots * kSlotStride) + ((blockIdx.x * 4 + threadIdx.x / kWave) % kSlots) * kSlotStride],
               (unsigned long long)c);
 }
+// Batch: count (and clear) the processed vertices of each member.  A thread
+// walks 64 consecutive vertices (members are vertex ranges) and issues one
+// atomic per member run.
+__global__ void __launch_bounds__(256) k_count_ever_members(uint8_t* ever, int32_t n, const int32_t* __restrict__ gid,
+                                                            int64_t* g_ever) {
+  constexpr int64_t kRun = 64;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t * kRun < n; t += stride) {
+    const int64_t lo = t * kRun, hi = min(lo + kRun, (int64_t)n);
+    int32_t cg = -1;
+    int64_t c = 0;
+    for (int64_t v = lo; v < hi; v++) {
+      if (!ever[v]) continue;
+      ever[v] = 0;
+      const int32_t gv = gid[v];
+      if (gv != cg) {
+        if (c) atomicAdd((unsigned long long*)&g_ever[cg], (unsigned long long)c);
+        cg = gv;
+        c = 0;
+      }
+      c++;
+    }
+    if (c) atomicAdd((unsigned long long*)&g_ever[cg], (unsigned long long)c);
+  }
+}
 __global__ void k_fill_u8(uint8_t* p, int64_t n, uint8_t v) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
 }
@@ -759,12 +909,22 @@ static int bin_vertices(dfpr_graph* g, const uint8_t* flags, int32_t* wl, uint8_
   size_t tok;
   DFPR_TRY(g->pool.start(&tok));
   const int64_t nb = ((int64_t)n + kBinTile - 1) / kBinTile;
-  k_bin_count<<<(unsigned)nb, 256, 0, s>>>(flags, g->in.off, n, bounds_of(g), g->bin_blk, nb, &g->ctl->acc_slots[0][0]);
+  // the cached all-vertex bins (flags == null) never drop converged members
+  const MemberMask mm{flags ? g->gidv : nullptr, flags ? g->done : nullptr};
+  k_bin_count<<<(unsigned)nb, 256, 0, s>>>(flags, g->in.off, n, mm, bounds_of(g), g->bin_blk, nb,
+                                           &g->ctl->acc_slots[0][0]);
   DFPR_TRY(scan_i64(g->bin_blk, g->bin_blk, kBins * nb, g->scan_tmp, s));
-  k_bin_scatter<<<(unsigned)nb, 256, 0, s>>>(flags, g->in.off, n, bounds_of(g), g->bin_blk, nb, wl, ever,
+  k_bin_scatter<<<(unsigned)nb, 256, 0, s>>>(flags, g->in.off, n, mm, bounds_of(g), g->bin_blk, nb, wl, ever,
                                              g->ctl->bin_end);
   DFPR_HIP(hipGetLastError());
   DFPR_TRY(g->pool.stop(kTBin, tok));
+  return DFPR_OK;
+}
+
+// Per-member convergence of iteration `it` (sets head.dR and head.active).
+static int dr_finish(dfpr_graph* g, const dfpr_params& p, int it, hipStream_t s) {
+  k_dr_finish<<<1, 256, 0, s>>>(g->gslots, g->gsub, g->ngraphs, g->done, g->g_dr, g->g_iters, it, p.tol, g->ctl);
+  DFPR_HIP(hipGetLastError());
   return DFPR_OK;
 }
 
@@ -851,7 +1011,11 @@ static PullArgs make_args(dfpr_graph* g, const dfpr_params& p) {
   a.in_off = g->in.off;
   a.in_idx = g->in.idx;
   a.out_off = g->out.off;
-  a.dR_slots = g->ctl->dR_slots;
+  a.gslots = g->gslots;
+  a.gsub = g->gsub;
+  a.gid = g->gidv;
+  a.nk = g->nk;
+  a.done = g->ngraphs > 1 ? g->done : nullptr;
   a.acc = &g->ctl->acc_slots[0][0];
   a.partial = g->partial;
   a.partial_x = g->partial_x;
@@ -863,22 +1027,17 @@ static PullArgs make_args(dfpr_graph* g, const dfpr_params& p) {
   return a;
 }
 
+static int ensure_all_bins(dfpr_graph* g, hipStream_t s);
+
 static int run_sync(dfpr_graph* g, bool cold, const dfpr_params& p, const double* r_prev, double* r_out,
                     hipStream_t s, dfpr_stats* st) {
   const int32_t n = g->n;
   k_reset_ctl<<<64, 256, 0, s>>>(g->ctl);
-  if (!g->all_bins_valid) {
-    DFPR_TRY(bin_vertices(g, nullptr, g->all_bins, nullptr, s));
-    DFPR_TRY(finish_and_read(g, s));
-    std::copy(g->ctl_host->bin_end, g->ctl_host->bin_end + kBins, g->all_bin_end);
-    std::copy(g->ctl_host->bin_edges, g->ctl_host->bin_edges + kBins, g->all_bin_edges);
-    g->all_bins_valid = true;
-    g->all_chunks_valid = false;
-  }
+  DFPR_TRY(ensure_all_bins(g, s));
   const unsigned gi = grid_for(n, 256, 2048);
   double* R0 = g->perm ? g->rint : r_out;  // ranks in internal order
   if (cold)
-    k_init_static<<<gi, 256, 0, s>>>(R0, g->contrib, g->out.off, n);
+    k_init_static<<<gi, 256, 0, s>>>(R0, g->contrib, g->out.off, n, g->gidv, g->nk);
   else if (g->perm)
     k_gather_ranks<<<gi, 256, 0, s>>>(r_prev, g->inv, R0, g->contrib, g->out.off, n);
   else
@@ -897,6 +1056,7 @@ static int run_sync(dfpr_graph* g, bool cold, const dfpr_params& p, const double
     DFPR_TRY(pull_all<kSync>(g, a, g->all_bins, g->all_bin_end, g->all_bin_edges, g->all_chunk_pre,
                              g->all_chunks_valid, s, st));
     g->all_chunks_valid = true;
+    DFPR_TRY(dr_finish(g, p, it, s));
     DFPR_TRY(finish_and_read(g, s));
     dR = bits_to_double(g->ctl_host->dR);
     st->vertex_updates += n;
@@ -905,7 +1065,7 @@ static int run_sync(dfpr_graph* g, bool cold, const dfpr_params& p, const double
     add_bins(st, g->all_bin_end, g->all_bin_edges);
     std::swap(Ra, Rb);
     std::swap(ca, cb);
-    if (dR <= p.tol) {
+    if (g->ctl_host->active == 0) {
       conv = true;
       it++;
       break;
@@ -926,6 +1086,18 @@ static int run_sync(dfpr_graph* g, bool cold, const dfpr_params& p, const double
   st->converged = conv ? 1 : 0;
   st->last_delta = dR;
   st->ever_affected = n;
+  return DFPR_OK;
+}
+
+// dense pull over all vertices needs the cached all-vertex bins
+static int ensure_all_bins(dfpr_graph* g, hipStream_t s) {
+  if (g->all_bins_valid) return DFPR_OK;
+  DFPR_TRY(bin_vertices(g, nullptr, g->all_bins, nullptr, s));
+  DFPR_TRY(finish_and_read(g, s));
+  std::copy(g->ctl_host->bin_end, g->ctl_host->bin_end + kBins, g->all_bin_end);
+  std::copy(g->ctl_host->bin_edges, g->ctl_host->bin_edges + kBins, g->all_bin_edges);
+  g->all_bins_valid = true;
+  g->all_chunks_valid = false;
   return DFPR_OK;
 }
 
@@ -985,14 +1157,7 @@ static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_pre
       use_x = false;
     }
     if (dense) {
-      if (!g->all_bins_valid) {
-        DFPR_TRY(bin_vertices(g, nullptr, g->all_bins, nullptr, s));
-        DFPR_TRY(finish_and_read(g, s));
-        std::copy(g->ctl_host->bin_end, g->ctl_host->bin_end + kBins, g->all_bin_end);
-        std::copy(g->ctl_host->bin_edges, g->ctl_host->bin_edges + kBins, g->all_bin_edges);
-        g->all_bins_valid = true;
-        g->all_chunks_valid = false;
-      }
+      DFPR_TRY(ensure_all_bins(g, s));
       a.contrib = ca;
       a.R = Ra;
       a.Rw = Rb;
@@ -1006,6 +1171,7 @@ static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_pre
       DFPR_TRY((pull_all<MODE, true>(g, a, g->all_bins, g->all_bin_end, g->all_bin_edges, g->all_chunk_pre,
                                      g->all_chunks_valid, s, st)));
       g->all_chunks_valid = true;
+      DFPR_TRY(dr_finish(g, p, it, s));
       DFPR_TRY(finish_and_read(g, s));
       const IterCtl* h = g->ctl_host;
       dR = bits_to_double(h->dR);
@@ -1019,7 +1185,7 @@ static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_pre
       std::swap(xa, xb);     // xa = expand flags of this iteration
       use_x = true;
       front_edges = h->dense_edges;  // next frontier about as large as this one
-      if (dR <= p.tol) {
+      if (h->active == 0) {
         conv = true;
         it++;
         break;
@@ -1051,6 +1217,7 @@ static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_pre
     st->pull_bytes += 30.0 * cnt + 12.0 * (double)front_edges;
     add_bins(st, be, bedges);
     if (cnt == 0) {  // nothing affected: the L-inf change of this iteration is 0
+      DFPR_TRY(dr_finish(g, p, it, s));  // retires every member still running
       dR = 0.0;
       conv = true;
       it++;
@@ -1067,6 +1234,7 @@ static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_pre
     DFPR_HIP(hipGetLastError());
     DFPR_TRY(mark_big(g, next, s));
     DFPR_TRY(g->pool.stop(kTCommit, tok));
+    DFPR_TRY(dr_finish(g, p, it, s));  // before binning: converged members drop out
     std::swap(cur, next);
     DFPR_TRY(bin_vertices(g, cur, g->worklist, g->ever, s));
     DFPR_TRY(finish_and_read(g, s));
@@ -1074,7 +1242,7 @@ static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_pre
     front_edges = 0;
     for (int k = 0; k < kBins; k++) front_edges += g->ctl_host->bin_edges[k];
     front_cnt = g->ctl_host->bin_end[kBins - 1];
-    if (dR <= p.tol) {
+    if (g->ctl_host->active == 0) {
       conv = true;
       it++;
       break;
@@ -1084,14 +1252,19 @@ static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_pre
     k_scatter_ranks<<<gi, 256, 0, s>>>(Ra, g->inv, r_out, n);
   else if (Ra != r_out)
     DFPR_HIP(hipMemcpyAsync(r_out, Ra, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
-  // leave every flag array clear for the next batch
+  // leave every flag array clear for the next batch (converged members of a
+  // batch may leave flags in both keep arrays)
   k_fill_u8<<<gi, 256, 0, s>>>(cur, n, 0);
+  if (g->ngraphs > 1 && !st->dense_iterations) k_fill_u8<<<gi, 256, 0, s>>>(next, n, 0);
   if (st->dense_iterations) {
     k_fill_u8<<<gi, 256, 0, s>>>(next, n, 0);
     k_fill_u8<<<gi, 256, 0, s>>>(xa, n, 0);
     k_fill_u8<<<gi, 256, 0, s>>>(xb, n, 0);
   }
-  k_count_clear_ever<<<gi, 256, 0, s>>>(g->ever, n, &g->ctl->acc_slots[0][0]);
+  if (g->ngraphs > 1)
+    k_count_ever_members<<<grid_for((n + 63) / 64, 256, 2048), 256, 0, s>>>(g->ever, n, g->gidv, g->g_ever);
+  else
+    k_count_clear_ever<<<gi, 256, 0, s>>>(g->ever, n, &g->ctl->acc_slots[0][0]);
   DFPR_HIP(hipGetLastError());
   DFPR_TRY(finish_and_read(g, s));
   g->flag_cur = cur;
@@ -1105,13 +1278,34 @@ static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_pre
   return DFPR_OK;
 }
 
+// Pinned host mirror of the per-member results.
+struct MemberHost {
+  double* dr;
+  int64_t* ever;
+  int32_t* iters;
+  uint8_t* done;
+};
+static MemberHost member_host(dfpr_graph* g) {
+  const size_t G = (size_t)g->ngraphs;
+  char* b = static_cast<char*>(g->g_host);
+  MemberHost h;
+  h.dr = reinterpret_cast<double*>(b);
+  h.ever = reinterpret_cast<int64_t*>(b + 8 * G);
+  h.iters = reinterpret_cast<int32_t*>(b + 32 * G);  // g_eff's mirror sits at 16 G
+  h.done = reinterpret_cast<uint8_t*>(b + 36 * G);
+  return h;
+}
+
 int update_ranks(dfpr_graph* g, dfpr_mode mode, const dfpr_params& p, const double* r_prev, double* r_out,
-                 hipStream_t s, dfpr_stats* st_out) {
+                 hipStream_t s, dfpr_stats* st_out, dfpr_stats* per_member) {
   dfpr_stats st{};
   EventPool& ep = g->pool;
   ep.reset(g->timing || (p.flags & DFPR_FLAG_TIMING) != 0, s);
   size_t tok;
   DFPR_TRY(ep.start(&tok));
+  k_member_reset<<<grid_for((int64_t)g->ngraphs * g->gsub, 256, 64), 256, 0, s>>>(
+      g->ngraphs, g->gsub, g->gslots, g->done, g->g_dr, g->g_iters, g->g_ever);
+  DFPR_HIP(hipGetLastError());
   int rc;
   switch (mode) {
     case DFPR_STATIC: rc = run_sync(g, true, p, r_prev, r_out, s, &st); break;
@@ -1131,6 +1325,39 @@ int update_ranks(dfpr_graph* g, dfpr_mode mode, const dfpr_params& p, const doub
     st.ms_commit = ms[kTCommit];
     st.ms_bin = ms[kTBin];
     st.ms_mark = ms[kTMark];
+  }
+  if (g->ngraphs > 1) {
+    // batch: iteration counts, convergence and changes are per member; the
+    // totals report the slowest member and the sum of processed vertices
+    const size_t G = (size_t)g->ngraphs;
+    const MemberHost h = member_host(g);
+    DFPR_HIP(hipMemcpyAsync(h.dr, g->g_dr, G * sizeof(double), hipMemcpyDeviceToHost, s));
+    DFPR_HIP(hipMemcpyAsync(h.ever, g->g_ever, G * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    DFPR_HIP(hipMemcpyAsync(h.iters, g->g_iters, G * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    DFPR_HIP(hipMemcpyAsync(h.done, g->done, G, hipMemcpyDeviceToHost, s));
+    DFPR_HIP(hipStreamSynchronize(s));
+    const bool sync_mode = mode == DFPR_STATIC || mode == DFPR_ND;
+    int64_t ever = 0;
+    double worst = 0.0;
+    int32_t conv = 1;
+    for (size_t k = 0; k < G; k++) {
+      const int64_t nkk = g->vbase[k + 1] - g->vbase[k];
+      const int64_t ek = sync_mode ? nkk : h.ever[k];
+      ever += ek;
+      worst = std::max(worst, h.dr[k]);
+      conv &= h.done[k] ? 1 : 0;
+      if (per_member) {
+        dfpr_stats m{};
+        m.iterations = h.iters[k];
+        m.converged = h.done[k] ? 1 : 0;
+        m.last_delta = h.dr[k];
+        m.ever_affected = ek;
+        per_member[k] = m;
+      }
+    }
+    st.ever_affected = ever;
+    st.converged = conv;
+    st.last_delta = worst;
   }
   if (st_out) *st_out = st;
   return DFPR_OK;

@@ -52,6 +52,23 @@ def test_invalid_arguments_rejected_before_device_work(lib):
     assert lib.dfpr_set_tuning(None, (ctypes.c_int32 * 5)(4, 8, 16, 32, 64)) == _capi.DFPR_EINVAL
     assert lib.dfpr_apply_batch(None, -1, None, None, 0, None, None, 0, None, None) == _capi.DFPR_EINVAL
     assert lib.dfpr_graph_destroy(None) == _capi.DFPR_OK
+    # batched form
+    n1 = (ctypes.c_int32 * 1)(5)
+    m1 = (ctypes.c_int64 * 1)(0)
+    pp = (ctypes.c_void_p * 1)()
+    assert lib.dfpr_batch_create(0, n1, m1, pp, pp, 0, 0, None, ctypes.byref(h)) == _capi.DFPR_EINVAL
+    n0 = (ctypes.c_int32 * 1)(0)
+    assert lib.dfpr_batch_create(1, n0, m1, pp, pp, 0, 0, None, ctypes.byref(h)) == _capi.DFPR_EINVAL
+    m3 = (ctypes.c_int64 * 1)(3)
+    assert lib.dfpr_batch_create(1, n1, m3, pp, pp, 0, 0, None, ctypes.byref(h)) == _capi.DFPR_EINVAL
+    assert b"member 0" in lib.dfpr_last_error()
+    assert lib.dfpr_batch_create(1, n1, m1, pp, pp, 0, 2, None, ctypes.byref(h)) == _capi.DFPR_EINVAL
+    cnt = ctypes.c_int32()
+    assert lib.dfpr_batch_count(None, ctypes.byref(cnt)) == _capi.DFPR_EINVAL
+    b, n = ctypes.c_int32(), ctypes.c_int32()
+    assert lib.dfpr_batch_member(None, 0, ctypes.byref(b), ctypes.byref(n)) == _capi.DFPR_EINVAL
+    assert lib.dfpr_apply_batch_many(None, None, None, None, None, None, None, 0, None, None) == _capi.DFPR_EINVAL
+    assert lib.dfpr_update_ranks_many(None, 3, None, None, None, None, None, None) == _capi.DFPR_EINVAL
     assert lib.dfpr_version().startswith(b"dfpr")
 
 

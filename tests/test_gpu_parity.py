@@ -165,6 +165,8 @@ def test_all_bins(mode, bounds):
     assert np.abs(r - ref.ranks).max() <= LINF
     assert st["bin_vertices"][5] > 0 and st["bin_vertices"][3] > 0
     if mode != "static":
+        p, r0 = _setup(12, 1e-2, seed=31)  # the update consumed the batch marks: same batch again
+        p.g.set_tuning(bounds)
         r2, st2, _ = p.rank(mode, r0, dense_switch=0.0)  # dense form over the all-vertex bins
         assert np.array_equal(r, r2) and st2["dense_iterations"] == st2["iterations"]
 

@@ -9,7 +9,7 @@ Shapes follow the paper's workloads: R-MAT graphs with a self-loop added on
 every vertex downstream (Sections 5.1.3 and 5.2.2), uniform 80/20
 insert/delete batches sized as a fraction of |E| (Section 5.2.2), and a
 preferential-attachment temporal stream replayed in insertion-only batches
-standing in for the SNAP temporal graphs of Table 1 (Section 5.1.4).
+standing in for the SNAP temporal graphs of Table 1 (Sections 5.1.3-5.1.4).
 """
 from __future__ import annotations
 

@@ -33,12 +33,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "DF-P update time & edges/s vs GPU Static at L∞ err ≤1e-9; p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
-# algorithmic bytes (every gather counted): per pulled in-edge 4 B index + 8 B contribution
-EDGE_BYTES = 12
-# per processed vertex in the pull kernels: worklist 4, in-offset 4, out-offset 4,
-# R read 8, R write 8, next/expand flags 2 (DF, DF-P); Static/ND write R and contrib (36 B)
-VERTEX_BYTES_DFP = 30
-VERTEX_BYTES_SYNC = 36
+# HBM traffic of the pull kernel measured with rocprofv3 counters (FETCH_SIZE and
+# WRITE_SIZE runs, scaled by a plain-copy calibration), valid for the rank
+# engine source it was taken on; see profiles/.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pull_rmat24_dfp_traffic.txt")
 
 
 def log(*a):
@@ -87,8 +85,236 @@ def chained_batches(n, src, dst, frac, count, seed):
     return out
 
 
+def rank_source_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("rank.hip", "dfpr_impl.hpp"):
+        with open(os.path.join(ROOT, "paper_2401_15870_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_kv(path):
+    """`key: value` lines of a profile summary."""
+    out = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith(("#", " ", "|", "`")):
+                k, v = line.split(":", 1)
+                out[k.strip()] = v.strip()
+    return out
+
+
+def measured_traffic(workload_key):
+    """Counter-measured HBM bytes per pull launch, or None when the kernel source
+    changed since the counters were taken (or none were taken for this workload)."""
+    try:
+        t = read_kv(TRAFFIC_FILE)
+    except OSError:
+        return None
+    if t.get("source_sha") != rank_source_sha() or t.get("workload") != workload_key:
+        return None
+    try:
+        return float(t["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+# ---------------------------------------------------------------- profile summaries
+def _csv_rows(path):
+    import csv
+    with open(path) as fh:
+        return list(csv.DictReader(fh))
+
+
+def _short(name):
+    name = name.replace("void ", "")
+    return name.split("(")[0]
+
+
+def summarize_trace(d):
+    """Markdown table of a `rocprofv3 --kernel-trace --stats` run (directory d)."""
+    import glob
+    f = glob.glob(os.path.join(d, "*kernel_stats.csv"))[0]
+    rows = _csv_rows(f)
+    lines = ["| kernel | calls | total ms | avg us | % |", "|---|---|---|---|---|"]
+    for r in rows[:20]:
+        lines.append(f"| {_short(r['Name'])} | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.1f} | "
+                     f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['Percentage']):.1f} |")
+    return "\n".join(lines)
+
+
+def summarize_counters(fetch_dir, write_dir, kernel_prefix):
+    """Per-launch HBM bytes of the kernels whose name starts with kernel_prefix,
+    from FETCH_SIZE and WRITE_SIZE runs (KiB per dispatch), each scaled by what the
+    counter reads for the 1 GiB device copies that end a --calib run."""
+    import glob
+    out = {}
+    for key, d in (("fetch", fetch_dir), ("write", write_dir)):
+        rows = _csv_rows(glob.glob(os.path.join(d, "*counter_collection.csv"))[0])
+        copies = [r for r in rows if "copy" in r["Kernel_Name"].lower() or "elementwise" in r["Kernel_Name"].lower()]
+        copies = copies[-3:]
+        kib_copy = sum(float(r["Counter_Value"]) for r in copies) / len(copies)
+        factor = (1 << 30) / 1024 / kib_copy
+        mine = [float(r["Counter_Value"]) for r in rows if _short(r["Kernel_Name"]).startswith(kernel_prefix)]
+        out[key] = {"factor": factor, "launches": len(mine),
+                    "kib_per_launch": sum(mine) / max(len(mine), 1)}
+    fb = out["fetch"]["kib_per_launch"] * 1024 * out["fetch"]["factor"]
+    wb = out["write"]["kib_per_launch"] * 1024 * out["write"]["factor"]
+    return out, fb + wb
+
+
 def pct(a, q):
     return float(np.percentile(np.asarray(a, dtype=np.float64), q))
+
+
+def batched_members(count, seed):
+    """Member graphs of the batched configuration: vertex counts log-uniform in
+    [1e3, 1e6], edge factor uniform in [8, 32], R-MAT draws at scale
+    ceil(log2 n) with endpoints >= n redrawn, duplicates and self draws dropped."""
+    import workloads as W
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for k in range(count):
+        n = int(round(np.exp(rng.uniform(np.log(1e3), np.log(1e6)))))
+        ef = float(rng.uniform(8, 32))
+        scale = int(np.ceil(np.log2(n)))
+        fr = float(np.exp(rng.uniform(np.log(1e-4), np.log(1e-2))))
+        _, s, d = W.rmat_graph(scale, ef, seed=seed * 7919 + k, n_limit=n)
+        out.append((n, s, d, fr))
+        if (k + 1) % 64 == 0:
+            log(f"  generated {k + 1}/{count} member graphs")
+    return out
+
+
+def bench_batched(args):
+    """Batched form: every member's apply + DF-P update in one batch handle,
+    against the same updates as sequential calls on per-graph handles."""
+    import torch
+    import paper_2401_15870_amd as dfpr
+
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    mem = batched_members(args.graphs, args.seed)
+    total_steps = args.warmup + args.steps
+    chains = []
+    for k, (n, s, d, fr) in enumerate(mem):
+        chains.append(chained_batches(n, s, d, fr, total_steps, seed=args.seed * 104729 + k))
+        if (k + 1) % 128 == 0:
+            log(f"  batches for {k + 1}/{len(mem)} graphs")
+    m_draw = sum(len(s) for _, s, _, _ in mem)
+    log(f"batched: {len(mem)} graphs, {sum(n for n, _, _, _ in mem)} vertices, {m_draw} edges "
+        f"(no self-loops), gen {time.time() - t0:.1f}s")
+
+    t0 = time.time()
+    dmem = [(n, torch.from_numpy(s).to(dev), torch.from_numpy(d).to(dev)) for n, s, d, _ in mem]
+    bg = dfpr.BatchGraph.from_coo(dmem)
+    plain = [dfpr.Graph.from_coo(n, s, d) for n, s, d in dmem]
+    del dmem
+    torch.cuda.synchronize()
+    m_total = bg.m
+    log(f"create: arena m={m_total}, {len(plain)} plain handles, {time.time() - t0:.1f}s")
+    if not args.no_autotune:
+        bounds, ms = bg.autotune()
+        for g in plain:
+            g.set_tuning(bounds)
+        log(f"autotune (arena): {bounds} pull {ms:.3f} ms")
+    dev_chains = [[tuple(torch.from_numpy(a).to(dev) for a in b) for b in ch] for ch in chains]
+
+    # R0: per-member Static (cold) computed once on the arena; plain handles start
+    # from their slices of the same bits
+    r_arena, tot0, _ = bg.update_ranks_many("static", None)
+    r_plain = [bg.member(r_arena, k).clone() for k in range(len(plain))]
+    log(f"R0: static over the arena, {tot0['iterations']} iterations (slowest member)")
+
+    def step_batched(i):
+        info = bg.apply_batch_many([dev_chains[k][i] for k in range(len(plain))])
+        r, tot, per = bg.update_ranks_many(args.mode, r_arena, out=r_arena)
+        return info, tot, per
+
+    def step_plain(i):
+        its = 0
+        for k, g in enumerate(plain):
+            g.apply_batch(*dev_chains[k][i])
+            _, st = g.update_ranks(args.mode, r_plain[k], out=r_plain[k])
+            its += st["iterations"]
+        return its
+
+    tb, tp = [], []
+    worst = 0.0
+    delta_edges = 0
+    iters_b = []
+    for i in range(total_steps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        info, tot, per = step_batched(i)
+        torch.cuda.synchronize()
+        t_b = time.perf_counter() - t
+        t = time.perf_counter()
+        step_plain(i)
+        torch.cuda.synchronize()
+        t_p = time.perf_counter() - t
+        for k in range(len(plain)):
+            diff = (bg.member(r_arena, k) - r_plain[k]).abs().max().item() if plain[k].n else 0.0
+            worst = max(worst, diff)
+        if i >= args.warmup:
+            tb.append(t_b)
+            tp.append(t_p)
+            iters_b.append(tot["iterations"])
+            delta_edges += sum(x["ins_in"] + x["del_in"] for x in info)
+        log(f"step {i}: batched {t_b * 1e3:.1f} ms (max member iterations {tot['iterations']}), "
+            f"sequential {t_p * 1e3:.1f} ms, max |batched - plain| {worst:.3e}")
+    assert worst <= 1e-9, f"batched and plain results differ: {worst}"
+    K = len(tb)
+    tb_s, tp_s = sum(tb), sum(tp)
+    G = len(plain)
+    res = {
+        "metric": "batched DF-P update throughput vs sequential per-graph calls at equal accuracy",
+        "value": G * K / tb_s,
+        "unit": "graphs/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": tb_s * 1e3 / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{G} R-MAT graphs, n log-uniform in [1e3, 1e6], edge factor U[8, 32], one chained "
+                               f"80/20 batch of f*|E| per graph per step, f log-uniform in [1e-4, 1e-2]; apply + "
+                               f"{args.mode.upper()} update of every graph per step",
+                   "graphs": G, "m_total": int(m_total), "mode": args.mode, "parallelism": "1 GPU",
+                   "bin_bounds": bg.get_tuning()},
+        "graph_edges_per_s": m_total * K / tb_s,
+        "batch_edges_per_s": delta_edges / tb_s,
+        "sequential_ms_per_step": tp_s * 1e3 / K,
+        "sequential_graphs_per_s": G * K / tp_s,
+        "speedup_vs_sequential": tp_s / tb_s,
+        "max_member_iterations_mean": float(np.mean(iters_b)),
+        "max_abs_diff_vs_plain": worst,
+    }
+    print(json.dumps(res))
+
+
+def summarize_main(args):
+    """Print the profile summaries of a profiled run directory (see profiles/)."""
+    d = args.summarize
+    if os.path.isdir(os.path.join(d, "prof")):
+        print(summarize_trace(os.path.join(d, "prof")))
+    fd, wd = os.path.join(d, "pmc_FETCH_SIZE"), os.path.join(d, "pmc_WRITE_SIZE")
+    if os.path.isdir(fd) and os.path.isdir(wd):
+        c, total = summarize_counters(fd, wd, args.kernel)
+        wkey = f"rmat{args.scale}_ef{args.edge_factor:g}_{args.mode}_f{args.frac:g}"
+        print(f"workload: {wkey}")
+        print(f"kernel: {args.kernel}")
+        print(f"source_sha: {rank_source_sha()}")
+        print(f"launches: {c['fetch']['launches']}")
+        print(f"fetch_kib_per_launch: {c['fetch']['kib_per_launch']:.1f}")
+        print(f"fetch_copy_factor: {c['fetch']['factor']:.3f}")
+        print(f"write_kib_per_launch: {c['write']['kib_per_launch']:.1f}")
+        print(f"write_copy_factor: {c['write']['factor']:.3f}")
+        print(f"hbm_bytes_per_launch: {total:.0f}")
 
 
 def main():
@@ -106,7 +332,16 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--calib", action="store_true",
                     help="finish with three 1 GiB device copies (counter calibration under a profiler)")
+    ap.add_argument("--workload", default="rmat", choices=["rmat", "batched"],
+                    help="rmat: one large R-MAT graph (default); batched: many graphs in one batch handle")
+    ap.add_argument("--graphs", type=int, default=512, help="batched: number of member graphs")
+    ap.add_argument("--summarize", metavar="DIR",
+                    help="print summaries of rocprofv3 output under DIR (prof/, pmc_FETCH_SIZE/, pmc_WRITE_SIZE/)")
+    ap.add_argument("--kernel", default="dfpr::k_pull<3", help="kernel name prefix for --summarize counters")
     args = ap.parse_args()
+    if args.summarize:
+        summarize_main(args)
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design note, "
@@ -120,6 +355,9 @@ def main():
     assert torch.cuda.is_available(), "bench needs a GPU"
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
+    if args.workload == "batched":
+        bench_batched(args)
+        return
 
     t0 = time.time()
     n, src, dst = W.rmat_graph(args.scale, args.edge_factor, seed=args.seed)
@@ -179,7 +417,7 @@ def main():
     step_ms, apply_ms, rank_ms, iters, ever = [], [], [], [], []
     kern = {"pull": 0.0, "commit": 0.0, "bin": 0.0, "mark": 0.0, "sort": 0.0, "rebuild_out": 0.0,
             "rebuild_in": 0.0}
-    pull_launches, v_upd, e_pull = 0, 0, 0
+    pull_launches, v_upd, e_pull, pull_bytes = 0, 0, 0, 0.0
     m_sum = 0
     total = args.warmup + args.steps
     torch.cuda.synchronize()
@@ -209,6 +447,7 @@ def main():
             pull_launches += st["pull_launches"]
             v_upd += st["vertex_updates"]
             e_pull += st["edges_pulled"]
+            pull_bytes += st["pull_bytes"]
             kern["commit"] += st["ms_commit"]
             kern["bin"] += st["ms_bin"]
             kern["mark"] += st["ms_mark"]
@@ -225,9 +464,8 @@ def main():
     m_mean = m_sum / K
     value = m_mean * K / elapsed
 
-    # ---- roofline of the dominant kernel (largest summed time)
-    vb = VERTEX_BYTES_DFP if args.mode in ("df", "dfp") else VERTEX_BYTES_SYNC
-    pull_bytes = v_upd * vb + e_pull * EDGE_BYTES
+    # ---- roofline of the dominant kernel (largest summed time).  Pull bytes are
+    # the library's per-launch algorithmic count (every gather counted).
     # rebuild: 4 B read + 4 B write per edge, plus old/new offset and touched flag per row
     rebuild_bytes = K * (8 * m_mean + 9 * n)
     cand = {"k_pull": (kern["pull"], pull_bytes, max(pull_launches, 1)),
@@ -235,9 +473,12 @@ def main():
     dom = max(cand, key=lambda k: cand[k][0])
     ms_k, bytes_k, nl = cand[dom]
     achieved = (bytes_k / nl) / (ms_k / nl * 1e-3) / 1e9 if ms_k > 0 else 0.0
+    wkey = f"rmat{args.scale}_ef{args.edge_factor:g}_{args.mode}_f{args.frac:g}"
+    traffic = measured_traffic(wkey) if dom == "k_pull" else None
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
-            "launches": nl, "avg_launch_ms": round(ms_k / nl, 5), "bytes_per_launch": int(bytes_k / nl)}
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
+            "launches": nl, "avg_launch_ms": round(ms_k / nl, 5), "bytes_per_launch": int(bytes_k / nl),
+            "source_sha": rank_source_sha()}
 
     res = {
         "metric": METRIC,

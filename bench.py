@@ -227,9 +227,22 @@ def bench_batched(args):
     r_plain = [bg.member(r_arena, k).clone() for k in range(len(plain))]
     log(f"R0: static over the arena, {tot0['iterations']} iterations (slowest member)")
 
+    bg.set_timing(True)
+    phases = {"apply": 0.0, "pull": 0.0, "commit": 0.0, "bin": 0.0, "mark": 0.0, "rank_total": 0.0}
+    counts = {"pull_launches": 0, "dense_iterations": 0, "edges_pulled": 0, "pull_bytes": 0.0}
+
     def step_batched(i):
         info = bg.apply_batch_many([dev_chains[k][i] for k in range(len(plain))])
         r, tot, per = bg.update_ranks_many(args.mode, r_arena, out=r_arena)
+        if i >= args.warmup:
+            phases["apply"] += info[0]["ms_total"]
+            phases["pull"] += tot["ms_pull"]
+            phases["commit"] += tot["ms_commit"]
+            phases["bin"] += tot["ms_bin"]
+            phases["mark"] += tot["ms_mark"]
+            phases["rank_total"] += tot["ms_total"]
+            for key in counts:
+                counts[key] += tot[key]
         return info, tot, per
 
     def step_plain(i):
@@ -293,6 +306,9 @@ def bench_batched(args):
         "speedup_vs_sequential": tp_s / tb_s,
         "max_member_iterations_mean": float(np.mean(iters_b)),
         "max_abs_diff_vs_plain": worst,
+        "batched_ms_per_step_by_phase": {k: v / K for k, v in phases.items()},
+        "batched_counts_per_step": {k: v / K for k, v in counts.items()},
+        "pull_achieved_gbs": (counts["pull_bytes"] / (phases["pull"] * 1e-3) / 1e9) if phases["pull"] else None,
     }
     print(json.dumps(res))
 

@@ -420,27 +420,12 @@ __device__ __forceinline__ void pull_chunks(const PullArgs& a, const int32_t* __
   }
 }
 
-// Workgroups are dispatched to the 8 XCDs round-robin by index, and each XCD has
-// its own L2.  Renumber a bin's workgroups so that those landing on one XCD
-// take one contiguous share of the bin's work: neighbouring vertices (in a
-// batch, the same member graph, whose in-neighbours are its own vertices) then
-// meet in the same L2.  j = index within the bin; the result is a bijection
-// on [0, nb).
-constexpr int kXcds = 8;
-__device__ __forceinline__ int xcd_contiguous(int j, int nb) {
-  const int p = j % kXcds;
-  int off = 0;
-  for (int q = 0; q < p; q++) off += (nb + kXcds - 1 - q) / kXcds;
-  return off + j / kXcds;
-}
-
 template <int MODE, bool DENSE>
 __global__ void __launch_bounds__(256) k_pull(PullArgs a, const int32_t* __restrict__ wl, PullLayout L) {
   const int b = blockIdx.x;
   int k = 0;
   while (k < kBins - 1 && b >= L.blk[k + 1]) k++;
-  const int nb = L.blk[k + 1] - L.blk[k];
-  const int lb = xcd_contiguous(b - L.blk[k], nb);
+  const int lb = b - L.blk[k], nb = L.blk[k + 1] - L.blk[k];
   Acc acc;
   __shared__ GTab tab;
   if (a.gid) {

@@ -103,6 +103,7 @@ struct GTab {
 __device__ __forceinline__ void gtab_max(GTab* t, int g, double x, unsigned long long* gslots, int gsub) {
   if (!(x > 0.0)) return;
   const unsigned long long bits = (unsigned long long)__double_as_longlong(x);
+#pragma unroll 1
   for (int i = 0; i < kGTab; i++) {
     const int sl = (g + i) & (kGTab - 1);
     const int cur = atomicCAS(&t->key[sl], -1, g);
@@ -421,7 +422,7 @@ __device__ __forceinline__ void pull_chunks(const PullArgs& a, const int32_t* __
 }
 
 template <int MODE, bool DENSE>
-__global__ void __launch_bounds__(256) k_pull(PullArgs a, const int32_t* __restrict__ wl, PullLayout L) {
+__global__ void __launch_bounds__(256, 8) k_pull(PullArgs a, const int32_t* __restrict__ wl, PullLayout L) {
   const int b = blockIdx.x;
   int k = 0;
   while (k < kBins - 1 && b >= L.blk[k + 1]) k++;

@@ -251,6 +251,75 @@ int dfpr_apply_batch_many(dfpr_graph* g, const int64_t* n_del, const int32_t* co
 int dfpr_update_ranks_many(dfpr_graph* g, dfpr_mode mode, const dfpr_params* p, const double* r_prev,
                            double* r_out, void* stream, dfpr_stats* total, dfpr_stats* per_graph);
 
+/* ---- Serving form: a request loop over graphs resident in HBM.
+ *
+ * The server owns graphs and their current ranks in device memory.  A request
+ * (graph id, batch) applies the batch to that graph (Section 3.2) and updates
+ * its resident ranks with the server's mode, DF-P by default (Algorithm 1 from
+ * the ranks left by the previous request).  Requests for one graph run one at
+ * a time in submission order (a single writer per graph, Section 3.2);
+ * requests for different graphs run concurrently on `lanes` worker lanes, each
+ * with its own HIP stream, so their kernels overlap on the device.  A request
+ * is admitted when a lane is free, its graph is idle and its scratch (the
+ * vertex arrays of one update plus its batch sort buffers) can be taken from
+ * the server's scratch heap of `heap_bytes`, reserved once at create; requests
+ * that do not fit wait (later ones do not overtake them), so a small heap
+ * serialises work instead of failing it.  A request whose scratch exceeds the
+ * whole heap fails with ENOMEM.  Results are those of the plain entry points:
+ * a graph's ranks do not depend on what else is in flight. */
+typedef struct dfpr_server dfpr_server;
+
+typedef struct {
+  int64_t submitted, completed, failed; /* requests so far                          */
+  int64_t queued;                       /* waiting for admission                    */
+  int64_t peak_in_flight;               /* most requests running at once            */
+  int32_t in_flight, graphs, lanes, reserved;
+  int64_t heap_bytes, heap_used, heap_peak;
+} dfpr_server_stats;
+
+/* Create a server on the current device: heap_bytes > 0 of scratch heap, lanes
+ * in [1, 64], mode STATIC/ND/DF/DFP, p as for dfpr_update_ranks (NULL =
+ * defaults).  Errors: EINVAL, ENOMEM, EHIP. */
+int dfpr_server_create(size_t heap_bytes, int32_t lanes, dfpr_mode mode, const dfpr_params* p,
+                       dfpr_server** out);
+
+/* Drain every queued and running request, then free the server, its graphs and
+ * their resident ranks. */
+int dfpr_server_destroy(dfpr_server* sv);
+
+/* Move a plain graph handle into the server (on success the caller must not
+ * use or destroy g any more) and give it resident ranks: a copy
+ * of r0 (device, n doubles) or, with r0 = NULL, a Static solve.  The handle's
+ * own scratch is released: from now on each request borrows scratch from the
+ * heap.  On error the handle still belongs to the caller.  Errors: EINVAL
+ * (batch handle), ENOMEM, EHIP. */
+int dfpr_server_add_graph(dfpr_server* sv, dfpr_graph* g, const double* r0, int32_t* gid);
+
+/* Queue a request: one batch (host arrays, copied before return; ids in
+ * [0, n) of graph gid, read as sets as in dfpr_apply_batch).  r_out (nullable)
+ * is a host array of n doubles that receives the graph's ranks after this
+ * request; it must stay valid until dfpr_server_wait returns for the ticket.
+ * Errors: EINVAL (unknown graph, negative counts, null arrays). */
+int dfpr_server_submit(dfpr_server* sv, int32_t gid, int64_t n_del, const int32_t* del_src,
+                       const int32_t* del_dst, int64_t n_ins, const int32_t* ins_src, const int32_t* ins_dst,
+                       double* r_out, int64_t* ticket);
+
+/* Wait for a request and collect it (each ticket once).  st, info, latency_ms
+ * (submit to result ready) and queue_ms (submit to admission) are nullable.
+ * Returns the request's own status: ERANGE (an id outside [0, n); the graph and
+ * its ranks are unchanged), ENOMEM (scratch larger than the heap), ESTATE/EHIP. */
+int dfpr_server_wait(dfpr_server* sv, int64_t ticket, dfpr_stats* st, dfpr_batch_info* info,
+                     double* latency_ms, double* queue_ms);
+
+/* Copy graph gid's resident ranks (n doubles, caller order) to r_out once no
+ * request for it is queued or running. */
+int dfpr_server_ranks(dfpr_server* sv, int32_t gid, double* r_out, dfpr_where where);
+
+/* Vertex count of graph gid. */
+int dfpr_server_graph_size(dfpr_server* sv, int32_t gid, int32_t* n);
+
+int dfpr_server_get_stats(dfpr_server* sv, dfpr_server_stats* out);
+
 /* Thread-local message for the last failing call on this thread ("" if none). */
 const char* dfpr_last_error(void);
 

@@ -272,5 +272,85 @@ class BatchGraph(Graph):
         return out, st.as_dict(), [x.as_dict() for x in per]
 
 
+class Server:
+    """Request loop over graphs resident in HBM (see include/dfpr.h, serving form).
+
+    srv = Server(heap_bytes=8 << 30, lanes=4)
+    gid = srv.add_graph(Graph.from_coo(n, src, dst))      # the handle moves into the server
+    t = srv.submit(gid, del_src, del_dst, ins_src, ins_dst, want_ranks=True)
+    ranks, st, info, latency_ms, queue_ms = srv.wait(t)
+    """
+
+    def __init__(self, heap_bytes, lanes=4, mode="dfp", **kw):
+        p = default_params()
+        for k, v in kw.items():
+            setattr(p, k, v)
+        m = MODES[mode] if isinstance(mode, str) else int(mode)
+        h = ctypes.c_void_p()
+        _check(lib().dfpr_server_create(int(heap_bytes), int(lanes), m, ctypes.byref(p), ctypes.byref(h)))
+        self._h = h
+        self._n = {}
+        self._keep = {}
+
+    def close(self):
+        if self._h:
+            lib().dfpr_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 - interpreter shutdown
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def add_graph(self, graph, r0=None) -> int:
+        """Move `graph` (a plain Graph) into the server; r0: float64 CUDA tensor or None (Static)."""
+        gid = ctypes.c_int32()
+        rp = ctypes.c_void_p(r0.data_ptr()) if r0 is not None else None
+        _check(lib().dfpr_server_add_graph(self._h, graph._h, rp, ctypes.byref(gid)))
+        self._n[gid.value] = graph.n
+        graph._h = None  # owned by the server now
+        return gid.value
+
+    def submit(self, gid, del_src=(), del_dst=(), ins_src=(), ins_dst=(), want_ranks=False) -> int:
+        arrs = [np.ascontiguousarray(np.asarray(a, dtype=np.int32)) for a in (del_src, del_dst, ins_src, ins_dst)]
+        if arrs[0].size != arrs[1].size or arrs[2].size != arrs[3].size:
+            raise ValueError("src/dst length mismatch")
+        ptr = [ctypes.c_void_p(a.ctypes.data if a.size else 0) for a in arrs]
+        out = np.empty(self._n[gid], np.float64) if want_ranks else None
+        t = ctypes.c_int64()
+        _check(lib().dfpr_server_submit(self._h, int(gid), arrs[0].size, ptr[0], ptr[1], arrs[2].size, ptr[2], ptr[3],
+                                        ctypes.c_void_p(out.ctypes.data) if out is not None else None,
+                                        ctypes.byref(t)))
+        self._keep[t.value] = out
+        return t.value
+
+    def wait(self, ticket):
+        """(ranks or None, stats, batch info, latency ms, queue ms); raises DfprError on a failed request."""
+        st, info = Stats(), BatchInfo()
+        lat, qms = ctypes.c_double(), ctypes.c_double()
+        rc = lib().dfpr_server_wait(self._h, int(ticket), ctypes.byref(st), ctypes.byref(info), ctypes.byref(lat),
+                                    ctypes.byref(qms))
+        out = self._keep.pop(ticket, None)
+        _check(rc)
+        return out, st.as_dict(), info.as_dict(), lat.value, qms.value
+
+    def ranks(self, gid):
+        out = np.empty(self._n[gid], np.float64)
+        _check(lib().dfpr_server_ranks(self._h, int(gid), ctypes.c_void_p(out.ctypes.data), _capi.HOST))
+        return out
+
+    def stats(self) -> dict:
+        s = _capi.ServerStats()
+        _check(lib().dfpr_server_get_stats(self._h, ctypes.byref(s)))
+        return s.as_dict()
+
+
 def version() -> str:
     return lib().dfpr_version().decode()

@@ -17,7 +17,9 @@ CREATE_KEEP_IDS = 1
 EXPORTS = ("dfpr_params_default", "dfpr_graph_create", "dfpr_graph_destroy", "dfpr_graph_size",
            "dfpr_graph_export", "dfpr_apply_batch", "dfpr_update_ranks", "dfpr_set_tuning",
            "dfpr_get_tuning", "dfpr_autotune", "dfpr_set_timing", "dfpr_batch_create", "dfpr_batch_count",
-           "dfpr_batch_member", "dfpr_apply_batch_many", "dfpr_update_ranks_many", "dfpr_last_error",
+           "dfpr_batch_member", "dfpr_apply_batch_many", "dfpr_update_ranks_many", "dfpr_server_create",
+           "dfpr_server_destroy", "dfpr_server_add_graph", "dfpr_server_submit", "dfpr_server_wait",
+           "dfpr_server_ranks", "dfpr_server_graph_size", "dfpr_server_get_stats", "dfpr_last_error",
            "dfpr_version")
 
 
@@ -63,6 +65,18 @@ class Stats(ctypes.Structure):
         return out
 
 
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("failed", ctypes.c_int64),
+                ("queued", ctypes.c_int64), ("peak_in_flight", ctypes.c_int64), ("in_flight", ctypes.c_int32),
+                ("graphs", ctypes.c_int32), ("lanes", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("heap_bytes", ctypes.c_int64), ("heap_used", ctypes.c_int64), ("heap_peak", ctypes.c_int64)]
+
+    def as_dict(self):
+        out = {k: getattr(self, k) for k, _ in self._fields_}
+        out.pop("reserved", None)
+        return out
+
+
 def declare(lib):
     P = ctypes.c_void_p
     i32, i64 = ctypes.c_int32, ctypes.c_int64
@@ -102,6 +116,23 @@ def declare(lib):
     lib.dfpr_update_ranks_many.argtypes = [P, ctypes.c_int, ctypes.POINTER(Params), P, P, P, ctypes.POINTER(Stats),
                                            ctypes.POINTER(Stats)]
     lib.dfpr_update_ranks_many.restype = ctypes.c_int
+    D = ctypes.POINTER(ctypes.c_double)
+    lib.dfpr_server_create.argtypes = [ctypes.c_size_t, i32, ctypes.c_int, ctypes.POINTER(Params), ctypes.POINTER(P)]
+    lib.dfpr_server_create.restype = ctypes.c_int
+    lib.dfpr_server_destroy.argtypes = [P]
+    lib.dfpr_server_destroy.restype = ctypes.c_int
+    lib.dfpr_server_add_graph.argtypes = [P, P, P, ctypes.POINTER(i32)]
+    lib.dfpr_server_add_graph.restype = ctypes.c_int
+    lib.dfpr_server_submit.argtypes = [P, i32, i64, P, P, i64, P, P, P, ctypes.POINTER(i64)]
+    lib.dfpr_server_submit.restype = ctypes.c_int
+    lib.dfpr_server_wait.argtypes = [P, i64, ctypes.POINTER(Stats), ctypes.POINTER(BatchInfo), D, D]
+    lib.dfpr_server_wait.restype = ctypes.c_int
+    lib.dfpr_server_ranks.argtypes = [P, i32, P, ctypes.c_int]
+    lib.dfpr_server_ranks.restype = ctypes.c_int
+    lib.dfpr_server_graph_size.argtypes = [P, i32, ctypes.POINTER(i32)]
+    lib.dfpr_server_graph_size.restype = ctypes.c_int
+    lib.dfpr_server_get_stats.argtypes = [P, ctypes.POINTER(ServerStats)]
+    lib.dfpr_server_get_stats.restype = ctypes.c_int
     lib.dfpr_last_error.argtypes = []
     lib.dfpr_last_error.restype = ctypes.c_char_p
     lib.dfpr_version.argtypes = []

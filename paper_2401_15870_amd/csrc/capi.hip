@@ -5,11 +5,6 @@
 
 #include "dfpr_impl.hpp"
 
-namespace dfpr {
-const char* last_error();
-void clear_error();
-}  // namespace dfpr
-
 using namespace dfpr;
 
 namespace {
@@ -268,6 +263,112 @@ int dfpr_update_ranks_many(dfpr_graph* g, dfpr_mode mode, const dfpr_params* p, 
     }
     return rc;
   });
+}
+
+int dfpr_server_create(size_t heap_bytes, int32_t lanes, dfpr_mode mode, const dfpr_params* p, dfpr_server** out) {
+  clear_error();
+  if (!out) {
+    set_error("out is null");
+    return DFPR_EINVAL;
+  }
+  *out = nullptr;
+  dfpr_params prm;
+  if (p) prm = *p; else dfpr_params_default(&prm);
+  if (heap_bytes == 0 || lanes < 1 || lanes > 64 || mode < DFPR_STATIC || mode > DFPR_DFP) {
+    set_error("invalid server arguments: heap_bytes=%zu lanes=%d mode=%d", heap_bytes, lanes, (int)mode);
+    return DFPR_EINVAL;
+  }
+  if (check_params(prm) != DFPR_OK) return DFPR_EINVAL;
+  try {
+    return server_create(heap_bytes, lanes, mode, prm, out);
+  } catch (const std::exception&) {
+    set_error("server creation failed (host resources)");
+    return DFPR_ENOMEM;
+  }
+}
+
+int dfpr_server_destroy(dfpr_server* sv) {
+  clear_error();
+  if (!sv) return DFPR_OK;
+  return server_destroy(sv);
+}
+
+int dfpr_server_add_graph(dfpr_server* sv, dfpr_graph* g, const double* r0, int32_t* gid) {
+  clear_error();
+  if (!sv || !g || !gid) {
+    set_error("null argument");
+    return DFPR_EINVAL;
+  }
+  if (g->poisoned) {
+    set_error("graph handle is unusable after an earlier HIP failure");
+    return DFPR_ESTATE;
+  }
+  try {
+    return server_add_graph(sv, g, r0, gid);
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return DFPR_ENOMEM;
+  }
+}
+
+int dfpr_server_submit(dfpr_server* sv, int32_t gid, int64_t n_del, const int32_t* del_src, const int32_t* del_dst,
+                       int64_t n_ins, const int32_t* ins_src, const int32_t* ins_dst, double* r_out,
+                       int64_t* ticket) {
+  clear_error();
+  if (!sv || !ticket || n_del < 0 || n_ins < 0 || (n_del > 0 && (!del_src || !del_dst)) ||
+      (n_ins > 0 && (!ins_src || !ins_dst))) {
+    set_error("invalid request arguments");
+    return DFPR_EINVAL;
+  }
+  try {
+    return server_submit(sv, gid, n_del, del_src, del_dst, n_ins, ins_src, ins_dst, r_out, ticket);
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return DFPR_ENOMEM;
+  }
+}
+
+int dfpr_server_wait(dfpr_server* sv, int64_t ticket, dfpr_stats* st, dfpr_batch_info* info, double* latency_ms,
+                     double* queue_ms) {
+  clear_error();
+  if (!sv) {
+    set_error("null server");
+    return DFPR_EINVAL;
+  }
+  return server_wait(sv, ticket, st, info, latency_ms, queue_ms);
+}
+
+int dfpr_server_ranks(dfpr_server* sv, int32_t gid, double* r_out, dfpr_where where) {
+  clear_error();
+  if (!sv || !r_out || (where != DFPR_HOST && where != DFPR_DEVICE)) {
+    set_error("invalid arguments");
+    return DFPR_EINVAL;
+  }
+  return server_ranks(sv, gid, r_out, where);
+}
+
+int dfpr_server_graph_size(dfpr_server* sv, int32_t gid, int32_t* n) {
+  clear_error();
+  if (!sv || !n) {
+    set_error("null argument");
+    return DFPR_EINVAL;
+  }
+  const int32_t v = server_graph_n(sv, gid);
+  if (v < 0) {
+    set_error("unknown graph id %d", gid);
+    return DFPR_EINVAL;
+  }
+  *n = v;
+  return DFPR_OK;
+}
+
+int dfpr_server_get_stats(dfpr_server* sv, dfpr_server_stats* out) {
+  clear_error();
+  if (!sv || !out) {
+    set_error("null argument");
+    return DFPR_EINVAL;
+  }
+  return server_stats(sv, out);
 }
 
 int dfpr_set_tuning(dfpr_graph* g, const int32_t bounds[5]) {

@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <cstddef>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -18,6 +19,8 @@ constexpr int kWave = 64;
 
 // ---------------------------------------------------------------- errors
 void set_error(const char* fmt, ...);
+const char* last_error();
+void clear_error();
 
 struct Status {
   int code = DFPR_OK;
@@ -41,11 +44,37 @@ struct Status {
   } while (0)
 
 // ---------------------------------------------------------------- buffers
+// Device sub-allocator over one hipMalloc'ed region: best fit over a free list
+// with coalescing, 256-byte granules.  alloc/free never call into the HIP
+// runtime, so they neither block nor synchronise the device.  Thread-safe.
+class Heap {
+ public:
+  static constexpr size_t kAlign = 256;
+  ~Heap();
+  int init(size_t bytes);                 // one hipMalloc'ed region, freed with the heap
+  void init_at(void* base, size_t bytes);  // a region lent by the caller
+  void* alloc(size_t bytes);  // nullptr when no free block is large enough
+  void free(void* p);
+  size_t capacity() const { return cap_; }
+  size_t used();
+  size_t peak();
+  size_t largest_free();
+
+ private:
+  std::mutex mu_;
+  char* base_ = nullptr;
+  bool owned_ = false;
+  size_t cap_ = 0, used_ = 0, peak_ = 0;
+  std::map<size_t, size_t> free_;   // offset -> length
+  std::map<size_t, size_t> taken_;  // offset -> length
+};
+
 // A growable device buffer (bytes).  Growth frees and reallocates; contents
-// are not preserved.
+// are not preserved.  With a heap the memory comes from it (exact sizes).
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  Heap* heap = nullptr;
   int ensure(size_t want);
   void release();
   template <class T> T* as() const { return static_cast<T*>(p); }
@@ -222,6 +251,10 @@ struct dfpr_graph {
   int32_t* partial_x = nullptr;  // per-chunk "an in-neighbour expanded" flags (dense mode)
   bool timing = false;        // record HIP-event timings of every call
   dfpr::EventPool pool;
+  // vertex-proportional scratch of apply and rank updates, carved from one block
+  void* scratch = nullptr;
+  size_t scratch_bytes = 0;
+  bool scratch_owned = false;  // block hipMalloc'ed by the handle (else lent by a server heap)
 };
 
 namespace dfpr {
@@ -254,11 +287,30 @@ int batch_apply(dfpr_graph* g, const int64_t* n_del, const int32_t* const* del_s
                 const int64_t* n_ins, const int32_t* const* ins_src, const int32_t* const* ins_dst, dfpr_where where,
                 hipStream_t s, dfpr_batch_info* info);
 int graph_destroy(dfpr_graph* g);
+// Scratch block: size, attach (carve the arrays, clear the zero-initialised
+// prefix on stream s) and detach.  Apply and rank updates need it attached.
+size_t scratch_size(const dfpr_graph* g);
+int attach_scratch(dfpr_graph* g, void* block, size_t bytes, hipStream_t s);
+void detach_scratch(dfpr_graph* g);
+// Device bytes an apply of nk batch pairs takes from its growable buffers.
+size_t apply_buffer_bytes(int64_t nk, bool host_input);
 int graph_export(const dfpr_graph* g, int in_csr, int32_t* off, int32_t* idx, dfpr_where where,
                  hipStream_t s);
 int graph_apply(dfpr_graph* g, int64_t n_del, const int32_t* del_src, const int32_t* del_dst,
                 int64_t n_ins, const int32_t* ins_src, const int32_t* ins_dst, dfpr_where where,
                 hipStream_t s, dfpr_batch_info* info);
+
+// ---- serving form (server.hip)
+int server_create(size_t heap_bytes, int32_t lanes, dfpr_mode mode, const dfpr_params& p, dfpr_server** out);
+int server_destroy(dfpr_server* sv);
+int server_add_graph(dfpr_server* sv, dfpr_graph* g, const double* r0, int32_t* gid);
+int server_submit(dfpr_server* sv, int32_t gid, int64_t n_del, const int32_t* del_src, const int32_t* del_dst,
+                  int64_t n_ins, const int32_t* ins_src, const int32_t* ins_dst, double* r_out, int64_t* ticket);
+int server_wait(dfpr_server* sv, int64_t ticket, dfpr_stats* st, dfpr_batch_info* info, double* latency_ms,
+                double* queue_ms);
+int server_ranks(dfpr_server* sv, int32_t gid, double* r_out, dfpr_where where);
+int server_stats(dfpr_server* sv, dfpr_server_stats* out);
+int32_t server_graph_n(dfpr_server* sv, int32_t gid);
 
 // ---- ranks (rank.hip)
 int update_ranks(dfpr_graph* g, dfpr_mode mode, const dfpr_params& p, const double* r_prev,

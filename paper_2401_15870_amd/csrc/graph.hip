@@ -9,6 +9,8 @@
 #include <cstdarg>
 #include <cstdio>
 
+#include <type_traits>
+
 #include "prim.hpp"
 
 namespace dfpr {
@@ -27,6 +29,16 @@ void clear_error() { g_err[0] = 0; }
 int DevBuf::ensure(size_t want) {
   if (want <= bytes) return DFPR_OK;
   release();
+  if (heap) {
+    const size_t nb = (want + Heap::kAlign - 1) / Heap::kAlign * Heap::kAlign;
+    p = heap->alloc(nb);
+    if (!p) {
+      set_error("scratch heap exhausted: %zu bytes wanted", nb);
+      return DFPR_ENOMEM;
+    }
+    bytes = nb;
+    return DFPR_OK;
+  }
   size_t nb = want + want / 4 + 4096;
   hipError_t e = hipMalloc(&p, nb);
   if (e != hipSuccess) {
@@ -40,7 +52,8 @@ int DevBuf::ensure(size_t want) {
   return DFPR_OK;
 }
 void DevBuf::release() {
-  if (p) (void)hipFree(p);
+  if (p && heap) heap->free(p);
+  else if (p) (void)hipFree(p);
   p = nullptr;
   bytes = 0;
 }
@@ -485,38 +498,113 @@ __global__ void k_clear_rows(const uint64_t* eff, const int64_t* count, int b, i
 __global__ void k_finish_apply(const int32_t* noff, int32_t n, int64_t* counters) { counters[5] = noff[n]; }
 
 // ------------------------------------------------------------------ host
-static int alloc_rank_scratch(dfpr_graph* g) {
+// Chunk partial sums of the pull's chunked bin: at most one chunk per vertex
+// plus one per kPullChunk edges of the capacity.
+static int64_t partial_entries(int32_t n, int64_t cap) { return (int64_t)n + 1 + cap / kPullChunk; }
+
+// Carve the scratch arrays from `base` (nullptr: only measure).  The arrays
+// that must start at zero come first, so one clear covers them; returns the
+// block size and, in *zero_bytes, the size of that prefix.
+static size_t carve_scratch(dfpr_graph* g, char* base, size_t* zero_bytes) {
   const size_t n = (size_t)g->n;
-  DFPR_TRY(dalloc(&g->contrib, n));
-  DFPR_TRY(dalloc(&g->contrib2, n));
-  DFPR_TRY(dalloc(&g->rn, n));
-  DFPR_TRY(dalloc(&g->flag_cur, n));
-  DFPR_TRY(dalloc(&g->flag_next, n));
-  DFPR_TRY(dalloc(&g->xflag, n));
-  DFPR_TRY(dalloc(&g->xflag2, n));
-  DFPR_TRY(dalloc(&g->ever, n));
-  DFPR_TRY(dalloc(&g->pend_src, n));
-  DFPR_TRY(dalloc(&g->touched_out, n));
-  DFPR_TRY(dalloc(&g->touched_in, n));
-  DFPR_TRY(dalloc(&g->delta_out, n));
-  DFPR_TRY(dalloc(&g->delta_in, n));
-  DFPR_TRY(dalloc(&g->worklist, n));
-  DFPR_TRY(dalloc(&g->all_bins, n));
-  DFPR_TRY(dalloc(&g->ctl, 1));
-  const int64_t nbins = ((int64_t)n + 2047) / 2048;
-  DFPR_TRY(dalloc(&g->bin_blk, (size_t)(kBins * nbins + 2)));
-  DFPR_TRY(dalloc(&g->arrive, n));
-  DFPR_HIP(hipMemset(g->arrive, 0, n * sizeof(int32_t)));
-  DFPR_TRY(dalloc(&g->chunk_pre, n + 1));
-  DFPR_TRY(dalloc(&g->piece_pre, n / kWave + 2));
-  DFPR_TRY(dalloc(&g->all_chunk_pre, n + 1));
-  DFPR_TRY(dalloc(&g->big_list, n));
-  DFPR_TRY(dalloc(&g->big_pre, n + 1));
-  g->partial_n = g->cap / kPullChunk + (int64_t)n + 1;
+  size_t off = 0;
+  auto take = [&](auto*& ptr, size_t count) {
+    using T = std::remove_reference_t<decltype(*ptr)>;
+    off = (off + Heap::kAlign - 1) / Heap::kAlign * Heap::kAlign;
+    if (base) ptr = reinterpret_cast<T*>(base + off);
+    off += count * sizeof(T);
+  };
+  // zero-initialised prefix
+  take(g->ctl, 1);
+  take(g->flag_cur, n);
+  take(g->flag_next, n);
+  take(g->xflag, n);
+  take(g->xflag2, n);
+  take(g->ever, n);
+  take(g->pend_src, n);
+  take(g->touched_out, n);
+  take(g->touched_in, n);
+  take(g->delta_out, n);
+  take(g->delta_in, n);
+  take(g->arrive, n);
+  if (zero_bytes) *zero_bytes = off;
+  // contents defined before use
+  take(g->contrib, n);
+  take(g->contrib2, n);
+  take(g->rn, n);
+  if (g->perm) take(g->rint, n);
+  take(g->worklist, n);
+  take(g->all_bins, n);
+  const size_t nbins = (n + 2047) / 2048;
+  take(g->bin_blk, kBins * nbins + 2);
+  take(g->chunk_pre, n + 1);
+  take(g->piece_pre, n / kWave + 2);
+  take(g->all_chunk_pre, n + 1);
+  take(g->big_list, n);
+  take(g->big_pre, n + 1);
+  g->scan_tmp_n = scan_tmp_elems((int64_t)n + 1);
+  take(g->scan_tmp, g->scan_tmp_n);
+  return (off + Heap::kAlign - 1) / Heap::kAlign * Heap::kAlign;
+}
+
+size_t scratch_size(const dfpr_graph* g) {
+  dfpr_graph probe_fields;  // carve writes only pointer and size fields
+  probe_fields.n = g->n;
+  probe_fields.perm = g->perm;
+  const size_t b = carve_scratch(&probe_fields, nullptr, nullptr);
+  probe_fields.perm = nullptr;
+  return b;
+}
+
+int attach_scratch(dfpr_graph* g, void* block, size_t bytes, hipStream_t s) {
+  size_t zero = 0;
+  if (carve_scratch(g, nullptr, &zero) > bytes) {
+    set_error("scratch block too small");
+    return DFPR_EINVAL;
+  }
+  carve_scratch(g, static_cast<char*>(block), &zero);
+  g->scratch = block;
+  g->scratch_bytes = bytes;
+  DFPR_HIP(hipMemsetAsync(block, 0, zero, s));
+  g->all_bins_valid = false;
+  g->all_chunks_valid = false;
+  g->pending_any = false;
+  return DFPR_OK;
+}
+
+void detach_scratch(dfpr_graph* g) {
+  g->ctl = nullptr;
+  g->flag_cur = g->flag_next = g->xflag = g->xflag2 = g->ever = g->pend_src = nullptr;
+  g->touched_out = g->touched_in = nullptr;
+  g->delta_out = g->delta_in = g->arrive = nullptr;
+  g->contrib = g->contrib2 = g->rn = g->rint = nullptr;
+  g->worklist = g->all_bins = g->big_list = nullptr;
+  g->bin_blk = g->chunk_pre = g->piece_pre = g->all_chunk_pre = g->big_pre = g->scan_tmp = nullptr;
+  g->scratch = nullptr;
+  g->scratch_bytes = 0;
+  g->all_bins_valid = false;
+  g->all_chunks_valid = false;
+  g->pending_any = false;
+}
+
+size_t apply_buffer_bytes(int64_t nk, bool host_input) {
+  auto r = [](size_t x) { return (x + Heap::kAlign - 1) / Heap::kAlign * Heap::kAlign; };
+  size_t t = 0;
+  t += 2 * r(nk * sizeof(uint64_t));                                              // keys_a, keys_b
+  t += r(nk * sizeof(uint64_t) + nk);                                             // keys_c + keep bytes
+  t += r((radix_hist_elems(nk) + std::max(radix_scan_tmp_elems(nk), scan_tmp_elems(nk + 1))) * sizeof(int64_t) +
+         64);                                                                     // sort_hist
+  t += r(2 * (nk + 1) * sizeof(int64_t));                                         // eff_pre
+  if (host_input) t += r(2 * nk * sizeof(int32_t));                               // batch_in
+  return t + 8 * Heap::kAlign;
+}
+
+// Per-handle state kept for the handle's life: control mirror, member tables
+// and the chunk partial sums (sized by the edge capacity).
+static int alloc_fixed_state(dfpr_graph* g) {
+  g->partial_n = partial_entries(g->n, g->cap);
   DFPR_TRY(dalloc(&g->partial, (size_t)g->partial_n));
   DFPR_TRY(dalloc(&g->partial_x, (size_t)g->partial_n));
-  g->scan_tmp_n = scan_tmp_elems((int64_t)n + 1);
-  DFPR_TRY(dalloc(&g->scan_tmp, g->scan_tmp_n));
   DFPR_HIP(hipHostMalloc((void**)&g->ctl_host, sizeof(IterCtl), hipHostMallocDefault));
   const size_t G = (size_t)g->ngraphs;
   DFPR_TRY(dalloc(&g->nk, G));
@@ -530,22 +618,25 @@ static int alloc_rank_scratch(dfpr_graph* g) {
   DFPR_HIP(hipHostMalloc(&g->g_host, G * (8 + 4 + 8 + 16 + 1) + 64, hipHostMallocDefault));
   DFPR_HIP(hipMemset(g->gslots, 0, G * g->gsub * kSlotStride * sizeof(unsigned long long)));
   DFPR_HIP(hipMemset(g->done, 0, G));
-  {
-    std::vector<int32_t> nkh(G);
-    for (size_t k = 0; k < G; k++) nkh[k] = (int32_t)(g->vbase[k + 1] - g->vbase[k]);
-    DFPR_HIP(hipMemcpy(g->nk, nkh.data(), G * sizeof(int32_t), hipMemcpyHostToDevice));
+  std::vector<int32_t> nkh(G);
+  for (size_t k = 0; k < G; k++) nkh[k] = (int32_t)(g->vbase[k + 1] - g->vbase[k]);
+  DFPR_HIP(hipMemcpy(g->nk, nkh.data(), G * sizeof(int32_t), hipMemcpyHostToDevice));
+  return DFPR_OK;
+}
+
+// A plain handle owns its scratch block for its whole life.
+static int alloc_rank_scratch(dfpr_graph* g) {
+  DFPR_TRY(alloc_fixed_state(g));
+  const size_t bytes = scratch_size(g);
+  void* block = nullptr;
+  if (hipMalloc(&block, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("device allocation of %zu scratch bytes failed", bytes);
+    return DFPR_ENOMEM;
   }
-  DFPR_HIP(hipMemset(g->flag_cur, 0, n));
-  DFPR_HIP(hipMemset(g->flag_next, 0, n));
-  DFPR_HIP(hipMemset(g->xflag, 0, n));
-  DFPR_HIP(hipMemset(g->xflag2, 0, n));
-  DFPR_HIP(hipMemset(g->ever, 0, n));
-  DFPR_HIP(hipMemset(g->pend_src, 0, n));
-  DFPR_HIP(hipMemset(g->touched_out, 0, n));
-  DFPR_HIP(hipMemset(g->touched_in, 0, n));
-  DFPR_HIP(hipMemset(g->delta_out, 0, n * sizeof(int32_t)));
-  DFPR_HIP(hipMemset(g->delta_in, 0, n * sizeof(int32_t)));
-  DFPR_HIP(hipMemset(g->ctl, 0, sizeof(IterCtl)));
+  g->scratch_owned = true;
+  DFPR_TRY(attach_scratch(g, block, bytes, nullptr));
+  DFPR_HIP(hipDeviceSynchronize());
   return DFPR_OK;
 }
 
@@ -566,35 +657,12 @@ int graph_destroy(dfpr_graph* g) {
   free_csr(&g->in);
   free_csr(&g->out2);
   free_csr(&g->in2);
-  dfree(g->contrib);
-  dfree(g->contrib2);
-  dfree(g->rn);
-  dfree(g->flag_cur);
-  dfree(g->flag_next);
-  dfree(g->xflag);
-  dfree(g->xflag2);
-  dfree(g->ever);
-  dfree(g->pend_src);
-  dfree(g->touched_out);
-  dfree(g->touched_in);
-  dfree(g->delta_out);
-  dfree(g->delta_in);
-  dfree(g->worklist);
-  dfree(g->all_bins);
-  dfree(g->ctl);
-  dfree(g->scan_tmp);
-  dfree(g->bin_blk);
-  dfree(g->chunk_pre);
-  dfree(g->piece_pre);
-  dfree(g->all_chunk_pre);
-  dfree(g->big_list);
-  dfree(g->big_pre);
+  if (g->scratch_owned && g->scratch) (void)hipFree(g->scratch);
+  detach_scratch(g);
   dfree(g->partial);
   dfree(g->partial_x);
-  dfree(g->arrive);
   dfree(g->perm);
   dfree(g->inv);
-  dfree(g->rint);
   if (g->ctl_host) (void)hipHostFree(g->ctl_host);
   g->ctl_host = nullptr;
   dfree(g->gidv);
@@ -704,7 +772,7 @@ int graph_create(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, d
       return fail(rc);
     int32_t* deg = nullptr;
     if (relabel) {
-      if ((rc = dalloc(&g->perm, n)) || (rc = dalloc(&g->inv, n)) || (rc = dalloc(&g->rint, n))) return fail(rc);
+      if ((rc = dalloc(&g->perm, n)) || (rc = dalloc(&g->inv, n))) return fail(rc);
       deg = reinterpret_cast<int32_t*>(t.kb);  // the second key buffer is free until the sort
       if (hipMemsetAsync(deg, 0, (size_t)n * sizeof(int32_t), s) != hipSuccess) return fail(DFPR_EHIP);
     }
@@ -820,7 +888,7 @@ static int grow_capacity(dfpr_graph* g, int64_t want, hipStream_t s) {
     c->idx = p;
   }
   g->cap = cap;
-  const int64_t pn = cap / kPullChunk + (int64_t)g->n + 1;
+  const int64_t pn = partial_entries(g->n, cap);
   if (pn > g->partial_n) {
     dfree(g->partial);
     dfree(g->partial_x);

@@ -69,6 +69,17 @@ def test_invalid_arguments_rejected_before_device_work(lib):
     assert lib.dfpr_batch_member(None, 0, ctypes.byref(b), ctypes.byref(n)) == _capi.DFPR_EINVAL
     assert lib.dfpr_apply_batch_many(None, None, None, None, None, None, None, 0, None, None) == _capi.DFPR_EINVAL
     assert lib.dfpr_update_ranks_many(None, 3, None, None, None, None, None, None) == _capi.DFPR_EINVAL
+    # serving form
+    assert lib.dfpr_server_create(0, 4, 3, None, ctypes.byref(h)) == _capi.DFPR_EINVAL
+    assert lib.dfpr_server_create(1 << 20, 0, 3, None, ctypes.byref(h)) == _capi.DFPR_EINVAL
+    assert lib.dfpr_server_create(1 << 20, 4, 9, None, ctypes.byref(h)) == _capi.DFPR_EINVAL
+    assert lib.dfpr_server_destroy(None) == _capi.DFPR_OK
+    t = ctypes.c_int64()
+    assert lib.dfpr_server_submit(None, 0, 0, None, None, 0, None, None, None, ctypes.byref(t)) == _capi.DFPR_EINVAL
+    assert lib.dfpr_server_wait(None, 1, None, None, None, None) == _capi.DFPR_EINVAL
+    assert lib.dfpr_server_add_graph(None, None, None, None) == _capi.DFPR_EINVAL
+    ss = _capi.ServerStats()
+    assert lib.dfpr_server_get_stats(None, ctypes.byref(ss)) == _capi.DFPR_EINVAL
     assert lib.dfpr_version().startswith(b"dfpr")
 
 
@@ -77,3 +88,4 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(_capi.Params) == 5 * 8 + 2 * 4
     assert ctypes.sizeof(_capi.BatchInfo) == 6 * 8 + 4 * 8
     assert ctypes.sizeof(_capi.Stats) == 4 + 4 + 8 + 3 * 8 + 12 * 8 + 8 + 8 + 4 + 4 + 3 * 8 + 8 + 4 + 4
+    assert ctypes.sizeof(_capi.ServerStats) == 5 * 8 + 4 * 4 + 3 * 8

@@ -136,7 +136,7 @@ def test_serving_errors():
     torch_cuda()
     m = dfpr()
     n_big, sb, db = rmat(14, seed=5)
-    srv = m.Server(2 << 20, lanes=2)  # 2 MiB: too little for the scale-14 graph's scratch
+    srv = m.Server(1 << 20, lanes=2)  # 1 MiB: too little for the scale-14 graph's scratch (~1.7 MB)
     small = srv.add_graph(m.Graph.from_coo(50, *W.random_digraph(50, 0.1, seed=5)))
     big = srv.add_graph(m.Graph.from_coo(n_big, sb, db))
     before = srv.ranks(small)

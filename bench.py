@@ -44,21 +44,23 @@ def log(*a):
 
 
 def chained_batches(n, src, dst, frac, count, seed):
-    """`count` 80/20 batches, each valid against the graph left by the previous ones.
+    """`count` 80/20 batches, each valid against the graph left by the previous ones
+    (frac: one fraction of |E| for all, or one per batch).
 
     Deletions are drawn uniformly among the original edges not yet deleted;
     insertions are uniform pairs u != v absent from the original graph and not
     inserted before."""
     rng = np.random.Generator(np.random.PCG64(seed))
     m_total = src.shape[0] + n
-    b = max(1, int(round(frac * m_total)))
-    b_ins = int(round(0.8 * b))
-    b_del = b - b_ins
+    fracs = list(frac) if hasattr(frac, "__len__") else [frac] * count
     keys0 = src.astype(np.int64) * n + dst.astype(np.int64)
     deleted = np.zeros(src.shape[0], dtype=bool)
     inserted = np.empty(0, dtype=np.int64)
     out = []
-    for _ in range(count):
+    for step in range(count):
+        b = max(1, int(round(fracs[step] * m_total)))
+        b_ins = int(round(0.8 * b))
+        b_del = min(b - b_ins, src.shape[0])
         sel = np.empty(0, dtype=np.int64)
         while sel.shape[0] < b_del:
             c = rng.integers(0, src.shape[0], size=2 * (b_del - sel.shape[0]) + 8)
@@ -313,6 +315,126 @@ def bench_batched(args):
     print(json.dumps(res))
 
 
+SERVING_MIX = ((26, 1), (25, 1), (24, 2), (23, 3), (22, 4), (21, 6), (20, 10), (19, 20), (18, 49))
+
+
+def bench_serving(args):
+    """Serving form: resident R-MAT graphs, Poisson request arrivals, p50/p99
+    latency and updates/s with the server's lanes against one lane (FIFO,
+    one request at a time) on the same graphs."""
+    import threading
+    import torch
+    import paper_2401_15870_amd as dfpr
+    import workloads as W
+
+    mix = [(max(8, sc - args.serving_scale_offset), cnt) for sc, cnt in SERVING_MIX]
+    rates = [float(x) for x in args.rates.split(",")]
+    per_run = args.requests
+    runs = 2 * len(rates)
+    rng = np.random.Generator(np.random.PCG64(args.seed + 77))
+    t0 = time.time()
+    srv = dfpr.Server(int(args.heap_gb * (1 << 30)), lanes=args.lanes)
+    graphs = []  # (gid, n, m, batches)
+    total_req = per_run * runs
+    owners = rng.integers(0, sum(c for _, c in mix), size=total_req)  # graph of every request, uniform
+    fracs = np.exp(rng.uniform(np.log(1e-6), np.log(1e-3), size=total_req))
+    k = 0
+    m_res = 0
+    for sc, cnt in mix:
+        for _ in range(cnt):
+            n, s, d = W.rmat_graph(sc, 16, seed=args.seed * 131 + k)
+            mine = np.nonzero(owners == k)[0]
+            ch = chained_batches(n, s, d, fracs[mine], len(mine), seed=args.seed * 7 + k)
+            g = dfpr.Graph.from_coo(n, torch.from_numpy(s).to("cuda"), torch.from_numpy(d).to("cuda"))
+            m_res += g.m
+            gid = srv.add_graph(g)
+            graphs.append((gid, n, ch))
+            k += 1
+            del s, d
+        log(f"  scale {sc}: {cnt} graphs resident ({time.time() - t0:.0f}s)")
+    log(f"serving: {len(graphs)} graphs, {m_res} edges resident, heap {args.heap_gb:g} GiB, "
+        f"{args.lanes} lanes, setup {time.time() - t0:.0f}s")
+    cursor = [0] * len(graphs)
+    order = list(owners)
+    pos = [0]
+
+    def run(rate, lanes):
+        srv.set_active_lanes(lanes)
+        gaps = rng.exponential(1.0 / rate, size=per_run)
+        reqs = []
+        for _ in range(per_run):
+            gk = int(order[pos[0]])
+            pos[0] += 1
+            reqs.append((gk, graphs[gk][2][cursor[gk]]))
+            cursor[gk] += 1
+        tickets = [None] * per_run
+        lat = [0.0] * per_run
+        edges = [0] * per_run
+
+        span = [0.0, 0.0]
+
+        def submitter():
+            t_start = time.perf_counter()
+            due = 0.0
+            for i, (gk, b) in enumerate(reqs):
+                due += gaps[i]
+                wait = t_start + due - time.perf_counter()
+                if wait > 0:
+                    time.sleep(wait)
+                edges[i] = len(b[0]) + len(b[2])
+                tickets[i] = srv.submit(graphs[gk][0], *b)
+            span[0], span[1] = t_start, time.perf_counter()
+
+        th = threading.Thread(target=submitter)
+        t_begin = time.perf_counter()
+        th.start()
+        for i in range(per_run):
+            while tickets[i] is None:
+                time.sleep(0.0002)
+            _, st, info, lat[i], _ = srv.wait(tickets[i])
+        t_end = time.perf_counter()
+        th.join()
+        el = t_end - t_begin
+        return {"rate_per_s": rate, "arrival_rate_actual": per_run / max(span[1] - span[0], 1e-9), "lanes": lanes,
+                "requests": per_run, "p50_ms": pct(lat, 50),
+                "p99_ms": pct(lat, 99), "mean_ms": float(np.mean(lat)), "updates_per_s": per_run / el,
+                "batch_edges_per_s": sum(edges) / el, "elapsed_s": el}
+
+    results = []
+    for rate in rates:
+        mixr = run(rate, args.lanes)
+        fifo = run(rate, 1)
+        log(f"rate {rate:g}/s: {args.lanes} lanes p50 {mixr['p50_ms']:.2f} p99 {mixr['p99_ms']:.2f} ms "
+            f"{mixr['updates_per_s']:.0f} upd/s | FIFO p50 {fifo['p50_ms']:.2f} p99 {fifo['p99_ms']:.2f} ms "
+            f"{fifo['updates_per_s']:.0f} upd/s")
+        results.append({"rate_per_s": rate, "served": mixr, "fifo": fifo})
+    st = srv.stats()
+    srv.close()
+    best = max(results, key=lambda r: r["served"]["updates_per_s"])
+    res = {
+        "metric": "serving DF-P: p50/p99 update latency and updates/s vs one-at-a-time FIFO",
+        "value": best["served"]["updates_per_s"],
+        "unit": "updates/s",
+        "n_gpus": 1,
+        "steps": per_run,
+        "warmup": 0,
+        "ms_per_step": best["served"]["mean_ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{len(graphs)} resident R-MAT graphs (edge factor 16, scales "
+                               + ", ".join(f"{c}x{sc}" for sc, c in mix) + "), Poisson arrivals, graph uniform, "
+                               "batch f log-uniform in [1e-6, 1e-3] of |E|, 80/20, DF-P per request",
+                   "edges_resident": int(m_res), "lanes": args.lanes, "heap_gib": args.heap_gb,
+                   "requests_per_rate": per_run, "parallelism": "1 GPU"},
+        "by_rate": results,
+        "server_stats": st,
+    }
+    print(json.dumps(res))
+
+
 def summarize_main(args):
     """Print the profile summaries of a profiled run directory (see profiles/)."""
     d = args.summarize
@@ -348,8 +470,15 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--calib", action="store_true",
                     help="finish with three 1 GiB device copies (counter calibration under a profiler)")
-    ap.add_argument("--workload", default="rmat", choices=["rmat", "batched"],
-                    help="rmat: one large R-MAT graph (default); batched: many graphs in one batch handle")
+    ap.add_argument("--workload", default="rmat", choices=["rmat", "batched", "serving"],
+                    help="rmat: one large R-MAT graph (default); batched: many graphs in one batch handle; "
+                         "serving: request loop over resident graphs")
+    ap.add_argument("--rates", default="100,1000,10000", help="serving: Poisson arrival rates per second")
+    ap.add_argument("--requests", type=int, default=1000, help="serving: requests per rate and server setting")
+    ap.add_argument("--lanes", type=int, default=4, help="serving: request lanes")
+    ap.add_argument("--heap-gb", type=float, default=24.0, help="serving: scratch heap (GiB)")
+    ap.add_argument("--serving-scale-offset", type=int, default=0,
+                    help="serving: subtract this from every graph scale (smaller runs)")
     ap.add_argument("--graphs", type=int, default=512, help="batched: number of member graphs")
     ap.add_argument("--summarize", metavar="DIR",
                     help="print summaries of rocprofv3 output under DIR (prof/, pmc_FETCH_SIZE/, pmc_WRITE_SIZE/)")
@@ -373,6 +502,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.workload == "batched":
         bench_batched(args)
+        return
+    if args.workload == "serving":
+        bench_serving(args)
         return
 
     t0 = time.time()

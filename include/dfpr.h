@@ -273,7 +273,7 @@ typedef struct {
   int64_t submitted, completed, failed; /* requests so far                          */
   int64_t queued;                       /* waiting for admission                    */
   int64_t peak_in_flight;               /* most requests running at once            */
-  int32_t in_flight, graphs, lanes, reserved;
+  int32_t in_flight, graphs, lanes, reserved;  /* lanes: active lanes */
   int64_t heap_bytes, heap_used, heap_peak;
 } dfpr_server_stats;
 
@@ -318,7 +318,13 @@ int dfpr_server_ranks(dfpr_server* sv, int32_t gid, double* r_out, dfpr_where wh
 /* Vertex count of graph gid. */
 int dfpr_server_graph_size(dfpr_server* sv, int32_t gid, int32_t* n);
 
+/* Counters, heap use and the number of active lanes. */
 int dfpr_server_get_stats(dfpr_server* sv, dfpr_server_stats* out);
+
+/* Limit how many lanes take new requests (1 <= k <= lanes at create); k = 1
+ * runs requests one at a time in submission order.  Running requests finish
+ * on their lanes.  Errors: EINVAL. */
+int dfpr_server_set_active_lanes(dfpr_server* sv, int32_t k);
 
 /* Thread-local message for the last failing call on this thread ("" if none). */
 const char* dfpr_last_error(void);

@@ -346,6 +346,9 @@ class Server:
         _check(lib().dfpr_server_ranks(self._h, int(gid), ctypes.c_void_p(out.ctypes.data), _capi.HOST))
         return out
 
+    def set_active_lanes(self, k):
+        _check(lib().dfpr_server_set_active_lanes(self._h, int(k)))
+
     def stats(self) -> dict:
         s = _capi.ServerStats()
         _check(lib().dfpr_server_get_stats(self._h, ctypes.byref(s)))

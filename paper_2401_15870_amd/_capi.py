@@ -19,7 +19,8 @@ EXPORTS = ("dfpr_params_default", "dfpr_graph_create", "dfpr_graph_destroy", "df
            "dfpr_get_tuning", "dfpr_autotune", "dfpr_set_timing", "dfpr_batch_create", "dfpr_batch_count",
            "dfpr_batch_member", "dfpr_apply_batch_many", "dfpr_update_ranks_many", "dfpr_server_create",
            "dfpr_server_destroy", "dfpr_server_add_graph", "dfpr_server_submit", "dfpr_server_wait",
-           "dfpr_server_ranks", "dfpr_server_graph_size", "dfpr_server_get_stats", "dfpr_last_error",
+           "dfpr_server_ranks", "dfpr_server_graph_size", "dfpr_server_get_stats", "dfpr_server_set_active_lanes",
+           "dfpr_last_error",
            "dfpr_version")
 
 
@@ -133,6 +134,8 @@ def declare(lib):
     lib.dfpr_server_graph_size.restype = ctypes.c_int
     lib.dfpr_server_get_stats.argtypes = [P, ctypes.POINTER(ServerStats)]
     lib.dfpr_server_get_stats.restype = ctypes.c_int
+    lib.dfpr_server_set_active_lanes.argtypes = [P, i32]
+    lib.dfpr_server_set_active_lanes.restype = ctypes.c_int
     lib.dfpr_last_error.argtypes = []
     lib.dfpr_last_error.restype = ctypes.c_char_p
     lib.dfpr_version.argtypes = []

@@ -371,6 +371,15 @@ int dfpr_server_get_stats(dfpr_server* sv, dfpr_server_stats* out) {
   return server_stats(sv, out);
 }
 
+int dfpr_server_set_active_lanes(dfpr_server* sv, int32_t k) {
+  clear_error();
+  if (!sv) {
+    set_error("null server");
+    return DFPR_EINVAL;
+  }
+  return server_set_active_lanes(sv, k);
+}
+
 int dfpr_set_tuning(dfpr_graph* g, const int32_t bounds[5]) {
   clear_error();
   if (!bounds) {

@@ -311,6 +311,7 @@ int server_wait(dfpr_server* sv, int64_t ticket, dfpr_stats* st, dfpr_batch_info
 int server_ranks(dfpr_server* sv, int32_t gid, double* r_out, dfpr_where where);
 int server_stats(dfpr_server* sv, dfpr_server_stats* out);
 int32_t server_graph_n(dfpr_server* sv, int32_t gid);
+int server_set_active_lanes(dfpr_server* sv, int32_t k);
 
 // ---- ranks (rank.hip)
 int update_ranks(dfpr_graph* g, dfpr_mode mode, const dfpr_params& p, const double* r_prev,

@@ -159,6 +159,7 @@ struct dfpr_server {
   bool stopping = false;
   int64_t next_ticket = 1;
   int32_t in_flight = 0;
+  int32_t active_lanes = 0;  // lanes at or above this index take no new work
   dfpr_server_stats counters{};
 };
 
@@ -231,7 +232,7 @@ void lane_main(dfpr_server* sv, int lane) {
   std::unique_lock<std::mutex> lk(sv->mu);
   for (;;) {
     Request* q = nullptr;
-    sv->cv_work.wait(lk, [&] { return sv->stopping || (q = pick(sv)) != nullptr; });
+    sv->cv_work.wait(lk, [&] { return sv->stopping || (lane < sv->active_lanes && (q = pick(sv)) != nullptr); });
     if (!q) return;  // stopping with nothing admissible
     Resident& r = sv->graphs[q->gid];
     r.busy = true;
@@ -275,6 +276,7 @@ int server_create(size_t heap_bytes, int32_t lanes, dfpr_mode mode, const dfpr_p
     sv->streams.push_back(s);
   }
   DFPR_HIP(hipStreamCreateWithFlags(&sv->ctl_stream, hipStreamNonBlocking));
+  sv->active_lanes = lanes;
   for (int32_t i = 0; i < lanes; i++) sv->lanes.emplace_back(lane_main, sv.get(), i);
   *out = sv.release();
   return DFPR_OK;
@@ -414,10 +416,21 @@ int server_stats(dfpr_server* sv, dfpr_server_stats* out) {
   out->queued = (int64_t)sv->queue.size();
   out->in_flight = sv->in_flight;
   out->graphs = (int32_t)sv->graphs.size();
-  out->lanes = (int32_t)sv->lanes.size();
+  out->lanes = sv->active_lanes;
   out->heap_bytes = (int64_t)sv->heap.capacity();
   out->heap_used = (int64_t)sv->heap.used();
   out->heap_peak = (int64_t)sv->heap.peak();
+  return DFPR_OK;
+}
+
+int server_set_active_lanes(dfpr_server* sv, int32_t k) {
+  std::lock_guard<std::mutex> lk(sv->mu);
+  if (k < 1 || k > (int32_t)sv->lanes.size()) {
+    set_error("active lanes must lie in [1, %d]", (int)sv->lanes.size());
+    return DFPR_EINVAL;
+  }
+  sv->active_lanes = k;
+  sv->cv_work.notify_all();
   return DFPR_OK;
 }
 

@@ -1,0 +1,130 @@
+"""Parity at the full sizes of the benchmark configurations, in the launch
+configuration the benchmark times (autotuned thresholds): CSRs compared in full,
+ranks compared in full against the oracle run from the same previous ranks.
+
+  * one large R-MAT graph: scale 24, edge factor 16, one 80/20 batch of 1e-4|E|;
+  * the temporal stream: 2M vertices, 40M edges, first 90 % as the initial
+    graph, insertion-only batches of 40,000 in time order (first three);
+  * the small-graph configuration: R-MAT scale 14, batches of 1e-3|E| each
+    applied to the same initial graph from the same ranks (Static, ND, DF, DF-P);
+  * the batched configuration's member distribution (64 of its graphs): every
+    member bit-identical to its plain-handle result, the smallest ones also
+    against the oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from gpu_common import LINF, Pair, assert_csr_equal, dfpr, torch_cuda
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+
+def _print(*a):
+    print(*a, flush=True)
+
+
+def test_fullsize_rmat24_dfp():
+    torch_cuda()
+    n, s, d = W.rmat_graph(24, 16, seed=1)
+    _print("rmat24: n", n, "edges", len(s))
+    p = Pair(n, s, d)
+    assert_csr_equal(p.g, p.og)
+    bounds, _ = p.g.autotune()
+    _print("  autotuned", bounds)
+    ref0 = O.rank("static", p.og)
+    r_gpu, st, ref = p.rank("static", None)
+    err0 = float(np.abs(r_gpu - ref0.ranks).max())
+    _print("  static linf", err0, "it", st["iterations"], ref0.iterations)
+    assert err0 <= LINF and st["iterations"] == ref0.iterations
+    ds, dd, is_, id_ = W.batch_8020(n, s, d, 1e-4, seed=1001)
+    p.apply(ds, dd, is_, id_, device=True)
+    assert_csr_equal(p.g, p.og)
+    for mode in ("dfp",):
+        r, st, ref = p.rank(mode, ref0.ranks)
+        err = float(np.abs(r - ref.ranks).max())
+        _print(f"  {mode}: linf {err:.3e} it {st['iterations']}/{ref.iterations} ever {st['ever_affected']}/"
+               f"{ref.ever_affected} dense its {st['dense_iterations']}")
+        assert err <= LINF
+        assert abs(st["iterations"] - ref.iterations) <= 1
+
+
+def test_fullsize_temporal():
+    torch_cuda()
+    n, total = 2_000_000, 40_000_000
+    src, dst = W.temporal_stream(n, total, seed=7)
+    k0 = int(0.9 * len(src))
+    p = Pair(n, src[:k0], dst[:k0])
+    _print("temporal: n", n, "initial edges", p.og.m)
+    assert_csr_equal(p.g, p.og)
+    p.g.autotune()
+    r = O.rank("static", p.og).ranks
+    B = 40_000
+    for i in range(3):
+        lo = k0 + i * B
+        info = p.apply([], [], src[lo:lo + B], dst[lo:lo + B])
+        assert_csr_equal(p.g, p.og)
+        gr, st, ref = p.rank("dfp", r)
+        err = float(np.abs(gr - ref.ranks).max())
+        _print(f"  batch {i}: effective {info['ins_effective']} of {B}, linf {err:.3e}, it {st['iterations']}")
+        assert err <= LINF
+        r = ref.ranks
+
+
+@pytest.mark.parametrize("mode", ["static", "nd", "df", "dfp"])
+def test_fullsize_small_graph(mode):
+    torch_cuda()
+    n, s, d = W.rmat_graph(14, 16, seed=3)
+    og0 = O.graph(n, s, d)
+    r0 = O.rank("static", og0).ranks
+    worst = 0.0
+    for k in range(12):
+        p = Pair(n, s, d)
+        ds, dd, is_, id_ = W.batch_8020(n, s, d, 1e-3, seed=500 + k)
+        p.apply(ds, dd, is_, id_)
+        r, st, ref = p.rank(mode, r0)
+        worst = max(worst, float(np.abs(r - ref.ranks).max()))
+        assert st["converged"] == ref.converged == 1
+    _print(f"small graph {mode}: worst linf over 12 batches {worst:.3e}")
+    assert worst <= LINF
+
+
+def test_fullsize_batched_members():
+    torch = torch_cuda()
+    m = dfpr()
+    rng = np.random.Generator(np.random.PCG64(11))
+    members, fracs = [], []
+    for k in range(64):
+        n = int(round(np.exp(rng.uniform(np.log(1e3), np.log(1e6)))))
+        ef = float(rng.uniform(8, 32))
+        scale = int(np.ceil(np.log2(n)))
+        _, s, d = W.rmat_graph(scale, ef, seed=9000 + k, n_limit=n)
+        members.append((n, s, d))
+        fracs.append(float(np.exp(rng.uniform(np.log(1e-4), np.log(1e-2)))))
+    _print("batched: 64 members,", sum(len(s) for _, s, _ in members), "edges")
+    bg = m.BatchGraph.from_coo(members)
+    bounds, _ = bg.autotune()
+    plain = [m.Graph.from_coo(n, s, d) for n, s, d in members]
+    for g in plain:
+        g.set_tuning(bounds)
+    r, _, _ = bg.update_ranks_many("static", None)
+    r_prev = r.clone()
+    batches = [W.batch_8020(n, s, d, f, seed=9500 + k) for k, ((n, s, d), f) in enumerate(zip(members, fracs))]
+    bg.apply_batch_many(batches)
+    r, tot, per = bg.update_ranks_many("dfp", r_prev)
+    torch.cuda.synchronize()
+    for k, g in enumerate(plain):
+        g.apply_batch(*batches[k])
+        rk, st = g.update_ranks("dfp", bg.member(r_prev, k).clone())
+        assert torch.equal(bg.member(r, k), rk), k
+        assert per[k]["iterations"] == st["iterations"]
+    order = np.argsort([n for n, _, _ in members])[:6]
+    for k in order:
+        n, s, d = members[k]
+        og = O.graph(n, s, d)
+        og2, ob = O.apply(og, *batches[k])
+        rp = bg.member(r_prev, k).cpu().numpy()
+        ref = O.rank("dfp", og2, rp, og, ob)
+        err = float(np.abs(bg.member(r, k).cpu().numpy() - ref.ranks).max())
+        assert err <= LINF, (k, err)

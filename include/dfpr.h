@@ -189,6 +189,15 @@ int dfpr_get_tuning(const dfpr_graph* g, int32_t bounds[5]);
  * memory for one rank vector; pending batch marks are left untouched. */
 int dfpr_autotune(dfpr_graph* g, void* stream, int32_t bounds_out[5], double* ms_out);
 
+/* Graphs of at most max_edges edges (self-loops included) run a whole rank
+ * update in one cooperative launch: every iteration's pull over all vertices
+ * (DF/DF-P in the dense form), a grid-wide barrier, and the stopping test on
+ * the device, instead of several launches and a readback per iteration.  The
+ * results are the same bits either way (same kernels, same work split); only
+ * the latency changes.  Default 4194304; 0 disables.  Batch handles always use
+ * the launch-per-iteration loop.  Errors: EINVAL (max_edges < 0). */
+int dfpr_set_fused_limit(dfpr_graph* g, int64_t max_edges);
+
 /* Turn HIP-event timing of every apply and update on this graph on (1) or
  * off (0).  Events are recorded between kernels and read after the call's
  * final synchronisation, so timing adds no host round trips. */

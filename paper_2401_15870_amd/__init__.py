@@ -172,6 +172,10 @@ class Graph:
         _check(lib().dfpr_autotune(self._h, _stream_ptr(stream), arr, ctypes.byref(ms)))
         return list(arr), ms.value
 
+    def set_fused_limit(self, max_edges):
+        """Edge count up to which a rank update runs in one cooperative launch (0: never)."""
+        _check(lib().dfpr_set_fused_limit(self._h, int(max_edges)))
+
     def set_timing(self, on=True):
         _check(lib().dfpr_set_timing(self._h, 1 if on else 0))
 

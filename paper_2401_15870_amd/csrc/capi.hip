@@ -406,6 +406,18 @@ int dfpr_autotune(dfpr_graph* g, void* stream, int32_t bounds_out[5], double* ms
   return guarded(g, [&] { return autotune(g, (hipStream_t)stream, bounds_out, ms_out); });
 }
 
+int dfpr_set_fused_limit(dfpr_graph* g, int64_t max_edges) {
+  clear_error();
+  if (max_edges < 0) {
+    set_error("max_edges must be >= 0");
+    return DFPR_EINVAL;
+  }
+  return guarded(g, [&] {
+    g->fused_limit = max_edges;
+    return (int)DFPR_OK;
+  });
+}
+
 int dfpr_set_timing(dfpr_graph* g, int on) {
   clear_error();
   return guarded(g, [&] {

@@ -174,6 +174,10 @@ struct IterCtl {
   int64_t active;            // member graphs not yet converged (1/0 for a plain graph)
   int64_t pad[2];
   unsigned long long acc_slots[kAccRows][kSlots * kSlotStride];
+  // single-launch loop: L-inf change of iteration i in fused_dr[(i % 3) * kSlotStride]
+  unsigned long long fused_dr[3 * kSlotStride];
+  int64_t fused_iters, fused_converged;
+  unsigned long long fused_last;
 };
 constexpr size_t kCtlHead = offsetof(IterCtl, pad);
 
@@ -250,6 +254,7 @@ struct dfpr_graph {
   int32_t* arrive = nullptr;  // n: per-vertex chunk arrival counters of bin 5
   int32_t* partial_x = nullptr;  // per-chunk "an in-neighbour expanded" flags (dense mode)
   bool timing = false;        // record HIP-event timings of every call
+  int64_t fused_limit = 1 << 22;  // run whole updates in one launch up to this many edges (0: never)
   dfpr::EventPool pool;
   // vertex-proportional scratch of apply and rank updates, carved from one block
   void* scratch = nullptr;

@@ -19,6 +19,8 @@
 // and no reduction funnels the whole chip into one atomic address.
 #include <algorithm>
 
+#include <hip/hip_cooperative_groups.h>
+
 #include "prim.hpp"
 
 namespace dfpr {
@@ -422,8 +424,76 @@ __device__ __forceinline__ void pull_chunks(const PullArgs& a, const int32_t* __
 }
 
 template <int MODE, bool DENSE>
+__device__ __forceinline__ void pull_virtual_block(const PullArgs& a, const int32_t* __restrict__ wl,
+                                                   const PullLayout& L, int b);
+
+template <int MODE, bool DENSE>
 __global__ void __launch_bounds__(256, 8) k_pull(PullArgs a, const int32_t* __restrict__ wl, PullLayout L) {
-  const int b = blockIdx.x;
+  pull_virtual_block<MODE, DENSE>(a, wl, L, blockIdx.x);
+}
+
+// Whole update in one cooperative launch (small graphs, where launch and
+// readback latency dominate): every iteration runs the pull of the layout's
+// workgroups (the same code and work split as k_pull, so the sums and ranks
+// are the same bits) spread over the resident workgroups, then one grid
+// barrier; every workgroup reads the iteration's L-inf change and stops at the
+// same iteration.  Ranks, contributions and (DF, DF-P, dense form) keep/expand
+// flags ping-pong.  The change of iteration i goes to slot i % 3: workgroup 0
+// clears slot i+1 at the start of iteration i, which no workgroup reads or
+// writes until after the barrier that ends iteration i.
+template <int MODE>
+__global__ void __launch_bounds__(256, 8) k_fused_loop(PullArgs a0, const int32_t* __restrict__ wl, PullLayout L,
+                                                       IterCtl* c, int max_iters, double tol) {
+  constexpr bool DENSE = MODE != kSync;
+  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+  PullArgs a = a0;
+  a.gsub = 1;
+  a.gid = nullptr;
+  a.done = nullptr;
+  const int nvb = L.blk[kBins];
+  for (int it = 0; it < max_iters; it++) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) c->fused_dr[((it + 1) % 3) * kSlotStride] = 0ull;
+    a.gslots = &c->fused_dr[(it % 3) * kSlotStride];
+    for (int vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
+      pull_virtual_block<MODE, DENSE>(a, wl, L, vb);
+      __syncthreads();
+    }
+    grid.sync();
+    const unsigned long long m = __hip_atomic_load(&c->fused_dr[(it % 3) * kSlotStride], __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+    double d;
+    __builtin_memcpy(&d, &m, sizeof d);
+    // next iteration reads what this one wrote
+    double* t = a.R;
+    a.R = a.Rw;
+    a.Rw = t;
+    t = const_cast<double*>(a.contrib);
+    a.contrib = a.cw;
+    a.cw = t;
+    if (DENSE) {
+      uint8_t* f = const_cast<uint8_t*>(a.stay_in);
+      a.stay_in = a.stay_out;
+      a.stay_out = f;
+      f = const_cast<uint8_t*>(a.x_in);
+      a.x_in = a.x_out;
+      a.x_out = f;
+      a.use_x = 1;
+    }
+    const bool stop = d <= tol;
+    if (stop || it + 1 == max_iters) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        c->fused_iters = it + 1;
+        c->fused_converged = stop ? 1 : 0;
+        c->fused_last = m;
+      }
+      break;
+    }
+  }
+}
+
+template <int MODE, bool DENSE>
+__device__ __forceinline__ void pull_virtual_block(const PullArgs& a, const int32_t* __restrict__ wl,
+                                                   const PullLayout& L, int b) {
   int k = 0;
   while (k < kBins - 1 && b >= L.blk[k + 1]) k++;
   const int lb = b - L.blk[k], nb = L.blk[k + 1] - L.blk[k];
@@ -1030,6 +1100,61 @@ static PullArgs make_args(dfpr_graph* g, const dfpr_params& p) {
 
 static int ensure_all_bins(dfpr_graph* g, hipStream_t s);
 
+// Whole-update single launch for small plain graphs (see k_fused_loop).
+static bool use_fused(const dfpr_graph* g) { return g->ngraphs == 1 && g->fused_limit > 0 && g->m <= g->fused_limit; }
+
+struct FusedResult {
+  int iters = 0;
+  bool converged = false;
+  double last = 0.0;
+};
+
+template <int MODE>
+static int fused_run(dfpr_graph* g, const dfpr_params& p, PullArgs a, hipStream_t s, dfpr_stats* st,
+                     FusedResult* out) {
+  DFPR_TRY(ensure_all_bins(g, s));
+  PullLayout L;
+  make_layout(g->all_bin_end, g->all_bin_edges, &L);
+  const int64_t n5 = L.hi[kBins - 1] - L.lo[kBins - 1];
+  if (n5 > 0 && !g->all_chunks_valid)
+    DFPR_TRY(scan_generic(LoadChunks{g->all_bins, g->in.off, L.lo[kBins - 1]}, StoreChunk{g->all_chunk_pre}, n5,
+                          g->scan_tmp, s));
+  g->all_chunks_valid = true;
+  a.chunk_pre = g->all_chunk_pre;
+  static int per_cu = -1, cus = 0;
+  if (per_cu < 0) {
+    int dev = 0;
+    DFPR_HIP(hipGetDevice(&dev));
+    DFPR_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    DFPR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_fused_loop<MODE>),
+                                                          256, 0));
+  }
+  const int grid = std::max(1, std::min(std::max(per_cu, 1) * cus, (int)L.blk[kBins]));
+  const int32_t* wl = g->all_bins;
+  IterCtl* c = g->ctl;
+  int mi = p.max_iters;
+  double tol = p.tol;
+  void* args[] = {&a, &wl, &L, &c, &mi, &tol};
+  size_t tok;
+  DFPR_TRY(g->pool.start(&tok));
+  DFPR_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_fused_loop<MODE>), dim3(grid), dim3(256), args,
+                                      0, s));
+  DFPR_TRY(g->pool.stop(kTPull0, tok));
+  st->pull_launches++;
+  // fold the dense counters and read the loop's outcome
+  k_iter_finish<<<1, kSlots, 0, s>>>(g->ctl);
+  DFPR_HIP(hipGetLastError());
+  const size_t lo = offsetof(IterCtl, fused_iters), hi = offsetof(IterCtl, fused_last) + sizeof(unsigned long long);
+  DFPR_HIP(hipMemcpyAsync(reinterpret_cast<char*>(g->ctl_host) + lo, reinterpret_cast<char*>(g->ctl) + lo, hi - lo,
+                          hipMemcpyDeviceToHost, s));
+  DFPR_HIP(hipMemcpyAsync(g->ctl_host, g->ctl, kCtlHead, hipMemcpyDeviceToHost, s));
+  DFPR_HIP(hipStreamSynchronize(s));
+  out->iters = (int)g->ctl_host->fused_iters;
+  out->converged = g->ctl_host->fused_converged != 0;
+  out->last = bits_to_double(g->ctl_host->fused_last);
+  return DFPR_OK;
+}
+
 static int run_sync(dfpr_graph* g, bool cold, const dfpr_params& p, const double* r_prev, double* r_out,
                     hipStream_t s, dfpr_stats* st) {
   const int32_t n = g->n;
@@ -1049,7 +1174,22 @@ static int run_sync(dfpr_graph* g, bool cold, const dfpr_params& p, const double
   int it = 0;
   double dR = 0.0;
   bool conv = false;
-  for (it = 0; it < p.max_iters; it++) {
+  if (use_fused(g)) {
+    a.R = Ra;
+    a.Rw = Rb;
+    a.contrib = ca;
+    a.cw = cb;
+    FusedResult fr;
+    DFPR_TRY(fused_run<kSync>(g, p, a, s, st, &fr));
+    it = fr.iters;
+    conv = fr.converged;
+    dR = fr.last;
+    st->vertex_updates += (int64_t)it * n;
+    st->edges_pulled += (int64_t)it * g->m;
+    st->pull_bytes += (double)it * (36.0 * n + 12.0 * (double)g->m);
+    if (it & 1) std::swap(Ra, Rb);
+  }
+  for (; !conv && it < p.max_iters; it++) {
     a.contrib = ca;
     a.R = Ra;
     a.Rw = Rb;
@@ -1136,6 +1276,41 @@ static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_pre
   DFPR_TRY(mark_big(g, g->flag_cur, s));
   DFPR_TRY(g->pool.stop(kTMark, tok));
   g->pending_any = false;
+  if (use_fused(g)) {
+    // every iteration in the dense form, all in one launch
+    PullArgs a = make_args(g, p);
+    a.R = Ra;
+    a.Rw = Rb;
+    a.contrib = ca;
+    a.cw = cb;
+    a.stay_in = g->flag_cur;
+    a.x_in = g->xflag;
+    a.stay_out = g->flag_next;
+    a.x_out = g->xflag2;
+    a.ever = g->ever;
+    a.use_x = 0;
+    FusedResult fr;
+    DFPR_TRY(fused_run<MODE>(g, p, a, s, st, &fr));
+    const IterCtl* h = g->ctl_host;
+    st->vertex_updates += h->dense_cnt;
+    st->edges_pulled += h->dense_edges;
+    st->pull_bytes += (double)fr.iters * (31.0 * n + 5.0 * (double)m) + 8.0 * (double)h->dense_edges;
+    st->dense_iterations += fr.iters;
+    double* Rf = (fr.iters & 1) ? Rb : Ra;
+    if (g->perm)
+      k_scatter_ranks<<<gi, 256, 0, s>>>(Rf, g->inv, r_out, n);
+    else if (Rf != r_out)
+      DFPR_HIP(hipMemcpyAsync(r_out, Rf, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    for (uint8_t* f : {g->flag_cur, g->flag_next, g->xflag, g->xflag2}) k_fill_u8<<<gi, 256, 0, s>>>(f, n, 0);
+    k_count_clear_ever<<<gi, 256, 0, s>>>(g->ever, n, &g->ctl->acc_slots[0][0]);
+    DFPR_HIP(hipGetLastError());
+    DFPR_TRY(finish_and_read(g, s));
+    st->iterations = fr.iters;
+    st->converged = fr.converged ? 1 : 0;
+    st->last_delta = fr.last;
+    st->ever_affected = g->ctl_host->ever_count;
+    return DFPR_OK;
+  }
   DFPR_TRY(bin_vertices(g, g->flag_cur, g->worklist, g->ever, s));
   DFPR_TRY(finish_and_read(g, s));
   uint8_t *cur = g->flag_cur, *next = g->flag_next, *xa = g->xflag, *xb = g->xflag2;

@@ -37,10 +37,14 @@ def assert_info_equal(info, ob):
 class Pair:
     """One graph on both sides, updated in lock-step."""
 
-    def __init__(self, n, src, dst, **kw):
+    def __init__(self, n, src, dst, fused=False, **kw):
+        """fused=False keeps the launch-per-iteration loop on small graphs too
+        (the library default runs them in one launch; both give the same bits)."""
         self.dfpr = dfpr()
         self.og = O.graph(n, src, dst)
         self.g = self.dfpr.Graph.from_coo(n, src, dst, **kw)
+        if not fused:
+            self.g.set_fused_limit(0)
         self.kw = kw
         self.og_prev = None
         self.batch = None

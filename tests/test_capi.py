@@ -50,6 +50,8 @@ def test_invalid_arguments_rejected_before_device_work(lib):
     st = _capi.Stats()
     assert lib.dfpr_update_ranks(None, 3, None, None, None, None, ctypes.byref(st)) == _capi.DFPR_EINVAL
     assert lib.dfpr_set_tuning(None, (ctypes.c_int32 * 5)(4, 8, 16, 32, 64)) == _capi.DFPR_EINVAL
+    assert lib.dfpr_set_fused_limit(None, -1) == _capi.DFPR_EINVAL
+    assert lib.dfpr_set_fused_limit(None, 5) == _capi.DFPR_EINVAL
     assert lib.dfpr_apply_batch(None, -1, None, None, 0, None, None, 0, None, None) == _capi.DFPR_EINVAL
     assert lib.dfpr_graph_destroy(None) == _capi.DFPR_OK
     # batched form

@@ -275,3 +275,66 @@ def test_temporal_chain():
         gr, st, ref = p.rank("dfp", r)
         assert np.abs(gr - ref.ranks).max() <= LINF
         r = ref.ranks
+
+
+# ------------------------------------------------------------------ single-launch loop
+def _fused_pair_case(case):
+    if case == "rmat12":
+        return rmat(12, seed=21)
+    if case == "rmat14":
+        return rmat(14, seed=22)
+    if case == "hub":
+        return hub_graph(20000, 9000, 12000, 60000, seed=23)
+    if case == "tiny":
+        s, d = W.random_digraph(40, 0.1, seed=24)
+        return 40, s, d
+    return 1, np.zeros(0, np.int32), np.zeros(0, np.int32)
+
+
+@pytest.mark.parametrize("bounds", [None, [1, 2, 3, 4, 5]])
+@pytest.mark.parametrize("mode", ["static", "nd", "df", "dfp"])
+@pytest.mark.parametrize("case", ["rmat12", "rmat14", "hub", "tiny", "single"])
+def test_fused_loop_matches_launch_loop(case, mode, bounds):
+    """One cooperative launch per update gives the same bits as the
+    launch-per-iteration loop (same kernels, same work split), and the oracle's
+    ranks within the bar."""
+    torch_cuda()
+    n, s, d = _fused_pair_case(case)
+    res = []
+    for fused in (False, True):
+        p = Pair(n, s, d, fused=fused)
+        if bounds:
+            p.g.set_tuning(bounds)
+        r0 = O.rank("static", p.og).ranks
+        if len(s):
+            ds, dd, is_, id_ = W.batch_8020(n, s, d, 2e-3, seed=25)
+        else:
+            ds = dd = np.zeros(0, np.int32)
+            is_ = id_ = np.zeros(0, np.int32)
+        p.apply(ds, dd, is_, id_)
+        r, st, ref = p.rank(mode, None if mode == "static" else r0)
+        assert np.abs(r - ref.ranks).max() <= LINF
+        res.append((r, st))
+    (r1, s1), (r2, s2) = res
+    assert np.array_equal(r1, r2), float(np.abs(r1 - r2).max())
+    for k in ("iterations", "converged", "last_delta", "ever_affected", "vertex_updates", "edges_pulled"):
+        assert s1[k] == s2[k], (k, s1[k], s2[k])
+    assert s2["pull_launches"] == 1
+
+
+@pytest.mark.parametrize("mode", ["static", "dfp"])
+def test_fused_loop_iteration_cap(mode):
+    """Stopping at max_iters (not converged) happens at the same iteration on both paths."""
+    torch_cuda()
+    n, s, d = rmat(12, seed=26)
+    out = []
+    for fused in (False, True):
+        p = Pair(n, s, d, fused=fused)
+        r0 = O.rank("static", p.og).ranks
+        ds, dd, is_, id_ = W.batch_8020(n, s, d, 1e-2, seed=27)
+        p.apply(ds, dd, is_, id_)
+        r, st, ref = p.rank(mode, None if mode == "static" else r0, max_iters=3)
+        assert st["iterations"] == ref.iterations == 3 and st["converged"] == ref.converged == 0
+        assert np.abs(r - ref.ranks).max() <= LINF
+        out.append(r)
+    assert np.array_equal(out[0], out[1])

@@ -178,6 +178,12 @@ struct IterCtl {
   unsigned long long fused_dr[3 * kSlotStride];
   int64_t fused_iters, fused_converged;
   unsigned long long fused_last;
+  int64_t fused_err;  // grid barrier gave up waiting (never expected)
+  // grid barrier of the single-launch loop: 16 group counters, a root counter
+  // and a generation, each on its own 128-byte line
+  unsigned bar_leaf[16 * 32];
+  unsigned bar_root[32];
+  unsigned bar_gen[32];
 };
 constexpr size_t kCtlHead = offsetof(IterCtl, pad);
 

@@ -19,8 +19,6 @@
 // and no reduction funnels the whole chip into one atomic address.
 #include <algorithm>
 
-#include <hip/hip_cooperative_groups.h>
-
 #include "prim.hpp"
 
 namespace dfpr {
@@ -441,11 +439,59 @@ __global__ void __launch_bounds__(256, 8) k_pull(PullArgs a, const int32_t* __re
 // flags ping-pong.  The change of iteration i goes to slot i % 3: workgroup 0
 // clears slot i+1 at the start of iteration i, which no workgroup reads or
 // writes until after the barrier that ends iteration i.
+// Grid barrier for a launch whose workgroups are all resident (cooperative
+// launch): workgroups arrive at one of 16 group counters, the last of each
+// group at the root counter, and the last of all bumps the generation the
+// others wait on.  Two levels keep each counter's atomics few (one counter for
+// the whole grid serialises every workgroup's atomic).  Each workgroup flushes
+// its writes (fence) before arriving; the acquire by thread 0 after the wait
+// makes the others' writes visible to the workgroup.  The wait is bounded: on
+// a timeout it raises c->fused_err and every workgroup leaves the loop.
+constexpr int kBarGroups = 16;
+__device__ __forceinline__ bool grid_barrier(IterCtl* c, unsigned nb) {
+  __threadfence();
+  __syncthreads();
+  __shared__ int ok_sh;
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    unsigned* gen = &c->bar_gen[0];
+    const unsigned g0 = __hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned grp = blockIdx.x % kBarGroups;
+    const unsigned groups = nb < (unsigned)kBarGroups ? nb : (unsigned)kBarGroups;
+    const unsigned gsize = nb / kBarGroups + (grp < nb % kBarGroups ? 1u : 0u);
+    unsigned* leaf = &c->bar_leaf[grp * 32];
+    bool released = false;
+    if (__hip_atomic_fetch_add(leaf, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == gsize - 1) {
+      __hip_atomic_store(leaf, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      unsigned* root = &c->bar_root[0];
+      if (__hip_atomic_fetch_add(root, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == groups - 1) {
+        __hip_atomic_store(root, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        released = true;
+      }
+    }
+    if (!released) {
+      int64_t spins = 0;
+      while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g0) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > ((int64_t)1 << 26) ||
+            __hip_atomic_load(&c->fused_err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+          __hip_atomic_store(&c->fused_err, (int64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          ok = 0;
+          break;
+        }
+      }
+    }
+    ok_sh = ok;
+  }
+  __syncthreads();
+  return ok_sh != 0;
+}
+
 template <int MODE>
 __global__ void __launch_bounds__(256, 8) k_fused_loop(PullArgs a0, const int32_t* __restrict__ wl, PullLayout L,
                                                        IterCtl* c, int max_iters, double tol) {
   constexpr bool DENSE = MODE != kSync;
-  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
   PullArgs a = a0;
   a.gsub = 1;
   a.gid = nullptr;
@@ -458,7 +504,7 @@ __global__ void __launch_bounds__(256, 8) k_fused_loop(PullArgs a0, const int32_
       pull_virtual_block<MODE, DENSE>(a, wl, L, vb);
       __syncthreads();
     }
-    grid.sync();
+    if (!grid_barrier(c, gridDim.x)) return;
     const unsigned long long m = __hip_atomic_load(&c->fused_dr[(it % 3) * kSlotStride], __ATOMIC_RELAXED,
                                                    __HIP_MEMORY_SCOPE_AGENT);
     double d;
@@ -1129,7 +1175,10 @@ static int fused_run(dfpr_graph* g, const dfpr_params& p, PullArgs a, hipStream_
     DFPR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_fused_loop<MODE>),
                                                           256, 0));
   }
-  const int grid = std::max(1, std::min(std::max(per_cu, 1) * cus, (int)L.blk[kBins]));
+  // the barrier costs grow with the workgroup count: a small graph's pull
+  // needs few workgroups anyway
+  constexpr int kFusedMaxGrid = 128;
+  const int grid = std::max(1, std::min({std::max(per_cu, 1) * cus, (int)L.blk[kBins], kFusedMaxGrid}));
   const int32_t* wl = g->all_bins;
   IterCtl* c = g->ctl;
   int mi = p.max_iters;
@@ -1144,11 +1193,15 @@ static int fused_run(dfpr_graph* g, const dfpr_params& p, PullArgs a, hipStream_
   // fold the dense counters and read the loop's outcome
   k_iter_finish<<<1, kSlots, 0, s>>>(g->ctl);
   DFPR_HIP(hipGetLastError());
-  const size_t lo = offsetof(IterCtl, fused_iters), hi = offsetof(IterCtl, fused_last) + sizeof(unsigned long long);
+  const size_t lo = offsetof(IterCtl, fused_iters), hi = offsetof(IterCtl, fused_err) + sizeof(int64_t);
   DFPR_HIP(hipMemcpyAsync(reinterpret_cast<char*>(g->ctl_host) + lo, reinterpret_cast<char*>(g->ctl) + lo, hi - lo,
                           hipMemcpyDeviceToHost, s));
   DFPR_HIP(hipMemcpyAsync(g->ctl_host, g->ctl, kCtlHead, hipMemcpyDeviceToHost, s));
   DFPR_HIP(hipStreamSynchronize(s));
+  if (g->ctl_host->fused_err) {
+    set_error("single-launch rank loop: grid barrier timed out");
+    return DFPR_EHIP;
+  }
   out->iters = (int)g->ctl_host->fused_iters;
   out->converged = g->ctl_host->fused_converged != 0;
   out->last = bits_to_double(g->ctl_host->fused_last);

@@ -156,6 +156,13 @@ def load(path: str | None = None):
     p = path or LIB_PATH
     if not os.path.exists(p):
         raise ImportError(f"dfpr HIP library not built: {p} is missing (run __graft_entry__.build())")
+    # One HIP runtime per process: torch carries its own copy of the runtime
+    # (same soname); loading it first lets the library bind to that copy
+    # instead of pulling in a second runtime, which would then see no device.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = declare(ctypes.CDLL(p))
     if path is None:
         _lib = lib

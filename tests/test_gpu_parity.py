@@ -338,3 +338,18 @@ def test_fused_loop_iteration_cap(mode):
         assert np.abs(r - ref.ranks).max() <= LINF
         out.append(r)
     assert np.array_equal(out[0], out[1])
+
+
+def test_library_loaded_before_torch_initialises():
+    """A fresh process that loads the library before torch has touched the GPU
+    still finds the device (one HIP runtime per process)."""
+    import subprocess
+    import sys
+    import os
+    code = ("import numpy as np, paper_2401_15870_amd as m; m.lib(); "
+            "g = m.Graph.from_coo(4, np.array([0, 1, 2], np.int32), np.array([1, 2, 3], np.int32)); "
+            "print('edges', g.m)")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stderr[-2000:]
+    assert "edges 7" in out.stdout

@@ -179,9 +179,9 @@ struct IterCtl {
   int64_t fused_iters, fused_converged;
   unsigned long long fused_last;
   int64_t fused_err;  // grid barrier gave up waiting (never expected)
-  // grid barrier of the single-launch loop: 16 group counters, a root counter
+  // grid barrier of the single-launch loop: 32 group counters, a root counter
   // and a generation, each on its own 128-byte line
-  unsigned bar_leaf[16 * 32];
+  unsigned bar_leaf[32 * 32];
   unsigned bar_root[32];
   unsigned bar_gen[32];
 };

@@ -440,22 +440,23 @@ __global__ void __launch_bounds__(256, 8) k_pull(PullArgs a, const int32_t* __re
 // clears slot i+1 at the start of iteration i, which no workgroup reads or
 // writes until after the barrier that ends iteration i.
 // Grid barrier for a launch whose workgroups are all resident (cooperative
-// launch): workgroups arrive at one of 16 group counters, the last of each
+// launch): workgroups arrive at one of 32 group counters, the last of each
 // group at the root counter, and the last of all bumps the generation the
 // others wait on.  Two levels keep each counter's atomics few (one counter for
-// the whole grid serialises every workgroup's atomic).  Each workgroup flushes
-// its writes (fence) before arriving; the acquire by thread 0 after the wait
-// makes the others' writes visible to the workgroup.  The wait is bounded: on
-// a timeout it raises c->fused_err and every workgroup leaves the loop.
-constexpr int kBarGroups = 16;
+// the whole grid serialises every workgroup's atomic).  Memory ordering: the
+// workgroup barrier completes the workgroup's stores, thread 0's arrival is a
+// release at device scope (it publishes them), the wait polls with relaxed
+// loads and ends with one acquire fence (so the workgroup then reads the other
+// workgroups' stores).  The wait is bounded: on a timeout it raises
+// c->fused_err and every workgroup leaves the loop.
+constexpr int kBarGroups = 32;
 __device__ __forceinline__ bool grid_barrier(IterCtl* c, unsigned nb) {
-  __threadfence();
   __syncthreads();
   __shared__ int ok_sh;
   if (threadIdx.x == 0) {
     int ok = 1;
     unsigned* gen = &c->bar_gen[0];
-    const unsigned g0 = __hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned g0 = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const unsigned grp = blockIdx.x % kBarGroups;
     const unsigned groups = nb < (unsigned)kBarGroups ? nb : (unsigned)kBarGroups;
     const unsigned gsize = nb / kBarGroups + (grp < nb % kBarGroups ? 1u : 0u);
@@ -472,7 +473,7 @@ __device__ __forceinline__ bool grid_barrier(IterCtl* c, unsigned nb) {
     }
     if (!released) {
       int64_t spins = 0;
-      while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g0) {
+      while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g0) {
         __builtin_amdgcn_s_sleep(1);
         if (++spins > ((int64_t)1 << 26) ||
             __hip_atomic_load(&c->fused_err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
@@ -482,6 +483,7 @@ __device__ __forceinline__ bool grid_barrier(IterCtl* c, unsigned nb) {
         }
       }
     }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     ok_sh = ok;
   }
   __syncthreads();
@@ -1175,10 +1177,7 @@ static int fused_run(dfpr_graph* g, const dfpr_params& p, PullArgs a, hipStream_
     DFPR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_fused_loop<MODE>),
                                                           256, 0));
   }
-  // the barrier costs grow with the workgroup count: a small graph's pull
-  // needs few workgroups anyway
-  constexpr int kFusedMaxGrid = 128;
-  const int grid = std::max(1, std::min({std::max(per_cu, 1) * cus, (int)L.blk[kBins], kFusedMaxGrid}));
+  const int grid = std::max(1, std::min(std::max(per_cu, 1) * cus, (int)L.blk[kBins]));
   const int32_t* wl = g->all_bins;
   IterCtl* c = g->ctl;
   int mi = p.max_iters;

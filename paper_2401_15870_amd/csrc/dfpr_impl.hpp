@@ -156,7 +156,8 @@ enum AccRow : int {
   kAccCnt = kBins + 1,     // dense pull: affected vertices
   kAccAffEdges = kBins + 2,// dense pull: summed in-degree of the affected vertices
   kAccXEdges = kBins + 3,  // dense pull: summed out-degree of the expanding vertices
-  kAccRows = kBins + 4
+  kAccStayEdges = kBins + 4,  // dense pull: summed in-degree of the kept vertices
+  kAccRows = kBins + 5
 };
 
 // Per-update control block in device memory.  The compact head is read back
@@ -171,6 +172,7 @@ struct IterCtl {
   int64_t dense_cnt;         // dense pull: affected vertices of the last iteration
   int64_t dense_edges;       // dense pull: their summed in-degree
   int64_t dense_xedges;      // dense pull: summed out-degree of its expanding vertices
+  int64_t dense_sedges;      // dense pull: summed in-degree of its kept vertices
   int64_t active;            // member graphs not yet converged (1/0 for a plain graph)
   int64_t pad[2];
   unsigned long long acc_slots[kAccRows][kSlots * kSlotStride];

@@ -118,7 +118,8 @@ __device__ __forceinline__ void gtab_max(GTab* t, int g, double x, unsigned long
 // Per-thread accumulators of one pull launch.
 struct Acc {
   double mx = 0.0;                          // L-inf change (plain graph)
-  int64_t cnt = 0, aedges = 0, xedges = 0;  // dense: affected, their in-edges, expander out-edges
+  int64_t cnt = 0, aedges = 0, xedges = 0, sedges = 0;  // dense: affected, their in-edges, expander
+                                                        // out-edges, kept vertices' in-edges
   GTab* tab = nullptr;                      // per-member maxima (batch)
 };
 __device__ __forceinline__ void acc_dr(Acc& acc, const PullArgs& a, int g, double dr) {
@@ -169,6 +170,7 @@ __device__ __forceinline__ void vertex_finish(const PullArgs& a, const VCtx& x, 
     acc.cnt++;
     acc.aedges += x.e - x.s;
     if (expand) acc.xedges += (int64_t)d;
+    if (stay) acc.sedges += x.e - x.s;
   } else {
     a.R[x.v] = r;
     if (stay) a.next[x.v] = 1;
@@ -181,20 +183,22 @@ __device__ __forceinline__ void vertex_finish(const PullArgs& a, const VCtx& x, 
 template <bool DENSE>
 __device__ __forceinline__ void block_acc_to_slots(Acc acc, const PullArgs& a) {
   __shared__ double shm[1024 / kWave];
-  __shared__ int64_t shc[3][1024 / kWave];
+  __shared__ int64_t shc[4][1024 / kWave];
   const int w = threadIdx.x / kWave;
   const double m = wave_max(acc.mx);
-  int64_t c0 = 0, c1 = 0, c2 = 0;
+  int64_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
   if (DENSE) {
     c0 = wave_sum_i64(acc.cnt);
     c1 = wave_sum_i64(acc.aedges);
     c2 = wave_sum_i64(acc.xedges);
+    c3 = wave_sum_i64(acc.sedges);
   }
   if (lane_id() == 0) {
     shm[w] = m;
     shc[0][w] = c0;
     shc[1][w] = c1;
     shc[2][w] = c2;
+    shc[3][w] = c3;
   }
   __syncthreads();
   if (acc.tab) {  // batch: flush the per-member maxima (all threads reached the barrier above)
@@ -204,12 +208,13 @@ __device__ __forceinline__ void block_acc_to_slots(Acc acc, const PullArgs& a) {
   }
   if (threadIdx.x == 0) {
     double mm = 0.0;
-    int64_t t0 = 0, t1 = 0, t2 = 0;
+    int64_t t0 = 0, t1 = 0, t2 = 0, t3 = 0;
     for (int i = 0; i < (int)(blockDim.x / kWave); i++) {
       mm = fmax(mm, shm[i]);
       t0 += shc[0][i];
       t1 += shc[1][i];
       t2 += shc[2][i];
+      t3 += shc[3][i];
     }
     const int slot = (blockIdx.x % kSlots) * kSlotStride;
     if (mm > 0.0)
@@ -219,6 +224,7 @@ __device__ __forceinline__ void block_acc_to_slots(Acc acc, const PullArgs& a) {
       if (t0) atomicAdd(&a.acc[kAccCnt * kRow + slot], (unsigned long long)t0);
       if (t1) atomicAdd(&a.acc[kAccAffEdges * kRow + slot], (unsigned long long)t1);
       if (t2) atomicAdd(&a.acc[kAccXEdges * kRow + slot], (unsigned long long)t2);
+      if (t3) atomicAdd(&a.acc[kAccStayEdges * kRow + slot], (unsigned long long)t3);
     }
   }
 }
@@ -925,6 +931,7 @@ __global__ void __launch_bounds__(kSlots) k_iter_finish(IterCtl* c) {
     c->dense_cnt = r[kAccCnt];
     c->dense_edges = r[kAccAffEdges];
     c->dense_xedges = r[kAccXEdges];
+    c->dense_sedges = r[kAccStayEdges];
     c->big_count = 0;
   }
 }
@@ -1412,7 +1419,13 @@ static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_pre
       std::swap(cur, next);  // cur = keep flags of the next iteration
       std::swap(xa, xb);     // xa = expand flags of this iteration
       use_x = true;
-      front_edges = h->dense_edges;  // next frontier about as large as this one
+      // next frontier: the kept vertices (affected again for sure) plus the
+      // out-neighbours of the expanding ones, whose in-degrees are estimated
+      // by the mean; switch back to the frontier form when that is small (the
+      // dense form scans every vertex's in-neighbour flags however few
+      // vertices are affected)
+      front_edges = std::min<int64_t>(
+          m, h->dense_sedges + (int64_t)((double)h->dense_xedges * ((double)m / (double)n)));
       if (h->active == 0) {
         conv = true;
         it++;

@@ -1431,7 +1431,7 @@ static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_pre
         it++;
         break;
       }
-      if (front_edges <= switch_edges / 2) {
+      if (front_edges < switch_edges / 2) {  // strict: dense_switch 0 keeps every iteration dense
         // back to the frontier form: mark out(v) of this iteration's expanders
         // into the keep flags (clears xa), then bin
         k_mark_pending<<<gi, 256, 0, s>>>(xa, n, g->out.off, g->out.idx, cur, g->big_list, &g->ctl->big_count);

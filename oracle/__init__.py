@@ -35,6 +35,8 @@ _lib = None
 
 STATIC, ND, DF, DFP = 0, 1, 2, 3
 MODES = {"static": STATIC, "nd": ND, "df": DF, "dfp": DFP}
+# frontier measure compared with tau_f / tau_p (Section 4.2)
+CRITERIA = {"relative": 0, "absolute": 1, "contrib": 2}
 
 ALPHA, TOL, TOL_F, TOL_P, MAX_ITERS = 0.85, 1e-10, 1e-6, 1e-6, 500
 
@@ -62,7 +64,7 @@ def _declare(lib):
     lib.orc_apply.argtypes = [i32, i64, P, P, i64, P, P, i64, P, P, P, P, P, P, P, P, P, P, P, P]
     lib.orc_apply.restype = ctypes.c_int
     lib.orc_rank.argtypes = [i32, i32, P, P, P, P, P, P, i64, P, P, i64, P, P, P,
-                             f64, f64, f64, f64, i32, P, P, P, P]
+                             f64, f64, f64, f64, i32, i32, P, P, P, P]
     lib.orc_rank.restype = ctypes.c_int
     lib.orc_num_threads.argtypes = []
     lib.orc_num_threads.restype = ctypes.c_int
@@ -185,7 +187,8 @@ EMPTY = np.zeros(1, np.int32)
 
 
 def rank(mode, g: Graph, r_prev=None, g_prev: Graph | None = None, batch: Batch | None = None,
-         alpha=ALPHA, tol=TOL, tol_f=TOL_F, tol_p=TOL_P, max_iters=MAX_ITERS, lib=None) -> Result:
+         alpha=ALPHA, tol=TOL, tol_f=TOL_F, tol_p=TOL_P, max_iters=MAX_ITERS, criterion="relative",
+         lib=None) -> Result:
     """Run Static / ND / DF / DF-P (Algorithm 1) on G^t; DF/DF-P need G^{t-1} and the batch."""
     lib = lib or load()
     mode = MODES.get(mode, mode) if isinstance(mode, str) else int(mode)
@@ -209,7 +212,8 @@ def rank(mode, g: Graph, r_prev=None, g_prev: Graph | None = None, batch: Batch 
     rc = lib.orc_rank(n, mode, _p(po), _p(pi), _p(g.out_off), _p(g.out_idx), _p(g.in_off),
                       _p(g.in_idx), dms.shape[0], _p(dms if dms.size else EMPTY), _p(dmd if dmd.size else EMPTY),
                       dps.shape[0], _p(dps if dps.size else EMPTY), _p(dpd if dpd.size else EMPTY), _p(rp),
-                      alpha, tol, tol_f, tol_p, max_iters, _p(out), _p(stats), ctypes.byref(last),
+                      alpha, tol, tol_f, tol_p, CRITERIA.get(criterion, criterion), max_iters, _p(out),
+                      _p(stats), ctypes.byref(last),
                       _p(frontier))
     if rc != 0:
         raise MemoryError("oracle allocation failed")

@@ -209,6 +209,8 @@ int orc_apply(int32_t n, int64_t m_old, const int32_t* osrc, const int32_t* odst
 /* ------------------------------------------------------------------------ */
 
 /*
+ * criterion: ORC_CRIT_RELATIVE (dr / max(r, R[v])), ORC_CRIT_ABSOLUTE (dr) or
+ * ORC_CRIT_CONTRIB (dr / |out(v)|), the measure compared with tau_f and tau_p.
  * n: |V^t|; out_off/out_idx and in_off/in_idx: G^t; prev_off/prev_idx:
  * G^{t-1}.out (needed by DF and DF-P only).  dm / dp: the effective deletions
  * and insertions.  r_prev: R^{t-1} (ignored by STATIC).
@@ -223,7 +225,7 @@ int orc_rank(int32_t n, int32_t mode,
              int64_t n_dm, const int32_t* dm_src, const int32_t* dm_dst,
              int64_t n_dp, const int32_t* dp_src, const int32_t* dp_dst,
              const double* r_prev, double alpha, double tol, double tol_f, double tol_p,
-             int32_t max_iters, double* r_out, int64_t* stats, double* last_delta,
+             int32_t criterion, int32_t max_iters, double* r_out, int64_t* stats, double* last_delta,
              int32_t* frontier) {
   (void)dm_dst; (void)dp_dst;
   const int dynamic = (mode == ORC_DF || mode == ORC_DFP);
@@ -286,7 +288,13 @@ int orc_rank(int32_t n, int32_t mode,
       const double dr = fabs(r - R[v]);
       if (dr > dR) dR = dr;
       if (dynamic) {
-        const double rel = dr / fmax(r, R[v]);
+        /* Section 4.2: the change measured as dr / max(previous, current rank)
+         * (the method's choice), as dr, or as the change dr/d of the
+         * contribution factor; the same measure decides pruning (DF-P). */
+        double rel;
+        if (criterion == ORC_CRIT_ABSOLUTE) rel = dr;
+        else if (criterion == ORC_CRIT_CONTRIB) rel = dr / d;
+        else rel = dr / fmax(r, R[v]);
         An[v] = (mode == ORC_DFP && rel <= tol_p) ? 0 : 1; /* prune (DF-P only) */
         if (rel > tol_f) X[v] = 1;                         /* expand             */
       } else {

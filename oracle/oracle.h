@@ -4,6 +4,8 @@
 #include <stdint.h>
 
 enum { ORC_STATIC = 0, ORC_ND = 1, ORC_DF = 2, ORC_DFP = 3 };
+/* Frontier measure (Section 4.2): relative rank change, rank change, change of the contribution factor. */
+enum { ORC_CRIT_RELATIVE = 0, ORC_CRIT_ABSOLUTE = 1, ORC_CRIT_CONTRIB = 2 };
 
 int64_t orc_canonical(int32_t n, int64_t m, const int32_t* src, const int32_t* dst,
                       int32_t* esrc, int32_t* edst);
@@ -22,7 +24,7 @@ int orc_rank(int32_t n, int32_t mode,
              int64_t n_dm, const int32_t* dm_src, const int32_t* dm_dst,
              int64_t n_dp, const int32_t* dp_src, const int32_t* dp_dst,
              const double* r_prev, double alpha, double tol, double tol_f, double tol_p,
-             int32_t max_iters, double* r_out, int64_t* stats, double* last_delta,
+             int32_t criterion, int32_t max_iters, double* r_out, int64_t* stats, double* last_delta,
              int32_t* frontier);
 int orc_num_threads(void);
 

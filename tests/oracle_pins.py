@@ -270,6 +270,30 @@ def pin_relative_criterion(lib):
     assert r.ever_affected == 3 and r.ranks[2] != 0.6
 
 
+def pin_other_criteria(lib):
+    """The two other measures of Section 4.2 on the same example: vertex 1 has
+    dr = 0.08 and out-degree 2, vertex 0 dr = 0.0075 (see pin_relative_criterion).
+    Rank change dr: expands at tau_f = 0.06 (vertex 2 then processed), not at 0.1.
+    Contribution-factor change dr/d = 0.04: no expansion at tau_f = 0.06, but
+    expansion at tau_f = 0.03."""
+    g0 = O.graph(3, [1], [2], lib=lib)
+    g1, b = O.apply(g0, [], [], [0], [1], lib=lib)
+    rp = np.array([0.1, 0.3, 0.6])
+    r = O.rank("df", g1, rp, g0, b, tol_f=0.06, criterion="absolute", lib=lib)
+    assert r.ever_affected == 3 and r.ranks[2] != 0.6
+    # at tau_f = 0.1 the rank change (0.08) stays below while the relative one (0.267) would not
+    r = O.rank("df", g1, rp, g0, b, tol_f=0.1, criterion="absolute", lib=lib)
+    assert r.ever_affected == 2 and r.ranks[2] == 0.6
+    r = O.rank("df", g1, rp, g0, b, tol_f=0.06, criterion="contrib", lib=lib)
+    assert r.ever_affected == 2 and r.ranks[2] == 0.6
+    r = O.rank("df", g1, rp, g0, b, tol_f=0.03, criterion="contrib", lib=lib)
+    assert r.ever_affected == 3
+    # DF-P prunes with the same measure: with tau_p above every change the
+    # marked vertices are processed once and dropped
+    r = O.rank("dfp", g1, rp, g0, b, tol_f=1.0, tol_p=1.0, criterion="absolute", lib=lib)
+    assert r.iterations == 2 and r.vertex_updates == 2
+
+
 def pin_lower_bound(lib):
     """Every iterate of every mode satisfies r >= (1-alpha)/N (all terms are
     non-negative and the Equation 2 factor 1/(1-alpha/d) is >= 1)."""
@@ -290,4 +314,4 @@ def pin_lower_bound(lib):
 
 ALL_PINS = [pin_canonical, pin_apply, pin_static_dense, pin_static_closed_forms, pin_nd_is_static_warm,
             pin_dfp_closed_loop, pin_dynamic_bruteforce, pin_dynamic_special_cases, pin_relative_criterion,
-            pin_lower_bound]
+            pin_other_criteria, pin_lower_bound]

@@ -33,8 +33,12 @@ MUTANTS = {
     "self_loop_replaced": ("{ fill[v] = start[v]; rows[fill[v]++] = v; }",
                            "{ fill[v] = start[v]; rows[fill[v]++] = (v + 1) % n; }"),
     "in_csr_keyed_by_source": ("const int32_t* key = by_dst ? edst : esrc;", "const int32_t* key = esrc;"),
-    "relative_change_over_min": ("const double rel = dr / fmax(r, R[v]);", "const double rel = dr / fmin(r, R[v]);"),
+    "relative_change_over_min": ("else rel = dr / fmax(r, R[v]);", "else rel = dr / fmin(r, R[v]);"),
     "expand_before_commit_lost": ("if (rel > tol_f) X[v] = 1;", "if (rel > tol_f && mode == ORC_DFP) X[v] = 1;"),
+    "absolute_measure_relative": ("if (criterion == ORC_CRIT_ABSOLUTE) rel = dr;",
+                                  "if (criterion == ORC_CRIT_ABSOLUTE) rel = dr / fmax(r, R[v]);"),
+    "contrib_measure_times_degree": ("else if (criterion == ORC_CRIT_CONTRIB) rel = dr / d;",
+                                     "else if (criterion == ORC_CRIT_CONTRIB) rel = dr * d;"),
 }
 
 

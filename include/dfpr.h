@@ -58,12 +58,20 @@ typedef enum { DFPR_HOST = 0, DFPR_DEVICE = 1 } dfpr_where;
  * this share of |E| in-edges run in the dense form (every vertex checks its
  * in-neighbours' expand flags instead of being marked); 0 = always dense, above
  * 1 = never.  Both forms give identical results; only speed differs.
- * max_iters >= 1.  flags: DFPR_FLAG_* bits. */
+ * max_iters >= 1.  flags: DFPR_FLAG_* bits.  criterion: DFPR_CRIT_*. */
 typedef struct {
   double alpha, tol, frontier_tol, prune_tol, dense_switch;
   int32_t max_iters;
   int32_t flags;
+  int32_t criterion; /* DFPR_CRIT_*: the change compared with frontier_tol and prune_tol */
+  int32_t reserved;  /* 0 */
 } dfpr_params;
+
+/* Frontier measures of Section 4.2.  RELATIVE (the method's choice and the
+ * default): |r - R[v]| / max(r, R[v]).  ABSOLUTE: |r - R[v]|.  CONTRIB: the
+ * change of the contribution factor, |r - R[v]| / |out(v)|.  DF-P prunes with
+ * the same measure. */
+enum { DFPR_CRIT_RELATIVE = 0, DFPR_CRIT_ABSOLUTE = 1, DFPR_CRIT_CONTRIB = 2 };
 
 /* flags: record per-phase and per-kernel timings with HIP events into dfpr_stats. */
 #define DFPR_FLAG_TIMING 1

@@ -140,7 +140,7 @@ class Graph:
         m = MODES[mode] if isinstance(mode, str) else int(mode)
         p = default_params()
         for k, v in kw.items():
-            setattr(p, k, v)
+            setattr(p, k, _capi.CRITERIA.get(v, v) if k == "criterion" else v)
         if timing:
             p.flags |= _capi.FLAG_TIMING
         if out is None:
@@ -259,7 +259,7 @@ class BatchGraph(Graph):
         m = MODES[mode] if isinstance(mode, str) else int(mode)
         p = default_params()
         for k, v in kw.items():
-            setattr(p, k, v)
+            setattr(p, k, _capi.CRITERIA.get(v, v) if k == "criterion" else v)
         if timing:
             p.flags |= _capi.FLAG_TIMING
         if out is None:
@@ -288,7 +288,7 @@ class Server:
     def __init__(self, heap_bytes, lanes=4, mode="dfp", **kw):
         p = default_params()
         for k, v in kw.items():
-            setattr(p, k, v)
+            setattr(p, k, _capi.CRITERIA.get(v, v) if k == "criterion" else v)
         m = MODES[mode] if isinstance(mode, str) else int(mode)
         h = ctypes.c_void_p()
         _check(lib().dfpr_server_create(int(heap_bytes), int(lanes), m, ctypes.byref(p), ctypes.byref(h)))

@@ -11,6 +11,7 @@ DFPR_OK, DFPR_EINVAL, DFPR_ERANGE, DFPR_ENOMEM, DFPR_EHIP, DFPR_ESTATE = 0, -1, 
 STATIC, ND, DF, DFP = 0, 1, 2, 3
 HOST, DEVICE = 0, 1
 FLAG_TIMING = 1
+CRITERIA = {"relative": 0, "absolute": 1, "contrib": 2}
 CREATE_KEEP_IDS = 1
 
 # Every exported function declared in include/dfpr.h.
@@ -27,7 +28,7 @@ EXPORTS = ("dfpr_params_default", "dfpr_graph_create", "dfpr_graph_destroy", "df
 class Params(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_double), ("tol", ctypes.c_double), ("frontier_tol", ctypes.c_double),
                 ("prune_tol", ctypes.c_double), ("dense_switch", ctypes.c_double), ("max_iters", ctypes.c_int32),
-                ("flags", ctypes.c_int32)]
+                ("flags", ctypes.c_int32), ("criterion", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class BatchInfo(ctypes.Structure):

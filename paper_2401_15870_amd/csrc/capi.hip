@@ -54,6 +54,10 @@ int check_params(const dfpr_params& p) {
     set_error("tol must be > 0, dense_switch >= 0 and tolerances must not be NaN");
     return DFPR_EINVAL;
   }
+  if (p.criterion < DFPR_CRIT_RELATIVE || p.criterion > DFPR_CRIT_CONTRIB) {
+    set_error("unknown frontier criterion %d", p.criterion);
+    return DFPR_EINVAL;
+  }
   if (p.max_iters < 1) {
     set_error("max_iters must be >= 1, got %d", p.max_iters);
     return DFPR_EINVAL;
@@ -74,6 +78,8 @@ void dfpr_params_default(dfpr_params* p) {
   p->dense_switch = 0.4;
   p->max_iters = 500;
   p->flags = 0;
+  p->criterion = DFPR_CRIT_RELATIVE;
+  p->reserved = 0;
 }
 
 const char* dfpr_last_error(void) { return last_error(); }

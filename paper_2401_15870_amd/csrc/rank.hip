@@ -53,6 +53,7 @@ struct PullArgs {
   int32_t* arrive;           // bin 5: chunks finished per vertex
   const int64_t* chunk_pre;  // bin 5: first chunk of each vertex (exclusive scan)
   double alpha, C0, tf, tp;
+  int crit;  // DFPR_CRIT_*
 };
 
 // Bin k covers worklist [lo[k], hi[k]) and workgroups [blk[k], blk[k+1]).
@@ -158,7 +159,8 @@ __device__ __forceinline__ void vertex_finish(const PullArgs& a, const VCtx& x, 
     a.cw[x.v] = r / d;
     return;
   }
-  const double rel = dr / fmax(r, Rv);
+  // change measure (Section 4.2): relative (default), absolute, or of the contribution factor
+  const double rel = a.crit == DFPR_CRIT_ABSOLUTE ? dr : a.crit == DFPR_CRIT_CONTRIB ? dr / d : dr / fmax(r, Rv);
   const bool stay = !(MODE == kDFP && rel <= a.tp);  // prune (DF-P) or keep
   const bool expand = rel > a.tf;
   if (DENSE) {
@@ -1150,6 +1152,7 @@ static PullArgs make_args(dfpr_graph* g, const dfpr_params& p) {
   a.C0 = (1.0 - p.alpha) / (double)g->n;
   a.tf = p.frontier_tol;
   a.tp = p.prune_tol;
+  a.crit = p.criterion;
   return a;
 }
 
@@ -1614,6 +1617,8 @@ static int time_pull(dfpr_graph* g, double* r, hipStream_t s, double* ms) {
   p.dense_switch = 0.4;
   p.max_iters = 4;
   p.flags = DFPR_FLAG_TIMING;
+  p.criterion = DFPR_CRIT_RELATIVE;
+  p.reserved = 0;
   // pending marks must survive: run_sync clears them only if pending_any
   const bool pend = g->pending_any;
   g->pending_any = false;

@@ -69,7 +69,7 @@ class Pair:
         rp = None if r_prev is None else torch.from_numpy(np.ascontiguousarray(r_prev)).cuda()
         r, st = self.g.update_ranks(mode, rp, **kw)
         torch.cuda.synchronize()
-        okw = {k: v for k, v in kw.items() if k in ("alpha", "tol", "max_iters")}  # dense_switch: GPU only
+        okw = {k: v for k, v in kw.items() if k in ("alpha", "tol", "max_iters", "criterion")}  # dense_switch: GPU only
         if "frontier_tol" in kw:
             okw["tol_f"] = kw["frontier_tol"]
         if "prune_tol" in kw:

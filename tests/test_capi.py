@@ -37,7 +37,7 @@ def test_params_default(lib):
     p = _capi.Params()
     lib.dfpr_params_default(ctypes.byref(p))
     assert (p.alpha, p.tol, p.frontier_tol, p.prune_tol, p.max_iters, p.flags) == (0.85, 1e-10, 1e-6, 1e-6, 500, 0)
-    assert p.dense_switch == 0.4
+    assert p.dense_switch == 0.4 and p.criterion == 0 and p.reserved == 0
 
 
 def test_invalid_arguments_rejected_before_device_work(lib):
@@ -87,7 +87,7 @@ def test_invalid_arguments_rejected_before_device_work(lib):
 
 def test_struct_layouts_match_header():
     # field counts and sizes of the ABI structs as declared in include/dfpr.h
-    assert ctypes.sizeof(_capi.Params) == 5 * 8 + 2 * 4
+    assert ctypes.sizeof(_capi.Params) == 5 * 8 + 4 * 4
     assert ctypes.sizeof(_capi.BatchInfo) == 6 * 8 + 4 * 8
     assert ctypes.sizeof(_capi.Stats) == 4 + 4 + 8 + 3 * 8 + 12 * 8 + 8 + 8 + 4 + 4 + 3 * 8 + 8 + 4 + 4
     assert ctypes.sizeof(_capi.ServerStats) == 5 * 8 + 4 * 4 + 3 * 8

@@ -353,3 +353,24 @@ def test_library_loaded_before_torch_initialises():
     out = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=120)
     assert out.returncode == 0, out.stderr[-2000:]
     assert "edges 7" in out.stdout
+
+
+@pytest.mark.parametrize("fused", [False, True])
+@pytest.mark.parametrize("mode", ["df", "dfp"])
+@pytest.mark.parametrize("criterion,tf", [("absolute", 1e-12), ("contrib", 1e-13), ("relative", 1e-6)])
+def test_frontier_criteria(criterion, tf, mode, fused):
+    """The three change measures of Section 4.2 against the oracle (the
+    tolerances of the absolute measures sit in the range the paper sweeps)."""
+    torch_cuda()
+    n, s, d = rmat(12, seed=41)
+    p = Pair(n, s, d, fused=fused)
+    r0 = O.rank("static", p.og).ranks
+    ds, dd, is_, id_ = W.batch_8020(n, s, d, 1e-3, seed=42)
+    p.apply(ds, dd, is_, id_)
+    r, st, ref = p.rank(mode, r0, criterion=criterion, frontier_tol=tf, prune_tol=tf)
+    err = float(np.abs(r - ref.ranks).max())
+    _print(f"criterion {criterion} tf {tf:g} {mode} fused={fused}: linf {err:.2e} it {st['iterations']}/"
+           f"{ref.iterations} ever {st['ever_affected']}/{ref.ever_affected}")
+    assert err <= LINF
+    assert st["ever_affected"] == ref.ever_affected
+    assert abs(st["iterations"] - ref.iterations) <= 1

@@ -435,6 +435,69 @@ def bench_serving(args):
     print(json.dumps(res))
 
 
+def bench_sweep(args):
+    """Frontier measures and tolerances (Section 4.2) on the temporal stream:
+    mean DF-P update time and rank error (L1 against a reference Static run to
+    500 iterations) per measure and tau_f (tau_p = tau_f), next to Static."""
+    import torch
+    import paper_2401_15870_amd as dfpr
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    n, total = 2_000_000, 40_000_000
+    t0 = time.time()
+    src, dst = W.temporal_stream(n, total, seed=args.seed + 6)
+    k0 = int(0.9 * len(src))
+    B = max(1, int(round(args.sweep_batch * len(src))))
+    log(f"sweep: temporal stream n={n} edges={len(src)} initial {k0}, batches of {B} ({time.time() - t0:.0f}s)")
+    configs = [("relative", tf) for tf in (1e-1, 1e-2, 1e-3, 1e-4, 1e-5, 1e-6)]
+    configs += [(c, tf) for c in ("absolute", "contrib") for tf in (1e-10, 1e-11, 1e-12, 1e-13, 1e-14, 1e-15)]
+    s0, d0 = torch.from_numpy(src[:k0]).to(dev), torch.from_numpy(dst[:k0]).to(dev)
+    ref_g = dfpr.Graph.from_coo(n, s0, d0)
+    static_g = dfpr.Graph.from_coo(n, s0, d0)
+    handles = [dfpr.Graph.from_coo(n, s0, d0) for _ in configs]
+    r_static, _ = static_g.update_ranks("static", None)
+    ranks = [r_static.clone() for _ in configs]
+    rows = {i: {"ms": [], "err": [], "it": [], "ever": []} for i in range(len(configs))}
+    st_ms, st_err = [], []
+    for b in range(args.steps):
+        lo = k0 + b * B
+        ins = (src[lo:lo + B], dst[lo:lo + B])
+        for g in [ref_g, static_g] + handles:
+            g.apply_batch([], [], *ins)
+        r_ref, _ = ref_g.update_ranks("static", None, tol=1e-300, max_iters=500)
+        rs, st = static_g.update_ranks("static", None, timing=True)
+        st_ms.append(st["ms_total"])
+        st_err.append(float((rs - r_ref).abs().sum()))
+        for i, (crit, tf) in enumerate(configs):
+            r, st = handles[i].update_ranks("dfp", ranks[i], out=ranks[i], timing=True, criterion=crit,
+                                            frontier_tol=tf, prune_tol=tf)
+            rows[i]["ms"].append(st["ms_total"])
+            rows[i]["err"].append(float((r - r_ref).abs().sum()))
+            rows[i]["it"].append(st["iterations"])
+            rows[i]["ever"].append(st["ever_affected"])
+        log(f"batch {b}: static {st_ms[-1]:.2f} ms L1 {st_err[-1]:.2e}")
+    static_mean = float(np.mean(st_ms))
+    table = []
+    for i, (crit, tf) in enumerate(configs):
+        ms = float(np.mean(rows[i]["ms"]))
+        table.append({"criterion": crit, "tau_f": tf, "tau_p": tf, "ms_mean": ms, "speedup_vs_static": static_mean / ms,
+                      "l1_error_mean": float(np.mean(rows[i]["err"])), "iterations_mean": float(np.mean(rows[i]["it"])),
+                      "ever_affected_mean": float(np.mean(rows[i]["ever"]))})
+        log(f"{crit:9s} tau_f {tf:7.0e}: {ms:7.2f} ms  x{static_mean / ms:5.1f}  L1 {table[-1]['l1_error_mean']:.2e}")
+    res = {"metric": "DF-P update time and L1 rank error per frontier measure and tolerance",
+           "value": max(t["speedup_vs_static"] for t in table if t["l1_error_mean"] <= float(np.mean(st_err))),
+           "unit": "speedup vs Static at no more error than Static", "n_gpus": 1, "steps": args.steps, "warmup": 0,
+           "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"temporal stream, {n} vertices, {len(src)} edges, initial 90 %, insertion-only "
+                                  f"batches of {B} edges ({args.sweep_batch:g} of the stream) in time order; DF-P with "
+                                  "tau_p = tau_f; error = L1 against Static run to 500 iterations",
+                      "parallelism": "1 GPU"},
+           "static": {"ms_mean": static_mean, "l1_error_mean": float(np.mean(st_err))},
+           "table": table}
+    print(json.dumps(res))
+
+
 def summarize_main(args):
     """Print the profile summaries of a profiled run directory (see profiles/)."""
     d = args.summarize
@@ -470,9 +533,10 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--calib", action="store_true",
                     help="finish with three 1 GiB device copies (counter calibration under a profiler)")
-    ap.add_argument("--workload", default="rmat", choices=["rmat", "batched", "serving"],
+    ap.add_argument("--sweep-batch", type=float, default=1e-5, help="sweep: batch size as a fraction of the stream")
+    ap.add_argument("--workload", default="rmat", choices=["rmat", "batched", "serving", "sweep"],
                     help="rmat: one large R-MAT graph (default); batched: many graphs in one batch handle; "
-                         "serving: request loop over resident graphs")
+                         "serving: request loop over resident graphs; sweep: frontier measures and tolerances")
     ap.add_argument("--rates", default="100,1000,10000", help="serving: Poisson arrival rates per second")
     ap.add_argument("--requests", type=int, default=1000, help="serving: requests per rate and server setting")
     ap.add_argument("--lanes", type=int, default=4, help="serving: request lanes")
@@ -505,6 +569,9 @@ def main():
         return
     if args.workload == "serving":
         bench_serving(args)
+        return
+    if args.workload == "sweep":
+        bench_sweep(args)
         return
 
     t0 = time.time()

@@ -75,6 +75,13 @@ enum { DFPR_CRIT_RELATIVE = 0, DFPR_CRIT_ABSOLUTE = 1, DFPR_CRIT_CONTRIB = 2 };
 
 /* flags: record per-phase and per-kernel timings with HIP events into dfpr_stats. */
 #define DFPR_FLAG_TIMING 1
+/* flags: DF and DF-P update ranks and contributions in place as vertices are
+ * processed, so vertices processed later in an iteration already read the new
+ * values: the asynchronous single-vector execution of Section 4.4.  Fewer
+ * iterations; the result depends on the order the device happens to run in,
+ * so it is not reproducible bit for bit and matches the synchronous result
+ * only within the convergence tolerance.  Static and ND ignore the flag. */
+#define DFPR_FLAG_ASYNC 2
 
 /* Effective-batch counts of one dfpr_apply_batch call (Section 3.2).  The ms_*
  * fields are filled when timing is on (dfpr_set_timing), else 0. */

@@ -134,8 +134,9 @@ class Graph:
         _check(lib().dfpr_apply_batch(self._h, nds, a, b, nis, c, d, where, _stream_ptr(stream), ctypes.byref(info)))
         return info.as_dict()
 
-    def update_ranks(self, mode, r_prev=None, out=None, stream=None, timing=False, **kw):
-        """Run Static / ND / DF / DF-P.  r_prev and out are float64 CUDA tensors of n entries."""
+    def update_ranks(self, mode, r_prev=None, out=None, stream=None, timing=False, asynchronous=False, **kw):
+        """Run Static / ND / DF / DF-P.  r_prev and out are float64 CUDA tensors of n entries.
+        asynchronous: DF/DF-P update ranks in place during each iteration (not bit-reproducible)."""
         import torch
         m = MODES[mode] if isinstance(mode, str) else int(mode)
         p = default_params()
@@ -143,6 +144,8 @@ class Graph:
             setattr(p, k, _capi.CRITERIA.get(v, v) if k == "criterion" else v)
         if timing:
             p.flags |= _capi.FLAG_TIMING
+        if asynchronous:
+            p.flags |= _capi.FLAG_ASYNC
         if out is None:
             out = torch.empty(self.n, dtype=torch.float64, device="cuda")
         for t in (out, r_prev):

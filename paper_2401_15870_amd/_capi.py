@@ -11,6 +11,7 @@ DFPR_OK, DFPR_EINVAL, DFPR_ERANGE, DFPR_ENOMEM, DFPR_EHIP, DFPR_ESTATE = 0, -1, 
 STATIC, ND, DF, DFP = 0, 1, 2, 3
 HOST, DEVICE = 0, 1
 FLAG_TIMING = 1
+FLAG_ASYNC = 2
 CRITERIA = {"relative": 0, "absolute": 1, "contrib": 2}
 CREATE_KEEP_IDS = 1
 

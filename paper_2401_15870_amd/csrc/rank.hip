@@ -53,7 +53,8 @@ struct PullArgs {
   int32_t* arrive;           // bin 5: chunks finished per vertex
   const int64_t* chunk_pre;  // bin 5: first chunk of each vertex (exclusive scan)
   double alpha, C0, tf, tp;
-  int crit;  // DFPR_CRIT_*
+  int crit;      // DFPR_CRIT_*
+  double* cmut;  // frontier form, asynchronous: contributions updated in the pull (else null)
 };
 
 // Bin k covers worklist [lo[k], hi[k]) and workgroups [blk[k], blk[k+1]).
@@ -175,6 +176,7 @@ __device__ __forceinline__ void vertex_finish(const PullArgs& a, const VCtx& x, 
     if (stay) acc.sedges += x.e - x.s;
   } else {
     a.R[x.v] = r;
+    if (a.cmut) a.cmut[x.v] = r / d;  // asynchronous: visible to the vertices processed after this one
     if (stay) a.next[x.v] = 1;
     if (expand) a.xflag[x.v] = 1;
   }
@@ -1321,6 +1323,7 @@ static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_pre
   const int64_t m = g->m;
   const unsigned gi = grid_for(n, 256, 2048);
   k_reset_ctl<<<64, 256, 0, s>>>(g->ctl);
+  const bool async = (p.flags & DFPR_FLAG_ASYNC) != 0;
   double* Ra = g->perm ? g->rint : r_out;  // current ranks, internal order
   double* Rb = g->rn;
   double* ca = g->contrib;
@@ -1342,9 +1345,9 @@ static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_pre
     // every iteration in the dense form, all in one launch
     PullArgs a = make_args(g, p);
     a.R = Ra;
-    a.Rw = Rb;
+    a.Rw = async ? Ra : Rb;  // asynchronous: one rank and one contribution vector
     a.contrib = ca;
-    a.cw = cb;
+    a.cw = async ? ca : cb;
     a.stay_in = g->flag_cur;
     a.x_in = g->xflag;
     a.stay_out = g->flag_next;
@@ -1358,7 +1361,7 @@ static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_pre
     st->edges_pulled += h->dense_edges;
     st->pull_bytes += (double)fr.iters * (31.0 * n + 5.0 * (double)m) + 8.0 * (double)h->dense_edges;
     st->dense_iterations += fr.iters;
-    double* Rf = (fr.iters & 1) ? Rb : Ra;
+    double* Rf = (fr.iters & 1) && !async ? Rb : Ra;
     if (g->perm)
       k_scatter_ranks<<<gi, 256, 0, s>>>(Rf, g->inv, r_out, n);
     else if (Rf != r_out)
@@ -1398,8 +1401,9 @@ static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_pre
       DFPR_TRY(ensure_all_bins(g, s));
       a.contrib = ca;
       a.R = Ra;
-      a.Rw = Rb;
-      a.cw = cb;
+      a.Rw = async ? Ra : Rb;
+      a.cw = async ? ca : cb;
+      a.cmut = nullptr;
       a.stay_in = cur;
       a.x_in = xa;
       a.stay_out = next;
@@ -1417,8 +1421,10 @@ static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_pre
       st->edges_pulled += h->dense_edges;
       st->pull_bytes += 31.0 * n + 5.0 * (double)m + 8.0 * (double)h->dense_edges;
       st->dense_iterations++;
-      std::swap(Ra, Rb);
-      std::swap(ca, cb);
+      if (!async) {
+        std::swap(Ra, Rb);
+        std::swap(ca, cb);
+      }
       std::swap(cur, next);  // cur = keep flags of the next iteration
       std::swap(xa, xb);     // xa = expand flags of this iteration
       use_x = true;
@@ -1468,6 +1474,7 @@ static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_pre
       break;
     }
     a.contrib = ca;
+    a.cmut = async ? ca : nullptr;
     a.R = Ra;
     a.next = next;
     a.xflag = xa;

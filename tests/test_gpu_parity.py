@@ -374,3 +374,29 @@ def test_frontier_criteria(criterion, tf, mode, fused):
     assert err <= LINF
     assert st["ever_affected"] == ref.ever_affected
     assert abs(st["iterations"] - ref.iterations) <= 1
+
+
+@pytest.mark.parametrize("fused", [False, True])
+@pytest.mark.parametrize("mode", ["df", "dfp"])
+def test_asynchronous_mode(mode, fused):
+    """In-place (asynchronous) DF/DF-P: not bit-reproducible, so accepted by
+    error: against a tightly converged Static solve of the updated graph it is
+    no worse than the synchronous result by more than the iteration tolerance,
+    it stays close to the synchronous oracle, and it needs no more iterations."""
+    torch_cuda()
+    n, s, d = rmat(14, seed=51)
+    p = Pair(n, s, d, fused=fused)
+    r0 = O.rank("static", p.og).ranks
+    ds, dd, is_, id_ = W.batch_8020(n, s, d, 1e-3, seed=52)
+    p.apply(ds, dd, is_, id_)
+    ra, sta, ref = p.rank(mode, r0, asynchronous=True)
+    exact = O.rank("static", p.og, tol=1e-15, max_iters=500).ranks
+    e_async = float(np.abs(ra - exact).max())
+    e_sync = float(np.abs(ref.ranks - exact).max())
+    e_cross = float(np.abs(ra - ref.ranks).max())
+    _print(f"async {mode} fused={fused}: it {sta['iterations']} (sync {ref.iterations}); linf vs exact "
+           f"{e_async:.2e} (sync {e_sync:.2e}); vs sync oracle {e_cross:.2e}")
+    assert sta["converged"] == 1
+    assert sta["iterations"] <= ref.iterations
+    assert e_async <= e_sync + 1e-9
+    assert e_cross <= 1e-8

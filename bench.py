@@ -528,6 +528,8 @@ def main():
     ap.add_argument("--frac", type=float, default=1e-4)
     ap.add_argument("--mode", default="dfp", choices=["dfp", "df", "nd", "static"])
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--asynchronous", action="store_true",
+                    help="DF/DF-P update ranks in place during iterations (not bit-reproducible)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (R0 from GPU Static)")
     ap.add_argument("--static-runs", type=int, default=3)
     ap.add_argument("--no-autotune", action="store_true")
@@ -644,13 +646,13 @@ def main():
         ta = time.perf_counter()
         info = g.apply_batch(*dev_batches[i])
         tb = time.perf_counter()
-        r, st = g.update_ranks(args.mode, r, out=r)
+        r, st = g.update_ranks(args.mode, r, out=r, asynchronous=args.asynchronous)
         tc = time.perf_counter()
         if i == 0 and cpu is not None:
             parity = float(np.abs(r.cpu().numpy() - ref1.ranks).max())
             log(f"full-size parity step 0: linf={parity:.3e} (gpu it={st['iterations']} "
                 f"oracle it={ref1.iterations}; ever gpu={st['ever_affected']} oracle={ref1.ever_affected})")
-            assert parity <= 1e-9, f"full-size parity failed: {parity}"
+            assert parity <= (1e-8 if args.asynchronous else 1e-9), f"full-size parity failed: {parity}"
         if i >= args.warmup:
             step_ms.append((tc - ta) * 1e3)
             apply_ms.append((tb - ta) * 1e3)
@@ -712,7 +714,8 @@ def main():
                                f"{args.edge_factor:g}, self-loops; chained 80/20 batches of "
                                f"{args.frac:g}*|E|; apply + {args.mode.upper()} update per step",
                    "n": n, "m": int(m0), "batch_edges": int(len(batches[0][0]) + len(batches[0][2])),
-                   "mode": args.mode, "parallelism": "1 GPU", "bin_bounds": g.get_tuning()},
+                   "mode": args.mode + (" asynchronous" if args.asynchronous else ""), "parallelism": "1 GPU",
+                   "bin_bounds": g.get_tuning()},
         "p50_ms": pct(step_ms, 50),
         "p99_ms": pct(step_ms, 99),
         "apply_p50_ms": pct(apply_ms, 50),

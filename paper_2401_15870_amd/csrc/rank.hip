@@ -266,6 +266,16 @@ __device__ __forceinline__ void pull_groups(const PullArgs& a, const int32_t* __
     if (aff) {
       if (G == 1) {
         int32_t p = x.s;
+        for (; p + 8 <= x.e; p += 8) {  // eight gathers in flight, then folded in order
+          int32_t u[8];
+          double xv[8];
+#pragma unroll
+          for (int t = 0; t < 8; t++) u[t] = ld_idx(a, p + t);
+#pragma unroll
+          for (int t = 0; t < 8; t++) xv[t] = gx(a, u[t], x);
+#pragma unroll
+          for (int t = 0; t < 8; t++) c = c + xv[t];
+        }
         for (; p + 4 <= x.e; p += 4) {
           const int32_t u0 = ld_idx(a, p), u1 = ld_idx(a, p + 1), u2 = ld_idx(a, p + 2), u3 = ld_idx(a, p + 3);
           const double x0 = gx(a, u0, x), x1 = gx(a, u1, x), x2 = gx(a, u2, x), x3 = gx(a, u3, x);
@@ -501,7 +511,7 @@ __device__ __forceinline__ bool grid_barrier(IterCtl* c, unsigned nb) {
 }
 
 template <int MODE>
-__global__ void __launch_bounds__(256, 8) k_fused_loop(PullArgs a0, const int32_t* __restrict__ wl, PullLayout L,
+__global__ void __launch_bounds__(256) k_fused_loop(PullArgs a0, const int32_t* __restrict__ wl, PullLayout L,
                                                        IterCtl* c, int max_iters, double tol) {
   constexpr bool DENSE = MODE != kSync;
   PullArgs a = a0;

@@ -194,6 +194,7 @@ constexpr int kPullChunk = 4096;   // in-edges per workgroup work item (bin 5)
 constexpr int kMarkChunk = 4096;   // out-edges per workgroup work item
 constexpr int kBigRow = 4096;      // out-rows longer than this go to the chunked marking
 constexpr int kGSub = 8;           // spread slots per member graph for its L-inf reduction
+constexpr int64_t kPartVertices = (int64_t)8 << 20;  // 64 MB of contributions per batch part
 
 }  // namespace dfpr
 
@@ -238,9 +239,17 @@ struct dfpr_graph {
   uint8_t* touched_out = nullptr, *touched_in = nullptr;  // rows changed by the batch
   int32_t* delta_out = nullptr, *delta_in = nullptr;      // row length changes
   int32_t* worklist = nullptr;   // n entries: thread bin | wave bin | block bin
-  int32_t* all_bins = nullptr;   // n entries: every vertex, binned (Static/ND)
-  int64_t all_bin_end[DFPR_BINS] = {0};
-  int64_t all_bin_edges[DFPR_BINS] = {0};
+  int32_t* all_bins = nullptr;   // n entries: every vertex, binned per part (Static/ND, dense form)
+  // Parts of the vertex range pulled one launch after another.  A batch is cut
+  // at member boundaries into parts of about kPartVertices vertices, so each
+  // launch gathers from one part's contributions only (they stay in the
+  // Infinity Cache); a plain graph is one part.
+  struct Part {
+    int64_t lo = 0, hi = 0;
+    int64_t bin_end[DFPR_BINS] = {0};    // relative to lo
+    int64_t bin_edges[DFPR_BINS] = {0};
+  };
+  std::vector<Part> parts;
   bool all_bins_valid = false;
   bool all_chunks_valid = false;  // all_chunk_pre matches all_bins
   dfpr::IterCtl* ctl = nullptr;      // device
@@ -249,7 +258,7 @@ struct dfpr_graph {
   size_t scan_tmp_n = 0;
   int64_t* bin_blk = nullptr;        // per-block bin counts (kBins * ceil(n/2048) + 1)
   int64_t* chunk_pre = nullptr;      // n+1: chunk prefix of the chunked bin (frontier worklist)
-  int64_t* all_chunk_pre = nullptr;  // n+1: the same for the all-vertex bins
+  int64_t* all_chunk_pre = nullptr;  // n + parts + 1: the same for the all-vertex bins (part k at lo + k)
   int64_t* piece_pre = nullptr;      // n/64+2: CSR rebuild work pieces per 64-row group
   double* partial = nullptr;         // partial sums of pull chunks
   int64_t partial_n = 0;

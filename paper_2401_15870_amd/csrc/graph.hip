@@ -539,7 +539,7 @@ static size_t carve_scratch(dfpr_graph* g, char* base, size_t* zero_bytes) {
   take(g->bin_blk, kBins * nbins + 2);
   take(g->chunk_pre, n + 1);
   take(g->piece_pre, n / kWave + 2);
-  take(g->all_chunk_pre, n + 1);
+  take(g->all_chunk_pre, n + std::max<size_t>(g->parts.size(), 1) + 1);
   take(g->big_list, n);
   take(g->big_pre, n + 1);
   g->scan_tmp_n = scan_tmp_elems((int64_t)n + 1);
@@ -551,6 +551,7 @@ size_t scratch_size(const dfpr_graph* g) {
   dfpr_graph probe_fields;  // carve writes only pointer and size fields
   probe_fields.n = g->n;
   probe_fields.perm = g->perm;
+  probe_fields.parts = g->parts;
   const size_t b = carve_scratch(&probe_fields, nullptr, nullptr);
   probe_fields.perm = nullptr;
   return b;
@@ -794,6 +795,21 @@ int graph_create(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, d
           hipSuccess)
         return fail(DFPR_EHIP);
       k_member_ids<<<grid_for(n, 256, 65536), 256, 0, s>>>(g->vbase_d, g->ngraphs, n, g->gidv);
+    }
+    // parts of the all-vertex pull: whole members, about kPartVertices vertices each
+    g->parts.clear();
+    {
+      dfpr_graph::Part pt;
+      pt.lo = 0;
+      for (int32_t k = 0; k < g->ngraphs; k++) {
+        const int64_t hi = g->vbase[k + 1];
+        if (hi - pt.lo >= kPartVertices || k + 1 == g->ngraphs) {
+          pt.hi = hi;
+          g->parts.push_back(pt);
+          pt = dfpr_graph::Part();
+          pt.lo = hi;
+        }
+      }
     }
     if (relabel) {
       // order vertices by member, then decreasing degree (ties by id)

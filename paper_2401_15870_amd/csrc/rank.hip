@@ -767,12 +767,13 @@ __device__ __forceinline__ unsigned tile_flags(const uint8_t* flags, int64_t bas
   return m;
 }
 
-__global__ void __launch_bounds__(256) k_bin_count(const uint8_t* flags, const int32_t* __restrict__ in_off, int32_t n,
-                                                   MemberMask mm, Bounds B, int64_t* blk, int64_t nb,
+// Vertices [lo, n) are binned (n: end of the range).
+__global__ void __launch_bounds__(256) k_bin_count(const uint8_t* flags, const int32_t* __restrict__ in_off, int64_t lo,
+                                                   int32_t n, MemberMask mm, Bounds B, int64_t* blk, int64_t nb,
                                                    unsigned long long* acc) {
   __shared__ int64_t sh[256 / kWave + 1];
   __shared__ int64_t she[256 / kWave][kBins];
-  const int64_t base = (int64_t)blockIdx.x * kBinTile + (int64_t)threadIdx.x * kBinItems;
+  const int64_t base = lo + (int64_t)blockIdx.x * kBinTile + (int64_t)threadIdx.x * kBinItems;
   const unsigned m = tile_flags(flags, base, n, mm);
   int64_t p0 = 0, p1 = 0;
   int64_t ed[kBins] = {0, 0, 0, 0, 0, 0};
@@ -814,10 +815,10 @@ __global__ void __launch_bounds__(256) k_bin_count(const uint8_t* flags, const i
 }
 
 __global__ void __launch_bounds__(256) k_bin_scatter(const uint8_t* flags, const int32_t* __restrict__ in_off,
-                                                     int32_t n, MemberMask mm, Bounds B, const int64_t* offs, int64_t nb,
-                                                     int32_t* wl, uint8_t* ever, int64_t* bin_end) {
+                                                     int64_t lo, int32_t n, MemberMask mm, Bounds B, const int64_t* offs,
+                                                     int64_t nb, int32_t* wl, uint8_t* ever, int64_t* bin_end) {
   __shared__ int64_t sh[256 / kWave + 1];
-  const int64_t base = (int64_t)blockIdx.x * kBinTile + (int64_t)threadIdx.x * kBinItems;
+  const int64_t base = lo + (int64_t)blockIdx.x * kBinTile + (int64_t)threadIdx.x * kBinItems;
   const unsigned m = tile_flags(flags, base, n, mm);
   uint8_t bins[kBinItems];
   int64_t p0 = 0, p1 = 0;
@@ -1044,18 +1045,20 @@ static Bounds bounds_of(const dfpr_graph* g) {
   return B;
 }
 
-static int bin_vertices(dfpr_graph* g, const uint8_t* flags, int32_t* wl, uint8_t* ever, hipStream_t s) {
-  const int32_t n = g->n;
+// Bin the vertices [lo, hi) (default: all) into wl[0 ..), bins back to back.
+static int bin_vertices(dfpr_graph* g, const uint8_t* flags, int32_t* wl, uint8_t* ever, hipStream_t s,
+                        int64_t lo = 0, int64_t hi = -1) {
+  if (hi < 0) hi = g->n;
   size_t tok;
   DFPR_TRY(g->pool.start(&tok));
-  const int64_t nb = ((int64_t)n + kBinTile - 1) / kBinTile;
+  const int64_t nb = std::max<int64_t>(1, (hi - lo + kBinTile - 1) / kBinTile);
   // the cached all-vertex bins (flags == null) never drop converged members
   const MemberMask mm{flags ? g->gidv : nullptr, flags ? g->done : nullptr};
-  k_bin_count<<<(unsigned)nb, 256, 0, s>>>(flags, g->in.off, n, mm, bounds_of(g), g->bin_blk, nb,
+  k_bin_count<<<(unsigned)nb, 256, 0, s>>>(flags, g->in.off, lo, (int32_t)hi, mm, bounds_of(g), g->bin_blk, nb,
                                            &g->ctl->acc_slots[0][0]);
   DFPR_TRY(scan_i64(g->bin_blk, g->bin_blk, kBins * nb, g->scan_tmp, s));
-  k_bin_scatter<<<(unsigned)nb, 256, 0, s>>>(flags, g->in.off, n, mm, bounds_of(g), g->bin_blk, nb, wl, ever,
-                                             g->ctl->bin_end);
+  k_bin_scatter<<<(unsigned)nb, 256, 0, s>>>(flags, g->in.off, lo, (int32_t)hi, mm, bounds_of(g), g->bin_blk, nb, wl,
+                                             ever, g->ctl->bin_end);
   DFPR_HIP(hipGetLastError());
   DFPR_TRY(g->pool.stop(kTBin, tok));
   return DFPR_OK;
@@ -1169,6 +1172,8 @@ static PullArgs make_args(dfpr_graph* g, const dfpr_params& p) {
 }
 
 static int ensure_all_bins(dfpr_graph* g, hipStream_t s);
+template <int MODE, bool DENSE>
+static int pull_parts(dfpr_graph* g, const PullArgs& a, hipStream_t s, dfpr_stats* st, bool count_bins);
 
 // Whole-update single launch for small plain graphs (see k_fused_loop).
 static bool use_fused(const dfpr_graph* g) { return g->ngraphs == 1 && g->fused_limit > 0 && g->m <= g->fused_limit; }
@@ -1184,7 +1189,7 @@ static int fused_run(dfpr_graph* g, const dfpr_params& p, PullArgs a, hipStream_
                      FusedResult* out) {
   DFPR_TRY(ensure_all_bins(g, s));
   PullLayout L;
-  make_layout(g->all_bin_end, g->all_bin_edges, &L);
+  make_layout(g->parts[0].bin_end, g->parts[0].bin_edges, &L);  // a plain graph: one part
   const int64_t n5 = L.hi[kBins - 1] - L.lo[kBins - 1];
   if (n5 > 0 && !g->all_chunks_valid)
     DFPR_TRY(scan_generic(LoadChunks{g->all_bins, g->in.off, L.lo[kBins - 1]}, StoreChunk{g->all_chunk_pre}, n5,
@@ -1268,16 +1273,13 @@ static int run_sync(dfpr_graph* g, bool cold, const dfpr_params& p, const double
     a.R = Ra;
     a.Rw = Rb;
     a.cw = cb;
-    DFPR_TRY(pull_all<kSync>(g, a, g->all_bins, g->all_bin_end, g->all_bin_edges, g->all_chunk_pre,
-                             g->all_chunks_valid, s, st));
-    g->all_chunks_valid = true;
+    DFPR_TRY((pull_parts<kSync, false>(g, a, s, st, true)));
     DFPR_TRY(dr_finish(g, p, it, s));
     DFPR_TRY(finish_and_read(g, s));
     dR = bits_to_double(g->ctl_host->dR);
     st->vertex_updates += n;
     st->edges_pulled += g->m;
     st->pull_bytes += 36.0 * n + 12.0 * (double)g->m;
-    add_bins(st, g->all_bin_end, g->all_bin_edges);
     std::swap(Ra, Rb);
     std::swap(ca, cb);
     if (g->ctl_host->active == 0) {
@@ -1307,12 +1309,27 @@ static int run_sync(dfpr_graph* g, bool cold, const dfpr_params& p, const double
 // dense pull over all vertices needs the cached all-vertex bins
 static int ensure_all_bins(dfpr_graph* g, hipStream_t s) {
   if (g->all_bins_valid) return DFPR_OK;
-  DFPR_TRY(bin_vertices(g, nullptr, g->all_bins, nullptr, s));
-  DFPR_TRY(finish_and_read(g, s));
-  std::copy(g->ctl_host->bin_end, g->ctl_host->bin_end + kBins, g->all_bin_end);
-  std::copy(g->ctl_host->bin_edges, g->ctl_host->bin_edges + kBins, g->all_bin_edges);
+  for (auto& pt : g->parts) {
+    DFPR_TRY(bin_vertices(g, nullptr, g->all_bins + pt.lo, nullptr, s, pt.lo, pt.hi));
+    DFPR_TRY(finish_and_read(g, s));
+    std::copy(g->ctl_host->bin_end, g->ctl_host->bin_end + kBins, pt.bin_end);
+    std::copy(g->ctl_host->bin_edges, g->ctl_host->bin_edges + kBins, pt.bin_edges);
+  }
   g->all_bins_valid = true;
   g->all_chunks_valid = false;
+  return DFPR_OK;
+}
+
+// One pull over every vertex: one launch per part.
+template <int MODE, bool DENSE>
+static int pull_parts(dfpr_graph* g, const PullArgs& a, hipStream_t s, dfpr_stats* st, bool count_bins) {
+  for (size_t k = 0; k < g->parts.size(); k++) {
+    const auto& pt = g->parts[k];
+    DFPR_TRY((pull_all<MODE, DENSE>(g, a, g->all_bins + pt.lo, pt.bin_end, pt.bin_edges,
+                                    g->all_chunk_pre + pt.lo + (int64_t)k, g->all_chunks_valid, s, st)));
+    if (count_bins) add_bins(st, pt.bin_end, pt.bin_edges);
+  }
+  g->all_chunks_valid = true;
   return DFPR_OK;
 }
 
@@ -1420,9 +1437,7 @@ static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_pre
       a.x_out = xb;
       a.ever = g->ever;
       a.use_x = use_x ? 1 : 0;
-      DFPR_TRY((pull_all<MODE, true>(g, a, g->all_bins, g->all_bin_end, g->all_bin_edges, g->all_chunk_pre,
-                                     g->all_chunks_valid, s, st)));
-      g->all_chunks_valid = true;
+      DFPR_TRY((pull_parts<MODE, true>(g, a, s, st, false)));
       DFPR_TRY(dr_finish(g, p, it, s));
       DFPR_TRY(finish_and_read(g, s));
       const IterCtl* h = g->ctl_host;

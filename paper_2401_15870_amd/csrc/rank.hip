@@ -250,15 +250,22 @@ __device__ __forceinline__ void pull_groups(const PullArgs& a, const int32_t* __
     if (DENSE && aff) {
       aff = a.stay_in[x.v] != 0;
       if (!aff && a.use_x) {
+        // any in-neighbour expanded?  Rounds of 4G edges with a group vote after
+        // each, stopping at the first hit (in-rows start with the high-degree
+        // sources, which expand most often).  The trip count is the same for
+        // the G lanes of a group, so the vote only reads active lanes.
         int any = 0;
-        int32_t p = x.s + gl;
-        for (; p + 3 * G < x.e; p += 4 * G) {
-          const int32_t u0 = ld_idx(a, p), u1 = ld_idx(a, p + G), u2 = ld_idx(a, p + 2 * G), u3 = ld_idx(a, p + 3 * G);
-          any |= a.x_in[u0] | a.x_in[u1] | a.x_in[u2] | a.x_in[u3];
-        }
-        for (; p < x.e; p += G) any |= a.x_in[ld_idx(a, p)];
+        for (int32_t base = x.s; base < x.e && !any; base += 4 * G) {
+          int f = 0;
 #pragma unroll
-        for (int o = G / 2; o >= 1; o >>= 1) any |= __shfl_xor(any, o, kWave);
+          for (int t = 0; t < 4; t++) {
+            const int32_t p = base + t * G + gl;
+            if (p < x.e) f |= a.x_in[ld_idx(a, p)];
+          }
+#pragma unroll
+          for (int o = G / 2; o >= 1; o >>= 1) f |= __shfl_xor(f, o, kWave);
+          any = f;
+        }
         aff = any != 0;
       }
     }
@@ -357,19 +364,26 @@ __device__ __forceinline__ void pull_block(const PullArgs& a, const int32_t* __r
                                            int lb, int nb, Acc& acc) {
   __shared__ double sh[256 / kWave];
   __shared__ int shx[256 / kWave];
-  __shared__ int aff_sh;
   for (int64_t k = lo + lb; k < hi; k += nb) {
     const VCtx x = load_vertex(a, wl[k]);
     bool aff = !member_done(a, x.g);
     if (DENSE && aff) {
       aff = a.stay_in[x.v] != 0;
-      if (!aff && a.use_x) {
+      if (!aff && a.use_x) {  // in-neighbour expand flags, stopping at the first hit
         int any = 0;
-        block_row_sum(a, x, x.s, x.e, false, true, &any, sh, shx);
-        if (threadIdx.x == 0) aff_sh = any;
-        __syncthreads();
-        aff = aff_sh != 0;
-        __syncthreads();
+        for (int32_t base = x.s; base < x.e; base += 4 * 256) {
+          int f = 0;
+#pragma unroll
+          for (int t = 0; t < 4; t++) {
+            const int32_t p = base + t * 256 + (int32_t)threadIdx.x;
+            if (p < x.e) f |= a.x_in[ld_idx(a, p)];
+          }
+          if (__syncthreads_or(f)) {
+            any = 1;
+            break;
+          }
+        }
+        aff = any != 0;
       }
     }
     int dummy;

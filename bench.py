@@ -84,6 +84,8 @@ def chained_batches(n, src, dst, frac, count, seed):
             ins = k[np.sort(first)][:b_ins]
         inserted = np.union1d(inserted, ins)
         out.append((src[sel].copy(), dst[sel].copy(), (ins // n).astype(np.int32), (ins % n).astype(np.int32)))
+        if b >= 1_000_000:  # large batches take a while on the host: show progress
+            log(f"  batch {step + 1}/{count} drawn ({b} edges)")
     return out
 
 

@@ -18,6 +18,7 @@
 // out-row marking is balanced across the wave by a prefix sum of row lengths,
 // and no reduction funnels the whole chip into one atomic address.
 #include <algorithm>
+#include <mutex>
 
 #include "prim.hpp"
 
@@ -1210,20 +1211,35 @@ static int fused_run(dfpr_graph* g, const dfpr_params& p, PullArgs a, hipStream_
                           g->scan_tmp, s));
   g->all_chunks_valid = true;
   a.chunk_pre = g->all_chunk_pre;
-  static int per_cu = -1, cus = 0;
-  if (per_cu < 0) {
-    int dev = 0;
-    DFPR_HIP(hipGetDevice(&dev));
-    DFPR_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    DFPR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_fused_loop<MODE>),
-                                                          256, 0));
+  // resident workgroups of this kernel on the device (queried once; the
+  // serving form's lanes may get here concurrently)
+  static const int resident = [] {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_fused_loop<MODE>), 256,
+                                                     0) != hipSuccess) {
+      (void)hipGetLastError();
+      return 0;
+    }
+    return per_cu * cus;
+  }();
+  if (resident < 1) {
+    set_error("occupancy query for the single-launch loop failed");
+    return DFPR_EHIP;
   }
-  const int grid = std::max(1, std::min(std::max(per_cu, 1) * cus, (int)L.blk[kBins]));
+  const int grid = std::max(1, std::min(resident, (int)L.blk[kBins]));
   const int32_t* wl = g->all_bins;
   IterCtl* c = g->ctl;
   int mi = p.max_iters;
   double tol = p.tol;
   void* args[] = {&a, &wl, &L, &c, &mi, &tol};
+  // One single-launch loop at a time in the process: its grid barrier needs
+  // all its workgroups resident, which two such kernels on concurrent streams
+  // (say, the serving form's lanes) could not both have.  Held until the loop
+  // has finished on the device.
+  static std::mutex fused_mu;
+  std::lock_guard<std::mutex> fused_lk(fused_mu);
   size_t tok;
   DFPR_TRY(g->pool.start(&tok));
   DFPR_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_fused_loop<MODE>), dim3(grid), dim3(256), args,

@@ -191,8 +191,8 @@ constexpr size_t kCtlHead = offsetof(IterCtl, pad);
 
 // Work split of the pull kernel's chunked bin and of long out-rows.
 constexpr int kPullChunk = 4096;   // in-edges per workgroup work item (bin 5)
-constexpr int kMarkChunk = 4096;   // out-edges per workgroup work item
-constexpr int kBigRow = 4096;      // out-rows longer than this go to the chunked marking
+constexpr int kMarkChunk = 1024;   // out-edges per workgroup work item
+constexpr int kBigRow = 1024;      // out-rows longer than this go to the chunked marking
 constexpr int kGSub = 8;           // spread slots per member graph for its L-inf reduction
 constexpr int64_t kPartVertices = (int64_t)8 << 20;  // 64 MB of contributions per batch part
 

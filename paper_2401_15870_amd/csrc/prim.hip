@@ -140,23 +140,20 @@ __global__ void __launch_bounds__(kRadixBlock) k_radix_small(uint64_t* keys, int
   __shared__ int wave_cnt[(kRadixBlock / kWave) * 256];
   __shared__ int running[256];
   __shared__ int cnt[256];
+  __shared__ int64_t scan_sh[kRadixBlock / kWave + 1];
   for (int i = threadIdx.x; i < kSmallSort; i += kRadixBlock) buf[0][i] = (i < n) ? keys[i] : 0;
   for (int i = threadIdx.x; i < (kRadixBlock / kWave) * 256; i += kRadixBlock) wave_cnt[i] = 0;
+  const int rounds = (int)((n + kRadixBlock - 1) / kRadixBlock);  // only the rounds that hold keys
   int src = 0;
   for (int shift = 0; shift < bits; shift += 8) {
     cnt[threadIdx.x] = 0;
     __syncthreads();
     for (int i = threadIdx.x; i < n; i += kRadixBlock) atomicAdd(&cnt[(buf[src][i] >> shift) & 255u], 1);
     __syncthreads();
-    if (threadIdx.x == 0) {
-      int run = 0;
-      for (int d = 0; d < 256; d++) {
-        running[d] = run;
-        run += cnt[d];
-      }
-    }
+    int64_t tot;
+    running[threadIdx.x] = (int)block_exclusive_scan(cnt[threadIdx.x], scan_sh, &tot);  // one digit per thread
     __syncthreads();
-    for (int j = 0; j < kSmallSort / kRadixBlock; j++) {
+    for (int j = 0; j < rounds; j++) {
       const int i = j * kRadixBlock + threadIdx.x;
       const bool valid = i < n;
       const uint64_t k = buf[src][i];

@@ -331,25 +331,45 @@ struct StoreI64b {
   __device__ void operator()(int64_t i, int64_t v) const { a[i] = v; }
 };
 
-// Rebuild one CSR.  Rows are taken in groups of 64 (one per lane); a group's
-// old edges are cut into pieces of at most kPiece edges (piece_pre = prefix of
-// the piece counts per group), and each wavefront takes one piece, so a long
-// row is spread over many wavefronts.  Untouched rows keep their content and
-// only shift, so a piece of a group without touched rows is one contiguous
-// copy.  In a touched row an old element x lands at j - #del(<x) + #ins(<x)
-// (counts by binary search over the row's sorted effective entries, delpre =
-// prefix count of deletions in that list); deleted elements are dropped.
-// Insertions are placed by k_place_inserts.
-constexpr int kPiece = 8192;
+// Rebuild one CSR in two kernels.  Rows are taken in groups of 64 (one per
+// lane).  A group without touched rows keeps its rows and only shifts them,
+// and the shift (new offset - old offset) stays the same up to the next
+// touched group, so k_shift_copy moves each run of untouched groups as one
+// contiguous copy.  k_rebuild handles the touched groups: their old edges are
+// cut into pieces of at most `piece` edges (piece_pre = prefix of the piece
+// counts per group, zero for untouched groups) and each wavefront takes one
+// piece, so a long row is spread over many wavefronts.  In a touched row an
+// old element x lands at j - #del(<x) + #ins(<x) (counts by binary search over
+// the row's sorted effective entries, delpre = prefix count of deletions in
+// that list); deleted elements are dropped.  Insertions are placed by
+// k_place_inserts.
+
+// True iff a row of group g (rows g*64 .. g*64+63, clipped to n) is touched.
+__device__ __forceinline__ bool group_touched(const uint8_t* touched, int64_t g, int32_t n) {
+  const int64_t r0 = g * kWave;
+  if (r0 + kWave <= n) {
+    const uint64_t* t8 = reinterpret_cast<const uint64_t*>(touched + r0);  // 64-byte aligned
+    uint64_t any = 0;
+#pragma unroll
+    for (int i = 0; i < kWave / 8; i++) any |= t8[i];
+    return any != 0;
+  }
+  bool any = false;
+  for (int64_t r = r0; r < n; r++) any |= touched[r] != 0;
+  return any;
+}
 
 struct LoadPieces {
   const int32_t* ooff;
+  const uint8_t* touched;  // 64-byte aligned, n entries
   int32_t n;
+  int32_t piece;
   __device__ int64_t operator()(int64_t g) const {
     const int32_t r0 = (int32_t)(g * kWave);
     const int32_t r1 = (int32_t)min((int64_t)r0 + kWave, (int64_t)n);
+    if (!group_touched(touched, g, n)) return 0;
     const int64_t len = (int64_t)ooff[r1] - ooff[r0];
-    return len > kPiece ? (len + kPiece - 1) / kPiece : 1;
+    return len > piece ? (len + piece - 1) / piece : 1;
   }
 };
 struct StorePieces {
@@ -376,11 +396,177 @@ __device__ __forceinline__ int lane_seg(int32_t st, int32_t e) {
   return lo;
 }
 
+__device__ __forceinline__ int64_t wave_min_i64(int64_t x) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) x = min(x, (int64_t)__shfl_xor(x, o, kWave));
+  return x;
+}
+__device__ __forceinline__ int64_t wave_max_i64(int64_t x) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) x = max(x, (int64_t)__shfl_xor(x, o, kWave));
+  return x;
+}
+
+// Each workgroup takes `chunk` entries of the new index array and fills those
+// that belong to untouched groups.  Its waves find runs of untouched groups 64
+// groups at a time (lane l looks at group g + l) and copy each run with its
+// shift.  mnew = noff[n] is read on the device; the grid covers an upper bound.
+constexpr int kCopyBlock = 256;
+
+__global__ void __launch_bounds__(kCopyBlock) k_shift_copy(const int32_t* __restrict__ ooff,
+                                                           const int32_t* __restrict__ oidx,
+                                                           const int32_t* __restrict__ noff,
+                                                           int32_t* __restrict__ nidx, const uint8_t* touched,
+                                                           int32_t n, int32_t chunk, int64_t* err) {
+  const int64_t mnew = noff[n];
+  const int64_t groups = ((int64_t)n + kWave - 1) / kWave;
+  const int lane = lane_id();
+  for (int64_t q0 = (int64_t)blockIdx.x * chunk; q0 < mnew; q0 += (int64_t)gridDim.x * chunk) {
+    const int64_t q1 = min(q0 + (int64_t)chunk, mnew);
+    // the row holding q0: the last row that starts at or before it
+    int64_t lo = 0, hi = (int64_t)n - 1;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) >> 1;
+      if ((int64_t)noff[mid] <= q0) lo = mid; else hi = mid - 1;
+    }
+    int64_t g = lo / kWave;
+    int64_t q = q0;
+    while (q < q1 && g < groups) {
+      const int64_t gl = g + lane;
+      const bool tl = gl < groups && group_touched(touched, gl, n);
+      const uint64_t tm = __ballot(tl);  // bit l: group g + l is touched
+      if (tm & 1ull) {  // touched groups are left to k_rebuild
+        const int run = (~tm == 0ull) ? kWave : __builtin_ctzll(~tm);
+        g = min(g + run, groups);
+        q = max(q, (int64_t)noff[min(g * kWave, (int64_t)n)]);
+        continue;
+      }
+      const int run = tm == 0ull ? kWave : __builtin_ctzll(tm);
+      const int64_t tg = min(g + run, groups);
+      const int32_t ra = (int32_t)(g * kWave), rb = (int32_t)min(tg * kWave, (int64_t)n);
+      const int64_t shift = (int64_t)noff[ra] - ooff[ra];
+      if ((int64_t)noff[rb] - ooff[rb] != shift) {  // offsets disagree: refuse to write
+        if (threadIdx.x == 0) atomicOr((unsigned long long*)err, 2ull);
+        break;
+      }
+      const int64_t end = min((int64_t)noff[rb], q1);
+      int64_t p = q + threadIdx.x;
+      for (; p + 7 * kCopyBlock < end; p += 8 * kCopyBlock) {
+        int32_t x[8];
+#pragma unroll
+        for (int k = 0; k < 8; k++) x[k] = __builtin_nontemporal_load(oidx + (p + k * kCopyBlock - shift));
+#pragma unroll
+        for (int k = 0; k < 8; k++) nidx[p + k * kCopyBlock] = x[k];
+      }
+      for (; p < end; p += kCopyBlock) nidx[p] = __builtin_nontemporal_load(oidx + (p - shift));
+      q = end;
+      g = tg;
+    }
+  }
+}
+
+// Few effective entries: the old index array cut at the entries is a list of
+// runs, each moved by one shift.  With the entries in (row, column) order,
+// opos[e] is entry e's position in the old array (a deleted element's own
+// position, an insertion's insertion point), non-decreasing in e.  Before
+// entry e the old elements have moved by S_e = #ins(<e) - #del(<e) =
+// e - 2 * delpre[e]; entry e cuts the new array at dcut(e) = opos[e] + S_e
+// (where an insertion lands), and the run after it starts at dcut(e) + ins(e)
+// with shift S_{e+1}.
+__global__ void k_eff_opos(const uint64_t* eff, const int64_t* count, int b, const int32_t* __restrict__ ooff,
+                           const int32_t* __restrict__ oidx, int64_t* opos) {
+  const uint64_t mask = (1ull << b) - 1;
+  const int64_t T = *count;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < T; e += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t k = eff[e];
+    const int32_t r = (int32_t)(k >> (b + 1));
+    const int32_t x = (int32_t)((k >> 1) & mask);
+    opos[e] = lower_bound_i32(oidx, ooff[r], ooff[r + 1], x);
+  }
+}
+
+__device__ __forceinline__ int64_t run_cut(const int64_t* opos, const int64_t* delpre, int64_t e) {
+  return opos[e] + e - 2 * delpre[e];
+}
+__device__ __forceinline__ int64_t run_begin(const uint64_t* eff, const int64_t* opos, const int64_t* delpre,
+                                             int64_t e) {
+  return e < 0 ? 0 : run_cut(opos, delpre, e) + (int64_t)(eff[e] & 1ull);
+}
+
+// Each workgroup fills `chunk` entries of the new index array from the runs
+// that cover them (insertions are written by k_run_inserts).
+__global__ void __launch_bounds__(kCopyBlock) k_run_copy(const int32_t* __restrict__ oidx,
+                                                         int32_t* __restrict__ nidx, const uint64_t* eff,
+                                                         const int64_t* delpre, const int64_t* opos,
+                                                         const int64_t* count, const int32_t* noff, int32_t n,
+                                                         int64_t m_old, int32_t chunk, int64_t* err) {
+  const int64_t mnew = noff[n];
+  const int64_t T = *count;
+  for (int64_t q0 = (int64_t)blockIdx.x * chunk; q0 < mnew; q0 += (int64_t)gridDim.x * chunk) {
+    const int64_t q1 = min(q0 + (int64_t)chunk, mnew);
+    // the run holding q0: the last e in [-1, T) whose run begins at or before q0
+    int64_t lo = -1, hi = T - 1;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) >> 1;
+      if (run_begin(eff, opos, delpre, mid) <= q0) lo = mid; else hi = mid - 1;
+    }
+    int64_t e = lo;
+    int64_t q = q0;
+    while (q < q1) {
+      const int64_t start = run_begin(eff, opos, delpre, e);
+      const int64_t end = e + 1 < T ? run_cut(opos, delpre, e + 1) : mnew;
+      const int64_t shift = e < 0 ? 0 : (e + 1) - 2 * delpre[e + 1];
+      const int64_t a = max(q, start), z = min(end, q1);
+      if (a < z) {
+        if (a - shift < 0 || z - shift > m_old) {  // runs disagree with the array: refuse to write
+          if (threadIdx.x == 0) atomicOr((unsigned long long*)err, 2ull);
+          break;
+        }
+        int64_t p = a + threadIdx.x;
+        for (; p + 7 * kCopyBlock < z; p += 8 * kCopyBlock) {
+          int32_t x[8];
+#pragma unroll
+          for (int k = 0; k < 8; k++) x[k] = __builtin_nontemporal_load(oidx + (p + k * kCopyBlock - shift));
+#pragma unroll
+          for (int k = 0; k < 8; k++) nidx[p + k * kCopyBlock] = x[k];
+        }
+        for (; p < z; p += kCopyBlock) nidx[p] = __builtin_nontemporal_load(oidx + (p - shift));
+      }
+      if (e + 1 >= T) break;
+      q = max(z, run_begin(eff, opos, delpre, e + 1));
+      e++;
+    }
+  }
+}
+
+__global__ void k_run_inserts(const uint64_t* eff, const int64_t* delpre, const int64_t* opos, const int64_t* count,
+                              int b, const int32_t* noff, int32_t n, int32_t* nidx, int64_t* err) {
+  const uint64_t mask = (1ull << b) - 1;
+  const int64_t T = *count;
+  const int64_t mnew = noff[n];
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < T; e += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t k = eff[e];
+    if (!(k & 1ull)) continue;
+    const int64_t d = run_cut(opos, delpre, e);
+    if (d < 0 || d >= mnew) {
+      atomicOr((unsigned long long*)err, 2ull);
+      continue;
+    }
+    nidx[d] = (int32_t)((k >> 1) & mask);
+  }
+}
+
+// Touched groups.  When the group's effective entries fit in one wavefront
+// (at most 63), lane k holds entry k and the deletion prefix count at k, and
+// each element's counts come from a search over the lanes instead of global
+// memory; otherwise the element searches its row's entries in memory.  Four
+// rounds of 64 elements are loaded before any is placed.
 __global__ void __launch_bounds__(256) k_rebuild(const int32_t* __restrict__ ooff, const int32_t* __restrict__ oidx,
                                                  const int32_t* __restrict__ noff, int32_t* __restrict__ nidx,
                                                  const uint8_t* touched, const uint64_t* eff, const int64_t* delpre,
                                                  const int64_t* count, int b, int32_t n, const int64_t* piece_pre,
-                                                 int64_t* err) {
+                                                 int32_t piece, int64_t* err) {
+  constexpr int kRounds = 4;
   const int lane = lane_id();
   const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
   const int64_t groups = ((int64_t)n + kWave - 1) / kWave;
@@ -394,27 +580,9 @@ __global__ void __launch_bounds__(256) k_rebuild(const int32_t* __restrict__ oof
     const int32_t r = r0 + lane;
     const bool valid = r < rend;
     const bool t = valid ? touched[r] != 0 : false;
-    const uint64_t any = __ballot(t);
-    const int32_t s0 = ooff[r0], s1 = ooff[rend];
-    const int32_t a = s0 + (int32_t)(k * kPiece);
-    const int32_t bnd = (int32_t)min((int64_t)a + kPiece, (int64_t)s1);
-    if (!any) {
-      const int64_t shift = (int64_t)noff[r0] - s0;
-      if ((int64_t)s1 + shift != (int64_t)noff[rend]) {  // offsets disagree: refuse to write
-        if (lane == 0) atomicOr((unsigned long long*)err, 2ull);
-        continue;
-      }
-      int32_t p = a + lane;
-      for (; p + 3 * kWave < bnd; p += 4 * kWave) {
-        const int32_t x0 = oidx[p], x1 = oidx[p + kWave], x2 = oidx[p + 2 * kWave], x3 = oidx[p + 3 * kWave];
-        nidx[p + shift] = x0;
-        nidx[p + kWave + shift] = x1;
-        nidx[p + 2 * kWave + shift] = x2;
-        nidx[p + 3 * kWave + shift] = x3;
-      }
-      for (; p < bnd; p += kWave) nidx[p + shift] = oidx[p];
-      continue;
-    }
+    const int32_t s1 = ooff[rend];
+    const int32_t a = ooff[r0] + (int32_t)(k * piece);
+    const int32_t bnd = (int32_t)min((int64_t)a + piece, (int64_t)s1);
     // per-lane row data of the group (lane l holds row r0 + l)
     const int32_t os = valid ? ooff[r] : INT32_MAX;
     const int32_t base = valid ? noff[r] : 0;
@@ -426,31 +594,68 @@ __global__ void __launch_bounds__(256) k_rebuild(const int32_t* __restrict__ oof
       hi = lower_bound_u64(eff, lo, T, rk + (1ull << (b + 1)));
       dlo = delpre[lo];
     }
-    for (int32_t p0 = a; p0 < bnd; p0 += kWave) {
-      const int32_t p = p0 + lane;
-      const bool ok = p < bnd;
-      const int j = lane_seg(os, ok ? p : a);
-      const int32_t r_os = __shfl(os, j, kWave), r_base = __shfl(base, j, kWave), r_lim = __shfl(lim, j, kWave);
-      const bool r_t = __shfl((int)t, j, kWave) != 0;
-      const int64_t r_lo = __shfl(lo, j, kWave), r_hi = __shfl(hi, j, kWave), r_dlo = __shfl(dlo, j, kWave);
-      if (!ok) continue;
-      const int32_t x = oidx[p];
-      const int32_t jj = p - r_os;
-      int64_t pos;
-      if (!r_t) {
-        pos = (int64_t)r_base + jj;
-      } else {
+    const int64_t glo = wave_min_i64(t ? lo : INT64_MAX);
+    const int64_t ghi = wave_max_i64(t ? hi : (int64_t)-1);
+    if (ghi < glo) {  // counted as touched but no touched row: refuse to write
+      if (lane == 0) atomicOr((unsigned long long*)err, 2ull);
+      continue;
+    }
+    const int64_t kg = ghi - glo;
+    const bool win = kg < kWave;
+    uint64_t wkey = ~0ull;  // padding sorts after every key
+    int64_t wdp = 0;
+    if (win) {
+      if (lane < kg) wkey = eff[glo + lane];
+      if (lane <= kg) wdp = delpre[glo + lane];
+    }
+    for (int32_t p0 = a; p0 < bnd; p0 += kRounds * kWave) {
+      int32_t xs[kRounds];
+#pragma unroll
+      for (int u = 0; u < kRounds; u++) {
+        const int32_t p = p0 + u * kWave + lane;
+        xs[u] = p < bnd ? oidx[p] : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < kRounds; u++) {
+        if (p0 + u * kWave >= bnd) break;  // the same for every lane
+        const int32_t p = p0 + u * kWave + lane;
+        const bool ok = p < bnd;
+        const int j = lane_seg(os, ok ? p : p0 + u * kWave);
+        const int32_t r_os = __shfl(os, j, kWave), r_base = __shfl(base, j, kWave), r_lim = __shfl(lim, j, kWave);
+        const bool r_t = __shfl((int)t, j, kWave) != 0;
+        const int64_t r_lo = __shfl(lo, j, kWave), r_hi = __shfl(hi, j, kWave), r_dlo = __shfl(dlo, j, kWave);
+        const int32_t x = xs[u];
+        const int32_t jj = p - r_os;
         const uint64_t xk = ((uint64_t)(r0 + j) << (b + 1)) | ((uint64_t)x << 1);
-        const int64_t qq = lower_bound_u64(eff, r_lo, r_hi, xk);
-        if (qq < r_hi && eff[qq] == xk) continue;  // deleted
-        const int64_t dels = delpre[qq] - r_dlo;
-        pos = (int64_t)r_base + jj - dels + ((qq - r_lo) - dels);
+        int64_t pos = (int64_t)r_base + jj;
+        bool drop = !ok;
+        if (win) {
+          // c = number of window entries below xk (every lane takes part)
+          int c = 0;
+#pragma unroll
+          for (int st = kWave / 2; st >= 1; st >>= 1)
+            if (__shfl(wkey, c + st - 1, kWave) < xk) c += st;
+          const uint64_t at = __shfl(wkey, min(c, kWave - 1), kWave);
+          const int64_t dp = __shfl(wdp, min(c, kWave - 1), kWave);
+          if (r_t) {
+            if (c < kg && at == xk) drop = true;  // deleted
+            const int64_t qq = glo + c;
+            const int64_t dels = dp - r_dlo;
+            pos = (int64_t)r_base + jj - dels + ((qq - r_lo) - dels);
+          }
+        } else if (ok && r_t) {
+          const int64_t qq = lower_bound_u64(eff, r_lo, r_hi, xk);
+          if (qq < r_hi && eff[qq] == xk) drop = true;  // deleted
+          const int64_t dels = delpre[qq] - r_dlo;
+          pos = (int64_t)r_base + jj - dels + ((qq - r_lo) - dels);
+        }
+        if (drop) continue;
+        if (pos < r_base || pos >= r_lim) {
+          atomicOr((unsigned long long*)err, 2ull);
+          continue;
+        }
+        nidx[pos] = x;
       }
-      if (pos < r_base || pos >= r_lim) {
-        atomicOr((unsigned long long*)err, 2ull);
-        continue;
-      }
-      nidx[pos] = x;
     }
   }
 }
@@ -595,7 +800,7 @@ size_t apply_buffer_bytes(int64_t nk, bool host_input) {
   t += r(nk * sizeof(uint64_t) + nk);                                             // keys_c + keep bytes
   t += r((radix_hist_elems(nk) + std::max(radix_scan_tmp_elems(nk), scan_tmp_elems(nk + 1))) * sizeof(int64_t) +
          64);                                                                     // sort_hist
-  t += r(2 * (nk + 1) * sizeof(int64_t));                                         // eff_pre
+  t += r(3 * (nk + 1) * sizeof(int64_t));                                         // eff_pre
   if (host_input) t += r(2 * nk * sizeof(int32_t));                               // batch_in
   return t + 8 * Heap::kAlign;
 }
@@ -915,15 +1120,35 @@ static int grow_capacity(dfpr_graph* g, int64_t want, hipStream_t s) {
   return DFPR_OK;
 }
 
-// One CSR: pieces of the old edges, then the insertions.
+// One CSR.  Few effective entries (at most one per 256 edges): runs between
+// the entries.  Otherwise: runs of untouched groups, pieces of the touched
+// groups, then the insertions.  Copy chunks and pieces get smaller on small
+// graphs so that the work still spreads over many wavefronts.
 static int rebuild_csr(dfpr_graph* g, const Csr& o, const Csr& nw, const uint8_t* touched, const uint64_t* eff,
-                       const int64_t* delpre, const int64_t* cnt, int64_t nk, int64_t* err, hipStream_t s) {
+                       const int64_t* delpre, int64_t* opos, const int64_t* cnt, int64_t nk, int64_t ni,
+                       int64_t* err, hipStream_t s) {
   const int32_t n = g->n;
   const int64_t groups = ((int64_t)n + kWave - 1) / kWave;
-  DFPR_TRY(scan_generic(LoadPieces{o.off, n}, StorePieces{g->piece_pre}, groups, g->scan_tmp, s));
-  const int64_t est = groups + g->m / kPiece + 1;  // upper bound on the piece count
-  k_rebuild<<<grid_for(est, 4, 1u << 16), 256, 0, s>>>(o.off, o.idx, nw.off, nw.idx, touched, eff, delpre, cnt,
-                                                       g->id_bits, n, g->piece_pre, err);
+  int32_t chunk = 1024;
+  while (chunk < 16384 && (int64_t)chunk * 2048 < g->m) chunk <<= 1;
+  const int64_t m_bound = g->m + ni;  // the new edge count is at most this
+  if (nk * 256 <= g->m) {
+    k_eff_opos<<<grid_for(nk, 256, 4096), 256, 0, s>>>(eff, cnt, g->id_bits, o.off, o.idx, opos);
+    k_run_copy<<<grid_for(m_bound, chunk, 1u << 16), kCopyBlock, 0, s>>>(o.idx, nw.idx, eff, delpre, opos, cnt,
+                                                                       nw.off, n, g->m, chunk, err);
+    k_run_inserts<<<grid_for(nk, 256, 4096), 256, 0, s>>>(eff, delpre, opos, cnt, g->id_bits, nw.off, n, nw.idx,
+                                                          err);
+    DFPR_HIP(hipGetLastError());
+    return DFPR_OK;
+  }
+  int32_t piece = 256;
+  while (piece < 4096 && (int64_t)piece * 65536 < g->m) piece <<= 1;
+  DFPR_TRY(scan_generic(LoadPieces{o.off, touched, n, piece}, StorePieces{g->piece_pre}, groups, g->scan_tmp, s));
+  k_shift_copy<<<grid_for(m_bound, chunk, 1u << 16), kCopyBlock, 0, s>>>(o.off, o.idx, nw.off, nw.idx, touched, n,
+                                                                       chunk, err);
+  const int64_t est = std::min(groups, nk) + g->m / piece + 1;  // upper bound on the piece count
+  k_rebuild<<<grid_for(est, 4, 4096), 256, 0, s>>>(o.off, o.idx, nw.off, nw.idx, touched, eff, delpre, cnt,
+                                                   g->id_bits, n, g->piece_pre, piece, err);
   k_place_inserts<<<grid_for(nk, 256, 4096), 256, 0, s>>>(o.off, o.idx, nw.off, nw.idx, eff, delpre, cnt, g->id_bits,
                                                           err);
   DFPR_HIP(hipGetLastError());
@@ -955,7 +1180,7 @@ int graph_apply(dfpr_graph* g, int64_t nd, const int32_t* del_src, const int32_t
   DFPR_TRY(g->keys_c.ensure(nk * sizeof(uint64_t) + nk));  // in-order keys + keep bytes
   DFPR_TRY(g->sort_hist.ensure((radix_hist_elems(nk) + std::max(radix_scan_tmp_elems(nk), scan_tmp_elems(nk + 1))) *
                                sizeof(int64_t)));
-  DFPR_TRY(g->eff_pre.ensure(2 * (nk + 1) * sizeof(int64_t)));
+  DFPR_TRY(g->eff_pre.ensure(3 * (nk + 1) * sizeof(int64_t)));  // deletion prefixes (out, in), opos
   uint64_t* ka = g->keys_a.as<uint64_t>();
   uint64_t* kb = g->keys_b.as<uint64_t>();
   uint64_t* kc = g->keys_c.as<uint64_t>();
@@ -964,6 +1189,7 @@ int graph_apply(dfpr_graph* g, int64_t nd, const int32_t* del_src, const int32_t
   int64_t* tmp = hist + radix_hist_elems(nk);
   int64_t* pre_out = g->eff_pre.as<int64_t>();
   int64_t* pre_in = pre_out + (nk + 1);
+  int64_t* opos = pre_in + (nk + 1);
   int64_t* counters = g->ctl->n_apply;
 
   const int32_t *ds = del_src, *dd = del_dst, *is = ins_src, *id = ins_dst;
@@ -1023,7 +1249,7 @@ int graph_apply(dfpr_graph* g, int64_t nd, const int32_t* del_src, const int32_t
   // ---- out-CSR
   DFPR_TRY(scan_row_offsets(g->out.off, g->delta_out, g->out2.off, n, g->scan_tmp, s));
   DFPR_TRY(ep.start(&tok));
-  DFPR_TRY(rebuild_csr(g, g->out, g->out2, g->touched_out, eff_out, pre_out, cnt, nk, counters + 4, s));
+  DFPR_TRY(rebuild_csr(g, g->out, g->out2, g->touched_out, eff_out, pre_out, opos, cnt, nk, ni, counters + 4, s));
   DFPR_TRY(ep.stop(kTRebuildOut, tok));
 
   // ---- in-CSR: the same entries ordered by (v, u)
@@ -1036,7 +1262,7 @@ int graph_apply(dfpr_graph* g, int64_t nd, const int32_t* del_src, const int32_t
   DFPR_TRY(scan_generic(LoadIsDel{eff_in, cnt}, StoreI64b{pre_in}, nk, tmp, s));
   DFPR_TRY(scan_row_offsets(g->in.off, g->delta_in, g->in2.off, n, g->scan_tmp, s));
   DFPR_TRY(ep.start(&tok));
-  DFPR_TRY(rebuild_csr(g, g->in, g->in2, g->touched_in, eff_in, pre_in, cnt, nk, counters + 4, s));
+  DFPR_TRY(rebuild_csr(g, g->in, g->in2, g->touched_in, eff_in, pre_in, opos, cnt, nk, ni, counters + 4, s));
   DFPR_TRY(ep.stop(kTRebuildIn, tok));
   k_clear_rows<<<grid_for(nk, 256, 65536), 256, 0, s>>>(eff_out, cnt, b, g->delta_out, g->delta_in, g->touched_out,
                                                         g->touched_in);

@@ -381,8 +381,10 @@ def test_frontier_criteria(criterion, tf, mode, fused):
 def test_asynchronous_mode(mode, fused):
     """In-place (asynchronous) DF/DF-P: not bit-reproducible, so accepted by
     error: against a tightly converged Static solve of the updated graph it is
-    about as accurate as the synchronous result and it stays within 1e-8 of
-    the synchronous oracle.  (Its iteration count depends on the execution
+    about as accurate as the synchronous result, and its distance from the
+    synchronous oracle stays within twice the synchronous result's own error
+    (both approximate the same fixed point; the triangle bound would allow
+    2.5 times).  (Its iteration count depends on the execution
     order too: near tau the interleaved updates can keep the L-inf change just
     above the tolerance for extra iterations.)"""
     torch_cuda()
@@ -402,4 +404,4 @@ def test_asynchronous_mode(mode, fused):
     # the result depends on the device's execution order: DF-P's error (its
     # pruning) moves by some 10 % from run to run; accept up to half again
     assert e_async <= max(1.5 * e_sync, e_sync + 1e-9)
-    assert e_cross <= 1e-8
+    assert e_cross <= 2 * e_sync + 1e-9

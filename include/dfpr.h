@@ -145,7 +145,7 @@ int dfpr_graph_create(int32_t n, int64_t m, const int32_t* src, const int32_t* d
                       dfpr_graph** out);
 
 /* create flags.  By default the library numbers vertices internally by
- * decreasing degree, so that the rank contributions of the high-degree
+ * decreasing in-degree, so that the rank contributions of the high-degree
  * vertices, which most edges read, sit together in cache; ids at the ABI are
  * always the caller's.  KEEP_IDS keeps the caller's numbering inside too
  * (then the one-lane bin sums in the caller's ascending source order). */

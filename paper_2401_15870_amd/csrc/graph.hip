@@ -78,7 +78,7 @@ static void dfree(T*& p) {
 // ------------------------------------------------------------------ kernels
 constexpr uint64_t kBadKey = ~0ull;
 
-// ---- internal numbering by decreasing degree (ties by caller id)
+// ---- internal numbering by decreasing in-degree (ties by caller id)
 __global__ void k_validate_count(const int32_t* src, const int32_t* dst, int64_t m, int32_t n, int32_t* deg,
                                  int64_t* err) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
@@ -86,13 +86,13 @@ __global__ void k_validate_count(const int32_t* src, const int32_t* dst, int64_t
     if (u < 0 || u >= n || v < 0 || v >= n) {
       atomicOr((unsigned long long*)err, 1ull);
     } else if (deg) {
-      atomicAdd(&deg[u], 1);
       atomicAdd(&deg[v], 1);
     }
   }
 }
-// Sort key of the internal numbering: member, then decreasing degree (capped
-// at 2^24-1), then caller id; members keep their contiguous vertex ranges.
+// Sort key of the internal numbering: member, then decreasing in-degree
+// (capped at 2^24-1), then caller id; members keep their contiguous vertex
+// ranges.
 __global__ void k_degree_keys(const int32_t* deg, const int32_t* gidv, int32_t n, int b, uint64_t* keys) {
   for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
     const uint64_t d = (uint64_t)min(deg[v], 0xFFFFFF);
@@ -1017,7 +1017,7 @@ int graph_create(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, d
       }
     }
     if (relabel) {
-      // order vertices by member, then decreasing degree (ties by id)
+      // order vertices by member, then decreasing in-degree (ties by id)
       k_degree_keys<<<grid_for(n, 256, 65536), 256, 0, s>>>(deg, g->gidv, n, b, t.ka);
       if ((rc = radix_sort(&t.ka, &t.kb, n, gbits + 24 + b, t.hist, t.tmp, s))) return fail(rc);
       k_perm_from_sorted<<<grid_for(n, 256, 65536), 256, 0, s>>>(t.ka, n, b, g->perm, g->inv);

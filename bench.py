@@ -500,6 +500,135 @@ def bench_sweep(args):
     print(json.dumps(res))
 
 
+def rocsparse_csrmv_ms(torch, crow, col, x, reps, timed):
+    """rocSPARSE's FP64 CSR SpMV (analysis once, then y = A x with A's values
+    all 1) on the caller's device tensors, through its C API."""
+    import ctypes
+    rs = ctypes.CDLL("librocsparse.so")
+    n = x.shape[0]
+    m = col.shape[0]
+    vp = ctypes.c_void_p
+    h, descr, info = vp(), vp(), vp()
+    for fn, arg in ((rs.rocsparse_create_handle, h), (rs.rocsparse_create_mat_descr, descr),
+                    (rs.rocsparse_create_mat_info, info)):
+        if fn(ctypes.byref(arg)) != 0:
+            raise RuntimeError(f"{fn.__name__} failed")
+    try:
+        stream = torch.cuda.current_stream().cuda_stream
+        if rs.rocsparse_set_stream(h, vp(stream)) != 0:
+            raise RuntimeError("rocsparse_set_stream failed")
+        vals = torch.ones(m, dtype=torch.float64, device=x.device)
+        y = torch.empty(n, dtype=torch.float64, device=x.device)
+        none = 111  # rocsparse_operation_none
+        ptr = lambda t: vp(t.data_ptr())
+        st = rs.rocsparse_dcsrmv_analysis(h, none, ctypes.c_int32(n), ctypes.c_int32(n), ctypes.c_int32(m), descr,
+                                          ptr(vals), ptr(crow), ptr(col), info)
+        if st != 0:
+            raise RuntimeError(f"rocsparse_dcsrmv_analysis status {st}")
+        alpha, beta = ctypes.c_double(1.0), ctypes.c_double(0.0)
+
+        def mv():
+            s = rs.rocsparse_dcsrmv(h, none, ctypes.c_int32(n), ctypes.c_int32(n), ctypes.c_int32(m),
+                                    ctypes.byref(alpha), descr, ptr(vals), ptr(crow), ptr(col), info, ptr(x),
+                                    ctypes.byref(beta), ptr(y))
+            if s != 0:
+                raise RuntimeError(f"rocsparse_dcsrmv status {s}")
+        ms = timed(mv, reps)
+        torch.cuda.synchronize()
+        return ms
+    finally:
+        torch.cuda.synchronize()
+        rs.rocsparse_destroy_mat_info(info)
+        rs.rocsparse_destroy_mat_descr(descr)
+        rs.rocsparse_destroy_handle(h)
+
+
+def bench_gather(args):
+    """The Static pull launch against library routines that do its core work on
+    the same graph in the library's internal vertex order: embedding_bag (sum
+    of gathered contributions per in-row, no values), rocSPARSE's CSR SpMV
+    (the same with an FP64 value per edge) and a plain gather of every
+    in-edge's contribution.  None of them reads or writes the rank, flag or degree
+    arrays the pull also handles, so they bound what the gathers alone cost."""
+    import torch
+    import paper_2401_15870_amd as dfpr
+    import workloads as W
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    n, src, dst = W.rmat_graph(args.scale, args.edge_factor, seed=args.seed)
+    g = dfpr.Graph.from_coo(n, torch.from_numpy(src).to(dev), torch.from_numpy(dst).to(dev))
+    m = g.m
+    log(f"gather: n={n} m={m} ({time.time() - t0:.1f}s)")
+    if not args.no_autotune:
+        bounds, _ = g.autotune()
+        log(f"autotune: bounds {bounds}")
+    g.set_timing(True)
+    r = torch.empty(n, dtype=torch.float64, device=dev)
+    g.update_ranks("static", None, out=r)
+    ms, launches = 0.0, 0
+    for _ in range(max(1, args.static_runs)):
+        _, st = g.update_ranks("static", None, out=r)
+        ms += st["ms_pull"]
+        launches += st["pull_launches"]
+    lib_ms = ms / launches
+    # the in-CSR in the library's internal order (decreasing in-degree, ties by id)
+    off, idx = g.export(in_csr=True)
+    off_t = torch.from_numpy(off.astype(np.int64)).to(dev)
+    idx_t = torch.from_numpy(idx).to(dev).long()
+    g.close()
+    deg = off_t[1:] - off_t[:-1]
+    key = (int(deg.max()) - deg) * n + torch.arange(n, device=dev)
+    order = torch.sort(key).indices
+    perm = torch.empty(n, dtype=torch.int64, device=dev)
+    perm[order] = torch.arange(n, device=dev)
+    rows = torch.repeat_interleave(torch.arange(n, device=dev), deg)
+    ekey = perm[rows] * n + perm[idx_t]
+    del rows, idx_t, key
+    ekey = torch.sort(ekey).values
+    col = (ekey % n).to(torch.int32)
+    crow = torch.zeros(n + 1, dtype=torch.int64, device=dev)
+    crow[1:] = torch.cumsum(torch.bincount(ekey // n, minlength=n), 0)
+    del ekey
+    contrib = torch.rand(n, dtype=torch.float64, device=dev)
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    reps = max(3, args.steps)
+    out = {"library_pull_static_ms": round(lib_ms, 4)}
+    col64 = col.long()
+    try:
+        out["embedding_bag_sum_ms"] = round(timed(lambda: torch.nn.functional.embedding_bag(
+            col64, contrib.view(n, 1), crow[:-1], mode="sum"), reps), 4)
+    except Exception as e:  # reported, not fatal
+        out["embedding_bag_sum_ms"] = f"failed: {type(e).__name__}: {e}"[:200]
+    try:
+        out["rocsparse_csrmv_ms"] = round(rocsparse_csrmv_ms(torch, crow.to(torch.int32), col, contrib, reps, timed), 4)
+    except Exception as e:
+        out["rocsparse_csrmv_ms"] = f"failed: {type(e).__name__}: {e}"[:200]
+    try:
+        out["index_select_ms"] = round(timed(lambda: torch.index_select(contrib, 0, col64), reps), 4)
+    except Exception as e:
+        out["index_select_ms"] = f"failed: {type(e).__name__}: {e}"[:200]
+    out["copy_index_stream_ms"] = round(timed(lambda: col.clone(), reps), 4)
+    log(json.dumps(out))
+    gathers_per_s = m / (lib_ms * 1e-3)
+    print(json.dumps({"metric": "Static pull launch vs library gather-sum routines on the same graph and order",
+                      "value": round(gathers_per_s, 1), "unit": "in-edges/s (library pull)", "n_gpus": 1,
+                      "steps": reps, "warmup": 1, "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+                      "config": {"workload": f"R-MAT scale {args.scale}, edge factor {args.edge_factor:g}, "
+                                             f"in-CSR in decreasing in-degree order", "n": n, "m": m},
+                      "times_ms": out}))
+
+
 def summarize_main(args):
     """Print the profile summaries of a profiled run directory (see profiles/)."""
     d = args.summarize
@@ -538,9 +667,10 @@ def main():
     ap.add_argument("--calib", action="store_true",
                     help="finish with three 1 GiB device copies (counter calibration under a profiler)")
     ap.add_argument("--sweep-batch", type=float, default=1e-5, help="sweep: batch size as a fraction of the stream")
-    ap.add_argument("--workload", default="rmat", choices=["rmat", "batched", "serving", "sweep"],
+    ap.add_argument("--workload", default="rmat", choices=["rmat", "batched", "serving", "sweep", "gather"],
                     help="rmat: one large R-MAT graph (default); batched: many graphs in one batch handle; "
-                         "serving: request loop over resident graphs; sweep: frontier measures and tolerances")
+                         "serving: request loop over resident graphs; sweep: frontier measures and tolerances; "
+                         "gather: the Static pull launch against library gather-sum routines")
     ap.add_argument("--rates", default="100,1000,10000", help="serving: Poisson arrival rates per second")
     ap.add_argument("--requests", type=int, default=1000, help="serving: requests per rate and server setting")
     ap.add_argument("--lanes", type=int, default=4, help="serving: request lanes")
@@ -576,6 +706,9 @@ def main():
         return
     if args.workload == "sweep":
         bench_sweep(args)
+        return
+    if args.workload == "gather":
+        bench_gather(args)
         return
 
     t0 = time.time()

@@ -133,6 +133,42 @@ __global__ void __launch_bounds__(kRadixBlock) k_radix_scatter(const uint64_t* k
   }
 }
 
+// Scatter for up to kFusedScanBlocks tiles: each block derives its digit
+// offsets from the raw per-tile counts itself (thread d sums digit d over the
+// tiles, then one block scan over the digits), so a pass needs no separate
+// scan of the counts.
+constexpr int64_t kFusedScanBlocks = 32;
+__global__ void __launch_bounds__(kRadixBlock) k_radix_scatter_own(const uint64_t* keys, uint64_t* out, int64_t n,
+                                                                   int shift, const int64_t* hist, int64_t nb) {
+  __shared__ int wave_cnt[(kRadixBlock / kWave) * 256];
+  __shared__ int running[256];
+  __shared__ int64_t gbase[256];
+  __shared__ int64_t scan_sh[kRadixBlock / kWave + 1];
+  for (int i = threadIdx.x; i < (kRadixBlock / kWave) * 256; i += kRadixBlock) wave_cnt[i] = 0;
+  running[threadIdx.x] = 0;
+  {
+    const int64_t* row = hist + (int64_t)threadIdx.x * nb;  // digit threadIdx.x over the tiles
+    int64_t before = 0, total = 0;
+    for (int64_t b = 0; b < nb; b++) {
+      const int64_t c = row[b];
+      if (b < blockIdx.x) before += c;
+      total += c;
+    }
+    int64_t all;
+    gbase[threadIdx.x] = block_exclusive_scan(total, scan_sh, &all) + before;
+  }
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+  for (int j = 0; j < kRadixItems; j++) {
+    const int64_t i = base + j * kRadixBlock + threadIdx.x;
+    const bool valid = i < n;
+    const uint64_t k = valid ? keys[i] : 0;
+    const uint32_t digit = (uint32_t)((k >> shift) & 255u);
+    const int pos = block_rank_round(digit, valid, wave_cnt, running);
+    if (valid) out[gbase[digit] + pos] = k;
+  }
+}
+
 // Whole sort inside one block for n <= kSmallSort keys.
 constexpr int kSmallSort = 2048;
 __global__ void __launch_bounds__(kRadixBlock) k_radix_small(uint64_t* keys, int64_t n, int bits) {
@@ -183,8 +219,12 @@ int radix_sort(uint64_t** keys, uint64_t** alt, int64_t n, int bits, int64_t* hi
   const int64_t nb = (n + kRadixTile - 1) / kRadixTile;
   for (int shift = 0; shift < bits; shift += 8) {
     k_radix_hist<<<(unsigned)nb, kRadixBlock, 0, s>>>(*keys, n, shift, hist, nb);
-    DFPR_TRY(scan_i64(hist, hist, 256 * nb, scan_tmp, s));
-    k_radix_scatter<<<(unsigned)nb, kRadixBlock, 0, s>>>(*keys, *alt, n, shift, hist, nb);
+    if (nb <= kFusedScanBlocks) {
+      k_radix_scatter_own<<<(unsigned)nb, kRadixBlock, 0, s>>>(*keys, *alt, n, shift, hist, nb);
+    } else {
+      DFPR_TRY(scan_i64(hist, hist, 256 * nb, scan_tmp, s));
+      k_radix_scatter<<<(unsigned)nb, kRadixBlock, 0, s>>>(*keys, *alt, n, shift, hist, nb);
+    }
     uint64_t* t = *keys;
     *keys = *alt;
     *alt = t;

@@ -778,6 +778,8 @@ def main():
         if i == args.warmup:
             torch.cuda.synchronize()
             t_begin = time.perf_counter()
+        if i == total - 1:
+            r_before_last = r.clone()  # for the ND comparison after the timed steps
         ta = time.perf_counter()
         info = g.apply_batch(*dev_batches[i])
         tb = time.perf_counter()
@@ -812,6 +814,17 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_begin
     K = args.steps
+    # ---- GPU ND (Static warm-started from the ranks before the last batch, on
+    # the graph after it): untimed by the step clock, reported beside Static
+    nd_ms, nd_it = [], 0
+    r_nd = torch.empty_like(r)
+    for _ in range(args.static_runs):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, st_nd = g.update_ranks("nd", r_before_last, out=r_nd)
+        nd_ms.append((time.perf_counter() - t) * 1e3)
+        nd_it = st_nd["iterations"]
+    log(f"GPU ND (warm, last batch): {np.median(nd_ms):.2f} ms, {nd_it} iterations")
     ms_per_step = elapsed * 1e3 / K
     m_mean = m_sum / K
     value = m_mean * K / elapsed
@@ -857,6 +870,8 @@ def main():
         "rank_p50_ms": pct(rank_ms, 50),
         "static_ms": float(np.median(static_ms)),
         "static_iterations": static_it,
+        "nd_ms": float(np.median(nd_ms)),
+        "nd_iterations": nd_it,
         "speedup_vs_static": float(np.median(static_ms)) / pct(step_ms, 50),
         "rank_speedup_vs_static": float(np.median(static_ms)) / pct(rank_ms, 50),
         "iterations_mean": float(np.mean(iters)),

@@ -89,6 +89,62 @@ def test_apply_hub_rows():
     assert_csr_equal(p.g, p.og)
 
 
+def _pairs_not_in(rng, og, count, u_range, v_range, taken):
+    """`count` distinct non-self pairs with u, v in the given ranges, absent from the graph and `taken`."""
+    existing = set(zip(og.esrc.tolist(), og.edst.tolist()))
+    out = []
+    while len(out) < count:
+        u = int(rng.integers(*u_range))
+        v = int(rng.integers(*v_range))
+        if u != v and (u, v) not in existing and (u, v) not in taken:
+            taken.add((u, v))
+            out.append((u, v))
+    return out
+
+
+@pytest.mark.parametrize("extra", [0, 1])
+def test_apply_run_and_group_paths(extra):
+    """Raw batch sizes on both sides of the switch between the run-by-run copy
+    (at most one raw entry per 256 edges) and the merge of touched groups."""
+    torch_cuda()
+    n, s, d = rmat(12, seed=61)
+    p = Pair(n, s, d)
+    rng = np.random.default_rng(62)
+    nk = p.og.m // 256 + extra
+    n_del = nk // 5
+    nonself = np.flatnonzero(p.og.esrc != p.og.edst)
+    pick = rng.choice(nonself, n_del, replace=False)
+    ins = _pairs_not_in(rng, p.og, nk - n_del, (0, n), (0, n), set())
+    _print("apply paths", nk, p.og.m)
+    p.apply(p.og.esrc[pick], p.og.edst[pick], np.array([u for u, _ in ins], np.int32),
+            np.array([v for _, v in ins], np.int32))
+    assert_csr_equal(p.g, p.og)
+
+
+@pytest.mark.parametrize("k", [63, 64, 65])
+def test_apply_group_entries_at_lane_count(k):
+    """Merge of touched groups: rows 0..63 (one group; caller ids kept inside)
+    get exactly 63, 64 or 65 effective entries, a third of them deletions; up
+    to 63 are held in the lanes, from 64 on they are searched in memory.  The
+    rest of the batch (rows >= 64) makes it large enough for the merge path."""
+    torch_cuda()
+    n, s, d = rmat(12, seed=63)
+    p = Pair(n, s, d, keep_ids=True)
+    og = p.og
+    rng = np.random.default_rng(64)
+    in_group = np.flatnonzero((og.esrc < 64) & (og.esrc != og.edst))
+    dels = rng.choice(in_group, k // 3, replace=False)
+    taken = set()
+    ins = _pairs_not_in(rng, og, k - k // 3, (0, 64), (0, n), taken)
+    pad = _pairs_not_in(rng, og, og.m // 256 + 1, (64, n), (0, n), taken)
+    ins_src = np.array([u for u, _ in ins + pad], np.int32)
+    ins_dst = np.array([v for _, v in ins + pad], np.int32)
+    _print("group entries", k, len(ins_src) + len(dels), og.m)
+    info = p.apply(og.esrc[dels], og.edst[dels], ins_src, ins_dst)
+    assert info["ins_effective"] == len(ins_src) and info["del_effective"] == len(dels)
+    assert_csr_equal(p.g, p.og)
+
+
 # ------------------------------------------------------------------ ranks
 def _setup(scale=12, frac=1e-3, seed=1, ef=16, keep_ids=False):
     n, s, d = rmat(scale, ef=ef, seed=seed)

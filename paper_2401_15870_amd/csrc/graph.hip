@@ -331,7 +331,8 @@ struct StoreI64b {
   __device__ void operator()(int64_t i, int64_t v) const { a[i] = v; }
 };
 
-// Rebuild one CSR in two kernels.  Rows are taken in groups of 64 (one per
+// Rebuild of one CSR for a batch with many effective entries (few entries take
+// the run-by-run copy further below).  Rows are taken in groups of 64 (one per
 // lane).  A group without touched rows keeps its rows and only shifts them,
 // and the shift (new offset - old offset) stays the same up to the next
 // touched group, so k_shift_copy moves each run of untouched groups as one

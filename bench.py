@@ -437,6 +437,94 @@ def bench_serving(args):
     print(json.dumps(res))
 
 
+def bench_temporal(args):
+    """The temporal stream: 2M vertices, a 40M-edge stream in time order, the
+    first 36M as G0, then insertion-only batches of 40,000 edges in time order
+    (repeats of present edges are no-ops).  DF-P, DF and ND are chained (each
+    starts from its own previous result); Static starts cold on every graph.
+    With the oracle leg, the GPU DF-P chain and the oracle's own DF-P chain are
+    compared after every one of the first batches (drift, not a parity gate:
+    the per-step gate with equal inputs is a test)."""
+    import torch
+    import paper_2401_15870_amd as dfpr
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    n, total, k0, B = 2_000_000, 40_000_000, 36_000_000, 40_000
+    t0 = time.time()
+    src, dst = W.temporal_stream(n, total, seed=args.seed + 6)
+    steps = min(args.steps, (len(src) - k0) // B)
+    log(f"temporal: n={n} stream={len(src)} initial {k0}, {steps} batches of {B} ({time.time() - t0:.0f}s)")
+    s0, d0 = torch.from_numpy(src[:k0]).to(dev), torch.from_numpy(dst[:k0]).to(dev)
+    modes = ("dfp", "df", "nd")
+    gs = {m: dfpr.Graph.from_coo(n, s0, d0) for m in modes + ("static",)}
+    if not args.no_autotune:
+        bounds, _ = gs["dfp"].autotune()
+        for m in modes + ("static",):
+            gs[m].set_tuning(bounds)
+    m0 = gs["dfp"].m
+    r0, _ = gs["static"].update_ranks("static", None)
+    ranks = {m: r0.clone() for m in modes}
+    oracle_steps = 0 if args.no_cpu else min(10, steps)
+    if oracle_steps:
+        import oracle as O
+        og = O.graph(n, src[:k0], dst[:k0])
+        r_or = r0.cpu().numpy()
+    ms = {m: [] for m in modes + ("static",)}
+    it = {m: [] for m in modes + ("static",)}
+    apply_ms, ever, drift, m_after = [], [], [], 0
+    for b in range(steps):
+        lo = k0 + b * B
+        ins_s, ins_d = src[lo:lo + B], dst[lo:lo + B]
+        dev_ins = (torch.from_numpy(ins_s).to(dev), torch.from_numpy(ins_d).to(dev))
+        for m, g in gs.items():
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            info = g.apply_batch([], [], *dev_ins)
+            torch.cuda.synchronize()
+            if m == "dfp":
+                apply_ms.append((time.perf_counter() - t) * 1e3)
+                m_after = info["m_after"]
+        for m in modes + ("static",):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            if m == "static":
+                _, st = gs[m].update_ranks("static", None)
+            else:
+                _, st = gs[m].update_ranks(m, ranks[m], out=ranks[m])
+            ms[m].append((time.perf_counter() - t) * 1e3)
+            it[m].append(st["iterations"])
+            if m == "dfp":
+                ever.append(st["ever_affected"])
+        if b < oracle_steps:
+            og2, ob = O.apply(og, [], [], ins_s, ins_d)
+            r_or = O.rank("dfp", og2, r_or, og, ob).ranks
+            og = og2
+            drift.append(float(np.abs(ranks["dfp"].cpu().numpy() - r_or).max()))
+        if b % 10 == 0 or b + 1 == steps:
+            log(f"batch {b}: apply {apply_ms[-1]:.2f} ms, dfp {ms['dfp'][-1]:.2f} ({it['dfp'][-1]} it), "
+                f"df {ms['df'][-1]:.2f}, nd {ms['nd'][-1]:.2f}, static {ms['static'][-1]:.2f} ms"
+                + (f", drift vs oracle chain {drift[-1]:.2e}" if b < oracle_steps else ""))
+    step = [a + r for a, r in zip(apply_ms, ms["dfp"])]
+    res = {
+        "metric": "DF-P update time & edges/s vs GPU Static at L\u221e err \u22641e-9; p50/p99 latency",
+        "value": m_after / (pct(step, 50) * 1e-3), "unit": "edges/s", "n_gpus": 1, "steps": steps, "warmup": 0,
+        "ms_per_step": float(np.mean(step)), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"temporal stream (preferential attachment, 10 % repeats), {n} vertices, "
+                               f"first {k0} of {len(src)} edges as G0, chained insertion-only batches of {B} "
+                               f"in time order; apply + DFP update per step",
+                   "n": n, "m0": int(m0), "parallelism": "1 GPU"},
+        "p50_ms": pct(step, 50), "p99_ms": pct(step, 99), "apply_p50_ms": pct(apply_ms, 50),
+        "update_p50_ms": {m: pct(ms[m], 50) for m in ms},
+        "iterations_mean": {m: float(np.mean(it[m])) for m in it},
+        "speedup_vs_static": {m: pct(ms["static"], 50) / pct(ms[m], 50) for m in modes},
+        "ever_affected_mean": float(np.mean(ever)),
+        "drift_vs_oracle_chain_linf": drift,
+    }
+    print(json.dumps(res))
+
+
 def bench_sweep(args):
     """Frontier measures and tolerances (Section 4.2) on the temporal stream:
     mean DF-P update time and rank error (L1 against a reference Static run to
@@ -667,10 +755,11 @@ def main():
     ap.add_argument("--calib", action="store_true",
                     help="finish with three 1 GiB device copies (counter calibration under a profiler)")
     ap.add_argument("--sweep-batch", type=float, default=1e-5, help="sweep: batch size as a fraction of the stream")
-    ap.add_argument("--workload", default="rmat", choices=["rmat", "batched", "serving", "sweep", "gather"],
+    ap.add_argument("--workload", default="rmat", choices=["rmat", "batched", "serving", "sweep", "gather", "temporal"],
                     help="rmat: one large R-MAT graph (default); batched: many graphs in one batch handle; "
                          "serving: request loop over resident graphs; sweep: frontier measures and tolerances; "
-                         "gather: the Static pull launch against library gather-sum routines")
+                         "gather: the Static pull launch against library gather-sum routines; "
+                         "temporal: chained insertion batches of the temporal stream")
     ap.add_argument("--rates", default="100,1000,10000", help="serving: Poisson arrival rates per second")
     ap.add_argument("--requests", type=int, default=1000, help="serving: requests per rate and server setting")
     ap.add_argument("--lanes", type=int, default=4, help="serving: request lanes")
@@ -709,6 +798,9 @@ def main():
         return
     if args.workload == "gather":
         bench_gather(args)
+        return
+    if args.workload == "temporal":
+        bench_temporal(args)
         return
 
     t0 = time.time()

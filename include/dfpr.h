@@ -56,8 +56,10 @@ typedef enum { DFPR_HOST = 0, DFPR_DEVICE = 1 } dfpr_where;
  * unmarks a processed vertex whose relative change is at most this.
  * dense_switch (>= 0): DF/DF-P iterations whose affected vertices hold more than
  * this share of |E| in-edges run in the dense form (every vertex checks its
- * in-neighbours' expand flags instead of being marked); 0 = always dense, above
- * 1 = never.  Both forms give identical results; only speed differs.
+ * in-neighbours' expand flags instead of being marked), unless those vertices
+ * are under 1/16 of |V| and have under a quarter as many out-edges as
+ * in-edges; 0 = always dense, above 1 = never.  Both forms give identical
+ * results; only speed differs.
  * max_iters >= 1.  flags: DFPR_FLAG_* bits.  criterion: DFPR_CRIT_*. */
 typedef struct {
   double alpha, tol, frontier_tol, prune_tol, dense_switch;

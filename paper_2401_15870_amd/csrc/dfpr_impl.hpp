@@ -157,7 +157,8 @@ enum AccRow : int {
   kAccAffEdges = kBins + 2,// dense pull: summed in-degree of the affected vertices
   kAccXEdges = kBins + 3,  // dense pull: summed out-degree of the expanding vertices
   kAccStayEdges = kBins + 4,  // dense pull: summed in-degree of the kept vertices
-  kAccRows = kBins + 5
+  kAccOutEdges = kBins + 5,   // binning pass: summed out-degree of the binned vertices
+  kAccRows = kBins + 6
 };
 
 // Per-update control block in device memory.  The compact head is read back
@@ -174,7 +175,8 @@ struct IterCtl {
   int64_t dense_xedges;      // dense pull: summed out-degree of its expanding vertices
   int64_t dense_sedges;      // dense pull: summed in-degree of its kept vertices
   int64_t active;            // member graphs not yet converged (1/0 for a plain graph)
-  int64_t pad[2];
+  int64_t bin_out_edges;     // summed out-degree of the vertices of the last binning pass
+  int64_t pad[1];
   unsigned long long acc_slots[kAccRows][kSlots * kSlotStride];
   // single-launch loop: L-inf change of iteration i in fused_dr[(i % 3) * kSlotStride]
   unsigned long long fused_dr[3 * kSlotStride];

@@ -783,19 +783,23 @@ __device__ __forceinline__ unsigned tile_flags(const uint8_t* flags, int64_t bas
 }
 
 // Vertices [lo, n) are binned (n: end of the range).
-__global__ void __launch_bounds__(256) k_bin_count(const uint8_t* flags, const int32_t* __restrict__ in_off, int64_t lo,
-                                                   int32_t n, MemberMask mm, Bounds B, int64_t* blk, int64_t nb,
+__global__ void __launch_bounds__(256) k_bin_count(const uint8_t* flags, const int32_t* __restrict__ in_off,
+                                                   const int32_t* __restrict__ out_off, int64_t lo, int32_t n,
+                                                   MemberMask mm, Bounds B, int64_t* blk, int64_t nb,
                                                    unsigned long long* acc) {
   __shared__ int64_t sh[256 / kWave + 1];
-  __shared__ int64_t she[256 / kWave][kBins];
+  __shared__ int64_t she[256 / kWave][kBins + 1];
   const int64_t base = lo + (int64_t)blockIdx.x * kBinTile + (int64_t)threadIdx.x * kBinItems;
   const unsigned m = tile_flags(flags, base, n, mm);
   int64_t p0 = 0, p1 = 0;
-  int64_t ed[kBins] = {0, 0, 0, 0, 0, 0};
+  int64_t ed[kBins + 1] = {0, 0, 0, 0, 0, 0, 0};  // per-bin in-degree sums, then the out-degree sum
   if (m) {
-    int32_t o[kBinItems + 1];
+    int32_t o[kBinItems + 1], q[kBinItems + 1];
 #pragma unroll
-    for (int j = 0; j <= kBinItems; j++) o[j] = base + j <= n ? in_off[base + j] : 0;
+    for (int j = 0; j <= kBinItems; j++) {
+      o[j] = base + j <= n ? in_off[base + j] : 0;
+      q[j] = base + j <= n ? out_off[base + j] : 0;
+    }
 #pragma unroll
     for (int j = 0; j < kBinItems; j++) {
       if (m & (1u << j)) {
@@ -804,6 +808,7 @@ __global__ void __launch_bounds__(256) k_bin_count(const uint8_t* flags, const i
         if (b < 3) p0 += (int64_t)1 << (kBinShift * b); else p1 += (int64_t)1 << (kBinShift * (b - 3));
 #pragma unroll
         for (int t = 0; t < kBins; t++) ed[t] += (t == b) ? d : 0;
+        ed[kBins] += q[j + 1] - q[j];
       }
     }
   }
@@ -818,14 +823,14 @@ __global__ void __launch_bounds__(256) k_bin_count(const uint8_t* flags, const i
     }
   }
 #pragma unroll
-  for (int t = 0; t < kBins; t++) ed[t] = wave_sum_i64(ed[t]);
+  for (int t = 0; t <= kBins; t++) ed[t] = wave_sum_i64(ed[t]);
   if (lane_id() == 0)
-    for (int t = 0; t < kBins; t++) she[threadIdx.x / kWave][t] = ed[t];
+    for (int t = 0; t <= kBins; t++) she[threadIdx.x / kWave][t] = ed[t];
   __syncthreads();
-  if (threadIdx.x < kBins) {
+  if (threadIdx.x <= kBins) {
     const int64_t s = she[0][threadIdx.x] + she[1][threadIdx.x] + she[2][threadIdx.x] + she[3][threadIdx.x];
-    if (s) atomicAdd(&acc[(kAccEdges0 + threadIdx.x) * (kSlots * kSlotStride) + (blockIdx.x % kSlots) * kSlotStride],
-                     (unsigned long long)s);
+    const int row = threadIdx.x < kBins ? kAccEdges0 + (int)threadIdx.x : kAccOutEdges;
+    if (s) atomicAdd(&acc[row * (kSlots * kSlotStride) + (blockIdx.x % kSlots) * kSlotStride], (unsigned long long)s);
   }
 }
 
@@ -962,6 +967,7 @@ __global__ void __launch_bounds__(kSlots) k_iter_finish(IterCtl* c) {
     c->dense_edges = r[kAccAffEdges];
     c->dense_xedges = r[kAccXEdges];
     c->dense_sedges = r[kAccStayEdges];
+    c->bin_out_edges = r[kAccOutEdges];
     c->big_count = 0;
   }
 }
@@ -1069,8 +1075,8 @@ static int bin_vertices(dfpr_graph* g, const uint8_t* flags, int32_t* wl, uint8_
   const int64_t nb = std::max<int64_t>(1, (hi - lo + kBinTile - 1) / kBinTile);
   // the cached all-vertex bins (flags == null) never drop converged members
   const MemberMask mm{flags ? g->gidv : nullptr, flags ? g->done : nullptr};
-  k_bin_count<<<(unsigned)nb, 256, 0, s>>>(flags, g->in.off, lo, (int32_t)hi, mm, bounds_of(g), g->bin_blk, nb,
-                                           &g->ctl->acc_slots[0][0]);
+  k_bin_count<<<(unsigned)nb, 256, 0, s>>>(flags, g->in.off, g->out.off, lo, (int32_t)hi, mm, bounds_of(g), g->bin_blk,
+                                           nb, &g->ctl->acc_slots[0][0]);
   DFPR_TRY(scan_i64(g->bin_blk, g->bin_blk, kBins * nb, g->scan_tmp, s));
   k_bin_scatter<<<(unsigned)nb, 256, 0, s>>>(flags, g->in.off, lo, (int32_t)hi, mm, bounds_of(g), g->bin_blk, nb, wl,
                                              ever, g->ctl->bin_end);
@@ -1372,7 +1378,14 @@ static int pull_parts(dfpr_graph* g, const PullArgs& a, hipStream_t s, dfpr_stat
 //    flags, so no marks are written); ranks and contributions ping-pong.
 // The affected sets, the per-vertex sums (same bins, same order) and so the
 // ranks are identical; dense is chosen while the frontier's in-edges exceed
-// dense_switch * |E|, where scanning everything beats scattered marking.
+// dense_switch * |E|, where scanning everything beats scattered marking,
+// unless the frontier holds under 1/kDenseVertexShare of the vertices and
+// its out-edges (what the frontier form marks) are under a quarter of its
+// in-edges: the dense form visits every vertex and scans the in-neighbour
+// flags of every vertex it does not keep, which a frontier of a few vertices
+// with many in-edges and few out-edges (a temporal graph's hubs) does not
+// repay.
+constexpr int64_t kDenseVertexShare = 16;
 template <int MODE>
 static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_prev, double* r_out, hipStream_t s,
                         dfpr_stats* st) {
@@ -1439,18 +1452,21 @@ static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_pre
   const double switch_edges = p.dense_switch * (double)m;
   bool need_bins = false;  // dense -> frontier: the frontier must be marked and binned first
   bool dense = false, use_x = false;
-  int64_t front_edges = 0, front_cnt = 0;
+  int64_t front_edges = 0, front_cnt = 0, front_out = 0;
   {
     const int64_t* h = g->ctl_host->bin_edges;
     for (int k = 0; k < kBins; k++) front_edges += h[k];
     front_cnt = g->ctl_host->bin_end[kBins - 1];
+    front_out = g->ctl_host->bin_out_edges;
   }
   PullArgs a = make_args(g, p);
   int it = 0;
   double dR = 0.0;
   bool conv = false;
   for (it = 0; it < p.max_iters; it++) {
-    if (!dense && front_edges > switch_edges && MODE != kSync) {
+    if (!dense && front_edges > switch_edges &&
+        (p.dense_switch == 0.0 || front_cnt * kDenseVertexShare >= n || front_out * 4 >= front_edges) &&
+        MODE != kSync) {
       dense = true;  // the complete frontier is in `cur`; no expand flags to read
       use_x = false;
     }
@@ -1495,7 +1511,9 @@ static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_pre
         it++;
         break;
       }
-      if (front_edges < switch_edges / 2) {  // strict: dense_switch 0 keeps every iteration dense
+      // strict comparisons: dense_switch 0 keeps every iteration dense
+      if (front_edges < switch_edges / 2 ||
+          (p.dense_switch > 0.0 && h->dense_cnt * 2 * kDenseVertexShare < n && h->dense_xedges * 4 < front_edges)) {
         // back to the frontier form: mark out(v) of this iteration's expanders
         // into the keep flags (clears xa), then bin
         k_mark_pending<<<gi, 256, 0, s>>>(xa, n, g->out.off, g->out.idx, cur, g->big_list, &g->ctl->big_count);
@@ -1509,6 +1527,7 @@ static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_pre
         front_edges = 0;
         for (int k = 0; k < kBins; k++) front_edges += g->ctl_host->bin_edges[k];
         front_cnt = g->ctl_host->bin_end[kBins - 1];
+        front_out = g->ctl_host->bin_out_edges;
       }
       continue;
     }
@@ -1548,6 +1567,7 @@ static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_pre
     front_edges = 0;
     for (int k = 0; k < kBins; k++) front_edges += g->ctl_host->bin_edges[k];
     front_cnt = g->ctl_host->bin_end[kBins - 1];
+    front_out = g->ctl_host->bin_out_edges;
     if (g->ctl_host->active == 0) {
       conv = true;
       it++;

@@ -397,8 +397,10 @@ __device__ __forceinline__ void pull_block(const PullArgs& a, const int32_t* __r
 // first chunk of the bin's j-th vertex (exclusive scan of the chunk counts);
 // workgroup lb takes the contiguous chunk range [lb*T/nb, (lb+1)*T/nb).  Each
 // chunk's sum goes to `partial`; the workgroup that finishes a vertex's last
-// chunk (arrival counter) adds the partials in chunk order and computes the
-// rank.  DENSE: each chunk also reports whether an in-neighbour expanded.
+// chunk (arrival counter) adds the partials (thread t takes chunks t, t+256,
+// ..., then a fixed reduction tree: the same bits whatever the arrival order)
+// and computes the rank.  DENSE: each chunk also reports whether an
+// in-neighbour expanded.
 __device__ __forceinline__ int64_t upper_bound_i64(const int64_t* a, int64_t lo, int64_t hi, int64_t x) {
   while (lo < hi) {
     int64_t mid = lo + ((hi - lo) >> 1);
@@ -440,17 +442,29 @@ __device__ __forceinline__ void pull_chunks(const PullArgs& a, const int32_t* __
       last = atomicAdd(&a.arrive[j], 1) == (int)(cj1 - cj - 1);
     }
     __syncthreads();
-    if (threadIdx.x == 0 && last) {
+    if (last) {  // the same in every thread: the whole workgroup adds the row's partials
       __threadfence();
       double c = 0.0;
       int anyx = 0;
-      for (int64_t t = cj; t < cj1; t++) {
+      for (int64_t t = cj + threadIdx.x; t < cj1; t += blockDim.x) {
         c += __hip_atomic_load(&a.partial[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (DENSE) anyx |= __hip_atomic_load(&a.partial_x[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
-      a.arrive[j] = 0;
-      const bool aff = !member_done(a, x.g) && (!DENSE || a.stay_in[x.v] || (a.use_x && anyx));
-      vertex_finish<MODE, DENSE>(a, x, aff ? c : 0.0, aff, acc);
+      c = wave_sum(c);
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) anyx |= __shfl_xor(anyx, o, kWave);
+      if (lane_id() == 0) {
+        sh[threadIdx.x / kWave] = c;
+        shx[threadIdx.x / kWave] = anyx;
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        c = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+        anyx = shx[0] | shx[1] | shx[2] | shx[3];
+        a.arrive[j] = 0;
+        const bool aff = !member_done(a, x.g) && (!DENSE || a.stay_in[x.v] || (a.use_x && anyx));
+        vertex_finish<MODE, DENSE>(a, x, aff ? c : 0.0, aff, acc);
+      }
     }
     __syncthreads();
   }

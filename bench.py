@@ -643,10 +643,17 @@ def bench_gather(args):
     import workloads as W
     dev = torch.device("cuda:0")
     t0 = time.time()
-    n, src, dst = W.rmat_graph(args.scale, args.edge_factor, seed=args.seed)
+    if args.gather_graph == "temporal":  # G0 of the temporal workload
+        n = 2_000_000
+        src, dst = W.temporal_stream(n, 40_000_000, seed=args.seed + 6)
+        src, dst = src[:36_000_000], dst[:36_000_000]
+        desc = "temporal stream G0 (2M vertices, first 36M of 40M stream edges)"
+    else:
+        n, src, dst = W.rmat_graph(args.scale, args.edge_factor, seed=args.seed)
+        desc = f"R-MAT scale {args.scale}, edge factor {args.edge_factor:g}"
     g = dfpr.Graph.from_coo(n, torch.from_numpy(src).to(dev), torch.from_numpy(dst).to(dev))
     m = g.m
-    log(f"gather: n={n} m={m} ({time.time() - t0:.1f}s)")
+    log(f"gather: {desc}: n={n} m={m} ({time.time() - t0:.1f}s)")
     if not args.no_autotune:
         bounds, _ = g.autotune()
         log(f"autotune: bounds {bounds}")
@@ -712,8 +719,7 @@ def bench_gather(args):
     print(json.dumps({"metric": "Static pull launch vs library gather-sum routines on the same graph and order",
                       "value": round(gathers_per_s, 1), "unit": "in-edges/s (library pull)", "n_gpus": 1,
                       "steps": reps, "warmup": 1, "higher_is_better": True, "dtype": "f64", "data": "synthetic",
-                      "config": {"workload": f"R-MAT scale {args.scale}, edge factor {args.edge_factor:g}, "
-                                             f"in-CSR in decreasing in-degree order", "n": n, "m": m},
+                      "config": {"workload": f"{desc}, in-CSR in decreasing in-degree order", "n": n, "m": m},
                       "times_ms": out}))
 
 
@@ -767,6 +773,8 @@ def main():
     ap.add_argument("--serving-scale-offset", type=int, default=0,
                     help="serving: subtract this from every graph scale (smaller runs)")
     ap.add_argument("--graphs", type=int, default=512, help="batched: number of member graphs")
+    ap.add_argument("--gather-graph", default="rmat", choices=["rmat", "temporal"],
+                    help="gather: the R-MAT graph of --scale or the temporal workload's initial graph")
     ap.add_argument("--summarize", metavar="DIR",
                     help="print summaries of rocprofv3 output under DIR (prof/, pmc_FETCH_SIZE/, pmc_WRITE_SIZE/)")
     ap.add_argument("--kernel", default="dfpr::k_pull<3", help="kernel name prefix for --summarize counters")

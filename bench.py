@@ -124,6 +124,23 @@ def measured_traffic(workload_key):
         return None
 
 
+def device_copy_gbs(torch, dev, nbytes=1 << 30, reps=5):
+    """Bytes read + written per second by a device-to-device copy of 1 GiB."""
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9
+
+
 # ---------------------------------------------------------------- profile summaries
 def _csv_rows(path):
     import csv
@@ -944,6 +961,16 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
             "launches": nl, "avg_launch_ms": round(ms_k / nl, 5), "bytes_per_launch": int(bytes_k / nl),
             "source_sha": rank_source_sha()}
+    if dom == "k_pull" and ms_k > 0:
+        # beside the algorithmic rate: the counter-measured rate (bytes fetched
+        # into L2 from the memory side, Infinity Cache hits included) and the
+        # rate of compulsory bytes (each contribution read once per launch)
+        if traffic is not None:
+            roof["traffic_gbs"] = round(traffic / (ms_k / nl * 1e-3) / 1e9, 1)
+        compulsory = (pull_bytes - 8.0 * e_pull + 8.0 * min(float(n) * nl, float(e_pull))) / nl
+        roof["compulsory_bytes_per_launch"] = int(compulsory)
+        roof["compulsory_gbs"] = round(compulsory / (ms_k / nl * 1e-3) / 1e9, 1)
+    roof["copy_gbs"] = round(device_copy_gbs(torch, dev), 1)  # streaming ceiling of this device
 
     res = {
         "metric": METRIC,

@@ -1025,19 +1025,44 @@ __global__ void k_scatter_ranks(const double* R, const int32_t* __restrict__ inv
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     r_ext[inv[i]] = R[i];
 }
-__global__ void __launch_bounds__(256) k_count_clear_ever(uint8_t* ever, int32_t n, unsigned long long* acc) {
+// End of an update: clears up to four byte-flag arrays of n entries (null ones
+// skipped) and, when `ever` is given, counts its set entries (each 0 or 1)
+// into the ever accumulator and clears it, 16 bytes per thread (the arrays
+// are 256-byte aligned), in one pass.
+__global__ void __launch_bounds__(256) k_clear_flags(uint8_t* f0, uint8_t* f1, uint8_t* f2, uint8_t* f3, uint8_t* ever,
+                                                     int32_t n, unsigned long long* acc) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t n16 = n / 16;
+  const uint4 z = make_uint4(0u, 0u, 0u, 0u);
   int64_t c = 0;
-  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
-    if (ever[v]) {
-      c++;
+  for (int64_t i = t0; i < n16; i += stride) {
+    if (f0) reinterpret_cast<uint4*>(f0)[i] = z;
+    if (f1) reinterpret_cast<uint4*>(f1)[i] = z;
+    if (f2) reinterpret_cast<uint4*>(f2)[i] = z;
+    if (f3) reinterpret_cast<uint4*>(f3)[i] = z;
+    if (ever) {
+      const uint4 e = reinterpret_cast<const uint4*>(ever)[i];
+      c += __popcll(((unsigned long long)e.y << 32) | e.x) + __popcll(((unsigned long long)e.w << 32) | e.z);
+      reinterpret_cast<uint4*>(ever)[i] = z;
+    }
+  }
+  for (int64_t v = n16 * 16 + t0; v < n; v += stride) {
+    if (f0) f0[v] = 0;
+    if (f1) f1[v] = 0;
+    if (f2) f2[v] = 0;
+    if (f3) f3[v] = 0;
+    if (ever) {
+      c += ever[v];
       ever[v] = 0;
     }
   }
   c = wave_sum_i64(c);
-  if (lane_id() == 0 && c)
+  if (ever && lane_id() == 0 && c)
     atomicAdd(&acc[kAccEver * (kSlots * kSlotStride) + ((blockIdx.x * 4 + threadIdx.x / kWave) % kSlots) * kSlotStride],
               (unsigned long long)c);
 }
+
 // Batch: count (and clear) the processed vertices of each member.  A thread
 // walks 64 consecutive vertices (members are vertex ranges) and issues one
 // atomic per member run.
@@ -1450,8 +1475,8 @@ static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_pre
       k_scatter_ranks<<<gi, 256, 0, s>>>(Rf, g->inv, r_out, n);
     else if (Rf != r_out)
       DFPR_HIP(hipMemcpyAsync(r_out, Rf, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
-    for (uint8_t* f : {g->flag_cur, g->flag_next, g->xflag, g->xflag2}) k_fill_u8<<<gi, 256, 0, s>>>(f, n, 0);
-    k_count_clear_ever<<<gi, 256, 0, s>>>(g->ever, n, &g->ctl->acc_slots[0][0]);
+    k_clear_flags<<<grid_for(n / 16 + 1, 256, 65536), 256, 0, s>>>(g->flag_cur, g->flag_next, g->xflag, g->xflag2,
+                                                                   g->ever, n, &g->ctl->acc_slots[0][0]);
     DFPR_HIP(hipGetLastError());
     DFPR_TRY(finish_and_read(g, s));
     st->iterations = fr.iters;
@@ -1594,17 +1619,15 @@ static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_pre
     DFPR_HIP(hipMemcpyAsync(r_out, Ra, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
   // leave every flag array clear for the next batch (converged members of a
   // batch may leave flags in both keep arrays)
-  k_fill_u8<<<gi, 256, 0, s>>>(cur, n, 0);
-  if (g->ngraphs > 1 && !st->dense_iterations) k_fill_u8<<<gi, 256, 0, s>>>(next, n, 0);
-  if (st->dense_iterations) {
-    k_fill_u8<<<gi, 256, 0, s>>>(next, n, 0);
-    k_fill_u8<<<gi, 256, 0, s>>>(xa, n, 0);
-    k_fill_u8<<<gi, 256, 0, s>>>(xb, n, 0);
+  {
+    const bool dense_used = st->dense_iterations > 0;
+    uint8_t* nx = (g->ngraphs > 1 || dense_used) ? next : nullptr;
+    k_clear_flags<<<grid_for(n / 16 + 1, 256, 65536), 256, 0, s>>>(
+        cur, nx, dense_used ? xa : nullptr, dense_used ? xb : nullptr, g->ngraphs > 1 ? nullptr : g->ever, n,
+        &g->ctl->acc_slots[0][0]);
   }
   if (g->ngraphs > 1)
     k_count_ever_members<<<grid_for((n + 63) / 64, 256, 2048), 256, 0, s>>>(g->ever, n, g->gidv, g->g_ever);
-  else
-    k_count_clear_ever<<<gi, 256, 0, s>>>(g->ever, n, &g->ctl->acc_slots[0][0]);
   DFPR_HIP(hipGetLastError());
   DFPR_TRY(finish_and_read(g, s));
   g->flag_cur = cur;

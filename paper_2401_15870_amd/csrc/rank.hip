@@ -541,7 +541,8 @@ __device__ __forceinline__ bool grid_barrier(IterCtl* c, unsigned nb) {
 
 template <int MODE>
 __global__ void __launch_bounds__(256) k_fused_loop(PullArgs a0, const int32_t* __restrict__ wl, PullLayout L,
-                                                       IterCtl* c, int max_iters, double tol) {
+                                                       IterCtl* c, int max_iters, double tol, double* r_out,
+                                                       const int32_t* __restrict__ inv, int32_t n) {
   constexpr bool DENSE = MODE != kSync;
   PullArgs a = a0;
   a.gsub = 1;
@@ -585,6 +586,36 @@ __global__ void __launch_bounds__(256) k_fused_loop(PullArgs a0, const int32_t* 
       }
       break;
     }
+  }
+  // Epilogue, after the last barrier (nothing reads the ranks or flags any
+  // more): the ranks go out in the caller's order, and DF/DF-P clear the four
+  // flag arrays and count (and clear) the processed vertices, so the host
+  // reads the outcome back once.
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t cnt = 0;
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += stride) {
+    const double r = a.R[v];
+    if (inv)
+      r_out[inv[v]] = r;
+    else if (r_out != a.R)
+      r_out[v] = r;
+    if (DENSE) {
+      const_cast<uint8_t*>(a.stay_in)[v] = 0;
+      a.stay_out[v] = 0;
+      const_cast<uint8_t*>(a.x_in)[v] = 0;
+      a.x_out[v] = 0;
+      if (a.ever[v]) {
+        cnt++;
+        a.ever[v] = 0;
+      }
+    }
+  }
+  if (DENSE) {
+    cnt = wave_sum_i64(cnt);
+    if (lane_id() == 0 && cnt)
+      atomicAdd(&a.acc[kAccEver * (kSlots * kSlotStride) + ((blockIdx.x * 4 + threadIdx.x / kWave) % kSlots) *
+                                                             kSlotStride],
+                (unsigned long long)cnt);
   }
 }
 
@@ -1244,9 +1275,11 @@ struct FusedResult {
   double last = 0.0;
 };
 
+// r_out: the final ranks in the caller's order (through g->inv when the graph
+// is renumbered), written by the kernel's epilogue.
 template <int MODE>
 static int fused_run(dfpr_graph* g, const dfpr_params& p, PullArgs a, hipStream_t s, dfpr_stats* st,
-                     FusedResult* out) {
+                     FusedResult* out, double* r_out) {
   DFPR_TRY(ensure_all_bins(g, s));
   PullLayout L;
   make_layout(g->parts[0].bin_end, g->parts[0].bin_edges, &L);  // a plain graph: one part
@@ -1278,7 +1311,9 @@ static int fused_run(dfpr_graph* g, const dfpr_params& p, PullArgs a, hipStream_
   IterCtl* c = g->ctl;
   int mi = p.max_iters;
   double tol = p.tol;
-  void* args[] = {&a, &wl, &L, &c, &mi, &tol};
+  const int32_t* inv = g->perm ? g->inv : nullptr;
+  int32_t nv = g->n;
+  void* args[] = {&a, &wl, &L, &c, &mi, &tol, &r_out, &inv, &nv};
   // One single-launch loop at a time in the process: its grid barrier needs
   // all its workgroups resident, which two such kernels on concurrent streams
   // (say, the serving form's lanes) could not both have.  Held until the loop
@@ -1328,13 +1363,14 @@ static int run_sync(dfpr_graph* g, bool cold, const dfpr_params& p, const double
   int it = 0;
   double dR = 0.0;
   bool conv = false;
+  bool ranks_out = false;
   if (use_fused(g)) {
     a.R = Ra;
     a.Rw = Rb;
     a.contrib = ca;
     a.cw = cb;
     FusedResult fr;
-    DFPR_TRY(fused_run<kSync>(g, p, a, s, st, &fr));
+    DFPR_TRY(fused_run<kSync>(g, p, a, s, st, &fr, r_out));
     it = fr.iters;
     conv = fr.converged;
     dR = fr.last;
@@ -1342,6 +1378,7 @@ static int run_sync(dfpr_graph* g, bool cold, const dfpr_params& p, const double
     st->edges_pulled += (int64_t)it * g->m;
     st->pull_bytes += (double)it * (36.0 * n + 12.0 * (double)g->m);
     if (it & 1) std::swap(Ra, Rb);
+    ranks_out = true;  // the loop ran to the end (converged or the cap) and wrote r_out
   }
   for (; !conv && it < p.max_iters; it++) {
     a.contrib = ca;
@@ -1363,10 +1400,12 @@ static int run_sync(dfpr_graph* g, bool cold, const dfpr_params& p, const double
       break;
     }
   }
-  if (g->perm)
+  if (ranks_out) {
+  } else if (g->perm) {
     k_scatter_ranks<<<gi, 256, 0, s>>>(Ra, g->inv, r_out, n);
-  else if (Ra != r_out)
+  } else if (Ra != r_out) {
     DFPR_HIP(hipMemcpyAsync(r_out, Ra, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
   // ranks now come from a full solve: pending batch marks are void
   if (g->pending_any) {
     k_fill_u8<<<gi, 256, 0, s>>>(g->pend_src, n, 0);
@@ -1464,21 +1503,14 @@ static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_pre
     a.ever = g->ever;
     a.use_x = 0;
     FusedResult fr;
-    DFPR_TRY(fused_run<MODE>(g, p, a, s, st, &fr));
+    // the kernel's epilogue writes r_out, clears the flags and counts the
+    // processed vertices; fused_run read the outcome back
+    DFPR_TRY(fused_run<MODE>(g, p, a, s, st, &fr, r_out));
     const IterCtl* h = g->ctl_host;
     st->vertex_updates += h->dense_cnt;
     st->edges_pulled += h->dense_edges;
     st->pull_bytes += (double)fr.iters * (31.0 * n + 5.0 * (double)m) + 8.0 * (double)h->dense_edges;
     st->dense_iterations += fr.iters;
-    double* Rf = (fr.iters & 1) && !async ? Rb : Ra;
-    if (g->perm)
-      k_scatter_ranks<<<gi, 256, 0, s>>>(Rf, g->inv, r_out, n);
-    else if (Rf != r_out)
-      DFPR_HIP(hipMemcpyAsync(r_out, Rf, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
-    k_clear_flags<<<grid_for(n / 16 + 1, 256, 65536), 256, 0, s>>>(g->flag_cur, g->flag_next, g->xflag, g->xflag2,
-                                                                   g->ever, n, &g->ctl->acc_slots[0][0]);
-    DFPR_HIP(hipGetLastError());
-    DFPR_TRY(finish_and_read(g, s));
     st->iterations = fr.iters;
     st->converged = fr.converged ? 1 : 0;
     st->last_delta = fr.last;

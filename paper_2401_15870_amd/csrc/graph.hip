@@ -540,6 +540,32 @@ __global__ void __launch_bounds__(kCopyBlock) k_run_copy(const int32_t* __restri
   }
 }
 
+// Few effective entries: the new row offsets are the old ones plus the shift
+// S(r) = #ins - #del over the entries of the rows before r (e - 2*delpre[e]
+// for the first entry e of row r or later, as in the run copy).  Each
+// workgroup takes `rows` of the n+1 offsets (256 to 4096, so that large graphs
+// get a few thousand workgroups and small ones one offset per thread) and
+// finds the chunk's entries once; a row's search then covers only those.
+static int32_t run_offset_rows(int32_t n) {
+  int32_t rows = 256;
+  while (rows < 4096 && ((int64_t)n + 1) / rows > 4096) rows <<= 1;
+  return rows;
+}
+__global__ void __launch_bounds__(256) k_run_offsets(const int32_t* __restrict__ ooff, int32_t* __restrict__ noff,
+                                                     const uint64_t* eff, const int64_t* delpre, const int64_t* count,
+                                                     int b, int32_t n, int32_t rows) {
+  const int64_t T = *count;
+  for (int64_t r0 = blockIdx.x * (int64_t)rows; r0 <= n; r0 += (int64_t)gridDim.x * rows) {
+    const int64_t r1 = min(r0 + rows, (int64_t)n + 1);
+    const int64_t e0 = lower_bound_u64(eff, 0, T, (uint64_t)r0 << (b + 1));
+    const int64_t e1 = lower_bound_u64(eff, e0, T, (uint64_t)r1 << (b + 1));
+    for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
+      const int64_t e = lower_bound_u64(eff, e0, e1, (uint64_t)r << (b + 1));
+      noff[r] = (int32_t)((int64_t)ooff[r] + e - 2 * delpre[e]);
+    }
+  }
+}
+
 __global__ void k_run_inserts(const uint64_t* eff, const int64_t* delpre, const int64_t* opos, const int64_t* count,
                               int b, const int32_t* noff, int32_t n, int32_t* nidx, int64_t* err) {
   const uint64_t mask = (1ull << b) - 1;
@@ -1133,7 +1159,7 @@ static int rebuild_csr(dfpr_graph* g, const Csr& o, const Csr& nw, const uint8_t
   int32_t chunk = 1024;
   while (chunk < 16384 && (int64_t)chunk * 2048 < g->m) chunk <<= 1;
   const int64_t m_bound = g->m + ni;  // the new edge count is at most this
-  if (nk * 256 <= g->m) {
+  if (nk * 256 <= g->m) {  // the same test as the offsets in graph_apply
     k_eff_opos<<<grid_for(nk, 256, 4096), 256, 0, s>>>(eff, cnt, g->id_bits, o.off, o.idx, opos);
     k_run_copy<<<grid_for(m_bound, chunk, 1u << 16), kCopyBlock, 0, s>>>(o.idx, nw.idx, eff, delpre, opos, cnt,
                                                                        nw.off, n, g->m, chunk, err);
@@ -1247,8 +1273,15 @@ int graph_apply(dfpr_graph* g, int64_t nd, const int32_t* del_src, const int32_t
   }
   DFPR_TRY(scan_generic(LoadIsDel{eff_out, cnt}, StoreI64b{pre_out}, nk, tmp, s));
 
-  // ---- out-CSR
-  DFPR_TRY(scan_row_offsets(g->out.off, g->delta_out, g->out2.off, n, g->scan_tmp, s));
+  // ---- out-CSR (few effective entries: offsets shifted run by run, as the
+  // index arrays are copied; otherwise a scan of the row-length deltas)
+  const bool few = nk * 256 <= g->m;
+  const int32_t off_rows = run_offset_rows(n);
+  if (few)
+    k_run_offsets<<<grid_for((int64_t)n + 1, off_rows, 65536), 256, 0, s>>>(g->out.off, g->out2.off, eff_out, pre_out,
+                                                                           cnt, b, n, off_rows);
+  else
+    DFPR_TRY(scan_row_offsets(g->out.off, g->delta_out, g->out2.off, n, g->scan_tmp, s));
   DFPR_TRY(ep.start(&tok));
   DFPR_TRY(rebuild_csr(g, g->out, g->out2, g->touched_out, eff_out, pre_out, opos, cnt, nk, ni, counters + 4, s));
   DFPR_TRY(ep.stop(kTRebuildOut, tok));
@@ -1261,7 +1294,11 @@ int graph_apply(dfpr_graph* g, int64_t nd, const int32_t* del_src, const int32_t
   DFPR_TRY(radix_sort(&eff_in, &alt, nk, 2 * b + 1, hist, tmp, s));
   DFPR_TRY(ep.stop(kTSort, tok));
   DFPR_TRY(scan_generic(LoadIsDel{eff_in, cnt}, StoreI64b{pre_in}, nk, tmp, s));
-  DFPR_TRY(scan_row_offsets(g->in.off, g->delta_in, g->in2.off, n, g->scan_tmp, s));
+  if (few)
+    k_run_offsets<<<grid_for((int64_t)n + 1, off_rows, 65536), 256, 0, s>>>(g->in.off, g->in2.off, eff_in, pre_in, cnt,
+                                                                           b, n, off_rows);
+  else
+    DFPR_TRY(scan_row_offsets(g->in.off, g->delta_in, g->in2.off, n, g->scan_tmp, s));
   DFPR_TRY(ep.start(&tok));
   DFPR_TRY(rebuild_csr(g, g->in, g->in2, g->touched_in, eff_in, pre_in, opos, cnt, nk, ni, counters + 4, s));
   DFPR_TRY(ep.stop(kTRebuildIn, tok));

@@ -251,18 +251,22 @@ __global__ void k_make_batch_keys(const int32_t* del_src, const int32_t* del_dst
 // pair was inserted; the pair was deleted iff (pair << 1) is present.
 //   effective insertion: inserted and not in E^{t-1}
 //   effective deletion:  deleted, in E^{t-1}, and not inserted (insert wins)
-// Effective pairs set row deltas, touched rows and the pending marks.
+// Effective pairs set row deltas, touched rows and the pending marks.  When
+// the batch failed validation (bit 0 of *bad) nothing is effective and nothing
+// is marked, so the graph's state is untouched and the host reports the error
+// after the (then trivial) rebuild.
 __global__ void k_classify(const uint64_t* keys, int64_t nk, int b, const int32_t* ooff, const int32_t* oidx,
                            uint8_t* keep, int32_t* delta_out, int32_t* delta_in, uint8_t* touched_out,
                            uint8_t* touched_in, uint8_t* pend_src, uint8_t* pend_tgt, int64_t* counters,
-                           const int32_t* gidv, int64_t* g_self) {
+                           const int32_t* gidv, int64_t* g_self, const int64_t* bad) {
   const uint64_t mask = (1ull << b) - 1;
+  const bool invalid = (*bad & 1) != 0;
   int64_t n_ins = 0, n_del = 0, n_self = 0;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nk; i += (int64_t)gridDim.x * blockDim.x) {
     const uint64_t k = keys[i];
     uint8_t kp = 0;
     const uint64_t pair = k >> 1;
-    const bool owner = (k != kBadKey) && (i + 1 == nk || (keys[i + 1] >> 1) != pair);
+    const bool owner = !invalid && (k != kBadKey) && (i + 1 == nk || (keys[i + 1] >> 1) != pair);
     if (owner) {
       const bool has_ins = k & 1ull;
       const int64_t q = lower_bound_u64(keys, 0, i + 1, pair << 1);
@@ -1241,17 +1245,14 @@ int graph_apply(dfpr_graph* g, int64_t nd, const int32_t* del_src, const int32_t
   ep.reset(g->timing, s);
   size_t t_total, tok;
   DFPR_TRY(ep.start(&t_total));
-  // ---- keys + validation (validation before mutation: one sync)
+  // ---- keys + validation.  An id out of range sets bit 0 of counters[4];
+  // the classification then marks nothing, the rebuild targets are not
+  // swapped in, and the error is reported after the one sync at the end, so
+  // a rejected batch leaves the graph and its pending marks as they were.
   DFPR_HIP(hipMemsetAsync(counters, 0, 6 * sizeof(int64_t), s));
   k_make_batch_keys<<<grid_for(nk, 256, 65536), 256, 0, s>>>(ds, dd, nd, is, id, ni, n, b, g->perm, ka,
                                                               counters + 4);
   DFPR_HIP(hipGetLastError());
-  DFPR_HIP(hipMemcpyAsync(g->ctl_host->n_apply, counters, 6 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  DFPR_HIP(hipStreamSynchronize(s));
-  if (g->ctl_host->n_apply[4]) {
-    set_error("vertex id outside [0, %d) in batch", n);
-    return DFPR_ERANGE;
-  }
 
   // ---- sort by (u, v, tag) and classify against the old out-CSR
   DFPR_TRY(ep.start(&tok));
@@ -1261,7 +1262,7 @@ int graph_apply(dfpr_graph* g, int64_t nd, const int32_t* del_src, const int32_t
   if (g_self) DFPR_HIP(hipMemsetAsync(g_self, 0, (size_t)g->ngraphs * sizeof(int64_t), s));
   k_classify<<<grid_for(nk, 256, 65536), 256, 0, s>>>(ka, nk, b, g->out.off, g->out.idx, keep, g->delta_out,
                                                        g->delta_in, g->touched_out, g->touched_in, g->pend_src,
-                                                       g->flag_cur, counters, g->gidv, g_self);
+                                                       g->flag_cur, counters, g->gidv, g_self, counters + 4);
   DFPR_HIP(hipGetLastError());
   // effective entries, sorted by (u, v): count lands in counters[3]
   DFPR_TRY(compact_keys(ka, keep, kb, nk, counters + 3, pre_out, tmp, s));
@@ -1311,6 +1312,10 @@ int graph_apply(dfpr_graph* g, int64_t nd, const int32_t* del_src, const int32_t
   DFPR_HIP(hipStreamSynchronize(s));
 
   const int64_t* h = g->ctl_host->n_apply;
+  if (h[4] & 1) {
+    set_error("vertex id outside [0, %d) in batch", n);
+    return DFPR_ERANGE;
+  }
   if (h[4] != 0 || h[5] != g->m + h[0] - h[1]) {
     set_error("internal inconsistency in the CSR rebuild (flag %lld, m %lld -> %lld)", (long long)h[4],
               (long long)g->m, (long long)h[5]);

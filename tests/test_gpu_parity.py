@@ -195,6 +195,35 @@ def test_dense_and_frontier_forms_agree(mode, frac):
     assert np.array_equal(outs[0.0][0], outs[2.0][0]) and np.array_equal(outs[0.4][0], outs[2.0][0])
 
 
+@pytest.mark.parametrize("mode", ["df", "dfp"])
+def test_hub_frontier_stays_in_frontier_form(mode):
+    """A preferential-attachment graph whose batch reaches a few hubs (many
+    in-edges, few out-edges): the default keeps such a frontier in the frontier
+    form although its in-edges pass the dense share; forcing the dense form
+    gives the same bits and statistics, and both match the oracle."""
+    torch_cuda()
+    n = 20000
+    src, dst = W.temporal_stream(n, 400000, seed=93)
+    k0 = 360000
+    s0, d0 = W.dedupe(n, src[:k0], dst[:k0])
+    outs = {}
+    for sw in (0.4, 0.0):
+        p = Pair(n, s0, d0)
+        r0 = O.rank("static", p.og).ranks
+        p.apply([], [], src[k0:k0 + 400], dst[k0:k0 + 400])
+        r, st, ref = p.rank(mode, r0, dense_switch=sw)
+        assert np.abs(r - ref.ranks).max() <= LINF
+        assert st["ever_affected"] == ref.ever_affected
+        outs[sw] = (r, st)
+    _print(f"hub frontier {mode}: dense iterations {outs[0.4][1]['dense_iterations']} of "
+           f"{outs[0.4][1]['iterations']} (default), edges pulled {outs[0.4][1]['edges_pulled']}")
+    assert outs[0.4][1]["dense_iterations"] < outs[0.4][1]["iterations"]
+    assert outs[0.0][1]["dense_iterations"] == outs[0.0][1]["iterations"]
+    for key in ("iterations", "ever_affected", "vertex_updates", "edges_pulled"):
+        assert outs[0.4][1][key] == outs[0.0][1][key], key
+    assert np.array_equal(outs[0.4][0], outs[0.0][0])
+
+
 @pytest.mark.parametrize("mode", ["static", "nd", "df", "dfp"])
 def test_ranks_bitexact_lane_bin(mode):
     """With every vertex in the one-lane bin the sums run in the oracle's order:

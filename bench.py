@@ -801,8 +801,8 @@ def main():
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design note, "
-                                   "not an implementation", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "the library runs on one GPU only: sharding over several GPUs is "
+                                   "described in the design notes, not implemented", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import torch

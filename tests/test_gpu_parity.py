@@ -121,6 +121,28 @@ def test_apply_run_and_group_paths(extra):
     assert_csr_equal(p.g, p.og)
 
 
+def test_apply_runs_in_one_row():
+    """Run-by-run copy with all the cuts in one row: a small batch (below one
+    raw entry per 256 edges) that inserts 300 new out-neighbours of vertex 7
+    and deletes 100 of its existing ones, so consecutive runs are empty or one
+    element long."""
+    torch_cuda()
+    n, s, d = rmat(15, seed=81)
+    p = Pair(n, s, d, keep_ids=True)
+    og = p.og
+    rng = np.random.default_rng(82)
+    row = og.out_idx[og.out_off[7]:og.out_off[8]]
+    row = row[row != 7]
+    dels = rng.choice(row, min(100, len(row)), replace=False).astype(np.int32)
+    cand = np.setdiff1d(np.arange(n, dtype=np.int32), np.concatenate([row, [7]]))
+    ins = rng.choice(cand, 300, replace=False).astype(np.int32)
+    assert len(dels) + len(ins) <= og.m // 256
+    _print("runs in one row", len(dels), len(ins), og.m)
+    info = p.apply(np.full(len(dels), 7, np.int32), dels, np.full(300, 7, np.int32), ins)
+    assert info["ins_effective"] == 300 and info["del_effective"] == len(dels)
+    assert_csr_equal(p.g, p.og)
+
+
 @pytest.mark.parametrize("k", [63, 64, 65])
 def test_apply_group_entries_at_lane_count(k):
     """Merge of touched groups: rows 0..63 (one group; caller ids kept inside)

@@ -176,13 +176,14 @@ struct IterCtl {
   int64_t dense_sedges;      // dense pull: summed in-degree of its kept vertices
   int64_t active;            // member graphs not yet converged (1/0 for a plain graph)
   int64_t bin_out_edges;     // summed out-degree of the vertices of the last binning pass
+  // single-launch loop outcome: iterations, converged, last L-inf change (bits)
+  int64_t fused_iters, fused_converged;
+  unsigned long long fused_last;
+  int64_t fused_err;  // grid barrier gave up waiting (never expected)
   int64_t pad[1];
   unsigned long long acc_slots[kAccRows][kSlots * kSlotStride];
   // single-launch loop: L-inf change of iteration i in fused_dr[(i % 3) * kSlotStride]
   unsigned long long fused_dr[3 * kSlotStride];
-  int64_t fused_iters, fused_converged;
-  unsigned long long fused_last;
-  int64_t fused_err;  // grid barrier gave up waiting (never expected)
   // grid barrier of the single-launch loop: 32 group counters, a root counter
   // and a generation, each on its own 128-byte line
   unsigned bar_leaf[32 * 32];

@@ -285,11 +285,13 @@ __global__ void k_classify(const uint64_t* keys, int64_t nk, int b, const int32_
         const bool eff_ins = has_ins && !exists;
         const bool eff_del = has_del && exists && !has_ins;
         if (eff_ins || eff_del) {
-          const int32_t d = eff_ins ? 1 : -1;
-          atomicAdd(&delta_out[u], d);
-          atomicAdd(&delta_in[v], d);
-          touched_out[u] = 1;
-          touched_in[v] = 1;
+          if (delta_out) {  // row deltas and touched rows: read by the rebuild for many entries only
+            const int32_t d = eff_ins ? 1 : -1;
+            atomicAdd(&delta_out[u], d);
+            atomicAdd(&delta_in[v], d);
+            touched_out[u] = 1;
+            touched_in[v] = 1;
+          }
           pend_src[u] = 1;
           if (eff_del) pend_tgt[v] = 1;
           kp = 1;
@@ -477,19 +479,8 @@ __global__ void __launch_bounds__(kCopyBlock) k_shift_copy(const int32_t* __rest
 // entry e the old elements have moved by S_e = #ins(<e) - #del(<e) =
 // e - 2 * delpre[e]; entry e cuts the new array at dcut(e) = opos[e] + S_e
 // (where an insertion lands), and the run after it starts at dcut(e) + ins(e)
-// with shift S_{e+1}.
-__global__ void k_eff_opos(const uint64_t* eff, const int64_t* count, int b, const int32_t* __restrict__ ooff,
-                           const int32_t* __restrict__ oidx, int64_t* opos) {
-  const uint64_t mask = (1ull << b) - 1;
-  const int64_t T = *count;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < T; e += (int64_t)gridDim.x * blockDim.x) {
-    const uint64_t k = eff[e];
-    const int32_t r = (int32_t)(k >> (b + 1));
-    const int32_t x = (int32_t)((k >> 1) & mask);
-    opos[e] = lower_bound_i32(oidx, ooff[r], ooff[r + 1], x);
-  }
-}
-
+// with shift S_{e+1}.  opos comes from a binary search of the entry's column
+// in its old row (k_run_offsets).
 __device__ __forceinline__ int64_t run_cut(const int64_t* opos, const int64_t* delpre, int64_t e) {
   return opos[e] + e - 2 * delpre[e];
 }
@@ -498,15 +489,24 @@ __device__ __forceinline__ int64_t run_begin(const uint64_t* eff, const int64_t*
   return e < 0 ? 0 : run_cut(opos, delpre, e) + (int64_t)(eff[e] & 1ull);
 }
 
-// Each workgroup fills `chunk` entries of the new index array from the runs
-// that cover them (insertions are written by k_run_inserts).
+// Each workgroup fills `chunk` entries of the new index array: the runs that
+// cover them and the insertions that land between the runs.  The runs and
+// the insertion slots tile the new array in entry order; the workgroup that
+// takes position 0 checks that the tiling ends inside the new array.
+// m_new (optional) receives the new edge count of `m_off`.
 __global__ void __launch_bounds__(kCopyBlock) k_run_copy(const int32_t* __restrict__ oidx,
                                                          int32_t* __restrict__ nidx, const uint64_t* eff,
                                                          const int64_t* delpre, const int64_t* opos,
-                                                         const int64_t* count, const int32_t* noff, int32_t n,
-                                                         int64_t m_old, int32_t chunk, int64_t* err) {
+                                                         const int64_t* count, int b, const int32_t* noff, int32_t n,
+                                                         int64_t m_old, int32_t chunk, int64_t* err,
+                                                         const int32_t* m_off, int64_t* m_new) {
+  const uint64_t mask = (1ull << b) - 1;
   const int64_t mnew = noff[n];
   const int64_t T = *count;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (m_new) *m_new = m_off[n];
+    if (T > 0 && run_begin(eff, opos, delpre, T - 1) > mnew) atomicOr((unsigned long long*)err, 2ull);
+  }
   for (int64_t q0 = (int64_t)blockIdx.x * chunk; q0 < mnew; q0 += (int64_t)gridDim.x * chunk) {
     const int64_t q1 = min(q0 + (int64_t)chunk, mnew);
     // the run holding q0: the last e in [-1, T) whose run begins at or before q0
@@ -538,6 +538,9 @@ __global__ void __launch_bounds__(kCopyBlock) k_run_copy(const int32_t* __restri
         for (; p < z; p += kCopyBlock) nidx[p] = __builtin_nontemporal_load(oidx + (p - shift));
       }
       if (e + 1 >= T) break;
+      // entry e+1 cuts at `end`; an insertion lands there
+      const uint64_t k = eff[e + 1];
+      if ((k & 1ull) && end >= q0 && end < q1 && threadIdx.x == 0) nidx[end] = (int32_t)((k >> 1) & mask);
       q = max(z, run_begin(eff, opos, delpre, e + 1));
       e++;
     }
@@ -555,11 +558,25 @@ static int32_t run_offset_rows(int32_t n) {
   while (rows < 4096 && ((int64_t)n + 1) / rows > 4096) rows <<= 1;
   return rows;
 }
+// The same launch computes the entries' old positions opos: workgroups
+// [0, off_blocks) take the offsets, the others the entries.
 __global__ void __launch_bounds__(256) k_run_offsets(const int32_t* __restrict__ ooff, int32_t* __restrict__ noff,
+                                                     const int32_t* __restrict__ oidx, int64_t* opos,
                                                      const uint64_t* eff, const int64_t* delpre, const int64_t* count,
-                                                     int b, int32_t n, int32_t rows) {
+                                                     int b, int32_t n, int32_t rows, int32_t off_blocks) {
   const int64_t T = *count;
-  for (int64_t r0 = blockIdx.x * (int64_t)rows; r0 <= n; r0 += (int64_t)gridDim.x * rows) {
+  if ((int)blockIdx.x >= off_blocks) {
+    const uint64_t mask = (1ull << b) - 1;
+    const int64_t stride = (int64_t)(gridDim.x - off_blocks) * blockDim.x;
+    for (int64_t e = (blockIdx.x - off_blocks) * (int64_t)blockDim.x + threadIdx.x; e < T; e += stride) {
+      const uint64_t k = eff[e];
+      const int32_t r = (int32_t)(k >> (b + 1));
+      const int32_t x = (int32_t)((k >> 1) & mask);
+      opos[e] = lower_bound_i32(oidx, ooff[r], ooff[r + 1], x);
+    }
+    return;
+  }
+  for (int64_t r0 = blockIdx.x * (int64_t)rows; r0 <= n; r0 += (int64_t)off_blocks * rows) {
     const int64_t r1 = min(r0 + rows, (int64_t)n + 1);
     const int64_t e0 = lower_bound_u64(eff, 0, T, (uint64_t)r0 << (b + 1));
     const int64_t e1 = lower_bound_u64(eff, e0, T, (uint64_t)r1 << (b + 1));
@@ -567,23 +584,6 @@ __global__ void __launch_bounds__(256) k_run_offsets(const int32_t* __restrict__
       const int64_t e = lower_bound_u64(eff, e0, e1, (uint64_t)r << (b + 1));
       noff[r] = (int32_t)((int64_t)ooff[r] + e - 2 * delpre[e]);
     }
-  }
-}
-
-__global__ void k_run_inserts(const uint64_t* eff, const int64_t* delpre, const int64_t* opos, const int64_t* count,
-                              int b, const int32_t* noff, int32_t n, int32_t* nidx, int64_t* err) {
-  const uint64_t mask = (1ull << b) - 1;
-  const int64_t T = *count;
-  const int64_t mnew = noff[n];
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < T; e += (int64_t)gridDim.x * blockDim.x) {
-    const uint64_t k = eff[e];
-    if (!(k & 1ull)) continue;
-    const int64_t d = run_cut(opos, delpre, e);
-    if (d < 0 || d >= mnew) {
-      atomicOr((unsigned long long*)err, 2ull);
-      continue;
-    }
-    nidx[d] = (int32_t)((k >> 1) & mask);
   }
 }
 
@@ -1155,20 +1155,20 @@ static int grow_capacity(dfpr_graph* g, int64_t want, hipStream_t s) {
 // the entries.  Otherwise: runs of untouched groups, pieces of the touched
 // groups, then the insertions.  Copy chunks and pieces get smaller on small
 // graphs so that the work still spreads over many wavefronts.
+// Few entries: opos was filled by k_run_offsets; m_new (optional) receives
+// the new edge count of `m_off` (run path only).
 static int rebuild_csr(dfpr_graph* g, const Csr& o, const Csr& nw, const uint8_t* touched, const uint64_t* eff,
                        const int64_t* delpre, int64_t* opos, const int64_t* cnt, int64_t nk, int64_t ni,
-                       int64_t* err, hipStream_t s) {
+                       int64_t* err, const int32_t* m_off, int64_t* m_new, hipStream_t s) {
   const int32_t n = g->n;
   const int64_t groups = ((int64_t)n + kWave - 1) / kWave;
   int32_t chunk = 1024;
   while (chunk < 16384 && (int64_t)chunk * 2048 < g->m) chunk <<= 1;
   const int64_t m_bound = g->m + ni;  // the new edge count is at most this
   if (nk * 256 <= g->m) {  // the same test as the offsets in graph_apply
-    k_eff_opos<<<grid_for(nk, 256, 4096), 256, 0, s>>>(eff, cnt, g->id_bits, o.off, o.idx, opos);
     k_run_copy<<<grid_for(m_bound, chunk, 1u << 16), kCopyBlock, 0, s>>>(o.idx, nw.idx, eff, delpre, opos, cnt,
-                                                                       nw.off, n, g->m, chunk, err);
-    k_run_inserts<<<grid_for(nk, 256, 4096), 256, 0, s>>>(eff, delpre, opos, cnt, g->id_bits, nw.off, n, nw.idx,
-                                                          err);
+                                                                       g->id_bits, nw.off, n, g->m, chunk, err,
+                                                                       m_off, m_new);
     DFPR_HIP(hipGetLastError());
     return DFPR_OK;
   }
@@ -1260,9 +1260,13 @@ int graph_apply(dfpr_graph* g, int64_t nd, const int32_t* del_src, const int32_t
   DFPR_TRY(ep.stop(kTSort, tok));
   int64_t* g_self = g->ngraphs > 1 ? g->g_eff + 3 * (size_t)g->ngraphs : nullptr;
   if (g_self) DFPR_HIP(hipMemsetAsync(g_self, 0, (size_t)g->ngraphs * sizeof(int64_t), s));
-  k_classify<<<grid_for(nk, 256, 65536), 256, 0, s>>>(ka, nk, b, g->out.off, g->out.idx, keep, g->delta_out,
-                                                       g->delta_in, g->touched_out, g->touched_in, g->pend_src,
-                                                       g->flag_cur, counters, g->gidv, g_self, counters + 4);
+  // few effective entries (at most one per 256 edges): the rebuild copies run
+  // by run and needs no per-row deltas or touched flags
+  const bool few = nk * 256 <= g->m;
+  k_classify<<<grid_for(nk, 256, 65536), 256, 0, s>>>(
+      ka, nk, b, g->out.off, g->out.idx, keep, few ? nullptr : g->delta_out, few ? nullptr : g->delta_in,
+      few ? nullptr : g->touched_out, few ? nullptr : g->touched_in, g->pend_src, g->flag_cur, counters, g->gidv,
+      g_self, counters + 4);
   DFPR_HIP(hipGetLastError());
   // effective entries, sorted by (u, v): count lands in counters[3]
   DFPR_TRY(compact_keys(ka, keep, kb, nk, counters + 3, pre_out, tmp, s));
@@ -1276,15 +1280,17 @@ int graph_apply(dfpr_graph* g, int64_t nd, const int32_t* del_src, const int32_t
 
   // ---- out-CSR (few effective entries: offsets shifted run by run, as the
   // index arrays are copied; otherwise a scan of the row-length deltas)
-  const bool few = nk * 256 <= g->m;
   const int32_t off_rows = run_offset_rows(n);
+  const unsigned off_blocks = grid_for((int64_t)n + 1, off_rows, 65536);
+  const unsigned pos_blocks = grid_for(nk, 256, 4096);
   if (few)
-    k_run_offsets<<<grid_for((int64_t)n + 1, off_rows, 65536), 256, 0, s>>>(g->out.off, g->out2.off, eff_out, pre_out,
-                                                                           cnt, b, n, off_rows);
+    k_run_offsets<<<off_blocks + pos_blocks, 256, 0, s>>>(g->out.off, g->out2.off, g->out.idx, opos, eff_out, pre_out,
+                                                          cnt, b, n, off_rows, (int32_t)off_blocks);
   else
     DFPR_TRY(scan_row_offsets(g->out.off, g->delta_out, g->out2.off, n, g->scan_tmp, s));
   DFPR_TRY(ep.start(&tok));
-  DFPR_TRY(rebuild_csr(g, g->out, g->out2, g->touched_out, eff_out, pre_out, opos, cnt, nk, ni, counters + 4, s));
+  DFPR_TRY(rebuild_csr(g, g->out, g->out2, g->touched_out, eff_out, pre_out, opos, cnt, nk, ni, counters + 4,
+                       nullptr, nullptr, s));
   DFPR_TRY(ep.stop(kTRebuildOut, tok));
 
   // ---- in-CSR: the same entries ordered by (v, u)
@@ -1296,16 +1302,20 @@ int graph_apply(dfpr_graph* g, int64_t nd, const int32_t* del_src, const int32_t
   DFPR_TRY(ep.stop(kTSort, tok));
   DFPR_TRY(scan_generic(LoadIsDel{eff_in, cnt}, StoreI64b{pre_in}, nk, tmp, s));
   if (few)
-    k_run_offsets<<<grid_for((int64_t)n + 1, off_rows, 65536), 256, 0, s>>>(g->in.off, g->in2.off, eff_in, pre_in, cnt,
-                                                                           b, n, off_rows);
+    k_run_offsets<<<off_blocks + pos_blocks, 256, 0, s>>>(g->in.off, g->in2.off, g->in.idx, opos, eff_in, pre_in, cnt,
+                                                          b, n, off_rows, (int32_t)off_blocks);
   else
     DFPR_TRY(scan_row_offsets(g->in.off, g->delta_in, g->in2.off, n, g->scan_tmp, s));
   DFPR_TRY(ep.start(&tok));
-  DFPR_TRY(rebuild_csr(g, g->in, g->in2, g->touched_in, eff_in, pre_in, opos, cnt, nk, ni, counters + 4, s));
+  // (few entries: the in-side copy also records the new edge count)
+  DFPR_TRY(rebuild_csr(g, g->in, g->in2, g->touched_in, eff_in, pre_in, opos, cnt, nk, ni, counters + 4,
+                       g->out2.off, counters + 5, s));
   DFPR_TRY(ep.stop(kTRebuildIn, tok));
-  k_clear_rows<<<grid_for(nk, 256, 65536), 256, 0, s>>>(eff_out, cnt, b, g->delta_out, g->delta_in, g->touched_out,
-                                                        g->touched_in);
-  k_finish_apply<<<1, 1, 0, s>>>(g->out2.off, n, counters);
+  if (!few) {
+    k_clear_rows<<<grid_for(nk, 256, 65536), 256, 0, s>>>(eff_out, cnt, b, g->delta_out, g->delta_in,
+                                                          g->touched_out, g->touched_in);
+    k_finish_apply<<<1, 1, 0, s>>>(g->out2.off, n, counters);
+  }
   DFPR_HIP(hipGetLastError());
   DFPR_HIP(hipMemcpyAsync(g->ctl_host->n_apply, counters, 6 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
   DFPR_TRY(ep.stop(kTTotal, t_total));

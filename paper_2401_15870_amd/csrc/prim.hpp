@@ -91,12 +91,45 @@ __global__ void __launch_bounds__(kScanBlock) k_scan_apply(Load ld, Store st, in
 template <class Store>
 __global__ void k_scan_empty(Store st) { st(0, 0); }
 
+// The whole scan in one workgroup when the input fits one tile (small
+// batches, short bin tables): one launch instead of three.
+template <class Load, class Store>
+__global__ void __launch_bounds__(kScanBlock) k_scan_one_tile(Load ld, Store st, int64_t n) {
+  __shared__ int64_t tile[kScanTile];
+  __shared__ int64_t sh[kScanBlock / kWave + 1];
+#pragma unroll
+  for (int j = 0; j < kScanItems; j++) {
+    const int64_t i = j * kScanBlock + threadIdx.x;
+    tile[i] = (i < n) ? ld(i) : 0;
+  }
+  __syncthreads();
+  int64_t v[kScanItems];
+  int64_t run = 0;
+#pragma unroll
+  for (int j = 0; j < kScanItems; j++) {
+    v[j] = run;
+    run += tile[threadIdx.x * kScanItems + j];
+  }
+  int64_t tot;
+  const int64_t pre = block_exclusive_scan(run, sh, &tot);
+#pragma unroll
+  for (int j = 0; j < kScanItems; j++) {
+    const int64_t i = threadIdx.x * kScanItems + j;
+    if (i < n) st(i, pre + v[j]);
+  }
+  if (threadIdx.x == 0) st(n, tot);
+}
+
 // Exclusive scan of ld(0..n) into st(0..n) (st(n, total) included).
 template <class Load, class Store>
 int scan_generic(Load ld, Store st, int64_t n, int64_t* tmp, hipStream_t s) {
   const int64_t nb = (n + kScanTile - 1) / kScanTile;
   if (nb == 0) {  // empty input: only the total, 0
     k_scan_empty<<<1, 1, 0, s>>>(st);
+    return hipGetLastError() == hipSuccess ? DFPR_OK : DFPR_EHIP;
+  }
+  if (nb == 1) {
+    k_scan_one_tile<<<1, kScanBlock, 0, s>>>(ld, st, n);
     return hipGetLastError() == hipSuccess ? DFPR_OK : DFPR_EHIP;
   }
   k_scan_reduce<<<(unsigned)nb, kScanBlock, 0, s>>>(ld, n, tmp);

@@ -1334,10 +1334,7 @@ static int fused_run(dfpr_graph* g, const dfpr_params& p, PullArgs a, hipStream_
   // fold the dense counters and read the loop's outcome
   k_iter_finish<<<1, kSlots, 0, s>>>(g->ctl);
   DFPR_HIP(hipGetLastError());
-  const size_t lo = offsetof(IterCtl, fused_iters), hi = offsetof(IterCtl, fused_err) + sizeof(int64_t);
-  DFPR_HIP(hipMemcpyAsync(reinterpret_cast<char*>(g->ctl_host) + lo, reinterpret_cast<char*>(g->ctl) + lo, hi - lo,
-                          hipMemcpyDeviceToHost, s));
-  DFPR_HIP(hipMemcpyAsync(g->ctl_host, g->ctl, kCtlHead, hipMemcpyDeviceToHost, s));
+  DFPR_HIP(hipMemcpyAsync(g->ctl_host, g->ctl, kCtlHead, hipMemcpyDeviceToHost, s));  // outcome in the head
   DFPR_HIP(hipStreamSynchronize(s));
   if (g->ctl_host->fused_err) {
     set_error("single-launch rank loop: grid barrier timed out");

@@ -655,7 +655,7 @@ __device__ __forceinline__ void pull_virtual_block(const PullArgs& a, const int3
 // row [os, oe) marked contributes its length to a wave prefix sum, then the
 // 64 lanes sweep the concatenated rows four edges at a time, locating each
 // edge's row by a binary search over the lanes' start offsets (cross-lane
-// reads).  Rows longer than kBigRow go to big_list for the chunked pass.
+// reads).  Rows longer than big_row go to big_list for the chunked pass.
 // Must be called with all 64 lanes active.
 __device__ __forceinline__ int seg_of(int32_t st, int32_t e) {
   int lo = 0, hi = kWave;
@@ -670,10 +670,10 @@ __device__ __forceinline__ int seg_of(int32_t st, int32_t e) {
 
 __device__ __forceinline__ void wave_mark_rows(bool want, int32_t v, int32_t os, int32_t oe,
                                                const int32_t* __restrict__ out_idx, uint8_t* flags,
-                                               int32_t* big_list, int64_t* big_count) {
+                                               int32_t* big_list, int64_t* big_count, int32_t big_row) {
   const int lane = lane_id();
   int32_t len = want ? oe - os : 0;
-  if (len > kBigRow) {
+  if (len > big_row) {
     const int64_t pos = (int64_t)atomicAdd((unsigned long long*)big_count, 1ull);
     big_list[pos] = v;
     len = 0;
@@ -704,10 +704,14 @@ __device__ __forceinline__ void wave_mark_rows(bool want, int32_t v, int32_t os,
 
 // Initial marking (Algorithm 1): for every pending source u mark out(u) in
 // G^t; the targets of effective deletions (the rest of out(u) in G^{t-1})
-// were set in `flags` when the batch was applied.
+// were set in `flags` when the batch was applied.  The batch's sources
+// include the high-degree vertices, which sit together in the first
+// wavefronts: rows over kPendBigRow go to the chunked pass, so no wavefront
+// sweeps more than a few hundred edges.
+constexpr int32_t kPendBigRow = 128;
 __global__ void __launch_bounds__(256) k_mark_pending(uint8_t* pend_src, int32_t n, const int32_t* __restrict__ out_off,
                                                       const int32_t* __restrict__ out_idx, uint8_t* flags,
-                                                      int32_t* big_list, int64_t* big_count) {
+                                                      int32_t* big_list, int64_t* big_count, int32_t big_row) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t base = blockIdx.x * (int64_t)blockDim.x + (threadIdx.x & ~(kWave - 1)); base < n; base += stride) {
     const int64_t u = base + lane_id();
@@ -719,7 +723,7 @@ __global__ void __launch_bounds__(256) k_mark_pending(uint8_t* pend_src, int32_t
       os = out_off[u];
       oe = out_off[u + 1];
     }
-    wave_mark_rows(want, (int32_t)u, os, oe, out_idx, flags, big_list, big_count);
+    wave_mark_rows(want, (int32_t)u, os, oe, out_idx, flags, big_list, big_count, big_row);
   }
 }
 
@@ -746,7 +750,7 @@ __global__ void __launch_bounds__(256) k_commit_expand(const int32_t* __restrict
         want = true;
       }
     }
-    wave_mark_rows(want, v, os, oe, out_idx, next, big_list, big_count);
+    wave_mark_rows(want, v, os, oe, out_idx, next, big_list, big_count, kBigRow);
   }
 }
 
@@ -1178,7 +1182,7 @@ static int finish_and_read(dfpr_graph* g, hipStream_t s) {
 // Chunked marking of the rows collected in big_list.
 static int mark_big(dfpr_graph* g, uint8_t* flags, hipStream_t s) {
   k_big_scan<<<1, 1024, 0, s>>>(g->big_list, &g->ctl->big_count, g->out.off, g->big_pre);
-  k_big_mark<<<256, 256, 0, s>>>(g->big_list, &g->ctl->big_count, g->big_pre, g->out.off, g->out.idx, flags);
+  k_big_mark<<<1024, 256, 0, s>>>(g->big_list, &g->ctl->big_count, g->big_pre, g->out.off, g->out.idx, flags);
   DFPR_HIP(hipGetLastError());
   return DFPR_OK;
 }
@@ -1486,7 +1490,7 @@ static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_pre
   size_t tok;
   DFPR_TRY(g->pool.start(&tok));
   k_mark_pending<<<gi, 256, 0, s>>>(g->pend_src, n, g->out.off, g->out.idx, g->flag_cur, g->big_list,
-                                    &g->ctl->big_count);
+                                    &g->ctl->big_count, kPendBigRow);
   DFPR_HIP(hipGetLastError());
   DFPR_TRY(mark_big(g, g->flag_cur, s));
   DFPR_TRY(g->pool.stop(kTMark, tok));
@@ -1589,7 +1593,8 @@ static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_pre
           (p.dense_switch > 0.0 && h->dense_cnt * 2 * kDenseVertexShare < n && h->dense_xedges * 4 < front_edges)) {
         // back to the frontier form: mark out(v) of this iteration's expanders
         // into the keep flags (clears xa), then bin
-        k_mark_pending<<<gi, 256, 0, s>>>(xa, n, g->out.off, g->out.idx, cur, g->big_list, &g->ctl->big_count);
+        k_mark_pending<<<gi, 256, 0, s>>>(xa, n, g->out.off, g->out.idx, cur, g->big_list, &g->ctl->big_count,
+                                          kBigRow);
         DFPR_HIP(hipGetLastError());
         DFPR_TRY(mark_big(g, cur, s));
         k_fill_u8<<<gi, 256, 0, s>>>(next, n, 0);

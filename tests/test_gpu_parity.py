@@ -143,6 +143,50 @@ def test_apply_runs_in_one_row():
     assert_csr_equal(p.g, p.og)
 
 
+@pytest.mark.parametrize("side", ["out", "in"])
+def test_apply_entries_at_copy_chunk_edges(side):
+    """Run-by-run copy where the cuts sit on the copy workgroups' chunk edges
+    (1024 positions of the new index array on a graph under 2M edges): the
+    batch inserts the edges that end up at positions q-1 and q of every chunk
+    edge q (and the first and last positions) of the out- or in-CSR, and
+    deletes, at every other chunk edge, an extra edge that sorts just before
+    position q, so a deletion's cut, an empty run and an insertion meet there.
+    Caller ids are kept, so the positions are those of the canonical CSR."""
+    torch_cuda()
+    n, s, d = rmat(14, seed=91)
+    full = O.graph(n, s, d)  # the graph after the batch
+    m = full.m
+    off, idx = (full.out_off, full.out_idx) if side == "out" else (full.in_off, full.in_idx)
+    row_of = np.repeat(np.arange(n, dtype=np.int64), np.diff(off))
+    edges = list(range(1024, m, 1024))
+    pos = sorted({p for q in edges + [0, m - 1] for p in (q - 1, q) if 0 <= p < m and row_of[p] != idx[p]})
+    extra = []
+    for q in edges[::2]:
+        r = int(row_of[q])
+        lo = int(idx[q - 1]) + 1 if row_of[q - 1] == r else 0
+        cand = [c for c in range(lo, int(idx[q])) if c != r]
+        if cand:
+            extra.append((r, cand[0]))
+    assert len(extra) > 20
+    keep = np.ones(m, bool)
+    keep[pos] = False
+    rows = np.concatenate([row_of[keep], [r for r, _ in extra]]).astype(np.int32)
+    cols = np.concatenate([idx[keep], [c for _, c in extra]]).astype(np.int32)
+    xr = np.array([r for r, _ in extra], np.int32)
+    xc = np.array([c for _, c in extra], np.int32)
+    if side == "out":
+        src, dst, ins_src, ins_dst, del_src, del_dst = rows, cols, row_of[pos], idx[pos], xr, xc
+    else:
+        src, dst, ins_src, ins_dst, del_src, del_dst = cols, rows, idx[pos], row_of[pos], xc, xr
+    p = Pair(n, src, dst, keep_ids=True)
+    assert len(pos) + len(extra) <= p.og.m // 256  # the run-by-run copy
+    _print("chunk edges", side, len(pos), len(extra), p.og.m)
+    info = p.apply(del_src, del_dst, ins_src.astype(np.int32), ins_dst.astype(np.int32))
+    assert info["ins_effective"] == len(pos) and info["del_effective"] == len(extra)
+    assert_csr_equal(p.g, p.og)
+    assert np.array_equal(p.og.out_idx, full.out_idx) and np.array_equal(p.og.in_idx, full.in_idx)
+
+
 @pytest.mark.parametrize("k", [63, 64, 65])
 def test_apply_group_entries_at_lane_count(k):
     """Merge of touched groups: rows 0..63 (one group; caller ids kept inside)

@@ -292,11 +292,12 @@ int scan_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* tmp, hipStream
 // Row offsets: out[u] = sum_{w<u} (base_off[w+1]-base_off[w] + delta[w]), u in [0,n].
 int scan_row_offsets(const int32_t* base_off, const int32_t* delta, int32_t* out, int32_t n,
                      int64_t* tmp, hipStream_t s);
-// LSD radix sort of n 64-bit keys on their low `bits` bits.  Result lands in
-// *keys (pointer may be swapped with alt).  hist must hold radix_hist_elems(n).
+// Stable LSD radix sort of n 64-bit keys on their bits [lo_bit, bits) (keys
+// equal there keep their input order).  Result lands in *keys (pointer may be
+// swapped with alt).  hist must hold radix_hist_elems(n).
 size_t radix_hist_elems(int64_t n);
 int radix_sort(uint64_t** keys, uint64_t** alt, int64_t n, int bits, int64_t* hist,
-               int64_t* hist_scan_tmp, hipStream_t s);
+               int64_t* hist_scan_tmp, hipStream_t s, int lo_bit = 0);
 size_t radix_scan_tmp_elems(int64_t n);
 // Stable compaction: out[k] = in[i] for the i with keep(i); count written to *count_dev.
 int compact_keys(const uint64_t* in, const uint8_t* keep, uint64_t* out, int64_t n,

@@ -576,13 +576,35 @@ __global__ void __launch_bounds__(256) k_run_offsets(const int32_t* __restrict__
     }
     return;
   }
+  // the chunk's entries (rows and shifts) staged in LDS when they fit
+  constexpr int kStage = 512;
+  __shared__ int32_t st_row[kStage];
+  __shared__ int64_t st_shift[kStage + 1];
   for (int64_t r0 = blockIdx.x * (int64_t)rows; r0 <= n; r0 += (int64_t)off_blocks * rows) {
     const int64_t r1 = min(r0 + rows, (int64_t)n + 1);
     const int64_t e0 = lower_bound_u64(eff, 0, T, (uint64_t)r0 << (b + 1));
     const int64_t e1 = lower_bound_u64(eff, e0, T, (uint64_t)r1 << (b + 1));
-    for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
-      const int64_t e = lower_bound_u64(eff, e0, e1, (uint64_t)r << (b + 1));
-      noff[r] = (int32_t)((int64_t)ooff[r] + e - 2 * delpre[e]);
+    const int cnt = (int)min(e1 - e0, (int64_t)kStage + 1);
+    if (cnt <= kStage) {  // the same in every thread
+      __syncthreads();    // the previous chunk's readers are done
+      for (int k = threadIdx.x; k <= cnt; k += blockDim.x) {
+        if (k < cnt) st_row[k] = (int32_t)(eff[e0 + k] >> (b + 1));
+        st_shift[k] = (e0 + k) - 2 * delpre[e0 + k];
+      }
+      __syncthreads();
+      for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
+        int lo = 0, hi = cnt;  // first staged entry of row r or later
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (st_row[mid] < r) lo = mid + 1; else hi = mid;
+        }
+        noff[r] = (int32_t)((int64_t)ooff[r] + st_shift[lo]);
+      }
+    } else {
+      for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
+        const int64_t e = lower_bound_u64(eff, e0, e1, (uint64_t)r << (b + 1));
+        noff[r] = (int32_t)((int64_t)ooff[r] + e - 2 * delpre[e]);
+      }
     }
   }
 }
@@ -1298,7 +1320,9 @@ int graph_apply(dfpr_graph* g, int64_t nd, const int32_t* del_src, const int32_t
   uint64_t* eff_in = ka;
   uint64_t* alt = kc;
   DFPR_TRY(ep.start(&tok));
-  DFPR_TRY(radix_sort(&eff_in, &alt, nk, 2 * b + 1, hist, tmp, s));
+  // the entries arrive in (u, v) order and each pair is one entry, so a
+  // stable sort on the v field alone gives (v, u) order
+  DFPR_TRY(radix_sort(&eff_in, &alt, nk, 2 * b + 1, hist, tmp, s, b + 1));
   DFPR_TRY(ep.stop(kTSort, tok));
   DFPR_TRY(scan_generic(LoadIsDel{eff_in, cnt}, StoreI64b{pre_in}, nk, tmp, s));
   if (few)

@@ -171,7 +171,7 @@ __global__ void __launch_bounds__(kRadixBlock) k_radix_scatter_own(const uint64_
 
 // Whole sort inside one block for n <= kSmallSort keys.
 constexpr int kSmallSort = 2048;
-__global__ void __launch_bounds__(kRadixBlock) k_radix_small(uint64_t* keys, int64_t n, int bits) {
+__global__ void __launch_bounds__(kRadixBlock) k_radix_small(uint64_t* keys, int64_t n, int lo_bit, int bits) {
   __shared__ uint64_t buf[2][kSmallSort];
   __shared__ int wave_cnt[(kRadixBlock / kWave) * 256];
   __shared__ int running[256];
@@ -181,7 +181,7 @@ __global__ void __launch_bounds__(kRadixBlock) k_radix_small(uint64_t* keys, int
   for (int i = threadIdx.x; i < (kRadixBlock / kWave) * 256; i += kRadixBlock) wave_cnt[i] = 0;
   const int rounds = (int)((n + kRadixBlock - 1) / kRadixBlock);  // only the rounds that hold keys
   int src = 0;
-  for (int shift = 0; shift < bits; shift += 8) {
+  for (int shift = lo_bit; shift < bits; shift += 8) {
     cnt[threadIdx.x] = 0;
     __syncthreads();
     for (int i = threadIdx.x; i < n; i += kRadixBlock) atomicAdd(&cnt[(buf[src][i] >> shift) & 255u], 1);
@@ -210,14 +210,14 @@ size_t radix_hist_elems(int64_t n) {
 size_t radix_scan_tmp_elems(int64_t n) { return scan_tmp_elems((int64_t)radix_hist_elems(n)); }
 
 int radix_sort(uint64_t** keys, uint64_t** alt, int64_t n, int bits, int64_t* hist, int64_t* scan_tmp,
-               hipStream_t s) {
+               hipStream_t s, int lo_bit) {
   if (n <= 1) return DFPR_OK;
   if (n <= kSmallSort) {
-    k_radix_small<<<1, kRadixBlock, 0, s>>>(*keys, n, bits);
+    k_radix_small<<<1, kRadixBlock, 0, s>>>(*keys, n, lo_bit, bits);
     return hipGetLastError() == hipSuccess ? DFPR_OK : DFPR_EHIP;
   }
   const int64_t nb = (n + kRadixTile - 1) / kRadixTile;
-  for (int shift = 0; shift < bits; shift += 8) {
+  for (int shift = lo_bit; shift < bits; shift += 8) {
     k_radix_hist<<<(unsigned)nb, kRadixBlock, 0, s>>>(*keys, n, shift, hist, nb);
     if (nb <= kFusedScanBlocks) {
       k_radix_scatter_own<<<(unsigned)nb, kRadixBlock, 0, s>>>(*keys, *alt, n, shift, hist, nb);

@@ -473,6 +473,34 @@ def test_fused_loop_matches_launch_loop(case, mode, bounds):
     assert s2["pull_launches"] == 1
 
 
+def test_single_launch_bins_after_failed_and_chained_applies():
+    """Single-launch updates after a batch rejected once its rebuild had run
+    (the cached all-vertex bins must be those of the unchanged graph) and
+    after two applies in a row (those of the last graph).  Thresholds
+    [1, 2, 3, 4, 5] put most vertices in the chunked bin, so the bins of two
+    graphs differ."""
+    torch_cuda()
+    import paper_2401_15870_amd as dfpr
+    n, s, d = rmat(12, seed=27)
+    p = Pair(n, s, d, fused=True)
+    p.g.set_tuning([1, 2, 3, 4, 5])
+    r0 = O.rank("static", p.og).ranks
+    p.apply(*W.batch_8020(n, s, d, 1e-2, seed=28))
+    with pytest.raises(dfpr.DfprError) as e:
+        p.g.apply_batch([0, 1], [2, n], [5, 6], [7, 8])
+    assert e.value.code == -2
+    assert_csr_equal(p.g, p.og)
+    r, st, ref = p.rank("dfp", r0)
+    assert np.abs(r - ref.ranks).max() <= LINF
+    assert st["pull_launches"] == 1
+    p.apply(*W.batch_8020(n, s, d, 1e-2, seed=29))
+    p.apply(*W.batch_8020(n, s, d, 3e-2, seed=30))
+    assert_csr_equal(p.g, p.og)
+    r, st, ref = p.rank("static", None)
+    assert np.abs(r - ref.ranks).max() <= LINF
+    assert st["pull_launches"] == 1 and st["iterations"] == ref.iterations
+
+
 @pytest.mark.parametrize("mode", ["static", "dfp"])
 def test_fused_loop_iteration_cap(mode):
     """Stopping at max_iters (not converged) happens at the same iteration on both paths."""

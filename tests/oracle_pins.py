@@ -312,6 +312,77 @@ def pin_lower_bound(lib):
                     assert abs(r.ranks.sum() - 1.0) <= 1e-12
 
 
+def pin_threshold_strictness(lib):
+    """Algorithm 1 prunes when the relative change is at most tau_p and expands
+    when it exceeds tau_f.  With alpha = 1/2, |V| = 4 (C0 = 1/8) and dyadic
+    ranks every quantity below is exact in binary floating point, so the
+    thresholds can be set to a vertex's computed change itself.
+
+    Expansion (DF, Equation 1).  G^{t-1} = {1->2} (+ self-loops), insert 0->1,
+    R_prev = (1/4, 1/2, 1/2, 1/4).  Marked: out(0) = {0, 1}; |out(0)| =
+    |out(1)| = 2.  Vertex 1: c = 1/8 + 1/4, r = 1/8 + c/2 = 5/16, change 3/16,
+    relative 3/16 / (1/2) = 3/8.  Vertex 0: r = 1/8 + 1/16 = 3/16, relative
+    1/4.  Both then shrink towards the fixed point (1/6, 2/9).  With tau_f = 3/8
+    nothing expands, so vertex 2 is never processed and keeps 1/2 exactly; a
+    non-strict test would expand vertex 1 and process vertex 2.
+
+    Pruning (DF-P, Equation 2).  G^{t-1} = {0->2, 1->2}, delete 0->2,
+    R_prev = (1/4, 1/2, 3/8, 1/4).  Marked: {0, 2}; afterwards |out(0)| =
+    |out(2)| = 1, so the factor 1/(1 - alpha/1) is 2.  Vertex 0: r = 2(1/8 +
+    (1/4 - 1/4)/2) = 1/4, change 0.  Vertex 2: in(2) = {1, 2}, c - R[2] = 1/4,
+    r = 2(1/8 + 1/8) = 1/2, change 1/8, relative 1/8 / (1/2) = 1/4.  With
+    tau_p = 1/4 (tau_f = 1: nothing expands) both are pruned after the first
+    iteration: the second processes nothing, 2 vertex updates in all.  A strict
+    test would keep vertex 2 for a second iteration (3 updates)."""
+    g0 = O.graph(4, [1], [2], lib=lib)
+    g1, b = O.apply(g0, [], [], [0], [1], lib=lib)
+    rp = np.array([0.25, 0.5, 0.5, 0.25])
+    r = O.rank("df", g1, rp, g0, b, alpha=0.5, tol_f=0.375, tol_p=0.375, lib=lib)
+    assert r.ever_affected == 2 and r.ranks[2] == 0.5
+    assert abs(r.ranks[0] - 1 / 6) < 1e-10 and abs(r.ranks[1] - 2 / 9) < 1e-10
+    # just below the computed change, vertex 1 expands and vertex 2 is processed
+    r = O.rank("df", g1, rp, g0, b, alpha=0.5, tol_f=np.nextafter(0.375, 0.0), tol_p=0.375, lib=lib)
+    assert r.ever_affected == 3 and r.ranks[2] != 0.5
+
+    g0 = O.graph(4, [0, 1], [2, 2], lib=lib)
+    g1, b = O.apply(g0, [0], [2], [], [], lib=lib)
+    rp = np.array([0.25, 0.5, 0.375, 0.25])
+    r = O.rank("dfp", g1, rp, g0, b, alpha=0.5, tol_f=1.0, tol_p=0.25, lib=lib)
+    assert list(r.frontier) == [2, 0] and r.vertex_updates == 2 and r.iterations == 2
+    assert r.ranks.tolist() == [0.25, 0.5, 0.5, 0.25]
+    r = O.rank("dfp", g1, rp, g0, b, alpha=0.5, tol_f=1.0, tol_p=np.nextafter(0.25, 0.0), lib=lib)
+    assert list(r.frontier) == [2, 1] and r.vertex_updates == 3
+
+
+def pin_marks_win_over_prunes(lib):
+    """A vertex pruned in an iteration is processed again in the next one when
+    an in-neighbour expanded in the same iteration (the expansion marks all of
+    its out-neighbours, Algorithm 1).
+
+    alpha = 1/2, |V| = 4, G^{t-1} = {1->2}, insert 0->2, R_prev = (1/2, 1/2,
+    3/4, 1/4), DF-P with tau_f = tau_p = 1/10.  Marked: out(0) = {0, 2};
+    |out(0)| = |out(1)| = 2, |out(2)| = 1.
+      iteration 1: vertex 0 (in(0) = {0}): r = C0/(1 - alpha/2) = 1/6, relative
+        change (1/2 - 1/6)/(1/2) = 2/3: kept and expands, marking {0, 2}.
+        Vertex 2: r = 2(1/8 + (1/4 + 1/4)/2) = 3/4, change 0: pruned, but
+        re-marked by vertex 0.
+      iteration 2: vertex 0: r = 1/6 again, change 0: pruned, no expansion.
+        Vertex 2: r = 2(1/8 + (1/12 + 1/4)/2) = 7/12, relative change
+        (1/6)/(3/4) = 2/9: kept and expands (marks itself).
+      iteration 3: vertex 2: r = 7/12, change 0.  Stop.
+    So 3 iterations, frontier sizes 2, 2, 1, and R[2] = 7/12.  If prunes won,
+    vertex 2 would stay at 3/4."""
+    g0 = O.graph(4, [1], [2], lib=lib)
+    g1, b = O.apply(g0, [], [], [0], [2], lib=lib)
+    rp = np.array([0.5, 0.5, 0.75, 0.25])
+    r = O.rank("dfp", g1, rp, g0, b, alpha=0.5, tol_f=0.1, tol_p=0.1, lib=lib)
+    assert r.iterations == 3 and r.converged == 1
+    assert list(r.frontier) == [2, 2, 1] and r.vertex_updates == 5 and r.ever_affected == 2
+    assert abs(r.ranks[2] - 7 / 12) < 1e-15 and abs(r.ranks[0] - 1 / 6) < 1e-15
+    assert r.ranks[1] == 0.5 and r.ranks[3] == 0.25
+
+
 ALL_PINS = [pin_canonical, pin_apply, pin_static_dense, pin_static_closed_forms, pin_nd_is_static_warm,
             pin_dfp_closed_loop, pin_dynamic_bruteforce, pin_dynamic_special_cases, pin_relative_criterion,
-            pin_other_criteria, pin_lower_bound]
+            pin_other_criteria, pin_lower_bound, pin_threshold_strictness,
+            pin_marks_win_over_prunes]

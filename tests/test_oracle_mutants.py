@@ -39,6 +39,11 @@ MUTANTS = {
                                   "if (criterion == ORC_CRIT_ABSOLUTE) rel = dr / fmax(r, R[v]);"),
     "contrib_measure_times_degree": ("else if (criterion == ORC_CRIT_CONTRIB) rel = dr / d;",
                                      "else if (criterion == ORC_CRIT_CONTRIB) rel = dr * d;"),
+    "prune_strict_less": ("An[v] = (mode == ORC_DFP && rel <= tol_p) ? 0 : 1;",
+                          "An[v] = (mode == ORC_DFP && rel < tol_p) ? 0 : 1;"),
+    "expand_non_strict": ("if (rel > tol_f) X[v] = 1;", "if (rel >= tol_f) X[v] = 1;"),
+    "prunes_win_over_marks": ("#pragma omp atomic write\n          An[out_idx[p]] = 1;",
+                              "if (!A[out_idx[p]]) An[out_idx[p]] = 1;"),
 }
 
 

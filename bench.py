@@ -1016,6 +1016,10 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         log("calibration: 3 copies of 1 GiB done")
+    # destroy the graph while the HIP runtime is certainly intact (not from a
+    # destructor at interpreter exit)
+    g.close()
+    torch.cuda.synchronize()
 
 
 if __name__ == "__main__":

@@ -12,7 +12,10 @@ only for device memory (rank vectors, device-resident edge arrays) and streams.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
+import sys
+import weakref
 
 import numpy as np
 
@@ -60,6 +63,26 @@ def _ids(a):
     return ctypes.c_void_p(arr.ctypes.data if arr.size else 0), arr.size, _capi.HOST, arr
 
 
+# Handles still open when the interpreter starts to exit are destroyed by an
+# atexit hook, which runs before interpreter finalisation, while torch (whose
+# HIP runtime the library is bound to) is still intact: servers first (they
+# own graphs and lane threads), then graphs.  Destructors that Python runs
+# later, during finalisation, do nothing: a destroy there could reach a HIP
+# runtime that is already being torn down, and the process is ending anyway.
+_live_servers: "weakref.WeakSet" = weakref.WeakSet()
+_live_graphs: "weakref.WeakSet" = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    for objs in (_live_servers, _live_graphs):
+        for o in list(objs):
+            try:
+                o.close()
+            except Exception:  # noqa: BLE001 - best effort at exit
+                pass
+
+
 def default_params() -> Params:
     p = Params()
     lib().dfpr_params_default(ctypes.byref(p))
@@ -72,6 +95,7 @@ class Graph:
     def __init__(self, handle, n):
         self._h = handle
         self.n = n
+        _live_graphs.add(self)
 
     @classmethod
     def from_coo(cls, n, src, dst, edge_capacity=0, keep_ids=False, stream=None):
@@ -93,9 +117,11 @@ class Graph:
             self._h = None
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
-        except Exception:  # noqa: BLE001 - interpreter shutdown
+        except Exception:  # noqa: BLE001
             pass
 
     def __enter__(self):
@@ -298,6 +324,7 @@ class Server:
         self._h = h
         self._n = {}
         self._keep = {}
+        _live_servers.add(self)
 
     def close(self):
         if self._h:
@@ -305,9 +332,11 @@ class Server:
             self._h = None
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
-        except Exception:  # noqa: BLE001 - interpreter shutdown
+        except Exception:  # noqa: BLE001
             pass
 
     def __enter__(self):

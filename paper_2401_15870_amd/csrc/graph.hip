@@ -79,14 +79,43 @@ static void dfree(T*& p) {
 constexpr uint64_t kBadKey = ~0ull;
 
 // ---- internal numbering by decreasing in-degree (ties by caller id)
-__global__ void k_validate_count(const int32_t* src, const int32_t* dst, int64_t m, int32_t n, int32_t* deg,
-                                 int64_t* err) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t u = src[i], v = dst[i];
-    if (u < 0 || u >= n || v < 0 || v >= n) {
-      atomicOr((unsigned long long*)err, 1ull);
-    } else if (deg) {
-      atomicAdd(&deg[v], 1);
+// Validates the ids and counts the in-degree of every target.  A hub can be
+// the target of a large share of all pairs, so the wavefront first sorts its
+// 64 targets (bitonic network over the lanes) and each run of equal targets
+// adds its length with one atomic: a hub costs one atomic per wavefront
+// instead of one per pair.
+__global__ void __launch_bounds__(256) k_validate_count(const int32_t* src, const int32_t* dst, int64_t m, int32_t n,
+                                                        int32_t* deg, int64_t* err) {
+  const int lane = lane_id();
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t base = blockIdx.x * (int64_t)blockDim.x + (threadIdx.x & ~(kWave - 1)); base < m; base += stride) {
+    const int64_t i = base + lane;
+    int32_t v = INT32_MAX;  // lanes past the end and invalid pairs sort last and count nothing
+    if (i < m) {
+      const int32_t u = src[i], w = dst[i];
+      if (u < 0 || u >= n || w < 0 || w >= n)
+        atomicOr((unsigned long long*)err, 1ull);
+      else
+        v = w;
+    }
+    if (!deg) continue;
+#pragma unroll
+    for (int k = 2; k <= kWave; k <<= 1) {
+#pragma unroll
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        const int32_t y = __shfl_xor(v, j, kWave);
+        const bool up = (lane & k) == 0;
+        const bool lower = (lane & j) == 0;
+        v = (lower == up) ? min(v, y) : max(v, y);
+      }
+    }
+    const int32_t prev = __shfl_up(v, 1, kWave);
+    const bool head = lane == 0 || prev != v;
+    const unsigned long long heads = __ballot(head);
+    if (head && v != INT32_MAX) {
+      const unsigned long long above = lane == kWave - 1 ? 0ull : (heads >> (lane + 1)) << (lane + 1);
+      const int next = above ? __ffsll((long long)above) - 1 : kWave;
+      atomicAdd(&deg[v], next - lane);
     }
   }
 }

@@ -42,13 +42,15 @@ def _chains(graphs, steps, seed):
     return out
 
 
-def _alone(graphs, chains):
+def _alone(graphs, chains, fused_limit=None):
     """Each graph's chain through a plain handle: the reference results."""
     torch = torch_cuda()
     m = dfpr()
     res = []
     for (n, s, d), ch in zip(graphs, chains):
         g = m.Graph.from_coo(n, s, d)
+        if fused_limit is not None:
+            g.set_fused_limit(fused_limit)
         r, _ = g.update_ranks("static", None)
         seq = [r.cpu().numpy()]
         for b in ch:
@@ -61,10 +63,17 @@ def _alone(graphs, chains):
     return res
 
 
-def _serve(graphs, chains, heap_bytes, lanes):
+def _handle(m, n, s, d, fused_limit):
+    g = m.Graph.from_coo(n, s, d)
+    if fused_limit is not None:
+        g.set_fused_limit(fused_limit)
+    return g
+
+
+def _serve(graphs, chains, heap_bytes, lanes, fused_limit=None):
     m = dfpr()
     srv = m.Server(heap_bytes, lanes=lanes)
-    gids = [srv.add_graph(m.Graph.from_coo(n, s, d)) for n, s, d in graphs]
+    gids = [srv.add_graph(_handle(m, n, s, d, fused_limit)) for n, s, d in graphs]
     r0 = [srv.ranks(g) for g in gids]
     tickets = []
     steps = len(chains[0])
@@ -94,6 +103,27 @@ def test_serving_alone_vs_mix():
     assert stats["completed"] == stats["submitted"] == len(graphs) * len(chains[0])
     assert stats["failed"] == 0 and stats["heap_used"] == 0
     assert stats["peak_in_flight"] > 1  # requests really overlapped
+    for k in range(len(graphs)):
+        for t in range(len(chains[k]) + 1):
+            assert np.array_equal(got[k][t], ref[k][t]), (k, t, float(np.abs(got[k][t] - ref[k][t]).max()))
+        assert np.array_equal(final[k], ref[k][-1])
+
+
+def test_serving_alone_vs_mix_multilaunch():
+    """The same with every update on the launch-per-iteration path (single
+    launch disabled, as for graphs above its edge limit): the lanes' pull,
+    commit and binning kernels then run concurrently on different streams, and
+    each result must still equal its graph's requests run alone, bit for bit."""
+    torch_cuda()
+    graphs = _graphs(4)
+    chains = _chains(graphs, 4, seed=4)
+    ref = _alone(graphs, chains, fused_limit=0)
+    _print("serving (launch per iteration): mix of", len(graphs), "graphs x", len(chains[0]), "requests, 4 lanes")
+    got, stats, final, lat = _serve(graphs, chains, heap_bytes=256 << 20, lanes=4, fused_limit=0)
+    _print("  stats", stats, "p50 latency ms", float(np.median(lat)))
+    assert stats["completed"] == stats["submitted"] == len(graphs) * len(chains[0])
+    assert stats["failed"] == 0 and stats["heap_used"] == 0
+    assert stats["peak_in_flight"] > 1
     for k in range(len(graphs)):
         for t in range(len(chains[k]) + 1):
             assert np.array_equal(got[k][t], ref[k][t]), (k, t, float(np.abs(got[k][t] - ref[k][t]).max()))

@@ -176,6 +176,25 @@ int dfpr_apply_batch(dfpr_graph* g, int64_t n_del, const int32_t* del_src, const
                      int64_t n_ins, const int32_t* ins_src, const int32_t* ins_dst,
                      dfpr_where where, void* stream, dfpr_batch_info* info);
 
+/* Allocation-free variant of dfpr_apply_batch, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Same arguments, effect, results and
+ * errors as dfpr_apply_batch, but the batch's sort and staging buffers come
+ * from a fixed scratch array inside the library (32 MiB of device memory per
+ * device the library runs on, held until the process ends) and the call makes
+ * no device allocation.  Limits: n_del + n_ins <= DFPR_NOALLOC_MAX_PAIRS (else
+ * EINVAL), and the insertions must fit the graph's edge capacity (m + n_ins
+ * <= the capacity reserved at create; else ENOMEM, where dfpr_apply_batch
+ * would grow it).  The call returns once its work on the stream has finished.
+ * No HIP-event timings are recorded (the info's ms_* fields stay 0).  Every
+ * call on a device shares that device's scratch array: calls from one process
+ * are serialised by a lock, and calls that overlap on one device from
+ * different processes race. */
+#define DFPR_NOALLOC_MAX_PAIRS (1 << 19)
+int dfpr_apply_batch_noalloc(dfpr_graph* g, int64_t n_del, const int32_t* del_src, const int32_t* del_dst,
+                             int64_t n_ins, const int32_t* ins_src, const int32_t* ins_dst, dfpr_where where,
+                             void* stream, dfpr_batch_info* info);
+
 /* Update ranks (Algorithm 1; Equations 1 and 2).  r_prev and r_out are device
  * arrays of n doubles owned by the caller; they may alias.  STATIC ignores
  * r_prev and starts from 1/n; ND processes every vertex from r_prev; DF and

@@ -160,6 +160,24 @@ class Graph:
         _check(lib().dfpr_apply_batch(self._h, nds, a, b, nis, c, d, where, _stream_ptr(stream), ctypes.byref(info)))
         return info.as_dict()
 
+    def apply_batch_noalloc(self, del_src=(), del_dst=(), ins_src=(), ins_dst=(), stream=None) -> dict:
+        """apply_batch through the allocation-free entry point (at most
+        NOALLOC_MAX_PAIRS pairs, within the edge capacity reserved at create)."""
+        a, nds, w1, k1 = _ids(del_src)
+        b, ndd, w2, k2 = _ids(del_dst)
+        c, nis, w3, k3 = _ids(ins_src)
+        d, nid, w4, k4 = _ids(ins_dst)
+        if nds != ndd or nis != nid:
+            raise ValueError("src/dst length mismatch")
+        wheres = {w for w, k in ((w1, nds), (w3, nis)) if k}
+        if len(wheres) > 1:
+            raise ValueError("deletions and insertions must live in the same memory")
+        where = wheres.pop() if wheres else _capi.HOST
+        info = BatchInfo()
+        _check(lib().dfpr_apply_batch_noalloc(self._h, nds, a, b, nis, c, d, where, _stream_ptr(stream),
+                                              ctypes.byref(info)))
+        return info.as_dict()
+
     def update_ranks(self, mode, r_prev=None, out=None, stream=None, timing=False, asynchronous=False, **kw):
         """Run Static / ND / DF / DF-P.  r_prev and out are float64 CUDA tensors of n entries.
         asynchronous: DF/DF-P update ranks in place during each iteration (not bit-reproducible)."""

@@ -12,12 +12,13 @@ STATIC, ND, DF, DFP = 0, 1, 2, 3
 HOST, DEVICE = 0, 1
 FLAG_TIMING = 1
 FLAG_ASYNC = 2
+NOALLOC_MAX_PAIRS = 1 << 19
 CRITERIA = {"relative": 0, "absolute": 1, "contrib": 2}
 CREATE_KEEP_IDS = 1
 
 # Every exported function declared in include/dfpr.h.
 EXPORTS = ("dfpr_params_default", "dfpr_graph_create", "dfpr_graph_destroy", "dfpr_graph_size",
-           "dfpr_graph_export", "dfpr_apply_batch", "dfpr_update_ranks", "dfpr_set_tuning",
+           "dfpr_graph_export", "dfpr_apply_batch", "dfpr_apply_batch_noalloc", "dfpr_update_ranks", "dfpr_set_tuning",
            "dfpr_get_tuning", "dfpr_autotune", "dfpr_set_timing", "dfpr_set_fused_limit", "dfpr_batch_create", "dfpr_batch_count",
            "dfpr_batch_member", "dfpr_apply_batch_many", "dfpr_update_ranks_many", "dfpr_server_create",
            "dfpr_server_destroy", "dfpr_server_add_graph", "dfpr_server_submit", "dfpr_server_wait",
@@ -95,6 +96,8 @@ def declare(lib):
     lib.dfpr_graph_export.restype = ctypes.c_int
     lib.dfpr_apply_batch.argtypes = [P, i64, P, P, i64, P, P, ctypes.c_int, P, ctypes.POINTER(BatchInfo)]
     lib.dfpr_apply_batch.restype = ctypes.c_int
+    lib.dfpr_apply_batch_noalloc.argtypes = [P, i64, P, P, i64, P, P, ctypes.c_int, P, ctypes.POINTER(BatchInfo)]
+    lib.dfpr_apply_batch_noalloc.restype = ctypes.c_int
     lib.dfpr_update_ranks.argtypes = [P, ctypes.c_int, ctypes.POINTER(Params), P, P, P, ctypes.POINTER(Stats)]
     lib.dfpr_update_ranks.restype = ctypes.c_int
     lib.dfpr_set_tuning.argtypes = [P, ctypes.POINTER(i32)]

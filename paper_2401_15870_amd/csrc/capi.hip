@@ -159,6 +159,30 @@ int dfpr_apply_batch(dfpr_graph* g, int64_t n_del, const int32_t* del_src, const
   });
 }
 
+int dfpr_apply_batch_noalloc(dfpr_graph* g, int64_t n_del, const int32_t* del_src, const int32_t* del_dst,
+                             int64_t n_ins, const int32_t* ins_src, const int32_t* ins_dst, dfpr_where where,
+                             void* stream, dfpr_batch_info* info) {
+  clear_error();
+  if (n_del < 0 || n_ins < 0 || (n_del > 0 && (!del_src || !del_dst)) || (n_ins > 0 && (!ins_src || !ins_dst)) ||
+      (where != DFPR_HOST && where != DFPR_DEVICE)) {
+    set_error("invalid batch arguments");
+    return DFPR_EINVAL;
+  }
+  if (n_del + n_ins > DFPR_NOALLOC_MAX_PAIRS) {
+    set_error("allocation-free apply: %lld batch pairs exceed the limit of %d", (long long)(n_del + n_ins),
+              DFPR_NOALLOC_MAX_PAIRS);
+    return DFPR_EINVAL;
+  }
+  return guarded(g, [&] {
+    if (g->ngraphs > 1) {
+      set_error("batch handle: use dfpr_apply_batch_many");
+      return (int)DFPR_EINVAL;
+    }
+    return graph_apply_noalloc(g, n_del, del_src, del_dst, n_ins, ins_src, ins_dst, where, (hipStream_t)stream,
+                               info);
+  });
+}
+
 int dfpr_update_ranks(dfpr_graph* g, dfpr_mode mode, const dfpr_params* p, const double* r_prev, double* r_out,
                       void* stream, dfpr_stats* st) {
   clear_error();

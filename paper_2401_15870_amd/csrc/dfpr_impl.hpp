@@ -325,6 +325,12 @@ int graph_export(const dfpr_graph* g, int in_csr, int32_t* off, int32_t* idx, df
 int graph_apply(dfpr_graph* g, int64_t n_del, const int32_t* del_src, const int32_t* del_dst,
                 int64_t n_ins, const int32_t* ins_src, const int32_t* ins_dst, dfpr_where where,
                 hipStream_t s, dfpr_batch_info* info);
+// graph_apply with its sort and staging buffers in the library's fixed device
+// scratch (no device allocation): at most DFPR_NOALLOC_MAX_PAIRS pairs and no
+// growth of the edge capacity.
+int graph_apply_noalloc(dfpr_graph* g, int64_t n_del, const int32_t* del_src, const int32_t* del_dst,
+                        int64_t n_ins, const int32_t* ins_src, const int32_t* ins_dst, dfpr_where where,
+                        hipStream_t s, dfpr_batch_info* info);
 
 // ---- serving form (server.hip)
 int server_create(size_t heap_bytes, int32_t lanes, dfpr_mode mode, const dfpr_params& p, dfpr_server** out);

@@ -1413,6 +1413,81 @@ int graph_apply(dfpr_graph* g, int64_t nd, const int32_t* del_src, const int32_t
 
 namespace dfpr {
 
+// ---- allocation-free apply.  The sort and staging buffers of one apply live
+// in a fixed device array instead of the handle's growable buffers.  In host
+// code `noalloc_scratch` names a host-side stand-in, never the device memory:
+// its device address is looked up once per device (hipGetSymbolAddress with
+// that device current) and only that address reaches kernels.  Every call on
+// a device uses the same array; a per-device lock, held until the call's work
+// has finished on its stream, serialises the calls of this process.
+constexpr size_t kNoallocBytes = (size_t)32 << 20;
+__device__ __align__(256) unsigned char noalloc_scratch[kNoallocBytes];
+
+namespace {
+constexpr int kNoallocDevices = 64;
+std::mutex g_noalloc_mu[kNoallocDevices];
+void* g_noalloc_ptr[kNoallocDevices] = {};  // device address of noalloc_scratch per device
+}  // namespace
+
+int graph_apply_noalloc(dfpr_graph* g, int64_t nd, const int32_t* del_src, const int32_t* del_dst, int64_t ni,
+                        const int32_t* ins_src, const int32_t* ins_dst, dfpr_where where, hipStream_t s,
+                        dfpr_batch_info* info) {
+  const int64_t nk = nd + ni;
+  if (nk > DFPR_NOALLOC_MAX_PAIRS) {
+    set_error("allocation-free apply: %lld batch pairs exceed the limit of %d", (long long)nk, DFPR_NOALLOC_MAX_PAIRS);
+    return DFPR_EINVAL;
+  }
+  if (g->m + ni > g->cap) {
+    set_error("allocation-free apply: %lld insertions could exceed the edge capacity (%lld edges of %lld)",
+              (long long)ni, (long long)g->m, (long long)g->cap);
+    return DFPR_ENOMEM;
+  }
+  const int dev = g->device;
+  if (dev < 0 || dev >= kNoallocDevices) {
+    set_error("allocation-free apply: device %d not supported", dev);
+    return DFPR_EINVAL;
+  }
+  auto r = [](size_t x) { return (x + Heap::kAlign - 1) / Heap::kAlign * Heap::kAlign; };
+  const size_t n8 = (size_t)nk * sizeof(uint64_t);
+  const size_t b_keys_c = r(n8 + (size_t)nk);
+  const size_t b_hist =
+      r((radix_hist_elems(nk) + std::max(radix_scan_tmp_elems(nk), scan_tmp_elems(nk + 1))) * sizeof(int64_t));
+  const size_t b_pre = r(3 * (size_t)(nk + 1) * sizeof(int64_t));
+  const size_t b_in = where == DFPR_HOST ? r(2 * (size_t)nk * sizeof(int32_t)) : 0;
+  const size_t need = 2 * r(n8) + b_keys_c + b_hist + b_pre + b_in;
+  if (need > kNoallocBytes) {
+    set_error("allocation-free apply: %zu scratch bytes needed, %zu available", need, kNoallocBytes);
+    return DFPR_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(g_noalloc_mu[dev]);
+  if (!g_noalloc_ptr[dev]) {
+    void* ptr = nullptr;
+    DFPR_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(noalloc_scratch)));
+    g_noalloc_ptr[dev] = ptr;
+  }
+  char* base = static_cast<char*>(g_noalloc_ptr[dev]);
+  // views over the array, sized as the apply's ensure() calls ask, so none of
+  // them allocates; the handle's own buffers are put back afterwards
+  DevBuf* bufs[6] = {&g->keys_a, &g->keys_b, &g->keys_c, &g->sort_hist, &g->eff_pre, &g->batch_in};
+  const size_t sizes[6] = {r(n8), r(n8), b_keys_c, b_hist, b_pre, b_in};
+  DevBuf saved[6];
+  size_t off = 0;
+  for (int i = 0; i < 6; i++) {
+    saved[i] = *bufs[i];
+    bufs[i]->p = sizes[i] ? base + off : nullptr;
+    bufs[i]->bytes = sizes[i];
+    bufs[i]->heap = nullptr;
+    off += sizes[i];
+  }
+  const bool timing = g->timing;
+  g->timing = false;  // no event creation on this path
+  const int rc = graph_apply(g, nd, del_src, del_dst, ni, ins_src, ins_dst, where, s, info);
+  (void)hipStreamSynchronize(s);  // the array is free for the next call only once this one's work is done
+  g->timing = timing;
+  for (int i = 0; i < 6; i++) *bufs[i] = saved[i];
+  return rc;
+}
+
 // ---- batches of graphs: one disjoint union, member ids local to each member
 int batch_create(int32_t count, const int32_t* n, const int64_t* m, const int32_t* const* src,
                  const int32_t* const* dst, dfpr_where where, int32_t flags, hipStream_t s, dfpr_graph** out) {

@@ -773,6 +773,9 @@ def main():
     ap.add_argument("--asynchronous", action="store_true",
                     help="DF/DF-P update ranks in place during iterations (not bit-reproducible)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (R0 from GPU Static)")
+    ap.add_argument("--dense-switch", type=float, default=None,
+                    help="DF/DF-P: frontier in-edge share above which an iteration runs in the dense form "
+                         "(default: the library's)")
     ap.add_argument("--static-runs", type=int, default=3)
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--calib", action="store_true",
@@ -882,6 +885,7 @@ def main():
     r = torch.from_numpy(np.ascontiguousarray(r0)).to(dev)
 
     # ---- steps
+    rank_kw = {} if args.dense_switch is None else {"dense_switch": args.dense_switch}
     g.set_timing(True)
     step_ms, apply_ms, rank_ms, iters, ever = [], [], [], [], []
     kern = {"pull": 0.0, "commit": 0.0, "bin": 0.0, "mark": 0.0, "sort": 0.0, "rebuild_out": 0.0,
@@ -900,7 +904,7 @@ def main():
         ta = time.perf_counter()
         info = g.apply_batch(*dev_batches[i])
         tb = time.perf_counter()
-        r, st = g.update_ranks(args.mode, r, out=r, asynchronous=args.asynchronous)
+        r, st = g.update_ranks(args.mode, r, out=r, asynchronous=args.asynchronous, **rank_kw)
         tc = time.perf_counter()
         if i == 0 and cpu is not None:
             parity = float(np.abs(r.cpu().numpy() - ref1.ranks).max())
@@ -926,8 +930,9 @@ def main():
             kern["rebuild_out"] += info["ms_rebuild"][0]
             kern["rebuild_in"] += info["ms_rebuild"][1]
             log(f"step {i - args.warmup}: {step_ms[-1]:.2f} ms (apply {apply_ms[-1]:.2f}, rank {rank_ms[-1]:.2f}) "
-                f"it={st['iterations']} ever={st['ever_affected']} pull {st['ms_pull']:.2f} "
-                f"commit {st['ms_commit']:.2f} bin {st['ms_bin']:.2f}")
+                f"it={st['iterations']} dense={st['dense_iterations']} ever={st['ever_affected']} "
+                f"upd={st['vertex_updates']} pulled={st['edges_pulled']} pull {st['ms_pull']:.2f} "
+                f"commit {st['ms_commit']:.2f} bin {st['ms_bin']:.2f} mark {st['ms_mark']:.2f}")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_begin
     K = args.steps
@@ -990,7 +995,8 @@ def main():
                                f"{args.frac:g}*|E|; apply + {args.mode.upper()} update per step",
                    "n": n, "m": int(m0), "batch_edges": int(len(batches[0][0]) + len(batches[0][2])),
                    "mode": args.mode + (" asynchronous" if args.asynchronous else ""), "parallelism": "1 GPU",
-                   "bin_bounds": g.get_tuning()},
+                   "bin_bounds": g.get_tuning(),
+                   **({"dense_switch": args.dense_switch} if args.dense_switch is not None else {})},
         "p50_ms": pct(step_ms, 50),
         "p99_ms": pct(step_ms, 99),
         "apply_p50_ms": pct(apply_ms, 50),

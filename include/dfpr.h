@@ -54,12 +54,15 @@ typedef enum { DFPR_HOST = 0, DFPR_DEVICE = 1 } dfpr_where;
  * of the rank change (> 0).  frontier_tol (tau_f): a processed vertex marks its
  * out-neighbours when its relative change exceeds it.  prune_tol (tau_p): DF-P
  * unmarks a processed vertex whose relative change is at most this.
- * dense_switch (>= 0): DF/DF-P iterations whose affected vertices hold more than
- * this share of |E| in-edges run in the dense form (every vertex checks its
- * in-neighbours' expand flags instead of being marked), unless those vertices
- * are under 1/16 of |V| and have under a quarter as many out-edges as
- * in-edges; 0 = always dense, above 1 = never.  Both forms give identical
- * results; only speed differs.
+ * dense_switch (>= 0, may be +infinity): weight w of the choice between the
+ * two forms of a DF/DF-P iteration, which give identical results and differ
+ * in how an iteration's expansion reaches the next one.  The frontier form
+ * pushes a mark along every out-edge of the expanding vertices; the dense form
+ * processes every vertex and lets each vertex it does not keep check its
+ * in-neighbours' expand flags.  An iteration runs dense when
+ * |E| - (in-edges of the affected vertices) + |V| < w * (out-edges of the
+ * last iteration's expanding vertices).  0 = never dense, infinity = always,
+ * default 1 (a pushed mark priced like a checked flag).
  * max_iters >= 1.  flags: DFPR_FLAG_* bits.  criterion: DFPR_CRIT_*. */
 typedef struct {
   double alpha, tol, frontier_tol, prune_tol, dense_switch;
@@ -131,7 +134,7 @@ typedef struct {
 typedef struct dfpr_graph dfpr_graph;
 
 /* Paper defaults: alpha 0.85, tol 1e-10, tau_f = tau_p = 1e-6, 500 iterations
- * (Section 5.1.2; Sections 4.2-4.3); dense_switch 0.4. */
+ * (Section 5.1.2; Sections 4.2-4.3); dense_switch 1. */
 void dfpr_params_default(dfpr_params* p);
 
 /* Create a graph on the current HIP device from a COO edge list of m pairs.

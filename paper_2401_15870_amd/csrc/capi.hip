@@ -75,7 +75,7 @@ void dfpr_params_default(dfpr_params* p) {
   p->tol = 1e-10;
   p->frontier_tol = 1e-6;
   p->prune_tol = 1e-6;
-  p->dense_switch = 0.4;
+  p->dense_switch = 1.0;
   p->max_iters = 500;
   p->flags = 0;
   p->criterion = DFPR_CRIT_RELATIVE;

@@ -18,6 +18,7 @@
 // out-row marking is balanced across the wave by a prefix sum of row lengths,
 // and no reduction funnels the whole chip into one atomic address.
 #include <algorithm>
+#include <cmath>
 #include <mutex>
 
 #include "prim.hpp"
@@ -179,7 +180,10 @@ __device__ __forceinline__ void vertex_finish(const PullArgs& a, const VCtx& x, 
     a.R[x.v] = r;
     if (a.cmut) a.cmut[x.v] = r / d;  // asynchronous: visible to the vertices processed after this one
     if (stay) a.next[x.v] = 1;
-    if (expand) a.xflag[x.v] = 1;
+    if (expand) {
+      a.xflag[x.v] = 1;
+      acc.xedges += (int64_t)d;  // out-edges the commit will mark
+    }
   }
 }
 
@@ -191,11 +195,11 @@ __device__ __forceinline__ void block_acc_to_slots(Acc acc, const PullArgs& a) {
   __shared__ int64_t shc[4][1024 / kWave];
   const int w = threadIdx.x / kWave;
   const double m = wave_max(acc.mx);
-  int64_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
+  int64_t c0 = 0, c1 = 0, c3 = 0;
+  const int64_t c2 = wave_sum_i64(acc.xedges);  // both forms: out-degree sum of the expanding vertices
   if (DENSE) {
     c0 = wave_sum_i64(acc.cnt);
     c1 = wave_sum_i64(acc.aedges);
-    c2 = wave_sum_i64(acc.xedges);
     c3 = wave_sum_i64(acc.sedges);
   }
   if (lane_id() == 0) {
@@ -224,11 +228,11 @@ __device__ __forceinline__ void block_acc_to_slots(Acc acc, const PullArgs& a) {
     const int slot = (blockIdx.x % kSlots) * kSlotStride;
     if (mm > 0.0)
       atomicMax(&a.gslots[(blockIdx.x % a.gsub) * kSlotStride], (unsigned long long)__double_as_longlong(mm));
+    constexpr int kRow = kSlots * kSlotStride;
+    if (t2) atomicAdd(&a.acc[kAccXEdges * kRow + slot], (unsigned long long)t2);
     if (DENSE) {
-      constexpr int kRow = kSlots * kSlotStride;
       if (t0) atomicAdd(&a.acc[kAccCnt * kRow + slot], (unsigned long long)t0);
       if (t1) atomicAdd(&a.acc[kAccAffEdges * kRow + slot], (unsigned long long)t1);
-      if (t2) atomicAdd(&a.acc[kAccXEdges * kRow + slot], (unsigned long long)t2);
       if (t3) atomicAdd(&a.acc[kAccStayEdges * kRow + slot], (unsigned long long)t3);
     }
   }
@@ -1461,15 +1465,23 @@ static int pull_parts(dfpr_graph* g, const PullArgs& a, hipStream_t s, dfpr_stat
 //    is set or an in-neighbour expanded (read from the in-neighbours' expand
 //    flags, so no marks are written); ranks and contributions ping-pong.
 // The affected sets, the per-vertex sums (same bins, same order) and so the
-// ranks are identical; dense is chosen while the frontier's in-edges exceed
-// dense_switch * |E|, where scanning everything beats scattered marking,
-// unless the frontier holds under 1/kDenseVertexShare of the vertices and
-// its out-edges (what the frontier form marks) are under a quarter of its
-// in-edges: the dense form visits every vertex and scans the in-neighbour
-// flags of every vertex it does not keep, which a frontier of a few vertices
-// with many in-edges and few out-edges (a temporal graph's hubs) does not
-// repay.
-constexpr int64_t kDenseVertexShare = 16;
+// ranks are identical.  The forms differ in how the expansion of an iteration
+// reaches the next one, and that is what the choice weighs: the frontier form
+// pushes a mark along every out-edge of the expanding vertices (a scattered
+// byte store each), the dense form makes every vertex it does not keep scan
+// its in-neighbours' expand flags (a gathered byte each, |E| minus the
+// in-edges of the affected set) and carries every vertex over (about one
+// gathered edge's time per vertex).  An iteration runs dense when
+//     |E| - (in-edges of the affected set) + |V| < w * (out-edges to mark),
+// w = dense_switch: 0 never dense, infinity always; the default 1 prices a
+// pushed mark like a scanned flag, which measurement on large R-MAT graphs
+// supports.  The out-edges to mark are those of the last iteration's
+// expanding vertices (counted in its pull), the best predictor of the next
+// ones; before the first iteration, those of the initially marked vertices.
+static bool prefer_dense(double w, int64_t m, int32_t n, int64_t aff_edges, int64_t mark_edges) {
+  if (std::isinf(w)) return true;
+  return (double)(m - aff_edges) + (double)n < w * (double)mark_edges;
+}
 template <int MODE>
 static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_prev, double* r_out, hipStream_t s,
                         dfpr_stats* st) {
@@ -1526,24 +1538,20 @@ static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_pre
   DFPR_TRY(bin_vertices(g, g->flag_cur, g->worklist, g->ever, s));
   DFPR_TRY(finish_and_read(g, s));
   uint8_t *cur = g->flag_cur, *next = g->flag_next, *xa = g->xflag, *xb = g->xflag2;
-  const double switch_edges = p.dense_switch * (double)m;
-  bool need_bins = false;  // dense -> frontier: the frontier must be marked and binned first
   bool dense = false, use_x = false;
-  int64_t front_edges = 0, front_cnt = 0, front_out = 0;
+  int64_t front_edges = 0, front_cnt = 0;
+  int64_t mark_edges = g->ctl_host->bin_out_edges;  // before the first pull: out-edges of the marked vertices
   {
     const int64_t* h = g->ctl_host->bin_edges;
     for (int k = 0; k < kBins; k++) front_edges += h[k];
     front_cnt = g->ctl_host->bin_end[kBins - 1];
-    front_out = g->ctl_host->bin_out_edges;
   }
   PullArgs a = make_args(g, p);
   int it = 0;
   double dR = 0.0;
   bool conv = false;
   for (it = 0; it < p.max_iters; it++) {
-    if (!dense && front_edges > switch_edges &&
-        (p.dense_switch == 0.0 || front_cnt * kDenseVertexShare >= n || front_out * 4 >= front_edges) &&
-        MODE != kSync) {
+    if (!dense && front_cnt > 0 && prefer_dense(p.dense_switch, m, n, front_edges, mark_edges)) {
       dense = true;  // the complete frontier is in `cur`; no expand flags to read
       use_x = false;
     }
@@ -1588,9 +1596,10 @@ static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_pre
         it++;
         break;
       }
-      // strict comparisons: dense_switch 0 keeps every iteration dense
-      if (front_edges < switch_edges / 2 ||
-          (p.dense_switch > 0.0 && h->dense_cnt * 2 * kDenseVertexShare < n && h->dense_xedges * 4 < front_edges)) {
+      // leave the dense form when pushing this iteration's marks costs less
+      // than scanning the flags of the vertices the next one will not keep
+      mark_edges = h->dense_xedges;
+      if (!prefer_dense(p.dense_switch, m, n, front_edges, mark_edges)) {
         // back to the frontier form: mark out(v) of this iteration's expanders
         // into the keep flags (clears xa), then bin
         k_mark_pending<<<gi, 256, 0, s>>>(xa, n, g->out.off, g->out.idx, cur, g->big_list, &g->ctl->big_count,
@@ -1601,15 +1610,12 @@ static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_pre
         DFPR_TRY(bin_vertices(g, cur, g->worklist, g->ever, s));
         DFPR_TRY(finish_and_read(g, s));
         dense = false;
-        need_bins = false;
         front_edges = 0;
         for (int k = 0; k < kBins; k++) front_edges += g->ctl_host->bin_edges[k];
         front_cnt = g->ctl_host->bin_end[kBins - 1];
-        front_out = g->ctl_host->bin_out_edges;
       }
       continue;
     }
-    (void)need_bins;
     int64_t be[kBins], bedges[kBins];
     std::copy(g->ctl_host->bin_end, g->ctl_host->bin_end + kBins, be);
     std::copy(g->ctl_host->bin_edges, g->ctl_host->bin_edges + kBins, bedges);
@@ -1645,7 +1651,7 @@ static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_pre
     front_edges = 0;
     for (int k = 0; k < kBins; k++) front_edges += g->ctl_host->bin_edges[k];
     front_cnt = g->ctl_host->bin_end[kBins - 1];
-    front_out = g->ctl_host->bin_out_edges;
+    mark_edges = g->ctl_host->dense_xedges;  // out-edges this iteration's expanders marked
     if (g->ctl_host->active == 0) {
       conv = true;
       it++;

@@ -37,7 +37,7 @@ def test_params_default(lib):
     p = _capi.Params()
     lib.dfpr_params_default(ctypes.byref(p))
     assert (p.alpha, p.tol, p.frontier_tol, p.prune_tol, p.max_iters, p.flags) == (0.85, 1e-10, 1e-6, 1e-6, 500, 0)
-    assert p.dense_switch == 0.4 and p.criterion == 0 and p.reserved == 0
+    assert p.dense_switch == 1.0 and p.criterion == 0 and p.reserved == 0
 
 
 def test_invalid_arguments_rejected_before_device_work(lib):

@@ -243,11 +243,12 @@ def test_dense_and_frontier_forms_agree(mode, frac):
     """The dense form (every vertex reads its in-neighbours' expand flags) and the
     frontier form (marks pushed to out-neighbours) give bit-identical ranks and
     frontier statistics, and both match the oracle; the default switches between
-    them as the frontier grows and shrinks."""
+    them by the cost rule (dense_switch: infinity always dense, 0 never)."""
     torch = torch_cuda()
     p, r0 = _setup(13, frac, seed=91)
     outs = {}
-    for sw in (0.0, 0.4, 2.0):
+    inf = float("inf")
+    for sw in (inf, 1.0, 0.0):
         p2 = Pair(p.n, p.og_prev.esrc, p.og_prev.edst)
         p2.apply(p.batch.dm_src, p.batch.dm_dst, p.batch.dp_src, p.batch.dp_dst)
         r, st, ref = p2.rank(mode, r0, dense_switch=sw)
@@ -255,17 +256,18 @@ def test_dense_and_frontier_forms_agree(mode, frac):
         assert np.abs(r - ref.ranks).max() <= LINF
         assert abs(st["iterations"] - ref.iterations) <= 1
     for key in ("iterations", "ever_affected", "vertex_updates", "edges_pulled"):
-        assert outs[0.0][1][key] == outs[0.4][1][key] == outs[2.0][1][key], key
-    assert outs[0.0][1]["dense_iterations"] == outs[0.0][1]["iterations"]
-    assert outs[2.0][1]["dense_iterations"] == 0
-    assert np.array_equal(outs[0.0][0], outs[2.0][0]) and np.array_equal(outs[0.4][0], outs[2.0][0])
+        assert outs[inf][1][key] == outs[1.0][1][key] == outs[0.0][1][key], key
+    assert outs[inf][1]["dense_iterations"] == outs[inf][1]["iterations"]
+    assert outs[0.0][1]["dense_iterations"] == 0
+    assert np.array_equal(outs[inf][0], outs[0.0][0]) and np.array_equal(outs[1.0][0], outs[0.0][0])
 
 
 @pytest.mark.parametrize("mode", ["df", "dfp"])
 def test_hub_frontier_stays_in_frontier_form(mode):
     """A preferential-attachment graph whose batch reaches a few hubs (many
     in-edges, few out-edges): the default keeps such a frontier in the frontier
-    form although its in-edges pass the dense share; forcing the dense form
+    form (its expanding vertices have few out-edges to mark, while the dense
+    form would scan the flags of almost every in-edge); forcing the dense form
     gives the same bits and statistics, and both match the oracle."""
     torch_cuda()
     n = 20000
@@ -273,7 +275,8 @@ def test_hub_frontier_stays_in_frontier_form(mode):
     k0 = 360000
     s0, d0 = W.dedupe(n, src[:k0], dst[:k0])
     outs = {}
-    for sw in (0.4, 0.0):
+    inf = float("inf")
+    for sw in (1.0, inf):
         p = Pair(n, s0, d0)
         r0 = O.rank("static", p.og).ranks
         p.apply([], [], src[k0:k0 + 400], dst[k0:k0 + 400])
@@ -281,13 +284,13 @@ def test_hub_frontier_stays_in_frontier_form(mode):
         assert np.abs(r - ref.ranks).max() <= LINF
         assert st["ever_affected"] == ref.ever_affected
         outs[sw] = (r, st)
-    _print(f"hub frontier {mode}: dense iterations {outs[0.4][1]['dense_iterations']} of "
-           f"{outs[0.4][1]['iterations']} (default), edges pulled {outs[0.4][1]['edges_pulled']}")
-    assert outs[0.4][1]["dense_iterations"] < outs[0.4][1]["iterations"]
-    assert outs[0.0][1]["dense_iterations"] == outs[0.0][1]["iterations"]
+    _print(f"hub frontier {mode}: dense iterations {outs[1.0][1]['dense_iterations']} of "
+           f"{outs[1.0][1]['iterations']} (default), edges pulled {outs[1.0][1]['edges_pulled']}")
+    assert outs[1.0][1]["dense_iterations"] < outs[1.0][1]["iterations"]
+    assert outs[inf][1]["dense_iterations"] == outs[inf][1]["iterations"]
     for key in ("iterations", "ever_affected", "vertex_updates", "edges_pulled"):
-        assert outs[0.4][1][key] == outs[0.0][1][key], key
-    assert np.array_equal(outs[0.4][0], outs[0.0][0])
+        assert outs[1.0][1][key] == outs[inf][1][key], key
+    assert np.array_equal(outs[1.0][0], outs[inf][0])
 
 
 @pytest.mark.parametrize("mode", ["static", "nd", "df", "dfp"])
@@ -312,13 +315,13 @@ def test_all_bins(mode, bounds):
     p, r0 = _setup(12, 1e-2, seed=31)
     p.g.set_tuning(bounds)
     assert p.g.get_tuning() == bounds
-    r, st, ref = p.rank(mode, r0, dense_switch=2.0)  # frontier form: the worklist bins are used
+    r, st, ref = p.rank(mode, r0, dense_switch=0.0)  # frontier form: the worklist bins are used
     assert np.abs(r - ref.ranks).max() <= LINF
     assert st["bin_vertices"][5] > 0 and st["bin_vertices"][3] > 0
     if mode != "static":
         p, r0 = _setup(12, 1e-2, seed=31)  # the update consumed the batch marks: same batch again
         p.g.set_tuning(bounds)
-        r2, st2, _ = p.rank(mode, r0, dense_switch=0.0)  # dense form over the all-vertex bins
+        r2, st2, _ = p.rank(mode, r0, dense_switch=float("inf"))  # dense form over the all-vertex bins
         assert np.array_equal(r, r2) and st2["dense_iterations"] == st2["iterations"]
 
 

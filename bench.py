@@ -189,15 +189,16 @@ def pct(a, q):
     return float(np.percentile(np.asarray(a, dtype=np.float64), q))
 
 
-def batched_members(count, seed):
+def batched_members(count, seed, n_lo=1e3, n_hi=1e6):
     """Member graphs of the batched configuration: vertex counts log-uniform in
-    [1e3, 1e6], edge factor uniform in [8, 32], R-MAT draws at scale
-    ceil(log2 n) with endpoints >= n redrawn, duplicates and self draws dropped."""
+    [n_lo, n_hi] (default [1e3, 1e6]), edge factor uniform in [8, 32], R-MAT
+    draws at scale ceil(log2 n) with endpoints >= n redrawn, duplicates and
+    self draws dropped."""
     import workloads as W
     rng = np.random.Generator(np.random.PCG64(seed))
     out = []
     for k in range(count):
-        n = int(round(np.exp(rng.uniform(np.log(1e3), np.log(1e6)))))
+        n = int(round(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi)))))
         ef = float(rng.uniform(8, 32))
         scale = int(np.ceil(np.log2(n)))
         fr = float(np.exp(rng.uniform(np.log(1e-4), np.log(1e-2))))
@@ -216,7 +217,8 @@ def bench_batched(args):
 
     dev = torch.device("cuda:0")
     t0 = time.time()
-    mem = batched_members(args.graphs, args.seed)
+    n_lo, n_hi = (float(x) for x in args.member_n.split(","))
+    mem = batched_members(args.graphs, args.seed, n_lo, n_hi)
     total_steps = args.warmup + args.steps
     chains = []
     for k, (n, s, d, fr) in enumerate(mem):
@@ -230,6 +232,8 @@ def bench_batched(args):
     t0 = time.time()
     dmem = [(n, torch.from_numpy(s).to(dev), torch.from_numpy(d).to(dev)) for n, s, d, _ in mem]
     bg = dfpr.BatchGraph.from_coo(dmem)
+    if args.batch_loop:
+        bg.set_fused_limit(0)  # launch per iteration instead of the single launch
     plain = [dfpr.Graph.from_coo(n, s, d) for n, s, d in dmem]
     del dmem
     torch.cuda.synchronize()
@@ -315,10 +319,13 @@ def bench_batched(args):
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"{G} R-MAT graphs, n log-uniform in [1e3, 1e6], edge factor U[8, 32], one chained "
+        "config": {"workload": f"{G} R-MAT graphs, n log-uniform in [{n_lo:g}, {n_hi:g}], edge factor U[8, 32], one chained "
                                f"80/20 batch of f*|E| per graph per step, f log-uniform in [1e-4, 1e-2]; apply + "
                                f"{args.mode.upper()} update of every graph per step",
                    "graphs": G, "m_total": int(m_total), "mode": args.mode, "parallelism": "1 GPU",
+                   # the library's default single-launch limit for batch arenas is 2^26 edges
+                   "batch_update": "launch per iteration" if args.batch_loop or m_total > (1 << 26)
+                   else "single launch",
                    "bin_bounds": bg.get_tuning()},
         "graph_edges_per_s": m_total * K / tb_s,
         "batch_edges_per_s": delta_edges / tb_s,
@@ -793,6 +800,9 @@ def main():
     ap.add_argument("--serving-scale-offset", type=int, default=0,
                     help="serving: subtract this from every graph scale (smaller runs)")
     ap.add_argument("--graphs", type=int, default=512, help="batched: number of member graphs")
+    ap.add_argument("--member-n", default="1e3,1e6", help="batched: range of member vertex counts (log-uniform)")
+    ap.add_argument("--batch-loop", action="store_true",
+                    help="batched: run the batch handle's updates with a launch per iteration (default: one launch)")
     ap.add_argument("--gather-graph", default="rmat", choices=["rmat", "temporal"],
                     help="gather: the R-MAT graph of --scale or the temporal workload's initial graph")
     ap.add_argument("--summarize", metavar="DIR",

@@ -233,8 +233,10 @@ int dfpr_autotune(dfpr_graph* g, void* stream, int32_t bounds_out[5], double* ms
  * (DF/DF-P in the dense form), a grid-wide barrier, and the stopping test on
  * the device, instead of several launches and a readback per iteration.  The
  * results are the same bits either way (same kernels, same work split); only
- * the latency changes.  Default 4194304; 0 disables.  Batch handles always use
- * the launch-per-iteration loop.  Errors: EINVAL (max_edges < 0). */
+ * the latency changes.  Default 4194304; 0 disables.  On a batch handle the
+ * limit applies to the arena (default 67108864): each member converges and
+ * drops out on its own inside the launch (a second grid barrier per iteration
+ * folds the members' changes).  Errors: EINVAL (max_edges < 0). */
 int dfpr_set_fused_limit(dfpr_graph* g, int64_t max_edges);
 
 /* Turn HIP-event timing of every apply and update on this graph on (1) or

@@ -182,8 +182,10 @@ struct IterCtl {
   int64_t fused_err;  // grid barrier gave up waiting (never expected)
   int64_t pad[1];
   unsigned long long acc_slots[kAccRows][kSlots * kSlotStride];
-  // single-launch loop: L-inf change of iteration i in fused_dr[(i % 3) * kSlotStride]
+  // single-launch loop: L-inf change of iteration i in fused_dr[(i % 3) * kSlotStride];
+  // batches: members still running after iteration i in fused_act[(i % 3) * kSlotStride]
   unsigned long long fused_dr[3 * kSlotStride];
+  unsigned long long fused_act[3 * kSlotStride];
   // grid barrier of the single-launch loop: 32 group counters, a root counter
   // and a generation, each on its own 128-byte line
   unsigned bar_leaf[32 * 32];
@@ -198,6 +200,10 @@ constexpr int kMarkChunk = 1024;   // out-edges per workgroup work item
 constexpr int kBigRow = 1024;      // out-rows longer than this go to the chunked marking
 constexpr int kGSub = 8;           // spread slots per member graph for its L-inf reduction
 constexpr int64_t kPartVertices = (int64_t)8 << 20;  // 64 MB of contributions per batch part
+// Default single-launch limit of batch handles (arena edges).  Many small
+// members gain most from it; on large arenas the launch-per-iteration loop is
+// faster (frontier-form iterations, twice the occupancy of the pull).
+constexpr int64_t kFusedBatchEdges = (int64_t)1 << 26;
 
 }  // namespace dfpr
 
@@ -274,7 +280,11 @@ struct dfpr_graph {
   int32_t* arrive = nullptr;  // n: per-vertex chunk arrival counters of bin 5
   int32_t* partial_x = nullptr;  // per-chunk "an in-neighbour expanded" flags (dense mode)
   bool timing = false;        // record HIP-event timings of every call
-  int64_t fused_limit = 1 << 22;  // run whole updates in one launch up to this many edges (0: never)
+  int64_t fused_limit = 1 << 22;  // run whole updates in one launch up to this many edges (0: never);
+                                  // batch handles: kFusedBatchEdges by default
+  void* fused_parts = nullptr;    // device: one pull layout per part for the single-launch loop (batches)
+  void* fused_parts_host = nullptr;  // pinned mirror of the part table last copied
+  bool fused_parts_stale = true;
   dfpr::EventPool pool;
   // vertex-proportional scratch of apply and rank updates, carved from one block
   void* scratch = nullptr;

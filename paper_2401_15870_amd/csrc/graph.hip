@@ -787,7 +787,12 @@ __global__ void k_finish_apply(const int32_t* noff, int32_t n, int64_t* counters
 // ------------------------------------------------------------------ host
 // Chunk partial sums of the pull's chunked bin: at most one chunk per vertex
 // plus one per kPullChunk edges of the capacity.
-static int64_t partial_entries(int32_t n, int64_t cap) { return (int64_t)n + 1 + cap / kPullChunk; }
+// Chunk partial sums of the long-row bin: at most |bin| + its edges / chunk per
+// pull; the single-launch loop gives every part its own range (one spare entry
+// per part, parts are at least kPartVertices vertices apart but for the last).
+static int64_t partial_entries(int32_t n, int64_t cap) {
+  return (int64_t)n + 1 + cap / kPullChunk + (int64_t)n / kPartVertices + 2;
+}
 
 // Carve the scratch arrays from `base` (nullptr: only measure).  The arrays
 // that must start at zero come first, so one clear covers them; returns the
@@ -964,6 +969,10 @@ int graph_destroy(dfpr_graph* g) {
   dfree(g->g_eff);
   if (g->g_host) (void)hipHostFree(g->g_host);
   g->g_host = nullptr;
+  if (g->fused_parts) (void)hipFree(g->fused_parts);
+  g->fused_parts = nullptr;
+  if (g->fused_parts_host) (void)hipHostFree(g->fused_parts_host);
+  g->fused_parts_host = nullptr;
   g->keys_a.release();
   g->keys_b.release();
   g->keys_c.release();
@@ -1542,6 +1551,7 @@ int batch_create(int32_t count, const int32_t* n, const int64_t* m, const int32_
   }
   if (rc == DFPR_OK)
     rc = graph_create((int32_t)vb[count], mt, coo, coo + mt, DFPR_DEVICE, 0, flags, s, out, &vb);
+  if (rc == DFPR_OK) (*out)->fused_limit = kFusedBatchEdges;
   dfree(coo);
   return rc;
 }

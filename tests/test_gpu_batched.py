@@ -36,10 +36,14 @@ def _member_csr(off, idx, base, n):
 class Batched:
     """A batch handle, a plain handle per member and an oracle graph per member."""
 
-    def __init__(self, members, keep_ids=False):
+    def __init__(self, members, keep_ids=False, fused=True):
+        """fused=False runs the batch handle's updates on the launch-per-iteration
+        loop instead of its default single launch (both give the same bits)."""
         m = dfpr()
         self.members = members
         self.bg = m.BatchGraph.from_coo(members, keep_ids=keep_ids)
+        if not fused:
+            self.bg.set_fused_limit(0)
         self.plain = [m.Graph.from_coo(n, s, d, keep_ids=keep_ids) for n, s, d in members]
         self.og = [O.graph(n, s, d) for n, s, d in members]
         self.og_prev = [None] * len(members)
@@ -106,10 +110,11 @@ class Batched:
         return results, tot, per
 
 
+@pytest.mark.parametrize("fused", [True, False])
 @pytest.mark.parametrize("keep_ids", [False, True])
-def test_batched_create_csr_and_static(keep_ids):
+def test_batched_create_csr_and_static(keep_ids, fused):
     torch_cuda()
-    b = Batched(_members(1), keep_ids=keep_ids)
+    b = Batched(_members(1), keep_ids=keep_ids, fused=fused)
     _print("batched create", [m[0] for m in b.members])
     assert b.bg.count == len(b.members)
     assert b.bg.sizes == [m[0] for m in b.members]
@@ -120,12 +125,13 @@ def test_batched_create_csr_and_static(keep_ids):
     assert len(set(its)) > 1  # members really converge at different iterations
 
 
+@pytest.mark.parametrize("fused", [True, False])
 @pytest.mark.parametrize("keep_ids", [False, True])
 @pytest.mark.parametrize("mode", ["nd", "df", "dfp"])
-def test_batched_update_matches_plain(mode, keep_ids):
+def test_batched_update_matches_plain(mode, keep_ids, fused):
     torch_cuda()
     members = _members(2)
-    b = Batched(members, keep_ids=keep_ids)
+    b = Batched(members, keep_ids=keep_ids, fused=fused)
     r0 = [O.rank("static", og).ranks for og in b.og]
     rng = np.random.default_rng(5)
     batches = []
@@ -146,7 +152,7 @@ def test_batched_update_matches_plain(mode, keep_ids):
 def test_batched_dense_and_frontier_forms(dense_switch):
     torch_cuda()
     members = _members(3)
-    b = Batched(members)
+    b = Batched(members, fused=False)  # the per-iteration loop, where the two forms are chosen
     r0 = [O.rank("static", og).ranks for og in b.og]
     batches = [W.batch_8020(n, s, d, 1e-2, seed=200 + k) if len(s) else (np.zeros(0, np.int32),) * 4
                for k, (n, s, d) in enumerate(members)]

@@ -161,3 +161,44 @@ def test_fullsize_batched_members():
         worst = max(worst, err)
         assert err <= LINF, (k, err)
     _print(f"  batched members vs oracle: worst linf {worst:.3e} over {len(members)} members")
+
+
+def test_batched_multipart_single_launch():
+    """A batch whose arena spans two pull parts (parts hold whole members of
+    about 8M vertices), updated in its default single launch, where the parts'
+    pulls run concurrently: each part keeps its own chunk partial sums and
+    arrival counters.  Small thresholds put long rows of every part in the
+    chunked bin.  Every member bit-identical to its plain handle (launch per
+    iteration at this size), and within the parity bar of the oracle."""
+    torch = torch_cuda()
+    m = dfpr()
+    members = [W.rmat_graph(22, 6, seed=9700 + k) for k in range(3)]
+    bounds = [4, 16, 128, 1024, 4096]
+    bg = m.BatchGraph.from_coo(members)
+    bg.set_fused_limit(1 << 40)  # the single launch at any arena size
+    bg.set_tuning(bounds)
+    plain = [m.Graph.from_coo(n, s, d) for n, s, d in members]
+    for g in plain:
+        g.set_tuning(bounds)
+    _print("multipart batch: members", [n for n, _, _ in members], "edges", bg.m)
+    r, _, _ = bg.update_ranks_many("static", None)
+    r_prev = r.clone()
+    for k, g in enumerate(plain):
+        rk, _ = g.update_ranks("static", None)
+        assert torch.equal(bg.member(r, k), rk), ("static", k)
+    batches = [W.batch_8020(n, s, d, 1e-4, seed=9800 + k) for k, (n, s, d) in enumerate(members)]
+    bg.apply_batch_many(batches)
+    r, tot, per = bg.update_ranks_many("dfp", r_prev)
+    torch.cuda.synchronize()
+    for k, g in enumerate(plain):
+        g.apply_batch(*batches[k])
+        rk, st = g.update_ranks("dfp", bg.member(r_prev, k).clone())
+        assert torch.equal(bg.member(r, k), rk), ("dfp", k, float((bg.member(r, k) - rk).abs().max()))
+        assert per[k]["iterations"] == st["iterations"]
+    n, s, d = members[0]
+    og = O.graph(n, s, d)
+    og2, ob = O.apply(og, *batches[0])
+    ref = O.rank("dfp", og2, bg.member(r_prev, 0).cpu().numpy(), og, ob)
+    err = float(np.abs(bg.member(r, 0).cpu().numpy() - ref.ranks).max())
+    _print(f"  member 0 vs oracle: linf {err:.3e}")
+    assert err <= LINF

@@ -796,7 +796,8 @@ def main():
     ap.add_argument("--rates", default="100,1000,10000", help="serving: Poisson arrival rates per second")
     ap.add_argument("--requests", type=int, default=1000, help="serving: requests per rate and server setting")
     ap.add_argument("--lanes", type=int, default=4, help="serving: request lanes")
-    ap.add_argument("--heap-gb", type=float, default=24.0, help="serving: scratch heap (GiB)")
+    ap.add_argument("--heap-gb", type=float, default=64.0,
+                    help="serving: device heap (GiB) for the graphs' CSRs and the requests' blocks")
     ap.add_argument("--serving-scale-offset", type=int, default=0,
                     help="serving: subtract this from every graph scale (smaller runs)")
     ap.add_argument("--graphs", type=int, default=512, help="batched: number of member graphs")

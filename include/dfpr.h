@@ -310,13 +310,18 @@ int dfpr_update_ranks_many(dfpr_graph* g, dfpr_mode mode, const dfpr_params* p, 
  * a time in submission order (a single writer per graph, Section 3.2);
  * requests for different graphs run concurrently on `lanes` worker lanes, each
  * with its own HIP stream, so their kernels overlap on the device.  A request
- * is admitted when a lane is free, its graph is idle and its scratch (the
- * vertex arrays of one update plus its batch sort buffers) can be taken from
- * the server's scratch heap of `heap_bytes`, reserved once at create; requests
- * that do not fit wait (later ones do not overtake them), so a small heap
- * serialises work instead of failing it.  A request whose scratch exceeds the
- * whole heap fails with ENOMEM.  Results are those of the plain entry points:
- * a graph's ranks do not depend on what else is in flight. */
+ * is admitted when a lane is free, its graph is idle and its blocks (the
+ * vertex arrays of one update, its batch sort buffers and the targets into
+ * which both CSRs are rebuilt) can be taken from the server's device heap of
+ * `heap_bytes`, reserved once at create.  The heap also holds every graph's
+ * current CSRs: a request's rebuild targets become the graph's CSRs and the
+ * old ones go back to the heap, so the heap bounds all graph memory but the
+ * rank vectors.  Requests that do not fit wait (later ones do not overtake
+ * them), so a small heap serialises work instead of failing it.  A request
+ * whose blocks exceed what the heap can ever free fails with ENOMEM.
+ * Single-launch updates of different lanes share the device's budget of
+ * resident workgroups.  Results are those of the plain entry points: a
+ * graph's ranks do not depend on what else is in flight. */
 typedef struct dfpr_server dfpr_server;
 
 typedef struct {
@@ -339,10 +344,11 @@ int dfpr_server_destroy(dfpr_server* sv);
 
 /* Move a plain graph handle into the server (on success the caller must not
  * use or destroy g any more) and give it resident ranks: a copy
- * of r0 (device, n doubles) or, with r0 = NULL, a Static solve.  The handle's
- * own scratch is released: from now on each request borrows scratch from the
- * heap.  On error the handle still belongs to the caller.  Errors: EINVAL
- * (batch handle), ENOMEM, EHIP. */
+ * of r0 (device, n doubles) or, with r0 = NULL, a Static solve.  Its CSRs
+ * move into the heap; its rebuild targets and scratch are released: from now
+ * on each request borrows them from the heap.  On error the handle still
+ * belongs to the caller.  Errors: EINVAL (batch handle), ENOMEM (the heap
+ * cannot hold the graph's CSRs), EHIP. */
 int dfpr_server_add_graph(dfpr_server* sv, dfpr_graph* g, const double* r0, int32_t* gid);
 
 /* Queue a request: one batch (host arrays, copied before return; ids in

@@ -59,6 +59,10 @@ class Heap {
   size_t used();
   size_t peak();
   size_t largest_free();
+  char* base() const { return base_; }
+  // Record that the taken blocks are exactly `lens` bytes each, packed from
+  // offset 0 in this order (after the caller moved their contents there).
+  void repack(const std::vector<size_t>& lens);
 
  private:
   std::mutex mu_;
@@ -234,6 +238,10 @@ struct dfpr_graph {
   double* rint = nullptr;   // n: ranks in internal order (when relabelled)
   dfpr::Csr out, in;        // current canonical CSRs
   dfpr::Csr out2, in2;      // rebuild targets (swapped in after a batch)
+  // A served graph keeps its CSRs in the server's heap: out and in share one
+  // block (csr_block) and the rebuild targets are lent per request.
+  dfpr::Heap* csr_heap = nullptr;
+  void* csr_block = nullptr;
   // rank scratch (n entries each)
   double* contrib = nullptr;   // R[u]/|out(u)| of the current iterate
   double* contrib2 = nullptr;  // ping-pong partner for Static/ND
@@ -282,6 +290,7 @@ struct dfpr_graph {
   bool timing = false;        // record HIP-event timings of every call
   int64_t fused_limit = 1 << 22;  // run whole updates in one launch up to this many edges (0: never);
                                   // batch handles: kFusedBatchEdges by default
+  int32_t fused_share = 1;        // a single-launch loop takes 1/fused_share of the device's budget
   void* fused_parts = nullptr;    // device: one pull layout per part for the single-launch loop (batches)
   void* fused_parts_host = nullptr;  // pinned mirror of the part table last copied
   bool fused_parts_stale = true;
@@ -330,6 +339,15 @@ int attach_scratch(dfpr_graph* g, void* block, size_t bytes, hipStream_t s);
 void detach_scratch(dfpr_graph* g);
 // Device bytes an apply of nk batch pairs takes from its growable buffers.
 size_t apply_buffer_bytes(int64_t nk, bool host_input);
+// One block holding an out-CSR and an in-CSR of n rows and cap edges: its
+// size, and the four arrays carved from it.
+size_t csr_pair_bytes(int32_t n, int64_t cap);
+void carve_csr_pair(void* block, int32_t n, int64_t cap, Csr* out, Csr* in);
+// Served graphs: move the CSRs into one block of `heap` (the rebuild targets
+// are released; requests lend them), or make room for cap edges in the chunk
+// partial sums before a request whose insertions raise the capacity.
+int move_csrs_to_heap(dfpr_graph* g, Heap* heap, hipStream_t s);
+int ensure_partials(dfpr_graph* g, int64_t cap);
 int graph_export(const dfpr_graph* g, int in_csr, int32_t* off, int32_t* idx, dfpr_where where,
                  hipStream_t s);
 int graph_apply(dfpr_graph* g, int64_t n_del, const int32_t* del_src, const int32_t* del_dst,

@@ -943,9 +943,57 @@ static void free_csr(Csr* c) {
   dfree(c->idx);
 }
 
+size_t csr_pair_bytes(int32_t n, int64_t cap) {
+  auto r = [](size_t x) { return (x + Heap::kAlign - 1) / Heap::kAlign * Heap::kAlign; };
+  return 2 * (r(((size_t)n + 1) * sizeof(int32_t)) + r((size_t)std::max<int64_t>(cap, 1) * sizeof(int32_t)));
+}
+void carve_csr_pair(void* block, int32_t n, int64_t cap, Csr* out, Csr* in) {
+  auto r = [](size_t x) { return (x + Heap::kAlign - 1) / Heap::kAlign * Heap::kAlign; };
+  const size_t bo = r(((size_t)n + 1) * sizeof(int32_t)), bi = r((size_t)std::max<int64_t>(cap, 1) * sizeof(int32_t));
+  char* p = static_cast<char*>(block);
+  out->off = reinterpret_cast<int32_t*>(p);
+  out->idx = reinterpret_cast<int32_t*>(p + bo);
+  in->off = reinterpret_cast<int32_t*>(p + bo + bi);
+  in->idx = reinterpret_cast<int32_t*>(p + 2 * bo + bi);
+}
+
+int move_csrs_to_heap(dfpr_graph* g, Heap* heap, hipStream_t s) {
+  void* block = heap->alloc(csr_pair_bytes(g->n, g->cap));
+  if (!block) {
+    set_error("the server heap cannot hold the graph's CSRs (%zu bytes)", csr_pair_bytes(g->n, g->cap));
+    return DFPR_ENOMEM;
+  }
+  Csr out, in;
+  carve_csr_pair(block, g->n, g->cap, &out, &in);
+  const size_t ob = ((size_t)g->n + 1) * sizeof(int32_t), eb = (size_t)g->m * sizeof(int32_t);
+  if (hipMemcpyAsync(out.off, g->out.off, ob, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(in.off, g->in.off, ob, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+      (eb && hipMemcpyAsync(out.idx, g->out.idx, eb, hipMemcpyDeviceToDevice, s) != hipSuccess) ||
+      (eb && hipMemcpyAsync(in.idx, g->in.idx, eb, hipMemcpyDeviceToDevice, s) != hipSuccess) ||
+      hipStreamSynchronize(s) != hipSuccess) {
+    heap->free(block);
+    set_error("copy of the graph's CSRs into the server heap failed");
+    return DFPR_EHIP;
+  }
+  free_csr(&g->out);
+  free_csr(&g->in);
+  free_csr(&g->out2);
+  free_csr(&g->in2);
+  g->out = out;
+  g->in = in;
+  g->csr_heap = heap;
+  g->csr_block = block;
+  return DFPR_OK;
+}
+
 int graph_destroy(dfpr_graph* g) {
   if (!g) return DFPR_OK;
   (void)hipDeviceSynchronize();
+  if (g->csr_heap) {  // served: one heap block; the rebuild targets belong to requests
+    g->csr_heap->free(g->csr_block);
+    g->csr_block = nullptr;
+    g->out = g->in = g->out2 = g->in2 = Csr();
+  }
   free_csr(&g->out);
   free_csr(&g->in);
   free_csr(&g->out2);
@@ -1187,7 +1235,23 @@ int graph_export(const dfpr_graph* g, int in_csr, int32_t* off, int32_t* idx, df
 }
 
 // Grow the edge capacity of all four index arrays to at least `want`.
+int ensure_partials(dfpr_graph* g, int64_t cap) {
+  const int64_t pn = partial_entries(g->n, cap);
+  if (pn > g->partial_n) {
+    dfree(g->partial);
+    dfree(g->partial_x);
+    DFPR_TRY(dalloc(&g->partial, (size_t)pn));
+    DFPR_TRY(dalloc(&g->partial_x, (size_t)pn));
+    g->partial_n = pn;
+  }
+  return DFPR_OK;
+}
+
 static int grow_capacity(dfpr_graph* g, int64_t want, hipStream_t s) {
+  if (g->csr_heap) {  // a served graph's rebuild targets, sized by the server, hold the batch
+    set_error("internal: a served graph's capacity is raised by its request");
+    return DFPR_EHIP;
+  }
   int64_t cap = std::min<int64_t>(std::max<int64_t>(want + want / 4, g->cap), INT32_MAX);
   DFPR_HIP(hipStreamSynchronize(s));
   for (Csr* c : {&g->out, &g->in, &g->out2, &g->in2}) {
@@ -1200,15 +1264,7 @@ static int grow_capacity(dfpr_graph* g, int64_t want, hipStream_t s) {
     c->idx = p;
   }
   g->cap = cap;
-  const int64_t pn = partial_entries(g->n, cap);
-  if (pn > g->partial_n) {
-    dfree(g->partial);
-    dfree(g->partial_x);
-    DFPR_TRY(dalloc(&g->partial, (size_t)pn));
-    DFPR_TRY(dalloc(&g->partial_x, (size_t)pn));
-    g->partial_n = pn;
-  }
-  return DFPR_OK;
+  return ensure_partials(g, cap);
 }
 
 // One CSR.  Few effective entries (at most one per 256 edges): runs between

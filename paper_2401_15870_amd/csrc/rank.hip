@@ -19,6 +19,7 @@
 // and no reduction funnels the whole chip into one atomic address.
 #include <algorithm>
 #include <cmath>
+#include <condition_variable>
 #include <mutex>
 
 #include "prim.hpp"
@@ -1415,6 +1416,46 @@ static int fused_resident() {
   return resident;
 }
 
+// Resident-workgroup budget of single-launch loops on one device.  Its
+// capacity is the resident grid of the most demanding single-launch kernel
+// (the fewest workgroups per compute unit), and every loop is charged one
+// unit per workgroup: loops whose grids fit the capacity together can all be
+// resident at once, whichever kernels they run.
+struct FusedBudget {
+  std::mutex mu;
+  std::condition_variable cv;
+  int64_t capacity = 0, free = 0;
+  struct Hold {
+    FusedBudget& b;
+    int64_t n;
+    Hold(FusedBudget& bb, int64_t nn) : b(bb), n(nn) {
+      std::unique_lock<std::mutex> lk(b.mu);
+      b.cv.wait(lk, [&] { return b.free >= n; });
+      b.free -= n;
+    }
+    ~Hold() {
+      {
+        std::lock_guard<std::mutex> lk(b.mu);
+        b.free += n;
+      }
+      b.cv.notify_all();
+    }
+  };
+};
+static FusedBudget& fused_budget(int dev) {
+  static FusedBudget budgets[64];
+  static std::once_flag once[64];
+  FusedBudget& b = budgets[dev & 63];
+  std::call_once(once[dev & 63], [&] {
+    const int r[] = {fused_resident<kSync, false>(), fused_resident<kDF, false>(), fused_resident<kDFP, false>(),
+                     fused_resident<kSync, true>(),  fused_resident<kDF, true>(),  fused_resident<kDFP, true>()};
+    int64_t c = r[0];
+    for (int x : r) c = std::min<int64_t>(c, x);
+    b.capacity = b.free = c;
+  });
+  return b;
+}
+
 // r_out: the final ranks in the caller's order (through g->inv when the graph
 // is renumbered), written by the kernel's epilogue.
 template <int MODE>
@@ -1471,11 +1512,16 @@ static int fused_run(dfpr_graph* g, const dfpr_params& p, PullArgs a, hipStream_
   }
   const bool batch = g->ngraphs > 1;
   const int resident = batch ? fused_resident<MODE, true>() : fused_resident<MODE, false>();
-  if (resident < 1) {
+  FusedBudget& budget = fused_budget(g->device);
+  if (resident < 1 || budget.capacity < 1) {
     set_error("occupancy query for the single-launch loop failed");
     return DFPR_EHIP;
   }
-  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(resident, total));
+  // the loop's share of the device: all of it alone, 1/fused_share of the
+  // budget when the caller runs several updates side by side (serving lanes)
+  int64_t cap = std::min<int64_t>(resident, budget.capacity);
+  if (g->fused_share > 1) cap = std::max<int64_t>(1, cap / g->fused_share);
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(cap, total));
   const FusedPart* parts = static_cast<const FusedPart*>(g->fused_parts);
   const int32_t* wl0 = fp[0].wl;  // a plain graph's one part, passed by value
   PullLayout L0 = fp[0].L;
@@ -1492,12 +1538,13 @@ static int fused_run(dfpr_graph* g, const dfpr_params& p, PullArgs a, hipStream_
   double* gdr = g->g_dr;
   int32_t* git = g->g_iters;
   void* args[] = {&a, &wl0, &L0, &parts, &nparts, &c, &mi, &tol, &r_out, &inv, &nv, &G, &gdr, &git};
-  // One single-launch loop at a time in the process: its grid barrier needs
-  // all its workgroups resident, which two such kernels on concurrent streams
-  // (say, the serving form's lanes) could not both have.  Held until the loop
-  // has finished on the device.
-  static std::mutex fused_mu;
-  std::lock_guard<std::mutex> fused_lk(fused_mu);
+  // The grid barrier needs all of the loop's workgroups resident at once.
+  // Loops on concurrent streams (the serving form's lanes) therefore draw
+  // their grids from the device's budget of resident workgroups and wait
+  // while it cannot hold them; the grids are held until the loop has
+  // finished on the device.  Ordinary kernels on other streams only delay a
+  // loop: their workgroups finish and free their slots.
+  FusedBudget::Hold hold(budget, grid);
   size_t tok;
   DFPR_TRY(g->pool.start(&tok));
   const void* fn = batch ? reinterpret_cast<const void*>(&k_fused_loop<MODE, true>)

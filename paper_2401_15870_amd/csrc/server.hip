@@ -104,6 +104,18 @@ size_t Heap::peak() {
   std::lock_guard<std::mutex> lk(mu_);
   return peak_;
 }
+void Heap::repack(const std::vector<size_t>& lens) {
+  std::lock_guard<std::mutex> lk(mu_);
+  free_.clear();
+  taken_.clear();
+  size_t off = 0;
+  for (size_t len : lens) {
+    taken_[off] = len;
+    off += len;
+  }
+  used_ = off;
+  if (off < cap_) free_[off] = cap_ - off;
+}
 size_t Heap::largest_free() {
   std::lock_guard<std::mutex> lk(mu_);
   size_t m = 0;
@@ -126,6 +138,9 @@ struct Request {
   size_t apply_bytes = 0;               // batch sort buffers of this request
   void* scratch = nullptr;              // vertex scratch, taken from the heap at admission
   void* apply_block = nullptr;          // sort buffers, taken from the heap at admission
+  void* targets = nullptr;              // rebuild targets (both CSRs), taken from the heap at admission;
+                                        // they hold the graph after the apply
+  int64_t target_cap = 0;               // their edge capacity
   int rc = DFPR_OK;
   std::string err;
   bool done = false;
@@ -170,17 +185,62 @@ namespace {
 // scratch does not fit stops the scan (later requests do not overtake it).
 // When nothing is in flight and it still does not fit, it never will: it is
 // returned with its blocks unset and fails with ENOMEM.
+// Idle server (no request in flight, so the only taken blocks are the graphs'
+// CSR blocks): slide every CSR block down to the lowest free address, in
+// address order, so that the free space is one range.  A block moves to a
+// lower address by chunks no longer than the distance it moves, so no chunk's
+// source overlaps its destination.  Returns false if a device copy failed.
+bool compact(dfpr_server* sv) {
+  std::vector<Resident*> res;
+  for (auto& r : sv->graphs) res.push_back(&r);
+  std::sort(res.begin(), res.end(), [](const Resident* a, const Resident* b) { return a->g->csr_block < b->g->csr_block; });
+  hipStream_t s = sv->ctl_stream;
+  std::vector<size_t> lens;
+  char* cursor = sv->heap.base();
+  for (Resident* r : res) {
+    dfpr_graph* g = r->g;
+    const size_t len = (csr_pair_bytes(g->n, g->cap) + Heap::kAlign - 1) / Heap::kAlign * Heap::kAlign;
+    char* src = static_cast<char*>(g->csr_block);
+    if (src != cursor) {
+      const size_t step = (size_t)(src - cursor);
+      for (size_t done = 0; done < len; done += step)
+        if (hipMemcpyAsync(cursor + done, src + done, std::min(step, len - done), hipMemcpyDeviceToDevice, s) !=
+            hipSuccess)
+          return false;
+      g->csr_block = cursor;
+      carve_csr_pair(cursor, g->n, g->cap, &g->out, &g->in);
+    }
+    lens.push_back(len);
+    cursor += len;
+  }
+  if (hipStreamSynchronize(s) != hipSuccess) return false;
+  sv->heap.repack(lens);
+  return true;
+}
+
+// Its blocks: the vertex scratch, the batch sort buffers and the rebuild
+// targets, sized for the graph's edges plus the batch's insertions.
 Request* pick(dfpr_server* sv) {
   for (auto it = sv->queue.begin(); it != sv->queue.end(); ++it) {
     Request* q = *it;
     Resident& r = sv->graphs[q->gid];
     if (r.busy) continue;
-    q->scratch = sv->heap.alloc(r.scratch);
-    q->apply_block = q->scratch ? sv->heap.alloc(q->apply_bytes) : nullptr;
-    if (!q->apply_block) {
+    const dfpr_graph* g = r.g;  // idle: no request changes it meanwhile
+    const int64_t need = g->m + (int64_t)q->is.size();
+    q->target_cap = need <= g->cap ? g->cap : std::min<int64_t>(need + need / 4, INT32_MAX);
+    for (int attempt = 0; attempt < 2; attempt++) {
+      q->scratch = sv->heap.alloc(r.scratch);
+      q->apply_block = q->scratch ? sv->heap.alloc(q->apply_bytes) : nullptr;
+      q->targets = q->apply_block ? sv->heap.alloc(csr_pair_bytes(g->n, q->target_cap)) : nullptr;
+      if (q->targets) break;
+      sv->heap.free(q->apply_block);
       sv->heap.free(q->scratch);
-      q->scratch = nullptr;
-      if (sv->in_flight > 0) return nullptr;
+      q->scratch = q->apply_block = nullptr;
+      if (sv->in_flight > 0) return nullptr;  // wait for running requests to free their blocks
+      // nothing runs: the free space is all there will be; gather it in one
+      // range (the heap fragments as requests' targets replace CSR blocks)
+      // and try once more
+      if (attempt == 0 && !compact(sv)) break;
     }
     sv->queue.erase(it);
     return q;
@@ -205,9 +265,28 @@ int serve(dfpr_server* sv, Request* q, hipStream_t s) {
   sub.init_at(q->apply_block, q->apply_bytes);
   for (auto b : kApplyBufs) (g->*b).heap = &sub;
   int rc = attach_scratch(g, q->scratch, r.scratch, s);
+  // the CSRs are rebuilt into the request's target block, which then holds
+  // the graph; the block of the old CSRs goes back to the heap
+  const int32_t* old_off = g->out.off;
+  const int64_t old_cap = g->cap;
+  carve_csr_pair(q->targets, g->n, q->target_cap, &g->out2, &g->in2);
+  if (rc == DFPR_OK && q->target_cap > g->cap) {
+    rc = ensure_partials(g, q->target_cap);
+    g->cap = q->target_cap;
+  }
+  g->fused_share = sv->active_lanes;  // single-launch loops share the device between lanes
   if (rc == DFPR_OK)
     rc = graph_apply(g, (int64_t)q->ds.size(), q->ds.data(), q->dd.data(), (int64_t)q->is.size(), q->is.data(),
                      q->id.data(), DFPR_HOST, s, &q->info);
+  if (g->out.off != old_off) {  // swapped in (a finished apply always swaps)
+    (void)hipStreamSynchronize(s);  // nothing reads the old block any more
+    sv->heap.free(g->csr_block);
+    g->csr_block = q->targets;
+    q->targets = nullptr;
+  } else {
+    g->cap = old_cap;
+  }
+  g->out2 = g->in2 = Csr();
   if (rc == DFPR_OK) rc = update_ranks(g, sv->mode, sv->params, r.R, r.R, s, &q->st);
   if (rc == DFPR_OK && q->r_out) {
     if (hipMemcpyAsync(q->r_out, r.R, (size_t)g->n * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -250,7 +329,8 @@ void lane_main(dfpr_server* sv, int lane) {
     q->done = true;
     sv->heap.free(q->apply_block);
     sv->heap.free(q->scratch);
-    q->apply_block = q->scratch = nullptr;
+    sv->heap.free(q->targets);  // unless the graph took them
+    q->apply_block = q->scratch = q->targets = nullptr;
     r.busy = false;
     sv->in_flight--;
     sv->counters.completed++;
@@ -322,9 +402,17 @@ int server_add_graph(dfpr_server* sv, dfpr_graph* g, const double* r0, int32_t* 
     } else {
       rc = update_ranks(g, DFPR_STATIC, sv->params, nullptr, R, s, nullptr);  // with the handle's own scratch
     }
-    if (rc == DFPR_OK && hipStreamSynchronize(s) != hipSuccess) rc = DFPR_EHIP;
+    if (rc == DFPR_OK && hipStreamSynchronize(s) != hipSuccess) {
+      set_error("resident rank initialisation failed");
+      rc = DFPR_EHIP;
+    }
+    // from now on the CSRs live in the heap and every request borrows its
+    // rebuild targets, vertex scratch and sort buffers from it
     if (rc == DFPR_OK) {
-      // from now on scratch is lent per request by the server heap
+      std::lock_guard<std::mutex> lk(sv->mu);  // the heap's layout changes only under the server lock
+      rc = move_csrs_to_heap(g, &sv->heap, s);
+    }
+    if (rc == DFPR_OK) {
       if (g->scratch_owned && g->scratch) (void)hipFree(g->scratch);
       g->scratch_owned = false;
       detach_scratch(g);
@@ -333,7 +421,6 @@ int server_add_graph(dfpr_server* sv, dfpr_graph* g, const double* r0, int32_t* 
   }
   if (rc != DFPR_OK) {
     (void)hipFree(R);
-    if (rc == DFPR_EHIP) set_error("resident rank initialisation failed");
     return rc;
   }
   std::lock_guard<std::mutex> lk(sv->mu);

@@ -564,8 +564,13 @@ def bench_sweep(args):
     k0 = int(0.9 * len(src))
     B = max(1, int(round(args.sweep_batch * len(src))))
     log(f"sweep: temporal stream n={n} edges={len(src)} initial {k0}, batches of {B} ({time.time() - t0:.0f}s)")
-    configs = [("relative", tf) for tf in (1e-1, 1e-2, 1e-3, 1e-4, 1e-5, 1e-6)]
-    configs += [(c, tf) for c in ("absolute", "contrib") for tf in (1e-10, 1e-11, 1e-12, 1e-13, 1e-14, 1e-15)]
+    # (measure, tau_f, tau_p): the frontier measures with tau_p = tau_f (Section 4.2), then the
+    # prune tolerance from tau_f down to tau_f / 1e4 at tau_f = 1e-6, 1e-7, 1e-8 (Section 4.3)
+    configs = [("relative", tf, tf) for tf in (1e-1, 1e-2, 1e-3, 1e-4, 1e-5, 1e-6)]
+    configs += [(c, tf, tf) for c in ("absolute", "contrib") for tf in (1e-10, 1e-11, 1e-12, 1e-13, 1e-14, 1e-15)]
+    if args.sweep_prune:
+        configs += [("relative", tf, tf / 10 ** k) for tf in (1e-6, 1e-7, 1e-8) for k in range(0, 5)
+                    if not (tf == 1e-6 and k == 0)]
     s0, d0 = torch.from_numpy(src[:k0]).to(dev), torch.from_numpy(dst[:k0]).to(dev)
     ref_g = dfpr.Graph.from_coo(n, s0, d0)
     static_g = dfpr.Graph.from_coo(n, s0, d0)
@@ -583,9 +588,9 @@ def bench_sweep(args):
         rs, st = static_g.update_ranks("static", None, timing=True)
         st_ms.append(st["ms_total"])
         st_err.append(float((rs - r_ref).abs().sum()))
-        for i, (crit, tf) in enumerate(configs):
+        for i, (crit, tf, tp) in enumerate(configs):
             r, st = handles[i].update_ranks("dfp", ranks[i], out=ranks[i], timing=True, criterion=crit,
-                                            frontier_tol=tf, prune_tol=tf)
+                                            frontier_tol=tf, prune_tol=tp)
             rows[i]["ms"].append(st["ms_total"])
             rows[i]["err"].append(float((r - r_ref).abs().sum()))
             rows[i]["it"].append(st["iterations"])
@@ -593,19 +598,20 @@ def bench_sweep(args):
         log(f"batch {b}: static {st_ms[-1]:.2f} ms L1 {st_err[-1]:.2e}")
     static_mean = float(np.mean(st_ms))
     table = []
-    for i, (crit, tf) in enumerate(configs):
+    for i, (crit, tf, tp) in enumerate(configs):
         ms = float(np.mean(rows[i]["ms"]))
-        table.append({"criterion": crit, "tau_f": tf, "tau_p": tf, "ms_mean": ms, "speedup_vs_static": static_mean / ms,
+        table.append({"criterion": crit, "tau_f": tf, "tau_p": tp, "ms_mean": ms, "speedup_vs_static": static_mean / ms,
                       "l1_error_mean": float(np.mean(rows[i]["err"])), "iterations_mean": float(np.mean(rows[i]["it"])),
                       "ever_affected_mean": float(np.mean(rows[i]["ever"]))})
-        log(f"{crit:9s} tau_f {tf:7.0e}: {ms:7.2f} ms  x{static_mean / ms:5.1f}  L1 {table[-1]['l1_error_mean']:.2e}")
+        log(f"{crit:9s} tau_f {tf:7.0e} tau_p {tp:7.0e}: {ms:7.2f} ms  x{static_mean / ms:5.1f}  "
+            f"L1 {table[-1]['l1_error_mean']:.2e}")
     res = {"metric": "DF-P update time and L1 rank error per frontier measure and tolerance",
            "value": max(t["speedup_vs_static"] for t in table if t["l1_error_mean"] <= float(np.mean(st_err))),
            "unit": "speedup vs Static at no more error than Static", "n_gpus": 1, "steps": args.steps, "warmup": 0,
            "higher_is_better": True, "dtype": "f64", "data": "synthetic",
            "config": {"workload": f"temporal stream, {n} vertices, {len(src)} edges, initial 90 %, insertion-only "
-                                  f"batches of {B} edges ({args.sweep_batch:g} of the stream) in time order; DF-P with "
-                                  "tau_p = tau_f; error = L1 against Static run to 500 iterations",
+                                  f"batches of {B} edges ({args.sweep_batch:g} of the stream) in time order; DF-P; "
+                                  "error = L1 against Static run to 500 iterations",
                       "parallelism": "1 GPU"},
            "static": {"ms_mean": static_mean, "l1_error_mean": float(np.mean(st_err))},
            "table": table}
@@ -788,6 +794,8 @@ def main():
     ap.add_argument("--calib", action="store_true",
                     help="finish with three 1 GiB device copies (counter calibration under a profiler)")
     ap.add_argument("--sweep-batch", type=float, default=1e-5, help="sweep: batch size as a fraction of the stream")
+    ap.add_argument("--sweep-prune", action="store_true",
+                    help="sweep: also vary tau_p from tau_f to tau_f/1e4 at tau_f = 1e-6, 1e-7, 1e-8")
     ap.add_argument("--workload", default="rmat", choices=["rmat", "batched", "serving", "sweep", "gather", "temporal"],
                     help="rmat: one large R-MAT graph (default); batched: many graphs in one batch handle; "
                          "serving: request loop over resident graphs; sweep: frontier measures and tolerances; "

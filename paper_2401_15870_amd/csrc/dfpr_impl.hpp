@@ -242,6 +242,11 @@ struct dfpr_graph {
   // block (csr_block) and the rebuild targets are lent per request.
   dfpr::Heap* csr_heap = nullptr;
   void* csr_block = nullptr;
+  // True degrees |out(v)| and |in(v)| (self-loop included).  Row v of a CSR
+  // holds its degree's worth of neighbours from off[v] on; any further entries
+  // up to off[v+1] are slack.
+  int32_t* out_deg = nullptr;
+  int32_t* in_deg = nullptr;
   // rank scratch (n entries each)
   double* contrib = nullptr;   // R[u]/|out(u)| of the current iterate
   double* contrib2 = nullptr;  // ping-pong partner for Static/ND

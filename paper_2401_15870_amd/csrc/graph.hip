@@ -164,10 +164,41 @@ __global__ void k_member_eff(const uint64_t* eff, const int64_t* count, int b, c
     }
   }
 }
-// Edge count of every member after a batch (its rows of the union out-CSR).
-__global__ void k_member_m(const int32_t* out_off, const int64_t* vbase, int32_t G, int64_t* m_out) {
-  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < G; k += (int64_t)gridDim.x * blockDim.x)
-    m_out[k] = (int64_t)out_off[vbase[k + 1]] - out_off[vbase[k]];
+// Edge count of every member after a batch: the sum of its vertices' out-degrees
+// (a workgroup per member).
+__global__ void __launch_bounds__(256) k_member_m(const int32_t* out_deg, const int64_t* vbase, int32_t G,
+                                                  int64_t* m_out) {
+  __shared__ int64_t sh[256 / kWave];
+  for (int64_t k = blockIdx.x; k < G; k += gridDim.x) {
+    int64_t t = 0;
+    for (int64_t v = vbase[k] + threadIdx.x; v < vbase[k + 1]; v += blockDim.x) t += out_deg[v];
+    t = wave_sum_i64(t);
+    if (lane_id() == 0) sh[threadIdx.x / kWave] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) m_out[k] = sh[0] + sh[1] + sh[2] + sh[3];
+    __syncthreads();
+  }
+}
+// Degrees of a CSR without slack: deg[v] = off[v+1] - off[v].
+__global__ void k_deg_from_off(const int32_t* off, int32_t n, int32_t* deg) {
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+    deg[v] = off[v + 1] - off[v];
+}
+// Degrees after an accepted batch: every effective insertion (u, v) adds one to
+// |out(u)| and |in(v)|, every effective deletion takes one off.  Nothing
+// changes when the batch was rejected (err set).
+__global__ void k_update_degrees(const uint64_t* eff, const int64_t* count, int b, const int64_t* err,
+                                 int32_t* out_deg, int32_t* in_deg) {
+  if (*err) return;
+  const uint64_t mask = (1ull << b) - 1;
+  const int64_t t = *count;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < t; i += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t k = eff[i];
+    const int32_t u = (int32_t)(k >> (b + 1)), v = (int32_t)((k >> 1) & mask);
+    const int32_t d = (k & 1ull) ? 1 : -1;
+    atomicAdd(&out_deg[u], d);
+    atomicAdd(&in_deg[v], d);
+  }
 }
 // Member-local batch ids -> union ids, with validation against the member size.
 __global__ void k_offset_ids(const int32_t* a, const int32_t* b, int64_t cnt, int32_t nmem, int64_t base, int32_t* oa,
@@ -1019,6 +1050,8 @@ int graph_destroy(dfpr_graph* g) {
   g->g_host = nullptr;
   if (g->fused_parts) (void)hipFree(g->fused_parts);
   g->fused_parts = nullptr;
+  dfree(g->out_deg);
+  dfree(g->in_deg);
   if (g->fused_parts_host) (void)hipHostFree(g->fused_parts_host);
   g->fused_parts_host = nullptr;
   g->keys_a.release();
@@ -1184,6 +1217,9 @@ int graph_create(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, d
     // in-CSR: transpose the keys and sort again
     k_transpose_keys<<<grid_for(mu, 256, 65536), 256, 0, s>>>(t.kb, mu, b, t.ka);
     if ((rc = build_csr_from_keys(&t.ka, &t.kb, mu, b, n, &g->in, t.hist, t.tmp, s))) return fail(rc);
+    if ((rc = dalloc(&g->out_deg, n)) || (rc = dalloc(&g->in_deg, n))) return fail(rc);
+    k_deg_from_off<<<grid_for(n, 256, 65536), 256, 0, s>>>(g->out.off, n, g->out_deg);
+    k_deg_from_off<<<grid_for(n, 256, 65536), 256, 0, s>>>(g->in.off, n, g->in_deg);
     if ((rc = alloc_rank_scratch(g))) return fail(rc);
     if (hipStreamSynchronize(s) != hipSuccess) {
       set_error("graph creation failed on the device");
@@ -1434,6 +1470,7 @@ int graph_apply(dfpr_graph* g, int64_t nd, const int32_t* del_src, const int32_t
                                                           g->touched_out, g->touched_in);
     k_finish_apply<<<1, 1, 0, s>>>(g->out2.off, n, counters);
   }
+  k_update_degrees<<<grid_for(nk, 256, 65536), 256, 0, s>>>(eff_out, cnt, b, counters + 4, g->out_deg, g->in_deg);
   DFPR_HIP(hipGetLastError());
   DFPR_HIP(hipMemcpyAsync(g->ctl_host->n_apply, counters, 6 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
   DFPR_TRY(ep.stop(kTTotal, t_total));
@@ -1669,7 +1706,7 @@ int batch_apply(dfpr_graph* g, const int64_t* n_del, const int32_t* const* del_s
     // per member: effective counts (set by the apply), edges after, ignored self-loop deletions
     std::vector<int64_t> eff(4 * (size_t)G, 0);
     if (G > 1) {
-      k_member_m<<<grid_for(G, 256, 64), 256, 0, s>>>(g->out.off, g->vbase_d, G, g->g_eff + 2 * (size_t)G);
+      k_member_m<<<(unsigned)std::min<int64_t>(G, 1024), 256, 0, s>>>(g->out_deg, g->vbase_d, G, g->g_eff + 2 * (size_t)G);
       DFPR_HIP(hipGetLastError());
       DFPR_HIP(hipMemcpyAsync(eff.data(), g->g_eff, eff.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s));
       DFPR_HIP(hipStreamSynchronize(s));

@@ -31,7 +31,8 @@ enum : int { kSync = 0, kDF = 2, kDFP = 3 };  // kSync = Static and ND (Equation
 struct PullArgs {
   const int32_t* __restrict__ in_off;
   const int32_t* __restrict__ in_idx;
-  const int32_t* __restrict__ out_off;
+  const int32_t* __restrict__ in_deg;   // row v of the in-CSR: in_idx[in_off[v], in_off[v] + in_deg[v])
+  const int32_t* __restrict__ out_deg;  // |out(v)|
   const double* __restrict__ contrib;
   double* R;       // ranks of this iteration (frontier DF/DF-P: written in place)
   double* Rw;      // Static/ND and dense DF/DF-P: ranks of the next iteration
@@ -82,8 +83,8 @@ __device__ __forceinline__ VCtx load_vertex(const PullArgs& a, int32_t v) {
   c.v = v;
   c.g = a.gid ? a.gid[v] : 0;
   c.s = a.in_off[v];
-  c.e = a.in_off[v + 1];
-  c.d = (double)(a.out_off[v + 1] - a.out_off[v]);
+  c.e = c.s + a.in_deg[v];
+  c.d = (double)a.out_deg[v];
   c.Rv = a.R[v];
   c.selfc = c.Rv / c.d;
   return c;
@@ -821,6 +822,7 @@ __device__ __forceinline__ void wave_mark_rows(bool want, int32_t v, int32_t os,
 // sweeps more than a few hundred edges.
 constexpr int32_t kPendBigRow = 128;
 __global__ void __launch_bounds__(256) k_mark_pending(uint8_t* pend_src, int32_t n, const int32_t* __restrict__ out_off,
+                                                      const int32_t* __restrict__ out_deg,
                                                       const int32_t* __restrict__ out_idx, uint8_t* flags,
                                                       int32_t* big_list, int64_t* big_count, int32_t big_row) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -832,7 +834,7 @@ __global__ void __launch_bounds__(256) k_mark_pending(uint8_t* pend_src, int32_t
       pend_src[u] = 0;
       want = true;
       os = out_off[u];
-      oe = out_off[u + 1];
+      oe = os + out_deg[u];
     }
     wave_mark_rows(want, (int32_t)u, os, oe, out_idx, flags, big_list, big_count, big_row);
   }
@@ -842,6 +844,7 @@ __global__ void __launch_bounds__(256) k_mark_pending(uint8_t* pend_src, int32_t
 // vertices, clear their current flag, and expand out(v) where flagged.
 __global__ void __launch_bounds__(256) k_commit_expand(const int32_t* __restrict__ wl, int64_t cnt, const double* R,
                                                        double* contrib, const int32_t* __restrict__ out_off,
+                                                       const int32_t* __restrict__ out_deg,
                                                        const int32_t* __restrict__ out_idx, uint8_t* cur,
                                                        uint8_t* next, uint8_t* xflag, int32_t* big_list,
                                                        int64_t* big_count) {
@@ -853,7 +856,7 @@ __global__ void __launch_bounds__(256) k_commit_expand(const int32_t* __restrict
     if (k < cnt) {
       v = wl[k];
       os = out_off[v];
-      oe = out_off[v + 1];
+      oe = os + out_deg[v];
       contrib[v] = R[v] / (double)(oe - os);
       cur[v] = 0;
       if (xflag[v]) {
@@ -867,7 +870,7 @@ __global__ void __launch_bounds__(256) k_commit_expand(const int32_t* __restrict
 
 // Chunk prefix of the long out-row list (one workgroup; the list is short).
 __global__ void __launch_bounds__(1024) k_big_scan(const int32_t* big_list, const int64_t* big_count,
-                                                   const int32_t* out_off, int64_t* big_pre) {
+                                                   const int32_t* out_deg, int64_t* big_pre) {
   __shared__ int64_t sh[1024 / kWave + 1];
   const int64_t nb = *big_count;
   const int64_t per = (nb + 1023) / 1024;
@@ -876,20 +879,21 @@ __global__ void __launch_bounds__(1024) k_big_scan(const int32_t* big_list, cons
   int64_t local = 0;
   for (int64_t i = lo; i < hi; i++) {
     const int32_t v = big_list[i];
-    local += ((int64_t)(out_off[v + 1] - out_off[v]) + kMarkChunk - 1) / kMarkChunk;
+    local += ((int64_t)out_deg[v] + kMarkChunk - 1) / kMarkChunk;
   }
   int64_t tot;
   int64_t run = block_exclusive_scan(local, sh, &tot);
   for (int64_t i = lo; i < hi; i++) {
     big_pre[i] = run;
     const int32_t v = big_list[i];
-    run += ((int64_t)(out_off[v + 1] - out_off[v]) + kMarkChunk - 1) / kMarkChunk;
+    run += ((int64_t)out_deg[v] + kMarkChunk - 1) / kMarkChunk;
   }
   if (threadIdx.x == 0) big_pre[nb] = tot;
 }
 
 __global__ void __launch_bounds__(256) k_big_mark(const int32_t* big_list, const int64_t* big_count,
                                                   const int64_t* big_pre, const int32_t* __restrict__ out_off,
+                                                  const int32_t* __restrict__ out_deg,
                                                   const int32_t* __restrict__ out_idx, uint8_t* flags) {
   const int64_t nb = *big_count;
   const int64_t total = big_pre[nb];
@@ -897,7 +901,7 @@ __global__ void __launch_bounds__(256) k_big_mark(const int32_t* big_list, const
     const int64_t j = upper_bound_i64(big_pre, 0, nb + 1, q) - 1;
     const int32_t v = big_list[j];
     const int32_t s = out_off[v] + (int32_t)((q - big_pre[j]) * kMarkChunk);
-    const int32_t e = min(s + kMarkChunk, out_off[v + 1]);
+    const int32_t e = min(s + kMarkChunk, out_off[v] + out_deg[v]);
     for (int32_t p = s + (int32_t)threadIdx.x; p < e; p += 4 * (int32_t)blockDim.x) {
       int32_t w[4];
 #pragma unroll
@@ -948,8 +952,8 @@ __device__ __forceinline__ unsigned tile_flags(const uint8_t* flags, int64_t bas
 }
 
 // Vertices [lo, n) are binned (n: end of the range).
-__global__ void __launch_bounds__(256) k_bin_count(const uint8_t* flags, const int32_t* __restrict__ in_off,
-                                                   const int32_t* __restrict__ out_off, int64_t lo, int32_t n,
+__global__ void __launch_bounds__(256) k_bin_count(const uint8_t* flags, const int32_t* __restrict__ in_deg,
+                                                   const int32_t* __restrict__ out_deg, int64_t lo, int32_t n,
                                                    MemberMask mm, Bounds B, int64_t* blk, int64_t nb,
                                                    unsigned long long* acc) {
   __shared__ int64_t sh[256 / kWave + 1];
@@ -959,21 +963,21 @@ __global__ void __launch_bounds__(256) k_bin_count(const uint8_t* flags, const i
   int64_t p0 = 0, p1 = 0;
   int64_t ed[kBins + 1] = {0, 0, 0, 0, 0, 0, 0};  // per-bin in-degree sums, then the out-degree sum
   if (m) {
-    int32_t o[kBinItems + 1], q[kBinItems + 1];
+    int32_t o[kBinItems], q[kBinItems];
 #pragma unroll
-    for (int j = 0; j <= kBinItems; j++) {
-      o[j] = base + j <= n ? in_off[base + j] : 0;
-      q[j] = base + j <= n ? out_off[base + j] : 0;
+    for (int j = 0; j < kBinItems; j++) {
+      o[j] = base + j < n ? in_deg[base + j] : 0;
+      q[j] = base + j < n ? out_deg[base + j] : 0;
     }
 #pragma unroll
     for (int j = 0; j < kBinItems; j++) {
       if (m & (1u << j)) {
-        const int32_t d = o[j + 1] - o[j];
+        const int32_t d = o[j];
         const int b = bin_of(d, B);
         if (b < 3) p0 += (int64_t)1 << (kBinShift * b); else p1 += (int64_t)1 << (kBinShift * (b - 3));
 #pragma unroll
         for (int t = 0; t < kBins; t++) ed[t] += (t == b) ? d : 0;
-        ed[kBins] += q[j + 1] - q[j];
+        ed[kBins] += q[j];
       }
     }
   }
@@ -999,7 +1003,7 @@ __global__ void __launch_bounds__(256) k_bin_count(const uint8_t* flags, const i
   }
 }
 
-__global__ void __launch_bounds__(256) k_bin_scatter(const uint8_t* flags, const int32_t* __restrict__ in_off,
+__global__ void __launch_bounds__(256) k_bin_scatter(const uint8_t* flags, const int32_t* __restrict__ in_deg,
                                                      int64_t lo, int32_t n, MemberMask mm, Bounds B, const int64_t* offs,
                                                      int64_t nb, int32_t* wl, uint8_t* ever, int64_t* bin_end) {
   __shared__ int64_t sh[256 / kWave + 1];
@@ -1010,13 +1014,13 @@ __global__ void __launch_bounds__(256) k_bin_scatter(const uint8_t* flags, const
 #pragma unroll
   for (int j = 0; j < kBinItems; j++) bins[j] = 0xFF;
   if (m) {
-    int32_t o[kBinItems + 1];
+    int32_t o[kBinItems];
 #pragma unroll
-    for (int j = 0; j <= kBinItems; j++) o[j] = base + j <= n ? in_off[base + j] : 0;
+    for (int j = 0; j < kBinItems; j++) o[j] = base + j < n ? in_deg[base + j] : 0;
 #pragma unroll
     for (int j = 0; j < kBinItems; j++) {
       if (m & (1u << j)) {
-        const int b = bin_of(o[j + 1] - o[j], B);
+        const int b = bin_of(o[j], B);
         bins[j] = (uint8_t)b;
         if (b < 3) p0 += (int64_t)1 << (kBinShift * b); else p1 += (int64_t)1 << (kBinShift * (b - 3));
       }
@@ -1147,29 +1151,29 @@ __global__ void k_reset_ctl(IterCtl* c) {
 
 // ---- small helpers
 // Uniform start 1/|V| (of the vertex's member graph in a batch).
-__global__ void k_init_static(double* R, double* contrib, const int32_t* __restrict__ out_off, int32_t n,
+__global__ void k_init_static(double* R, double* contrib, const int32_t* __restrict__ out_deg, int32_t n,
                               const int32_t* gid, const int32_t* nk) {
   for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
     const double r = 1.0 / (double)(gid ? nk[gid[v]] : n);
     R[v] = r;
-    contrib[v] = r / (double)(out_off[v + 1] - out_off[v]);
+    contrib[v] = r / (double)out_deg[v];
   }
 }
-__global__ void k_init_prev(const double* r_prev, double* R, double* contrib, const int32_t* __restrict__ out_off,
+__global__ void k_init_prev(const double* r_prev, double* R, double* contrib, const int32_t* __restrict__ out_deg,
                             int32_t n, int copy) {
   for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
     const double r = r_prev[v];
     if (copy) R[v] = r;
-    contrib[v] = r / (double)(out_off[v + 1] - out_off[v]);
+    contrib[v] = r / (double)out_deg[v];
   }
 }
 // Caller order <-> internal order of the rank vector.
 __global__ void k_gather_ranks(const double* r_ext, const int32_t* __restrict__ inv, double* R, double* contrib,
-                               const int32_t* __restrict__ out_off, int32_t n) {
+                               const int32_t* __restrict__ out_deg, int32_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const double r = r_ext[inv[i]];
     R[i] = r;
-    contrib[i] = r / (double)(out_off[i + 1] - out_off[i]);
+    contrib[i] = r / (double)out_deg[i];
   }
 }
 __global__ void k_scatter_ranks(const double* R, const int32_t* __restrict__ inv, double* r_ext, int32_t n) {
@@ -1265,10 +1269,10 @@ static int bin_vertices(dfpr_graph* g, const uint8_t* flags, int32_t* wl, uint8_
   const int64_t nb = std::max<int64_t>(1, (hi - lo + kBinTile - 1) / kBinTile);
   // the cached all-vertex bins (flags == null) never drop converged members
   const MemberMask mm{flags ? g->gidv : nullptr, flags ? g->done : nullptr};
-  k_bin_count<<<(unsigned)nb, 256, 0, s>>>(flags, g->in.off, g->out.off, lo, (int32_t)hi, mm, bounds_of(g), g->bin_blk,
+  k_bin_count<<<(unsigned)nb, 256, 0, s>>>(flags, g->in_deg, g->out_deg, lo, (int32_t)hi, mm, bounds_of(g), g->bin_blk,
                                            nb, &g->ctl->acc_slots[0][0]);
   DFPR_TRY(scan_i64(g->bin_blk, g->bin_blk, kBins * nb, g->scan_tmp, s));
-  k_bin_scatter<<<(unsigned)nb, 256, 0, s>>>(flags, g->in.off, lo, (int32_t)hi, mm, bounds_of(g), g->bin_blk, nb, wl,
+  k_bin_scatter<<<(unsigned)nb, 256, 0, s>>>(flags, g->in_deg, lo, (int32_t)hi, mm, bounds_of(g), g->bin_blk, nb, wl,
                                              ever, g->ctl->bin_end);
   DFPR_HIP(hipGetLastError());
   DFPR_TRY(g->pool.stop(kTBin, tok));
@@ -1292,8 +1296,9 @@ static int finish_and_read(dfpr_graph* g, hipStream_t s) {
 
 // Chunked marking of the rows collected in big_list.
 static int mark_big(dfpr_graph* g, uint8_t* flags, hipStream_t s) {
-  k_big_scan<<<1, 1024, 0, s>>>(g->big_list, &g->ctl->big_count, g->out.off, g->big_pre);
-  k_big_mark<<<1024, 256, 0, s>>>(g->big_list, &g->ctl->big_count, g->big_pre, g->out.off, g->out.idx, flags);
+  k_big_scan<<<1, 1024, 0, s>>>(g->big_list, &g->ctl->big_count, g->out_deg, g->big_pre);
+  k_big_mark<<<1024, 256, 0, s>>>(g->big_list, &g->ctl->big_count, g->big_pre, g->out.off, g->out_deg, g->out.idx,
+                                  flags);
   DFPR_HIP(hipGetLastError());
   return DFPR_OK;
 }
@@ -1321,11 +1326,11 @@ static bool make_layout(const int64_t* be, const int64_t* bedges, PullLayout* L)
 
 struct LoadChunks {
   const int32_t* wl;
-  const int32_t* in_off;
+  const int32_t* in_deg;
   int64_t lo;
   __device__ int64_t operator()(int64_t i) const {
     const int32_t v = wl[lo + i];
-    return ((int64_t)(in_off[v + 1] - in_off[v]) + kPullChunk - 1) / kPullChunk;
+    return ((int64_t)in_deg[v] + kPullChunk - 1) / kPullChunk;
   }
 };
 struct StoreChunk {
@@ -1344,7 +1349,7 @@ static int pull_all(dfpr_graph* g, PullArgs a, const int32_t* wl, const int64_t*
   DFPR_TRY(g->pool.start(&tok));
   const int64_t n5 = L.hi[kBins - 1] - L.lo[kBins - 1];
   if (n5 > 0 && !chunk_ready)
-    DFPR_TRY(scan_generic(LoadChunks{wl, g->in.off, L.lo[kBins - 1]}, StoreChunk{chunk_pre}, n5, g->scan_tmp, s));
+    DFPR_TRY(scan_generic(LoadChunks{wl, g->in_deg, L.lo[kBins - 1]}, StoreChunk{chunk_pre}, n5, g->scan_tmp, s));
   a.chunk_pre = chunk_pre;
   k_pull<MODE, DENSE><<<(unsigned)L.blk[kBins], 256, 0, s>>>(a, wl, L);
   DFPR_HIP(hipGetLastError());
@@ -1363,8 +1368,9 @@ static void add_bins(dfpr_stats* st, const int64_t* be, const int64_t* bedges) {
 static PullArgs make_args(dfpr_graph* g, const dfpr_params& p) {
   PullArgs a{};
   a.in_off = g->in.off;
+  a.in_deg = g->in_deg;
+  a.out_deg = g->out_deg;
   a.in_idx = g->in.idx;
-  a.out_off = g->out.off;
   a.gslots = g->gslots;
   a.gsub = g->gsub;
   a.gid = g->gidv;
@@ -1484,7 +1490,7 @@ static int fused_run(dfpr_graph* g, const dfpr_params& p, PullArgs a, hipStream_
       return DFPR_EHIP;
     }
     if (n5 > 0 && !g->all_chunks_valid)
-      DFPR_TRY(scan_generic(LoadChunks{fp[k].wl, g->in.off, fp[k].L.lo[kBins - 1]}, StoreChunk{pre}, n5, g->scan_tmp,
+      DFPR_TRY(scan_generic(LoadChunks{fp[k].wl, g->in_deg, fp[k].L.lo[kBins - 1]}, StoreChunk{pre}, n5, g->scan_tmp,
                             s));
     total += fp[k].L.blk[kBins];
   }
@@ -1577,11 +1583,11 @@ static int run_sync(dfpr_graph* g, bool cold, const dfpr_params& p, const double
   const unsigned gi = grid_for(n, 256, 2048);
   double* R0 = g->perm ? g->rint : r_out;  // ranks in internal order
   if (cold)
-    k_init_static<<<gi, 256, 0, s>>>(R0, g->contrib, g->out.off, n, g->gidv, g->nk);
+    k_init_static<<<gi, 256, 0, s>>>(R0, g->contrib, g->out_deg, n, g->gidv, g->nk);
   else if (g->perm)
-    k_gather_ranks<<<gi, 256, 0, s>>>(r_prev, g->inv, R0, g->contrib, g->out.off, n);
+    k_gather_ranks<<<gi, 256, 0, s>>>(r_prev, g->inv, R0, g->contrib, g->out_deg, n);
   else
-    k_init_prev<<<gi, 256, 0, s>>>(r_prev, r_out, g->contrib, g->out.off, n, r_prev != r_out);
+    k_init_prev<<<gi, 256, 0, s>>>(r_prev, r_out, g->contrib, g->out_deg, n, r_prev != r_out);
   DFPR_HIP(hipGetLastError());
   double *Ra = R0, *Rb = g->rn, *ca = g->contrib, *cb = g->contrib2;
   PullArgs a = make_args(g, p);
@@ -1710,13 +1716,13 @@ static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_pre
   double* ca = g->contrib;
   double* cb = g->contrib2;
   if (g->perm)
-    k_gather_ranks<<<gi, 256, 0, s>>>(r_prev, g->inv, Ra, ca, g->out.off, n);
+    k_gather_ranks<<<gi, 256, 0, s>>>(r_prev, g->inv, Ra, ca, g->out_deg, n);
   else
-    k_init_prev<<<gi, 256, 0, s>>>(r_prev, r_out, ca, g->out.off, n, r_prev != r_out);
+    k_init_prev<<<gi, 256, 0, s>>>(r_prev, r_out, ca, g->out_deg, n, r_prev != r_out);
   // initial marking: out(u) of pending sources (+ deletion targets already in flag_cur)
   size_t tok;
   DFPR_TRY(g->pool.start(&tok));
-  k_mark_pending<<<gi, 256, 0, s>>>(g->pend_src, n, g->out.off, g->out.idx, g->flag_cur, g->big_list,
+  k_mark_pending<<<gi, 256, 0, s>>>(g->pend_src, n, g->out.off, g->out_deg, g->out.idx, g->flag_cur, g->big_list,
                                     &g->ctl->big_count, kPendBigRow);
   DFPR_HIP(hipGetLastError());
   DFPR_TRY(mark_big(g, g->flag_cur, s));
@@ -1817,7 +1823,7 @@ static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_pre
       if (!prefer_dense(p.dense_switch, m, n, front_edges, mark_edges)) {
         // back to the frontier form: mark out(v) of this iteration's expanders
         // into the keep flags (clears xa), then bin
-        k_mark_pending<<<gi, 256, 0, s>>>(xa, n, g->out.off, g->out.idx, cur, g->big_list, &g->ctl->big_count,
+        k_mark_pending<<<gi, 256, 0, s>>>(xa, n, g->out.off, g->out_deg, g->out.idx, cur, g->big_list, &g->ctl->big_count,
                                           kBigRow);
         DFPR_HIP(hipGetLastError());
         DFPR_TRY(mark_big(g, cur, s));
@@ -1853,7 +1859,7 @@ static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_pre
     a.xflag = xa;
     DFPR_TRY(pull_all<MODE>(g, a, g->worklist, be, bedges, g->chunk_pre, false, s, st));
     DFPR_TRY(g->pool.start(&tok));
-    k_commit_expand<<<grid_for(cnt, 256, 2048), 256, 0, s>>>(g->worklist, cnt, Ra, ca, g->out.off, g->out.idx, cur,
+    k_commit_expand<<<grid_for(cnt, 256, 2048), 256, 0, s>>>(g->worklist, cnt, Ra, ca, g->out.off, g->out_deg, g->out.idx, cur,
                                                              next, xa, g->big_list, &g->ctl->big_count);
     DFPR_HIP(hipGetLastError());
     DFPR_TRY(mark_big(g, next, s));

@@ -481,7 +481,7 @@ def bench_temporal(args):
     log(f"temporal: n={n} stream={len(src)} initial {k0}, {steps} batches of {B} ({time.time() - t0:.0f}s)")
     s0, d0 = torch.from_numpy(src[:k0]).to(dev), torch.from_numpy(dst[:k0]).to(dev)
     modes = ("dfp", "df", "nd")
-    gs = {m: dfpr.Graph.from_coo(n, s0, d0) for m in modes + ("static",)}
+    gs = {m: dfpr.Graph.from_coo(n, s0, d0, row_slack=args.row_slack) for m in modes + ("static",)}
     if not args.no_autotune:
         bounds, _ = gs["dfp"].autotune()
         for m in modes + ("static",):
@@ -496,7 +496,7 @@ def bench_temporal(args):
         r_or = r0.cpu().numpy()
     ms = {m: [] for m in modes + ("static",)}
     it = {m: [] for m in modes + ("static",)}
-    apply_ms, ever, drift, m_after = [], [], [], 0
+    apply_ms, ever, drift, m_after, local_steps = [], [], [], 0, 0
     for b in range(steps):
         lo = k0 + b * B
         ins_s, ins_d = src[lo:lo + B], dst[lo:lo + B]
@@ -509,6 +509,7 @@ def bench_temporal(args):
             if m == "dfp":
                 apply_ms.append((time.perf_counter() - t) * 1e3)
                 m_after = info["m_after"]
+                local_steps += info["row_local"]
         for m in modes + ("static",):
             torch.cuda.synchronize()
             t = time.perf_counter()
@@ -538,7 +539,8 @@ def bench_temporal(args):
         "config": {"workload": f"temporal stream (preferential attachment, 10 % repeats), {n} vertices, "
                                f"first {k0} of {len(src)} edges as G0, chained insertion-only batches of {B} "
                                f"in time order; apply + DFP update per step",
-                   "n": n, "m0": int(m0), "parallelism": "1 GPU"},
+                   "n": n, "m0": int(m0), "parallelism": "1 GPU",
+                   **({"row_slack": args.row_slack, "row_local_steps": local_steps} if args.row_slack else {})},
         "p50_ms": pct(step, 50), "p99_ms": pct(step, 99), "apply_p50_ms": pct(apply_ms, 50),
         "update_p50_ms": {m: pct(ms[m], 50) for m in ms},
         "iterations_mean": {m: float(np.mean(it[m])) for m in it},
@@ -789,6 +791,8 @@ def main():
     ap.add_argument("--dense-switch", type=float, default=None,
                     help="DF/DF-P: frontier in-edge share above which an iteration runs in the dense form "
                          "(default: the library's)")
+    ap.add_argument("--row-slack", type=int, default=0,
+                    help="free slots after every CSR row: small batches then merge into the rows they touch")
     ap.add_argument("--static-runs", type=int, default=3)
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--calib", action="store_true",
@@ -857,10 +861,11 @@ def main():
     log(f"batches: {len(batches)} x (del {len(batches[0][0])}, ins {len(batches[0][2])})")
 
     t0 = time.time()
-    g = dfpr.Graph.from_coo(n, torch.from_numpy(src).to(dev), torch.from_numpy(dst).to(dev))
+    g = dfpr.Graph.from_coo(n, torch.from_numpy(src).to(dev), torch.from_numpy(dst).to(dev),
+                            row_slack=args.row_slack)
     m0 = g.m
     torch.cuda.synchronize()
-    log(f"create: m={m0} {time.time() - t0:.2f}s")
+    log(f"create: m={m0} row slack {args.row_slack} {time.time() - t0:.2f}s")
     dev_batches = [tuple(torch.from_numpy(a).to(dev) for a in b) for b in batches]
     if not args.no_autotune:
         t0 = time.time()
@@ -906,7 +911,7 @@ def main():
     # ---- steps
     rank_kw = {} if args.dense_switch is None else {"dense_switch": args.dense_switch}
     g.set_timing(True)
-    step_ms, apply_ms, rank_ms, iters, ever = [], [], [], [], []
+    step_ms, apply_ms, rank_ms, iters, ever, row_local = [], [], [], [], [], []
     kern = {"pull": 0.0, "commit": 0.0, "bin": 0.0, "mark": 0.0, "sort": 0.0, "rebuild_out": 0.0,
             "rebuild_in": 0.0}
     pull_launches, v_upd, e_pull, pull_bytes = 0, 0, 0, 0.0
@@ -937,6 +942,7 @@ def main():
             iters.append(st["iterations"])
             ever.append(st["ever_affected"])
             m_sum += info["m_after"]
+            row_local.append(info["row_local"])
             kern["pull"] += st["ms_pull"]
             pull_launches += st["pull_launches"]
             v_upd += st["vertex_updates"]
@@ -948,7 +954,8 @@ def main():
             kern["sort"] += info["ms_sort"]
             kern["rebuild_out"] += info["ms_rebuild"][0]
             kern["rebuild_in"] += info["ms_rebuild"][1]
-            log(f"step {i - args.warmup}: {step_ms[-1]:.2f} ms (apply {apply_ms[-1]:.2f}, rank {rank_ms[-1]:.2f}) "
+            log(f"step {i - args.warmup}: {step_ms[-1]:.2f} ms (apply {apply_ms[-1]:.2f}"
+                f"{' row-local' if info['row_local'] else ''}, rank {rank_ms[-1]:.2f}) "
                 f"it={st['iterations']} dense={st['dense_iterations']} ever={st['ever_affected']} "
                 f"upd={st['vertex_updates']} pulled={st['edges_pulled']} pull {st['ms_pull']:.2f} "
                 f"commit {st['ms_commit']:.2f} bin {st['ms_bin']:.2f} mark {st['ms_mark']:.2f}")
@@ -1015,7 +1022,9 @@ def main():
                    "n": n, "m": int(m0), "batch_edges": int(len(batches[0][0]) + len(batches[0][2])),
                    "mode": args.mode + (" asynchronous" if args.asynchronous else ""), "parallelism": "1 GPU",
                    "bin_bounds": g.get_tuning(),
-                   **({"dense_switch": args.dense_switch} if args.dense_switch is not None else {})},
+                   **({"dense_switch": args.dense_switch} if args.dense_switch is not None else {}),
+                   **({"row_slack": args.row_slack, "row_local_steps": int(sum(row_local))}
+                      if args.row_slack else {})},
         "p50_ms": pct(step_ms, 50),
         "p99_ms": pct(step_ms, 99),
         "apply_p50_ms": pct(apply_ms, 50),

@@ -98,6 +98,9 @@ typedef struct {
   double ms_total;                 /* whole call on the stream                   */
   double ms_sort;                  /* radix sorts of the batch                   */
   double ms_rebuild[2];            /* out-CSR and in-CSR rebuild kernels         */
+  int32_t row_local;               /* 1: merged into the touched rows' free slots
+                                      (dfpr_set_row_slack), other rows unmoved   */
+  int32_t reserved;
 } dfpr_batch_info;
 
 /* Number of in-degree bins of the pull kernel (see dfpr_set_tuning). */
@@ -238,6 +241,22 @@ int dfpr_autotune(dfpr_graph* g, void* stream, int32_t bounds_out[5], double* ms
  * drops out on its own inside the launch (a second grid barrier per iteration
  * folds the members' changes).  Errors: EINVAL (max_edges < 0). */
 int dfpr_set_fused_limit(dfpr_graph* g, int64_t max_edges);
+
+/* Free slots after every CSR row, so that small batches (Section 3.2) change
+ * only the rows they touch.  Lays both CSRs out again with `slack` free slots
+ * after the neighbours of every row (0, the default: rows packed).  Afterwards
+ * a batch of at most one effective pair per 256 slots whose touched rows all
+ * have room for their net insertions is merged into those rows in place:
+ * offsets and all other rows stay where they are, and the apply costs the
+ * touched rows plus the batch instead of a copy of both CSRs.  If some
+ * touched row has no room, the apply lays every row out again with `slack`
+ * fresh free slots; larger batches take the usual rebuild, which keeps each
+ * row's free slots.  The rank kernels read only the neighbours.  Exports,
+ * sizes and results are the same as without slack.  Each index array then
+ * holds m + n * slack slots (the edge capacity grows if needed).  A served
+ * graph keeps the layout it had when added.  Errors: EINVAL (slack outside
+ * [0, 65536], or more slots than int32 offsets reach), ENOMEM. */
+int dfpr_set_row_slack(dfpr_graph* g, int32_t slack, void* stream);
 
 /* Turn HIP-event timing of every apply and update on this graph on (1) or
  * off (0).  Events are recorded between kernels and read after the call's

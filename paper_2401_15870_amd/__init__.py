@@ -98,9 +98,10 @@ class Graph:
         _live_graphs.add(self)
 
     @classmethod
-    def from_coo(cls, n, src, dst, edge_capacity=0, keep_ids=False, stream=None):
+    def from_coo(cls, n, src, dst, edge_capacity=0, keep_ids=False, row_slack=0, stream=None):
         """keep_ids: keep the caller's vertex numbering inside the library
-        (default: internal numbering by decreasing degree, invisible outside)."""
+        (default: internal numbering by decreasing degree, invisible outside).
+        row_slack: free slots after every CSR row (see set_row_slack)."""
         ps, ms, ws, ks = _ids(src)
         pd, md, wd, kd = _ids(dst)
         if ms != md or ws != wd:
@@ -109,7 +110,10 @@ class Graph:
         flags = _capi.CREATE_KEEP_IDS if keep_ids else 0
         _check(lib().dfpr_graph_create(int(n), int(ms), ps, pd, ws, int(edge_capacity), flags, _stream_ptr(stream),
                                        ctypes.byref(h)))
-        return cls(h, int(n))
+        g = cls(h, int(n))
+        if row_slack:
+            g.set_row_slack(row_slack, stream=stream)
+        return g
 
     def close(self):
         if self._h:
@@ -223,6 +227,11 @@ class Graph:
         """Edge count up to which a rank update runs in one cooperative launch (0: never)."""
         _check(lib().dfpr_set_fused_limit(self._h, int(max_edges)))
 
+    def set_row_slack(self, slack, stream=None):
+        """Lay both CSRs out again with `slack` free slots after every row, so
+        that small batches merge into the rows they touch (0: packed rows)."""
+        _check(lib().dfpr_set_row_slack(self._h, int(slack), _stream_ptr(stream)))
+
     def set_timing(self, on=True):
         _check(lib().dfpr_set_timing(self._h, 1 if on else 0))
 
@@ -254,7 +263,7 @@ class BatchGraph(Graph):
         return len(self.sizes)
 
     @classmethod
-    def from_coo(cls, graphs, keep_ids=False, stream=None):
+    def from_coo(cls, graphs, keep_ids=False, row_slack=0, stream=None):
         """graphs: list of (n_k, src_k, dst_k) with member-local ids."""
         count = len(graphs)
         ns = (ctypes.c_int32 * count)(*[int(g[0]) for g in graphs])
@@ -274,7 +283,10 @@ class BatchGraph(Graph):
             _check(lib().dfpr_batch_member(h, k, ctypes.byref(b), ctypes.byref(n)))
             bases.append(b.value)
             sizes.append(n.value)
-        return cls(h, sum(sizes), bases, sizes)
+        g = cls(h, sum(sizes), bases, sizes)
+        if row_slack:
+            g.set_row_slack(row_slack, stream=stream)
+        return g
 
     def member(self, r, k):
         """Member k's slice of an arena rank vector."""

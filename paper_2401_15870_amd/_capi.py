@@ -19,7 +19,8 @@ CREATE_KEEP_IDS = 1
 # Every exported function declared in include/dfpr.h.
 EXPORTS = ("dfpr_params_default", "dfpr_graph_create", "dfpr_graph_destroy", "dfpr_graph_size",
            "dfpr_graph_export", "dfpr_apply_batch", "dfpr_apply_batch_noalloc", "dfpr_update_ranks", "dfpr_set_tuning",
-           "dfpr_get_tuning", "dfpr_autotune", "dfpr_set_timing", "dfpr_set_fused_limit", "dfpr_batch_create", "dfpr_batch_count",
+           "dfpr_get_tuning", "dfpr_autotune", "dfpr_set_timing", "dfpr_set_fused_limit",
+           "dfpr_set_row_slack", "dfpr_batch_create", "dfpr_batch_count",
            "dfpr_batch_member", "dfpr_apply_batch_many", "dfpr_update_ranks_many", "dfpr_server_create",
            "dfpr_server_destroy", "dfpr_server_add_graph", "dfpr_server_submit", "dfpr_server_wait",
            "dfpr_server_ranks", "dfpr_server_graph_size", "dfpr_server_get_stats", "dfpr_server_set_active_lanes",
@@ -37,7 +38,7 @@ class BatchInfo(ctypes.Structure):
     _fields_ = [("ins_in", ctypes.c_int64), ("ins_effective", ctypes.c_int64), ("del_in", ctypes.c_int64),
                 ("del_effective", ctypes.c_int64), ("self_loop_dels_ignored", ctypes.c_int64),
                 ("m_after", ctypes.c_int64), ("ms_total", ctypes.c_double), ("ms_sort", ctypes.c_double),
-                ("ms_rebuild", ctypes.c_double * 2)]
+                ("ms_rebuild", ctypes.c_double * 2), ("row_local", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         out = {}
@@ -108,6 +109,8 @@ def declare(lib):
     lib.dfpr_autotune.restype = ctypes.c_int
     lib.dfpr_set_fused_limit.argtypes = [P, i64]
     lib.dfpr_set_fused_limit.restype = ctypes.c_int
+    lib.dfpr_set_row_slack.argtypes = [P, i32, P]
+    lib.dfpr_set_row_slack.restype = ctypes.c_int
     lib.dfpr_set_timing.argtypes = [P, ctypes.c_int]
     lib.dfpr_set_timing.restype = ctypes.c_int
     PP = ctypes.POINTER(P)

@@ -436,6 +436,11 @@ int dfpr_autotune(dfpr_graph* g, void* stream, int32_t bounds_out[5], double* ms
   return guarded(g, [&] { return autotune(g, (hipStream_t)stream, bounds_out, ms_out); });
 }
 
+int dfpr_set_row_slack(dfpr_graph* g, int32_t slack, void* stream) {
+  clear_error();
+  return guarded(g, [&] { return graph_set_row_slack(g, slack, (hipStream_t)stream); });
+}
+
 int dfpr_set_fused_limit(dfpr_graph* g, int64_t max_edges) {
   clear_error();
   if (max_edges < 0) {

@@ -172,6 +172,7 @@ struct IterCtl {
   int64_t bin_end[kBins];    // worklist end offset of each bin
   int64_t bin_edges[kBins];  // summed in-degree of each bin
   int64_t n_apply[6];        // apply: eff ins, eff del, self dels, eff count, error flag, m_new
+  int64_t n_local[4];        // row-local apply: touched rows (out, in), rows without room
   int64_t big_count;         // entries in the long out-row list
   int64_t ever_count;        // vertices processed at least once in this update
   int64_t dense_cnt;         // dense pull: affected vertices of the last iteration
@@ -217,7 +218,9 @@ struct dfpr_graph {
   bool poisoned = false;
   int32_t n = 0;
   int64_t m = 0;
-  int64_t cap = 0;   // edge capacity of each index array
+  int64_t slots = 0;  // entries of each index array, slack included (out.off[n] == in.off[n])
+  int32_t slack = 0;  // free slots given to every row at the last re-layout
+  int64_t cap = 0;    // edge capacity of each index array
   int id_bits = 1;   // bits per vertex id in packed sort keys
   // members of a batch (disjoint union; member k owns vertices [vbase[k], vbase[k+1]))
   int32_t ngraphs = 1;
@@ -243,8 +246,8 @@ struct dfpr_graph {
   dfpr::Heap* csr_heap = nullptr;
   void* csr_block = nullptr;
   // True degrees |out(v)| and |in(v)| (self-loop included).  Row v of a CSR
-  // holds its degree's worth of neighbours from off[v] on; any further entries
-  // up to off[v+1] are slack.
+  // holds its degree's worth of neighbours, ascending, from off[v] on; any
+  // further entries up to off[v+1] are free slots holding the pad id n.
   int32_t* out_deg = nullptr;
   int32_t* in_deg = nullptr;
   // rank scratch (n entries each)
@@ -358,6 +361,12 @@ int graph_export(const dfpr_graph* g, int in_csr, int32_t* off, int32_t* idx, df
 int graph_apply(dfpr_graph* g, int64_t n_del, const int32_t* del_src, const int32_t* del_dst,
                 int64_t n_ins, const int32_t* ins_src, const int32_t* ins_dst, dfpr_where where,
                 hipStream_t s, dfpr_batch_info* info);
+// Re-lay out both CSRs with `slack` free slots per row (Section 3.2 batches
+// then merge into rows that have room, without moving the others).
+constexpr int32_t kMaxRowSlack = 1 << 16;
+int graph_set_row_slack(dfpr_graph* g, int32_t slack, hipStream_t s);
+// Slots an apply of n_ins insertions may need in each index array.
+int64_t slots_bound(const dfpr_graph* g, int64_t n_ins);
 // graph_apply with its sort and staging buffers in the library's fixed device
 // scratch (no device allocation): at most DFPR_NOALLOC_MAX_PAIRS pairs and no
 // growth of the edge capacity.

@@ -200,6 +200,138 @@ __global__ void k_update_degrees(const uint64_t* eff, const int64_t* count, int 
     atomicAdd(&in_deg[v], d);
   }
 }
+// ---- rows with free slots
+// Row v of a CSR with slack keeps its deg[v] neighbours, ascending, at
+// off[v] .. off[v] + deg[v] and the pad id n (above every real id) in its
+// remaining slots up to off[v + 1].  Pads sort after every real id, so a row
+// searched or copied as a whole stays ordered and the full rebuild carries
+// them along as ordinary entries.
+
+// Row lengths of a layout with `slack` free slots per row.
+struct LoadPadded {
+  const int32_t* deg;
+  int32_t slack;
+  __device__ int64_t operator()(int64_t v) const { return (int64_t)deg[v] + slack; }
+};
+struct StoreOff {
+  int32_t* a;
+  __device__ void operator()(int64_t i, int64_t v) const { a[i] = (int32_t)v; }
+};
+
+// Copy every row's neighbours to its place in a new layout (offsets noff) and
+// pad the rest of the new row.  Rows flagged in `skip` are left to the merge
+// below.  One lane per row; rows of more than 32 slots are then copied by the
+// whole wavefront, one after another.
+__global__ void k_relayout(const int32_t* __restrict__ ooff, const int32_t* __restrict__ oidx,
+                           const int32_t* __restrict__ deg, const int32_t* __restrict__ noff,
+                           int32_t* __restrict__ nidx, int32_t n, int32_t pad, const uint8_t* __restrict__ skip) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t base = blockIdx.x * (int64_t)blockDim.x + (threadIdx.x & ~(kWave - 1)); base < n; base += stride) {
+    const int64_t v = base + lane_id();
+    int32_t os = 0, d = 0, ns = 0, ne = 0;
+    if (v < n && !(skip && skip[v])) {
+      os = ooff[v];
+      d = deg[v];
+      ns = noff[v];
+      ne = noff[v + 1];
+    }
+    const bool big = ne - ns > 32;
+    if (!big) {
+      for (int32_t j = 0; j < d; j++) nidx[ns + j] = oidx[os + j];
+      for (int32_t p = ns + d; p < ne; p++) nidx[p] = pad;
+    }
+    uint64_t todo = __ballot(big);
+    while (todo) {
+      const int l = __builtin_ctzll(todo);
+      todo &= todo - 1;
+      const int32_t bos = __shfl(os, l, kWave), bd = __shfl(d, l, kWave);
+      const int32_t bns = __shfl(ns, l, kWave), bne = __shfl(ne, l, kWave);
+      for (int32_t j = lane_id(); j < bne - bns; j += kWave) nidx[bns + j] = j < bd ? oidx[bos + j] : pad;
+    }
+  }
+}
+
+// Row-local apply, first pass over a sorted effective batch (one entry per
+// pair; delpre = prefix count of its deletions): list each touched row (the
+// index of its first entry), flag it, and count the rows whose free slots
+// cannot take their net insertions.
+__global__ void k_local_rows(const uint64_t* __restrict__ eff, const int64_t* count,
+                             const int64_t* __restrict__ delpre, int b, const int32_t* __restrict__ off,
+                             const int32_t* __restrict__ deg, int64_t* heads, int64_t* nheads, int64_t* no_room,
+                             uint8_t* touched) {
+  const int64_t t = *count;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < t; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = (int64_t)(eff[e] >> (b + 1));
+    if (e > 0 && (int64_t)(eff[e - 1] >> (b + 1)) == r) continue;
+    const int64_t end = lower_bound_u64(eff, e + 1, t, (uint64_t)(r + 1) << (b + 1));
+    const int64_t dels = delpre[end] - delpre[e];
+    const int64_t grow = (end - e) - 2 * dels;  // insertions minus deletions
+    if (grow > (int64_t)off[r + 1] - off[r] - deg[r]) atomicAdd((unsigned long long*)no_room, 1ull);
+    heads[atomicAdd((unsigned long long*)nheads, 1ull)] = e;
+    touched[r] = 1;
+  }
+}
+
+// Row-local apply, second pass: one workgroup per listed row merges its old
+// neighbours (row r of soff/sidx) with the row's entries (a deletion drops an
+// old neighbour, an insertion adds one) into row r of doff/didx, ascending,
+// and pads the rest of that row.  The position of each result follows from
+// counts: an old neighbour x moves by the insertions minus the deletions
+// before it in the row's entries, an insertion y lands after the old
+// neighbours below y, less the deletions and plus the insertions before it.
+// In place (didx == sidx) the old neighbours are first copied to `cp` at the
+// same offsets.  `deg` holds the old degrees, or the new ones when deg_new.
+__global__ void __launch_bounds__(256) k_row_merge(const int64_t* __restrict__ heads, const int64_t* nheads,
+                                                   const uint64_t* __restrict__ eff, const int64_t* count,
+                                                   const int64_t* __restrict__ delpre, int b,
+                                                   const int32_t* __restrict__ deg, int deg_new, const int32_t* soff,
+                                                   const int32_t* sidx, int32_t* cp, const int32_t* doff,
+                                                   int32_t* didx, int32_t pad) {
+  const uint64_t mask = (1ull << b) - 1;
+  const int64_t t = *count, nr = *nheads;
+  for (int64_t q = blockIdx.x; q < nr; q += gridDim.x) {
+    const int64_t h = heads[q];
+    const int64_t r = (int64_t)(eff[h] >> (b + 1));
+    const int64_t end = lower_bound_u64(eff, h + 1, t, (uint64_t)(r + 1) << (b + 1));
+    const int64_t dels = delpre[end] - delpre[h];
+    const int64_t ins = (end - h) - dels;
+    const int32_t d = deg_new ? (int32_t)(deg[r] - ins + dels) : deg[r];
+    const int32_t os = soff[r];
+    const int32_t* old = sidx + os;
+    if (cp) {
+      for (int32_t i = threadIdx.x; i < d; i += blockDim.x) cp[os + i] = old[i];
+      __syncthreads();
+      old = cp + os;
+    }
+    const int32_t ds = doff[r];
+    const int32_t len = doff[r + 1] - ds;
+    const uint64_t rk = (uint64_t)r << (b + 1);
+    for (int32_t i = threadIdx.x; i < d; i += blockDim.x) {
+      const int32_t x = old[i];
+      const uint64_t kx = rk | ((uint64_t)x << 1);  // the deletion key of (r, x)
+      const int64_t e = lower_bound_u64(eff, h, end, kx);
+      if (e < end && eff[e] == kx) continue;
+      const int64_t dl = delpre[e] - delpre[h];
+      didx[ds + i + (e - h) - 2 * dl] = x;
+    }
+    for (int64_t j = h + threadIdx.x; j < end; j += blockDim.x) {
+      const uint64_t k = eff[j];
+      if (!(k & 1ull)) continue;
+      const int32_t y = (int32_t)((k >> 1) & mask);
+      const int64_t dl = delpre[j] - delpre[h];
+      didx[ds + lower_bound_i32(old, 0, d, y) + (j - h) - 2 * dl] = y;
+    }
+    for (int32_t p = (int32_t)(d + ins - dels) + threadIdx.x; p < len; p += blockDim.x) didx[ds + p] = pad;
+  }
+}
+
+__global__ void k_clear_touched(const int64_t* heads, const int64_t* nheads, const uint64_t* eff, int b,
+                                uint8_t* touched) {
+  const int64_t nr = *nheads;
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < nr; q += (int64_t)gridDim.x * blockDim.x)
+    touched[eff[heads[q]] >> (b + 1)] = 0;
+}
+
 // Member-local batch ids -> union ids, with validation against the member size.
 __global__ void k_offset_ids(const int32_t* a, const int32_t* b, int64_t cnt, int32_t nmem, int64_t base, int32_t* oa,
                              int32_t* ob, int64_t* err) {
@@ -265,12 +397,14 @@ __global__ void k_csr_from_sorted(const uint64_t* keys, int64_t m, int b, int32_
   if (blockIdx.x == 0 && threadIdx.x == 0) off[n] = (int32_t)m;
 }
 
-// Internal CSR -> (caller row << b | caller col) keys, one thread per row.
-__global__ void k_external_keys(const int32_t* off, const int32_t* idx, int32_t n, const int32_t* inv, int b,
-                                uint64_t* keys) {
+// Internal CSR -> (caller row << b | caller col) keys, one thread per row; the
+// keys of row i go to pos[i] on (its neighbours only, not its free slots).
+__global__ void k_external_keys(const int32_t* off, const int32_t* idx, const int32_t* deg, const int32_t* pos,
+                                int32_t n, const int32_t* inv, int b, uint64_t* keys) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const uint64_t r = (uint64_t)inv[i] << b;
-    for (int32_t p = off[i]; p < off[i + 1]; p++) keys[p] = r | (uint64_t)inv[idx[p]];
+    const int32_t s = off[i], q = pos[i], d = deg[i];
+    for (int32_t j = 0; j < d; j++) keys[q + j] = r | (uint64_t)inv[idx[s + j]];
   }
 }
 
@@ -996,7 +1130,7 @@ int move_csrs_to_heap(dfpr_graph* g, Heap* heap, hipStream_t s) {
   }
   Csr out, in;
   carve_csr_pair(block, g->n, g->cap, &out, &in);
-  const size_t ob = ((size_t)g->n + 1) * sizeof(int32_t), eb = (size_t)g->m * sizeof(int32_t);
+  const size_t ob = ((size_t)g->n + 1) * sizeof(int32_t), eb = (size_t)g->slots * sizeof(int32_t);
   if (hipMemcpyAsync(out.off, g->out.off, ob, hipMemcpyDeviceToDevice, s) != hipSuccess ||
       hipMemcpyAsync(in.off, g->in.off, ob, hipMemcpyDeviceToDevice, s) != hipSuccess ||
       (eb && hipMemcpyAsync(out.idx, g->out.idx, eb, hipMemcpyDeviceToDevice, s) != hipSuccess) ||
@@ -1204,7 +1338,7 @@ int graph_create(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, d
       set_error("unique count readback failed");
       return fail(DFPR_EHIP);
     }
-    g->m = mu;
+    g->m = g->slots = mu;
     int64_t cap = edge_capacity > 0 ? edge_capacity : mu + mu / 8 + 1024;
     cap = std::max<int64_t>(cap, mu);
     cap = std::min<int64_t>(cap, INT32_MAX);
@@ -1232,23 +1366,21 @@ int graph_create(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, d
 
 int graph_export(const dfpr_graph* g, int in_csr, int32_t* off, int32_t* idx, dfpr_where where, hipStream_t s) {
   const Csr& c = in_csr ? g->in : g->out;
+  const int32_t* deg = in_csr ? g->in_deg : g->out_deg;
   const hipMemcpyKind kind = where == DFPR_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
-  if (!g->perm) {
+  const bool padded = g->slots != g->m;  // some row has free slots
+  if (!g->perm && !padded) {
     DFPR_HIP(hipMemcpyAsync(off, c.off, ((size_t)g->n + 1) * sizeof(int32_t), kind, s));
     if (g->m > 0) DFPR_HIP(hipMemcpyAsync(idx, c.idx, (size_t)g->m * sizeof(int32_t), kind, s));
     DFPR_HIP(hipStreamSynchronize(s));
     return DFPR_OK;
   }
-  // caller numbering: map both ends of every edge back and sort again
   const int32_t n = g->n;
   const int64_t m = g->m;
   const int b = g->id_bits;
   CreateTmp t;
   Csr outc;
   int rc;
-  if ((rc = dalloc(&t.ka, m)) || (rc = dalloc(&t.kb, m)) || (rc = dalloc(&t.hist, radix_hist_elems(m))) ||
-      (rc = dalloc(&t.tmp, radix_scan_tmp_elems(m))))
-    return rc;
   int32_t* doff = off;
   int32_t* didx = idx;
   if (where == DFPR_HOST) {
@@ -1256,18 +1388,40 @@ int graph_export(const dfpr_graph* g, int in_csr, int32_t* off, int32_t* idx, df
     doff = t.coo;
     didx = t.coo + n + 1;
   }
-  k_external_keys<<<grid_for(n, 256, 65536), 256, 0, s>>>(c.off, c.idx, n, g->inv, b, t.ka);
-  DFPR_HIP(hipGetLastError());
-  outc.off = doff;
-  outc.idx = didx;
-  DFPR_TRY(build_csr_from_keys(&t.ka, &t.kb, m, b, n, &outc, t.hist, t.tmp, s));
+  // rows without their free slots: offsets from the degrees
+  const int32_t* pos = c.off;
+  if (padded) {
+    if ((rc = dalloc(&t.pre, scan_tmp_elems(n)))) return rc;
+    DFPR_TRY(scan_generic(LoadPadded{deg, 0}, StoreOff{doff}, n, t.pre, s));
+    pos = doff;
+  }
+  if (!g->perm) {
+    k_relayout<<<grid_for(n, 256, 65536), 256, 0, s>>>(c.off, c.idx, deg, doff, didx, n, n, nullptr);
+    DFPR_HIP(hipGetLastError());
+  } else {
+    // caller numbering: map both ends of every edge back and sort again
+    if ((rc = dalloc(&t.ka, m)) || (rc = dalloc(&t.kb, m)) || (rc = dalloc(&t.hist, radix_hist_elems(m))) ||
+        (rc = dalloc(&t.tmp, radix_scan_tmp_elems(m))))
+      return rc;
+    k_external_keys<<<grid_for(n, 256, 65536), 256, 0, s>>>(c.off, c.idx, deg, pos, n, g->inv, b, t.ka);
+    DFPR_HIP(hipGetLastError());
+    outc.off = doff;
+    outc.idx = didx;
+    DFPR_TRY(build_csr_from_keys(&t.ka, &t.kb, m, b, n, &outc, t.hist, t.tmp, s));
+    outc.off = outc.idx = nullptr;
+  }
   if (where == DFPR_HOST) {
     DFPR_HIP(hipMemcpyAsync(off, doff, ((size_t)n + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     if (m > 0) DFPR_HIP(hipMemcpyAsync(idx, didx, (size_t)m * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   }
   DFPR_HIP(hipStreamSynchronize(s));
-  outc.off = outc.idx = nullptr;
   return DFPR_OK;
+}
+
+// Index-array slots an apply of `ni` insertions may need: a rebuild adds at
+// most ni entries; a re-layout gives every row its free slots again.
+int64_t slots_bound(const dfpr_graph* g, int64_t ni) {
+  return std::max(g->slots, g->slack > 0 ? g->m + (int64_t)g->n * g->slack : (int64_t)0) + ni;
 }
 
 // Grow the edge capacity of all four index arrays to at least `want`.
@@ -1294,7 +1448,7 @@ static int grow_capacity(dfpr_graph* g, int64_t want, hipStream_t s) {
     int32_t* p = nullptr;
     DFPR_TRY(dalloc(&p, (size_t)cap));
     if (c == &g->out || c == &g->in)
-      DFPR_HIP(hipMemcpyAsync(p, c->idx, (size_t)g->m * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+      DFPR_HIP(hipMemcpyAsync(p, c->idx, (size_t)g->slots * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
     DFPR_HIP(hipStreamSynchronize(s));
     dfree(c->idx);
     c->idx = p;
@@ -1315,26 +1469,58 @@ static int rebuild_csr(dfpr_graph* g, const Csr& o, const Csr& nw, const uint8_t
   const int32_t n = g->n;
   const int64_t groups = ((int64_t)n + kWave - 1) / kWave;
   int32_t chunk = 1024;
-  while (chunk < 16384 && (int64_t)chunk * 2048 < g->m) chunk <<= 1;
-  const int64_t m_bound = g->m + ni;  // the new edge count is at most this
-  if (nk * 256 <= g->m) {  // the same test as the offsets in graph_apply
+  while (chunk < 16384 && (int64_t)chunk * 2048 < g->slots) chunk <<= 1;
+  const int64_t m_bound = g->slots + ni;  // the new slot count is at most this
+  if (nk * 256 <= g->slots) {  // the same test as the offsets in graph_apply
     k_run_copy<<<grid_for(m_bound, chunk, 1u << 16), kCopyBlock, 0, s>>>(o.idx, nw.idx, eff, delpre, opos, cnt,
-                                                                       g->id_bits, nw.off, n, g->m, chunk, err,
+                                                                       g->id_bits, nw.off, n, g->slots, chunk, err,
                                                                        m_off, m_new);
     DFPR_HIP(hipGetLastError());
     return DFPR_OK;
   }
   int32_t piece = 256;
-  while (piece < 4096 && (int64_t)piece * 65536 < g->m) piece <<= 1;
+  while (piece < 4096 && (int64_t)piece * 65536 < g->slots) piece <<= 1;
   DFPR_TRY(scan_generic(LoadPieces{o.off, touched, n, piece}, StorePieces{g->piece_pre}, groups, g->scan_tmp, s));
   k_shift_copy<<<grid_for(m_bound, chunk, 1u << 16), kCopyBlock, 0, s>>>(o.off, o.idx, nw.off, nw.idx, touched, n,
                                                                        chunk, err);
-  const int64_t est = std::min(groups, nk) + g->m / piece + 1;  // upper bound on the piece count
+  const int64_t est = std::min(groups, nk) + g->slots / piece + 1;  // upper bound on the piece count
   k_rebuild<<<grid_for(est, 4, 4096), 256, 0, s>>>(o.off, o.idx, nw.off, nw.idx, touched, eff, delpre, cnt,
                                                    g->id_bits, n, g->piece_pre, piece, err);
   k_place_inserts<<<grid_for(nk, 256, 4096), 256, 0, s>>>(o.off, o.idx, nw.off, nw.idx, eff, delpre, cnt, g->id_bits,
                                                           err);
   DFPR_HIP(hipGetLastError());
+  return DFPR_OK;
+}
+
+// Lay both CSRs out again with `slack` free slots after every row (0: none).
+int graph_set_row_slack(dfpr_graph* g, int32_t slack, hipStream_t s) {
+  if (slack < 0 || slack > kMaxRowSlack) {
+    set_error("row slack %d outside [0, %d]", slack, kMaxRowSlack);
+    return DFPR_EINVAL;
+  }
+  if (g->csr_heap) {
+    set_error("the row layout of a served graph is fixed when it is added");
+    return DFPR_EINVAL;
+  }
+  const int32_t n = g->n;
+  const int64_t want = g->m + (int64_t)n * slack;
+  if (want > INT32_MAX) {
+    set_error("%lld slots exceed int32 edge offsets", (long long)want);
+    return DFPR_EINVAL;
+  }
+  if (want > g->cap) DFPR_TRY(grow_capacity(g, want, s));
+  const unsigned gr = grid_for(n, 256, 65536);
+  DFPR_TRY(scan_generic(LoadPadded{g->out_deg, slack}, StoreOff{g->out2.off}, n, g->scan_tmp, s));
+  k_relayout<<<gr, 256, 0, s>>>(g->out.off, g->out.idx, g->out_deg, g->out2.off, g->out2.idx, n, n, nullptr);
+  DFPR_TRY(scan_generic(LoadPadded{g->in_deg, slack}, StoreOff{g->in2.off}, n, g->scan_tmp, s));
+  k_relayout<<<gr, 256, 0, s>>>(g->in.off, g->in.idx, g->in_deg, g->in2.off, g->in2.idx, n, n, nullptr);
+  DFPR_HIP(hipGetLastError());
+  DFPR_HIP(hipStreamSynchronize(s));
+  std::swap(g->out, g->out2);
+  std::swap(g->in, g->in2);
+  g->slots = want;
+  g->slack = slack;
+  g->all_bins_valid = false;
   return DFPR_OK;
 }
 
@@ -1351,11 +1537,12 @@ int graph_apply(dfpr_graph* g, int64_t nd, const int32_t* del_src, const int32_t
     info->m_after = g->m;
   }
   if (nk == 0) return DFPR_OK;
-  if (g->m + ni > INT32_MAX) {
+  const int64_t need = slots_bound(g, ni);
+  if (need > INT32_MAX) {
     set_error("batch would exceed int32 edge offsets");
     return DFPR_EINVAL;
   }
-  if (g->m + ni > g->cap) DFPR_TRY(grow_capacity(g, g->m + ni, s));
+  if (need > g->cap) DFPR_TRY(grow_capacity(g, need, s));
 
   // ---- scratch
   DFPR_TRY(g->keys_a.ensure(nk * sizeof(uint64_t)));
@@ -1414,7 +1601,7 @@ int graph_apply(dfpr_graph* g, int64_t nd, const int32_t* del_src, const int32_t
   if (g_self) DFPR_HIP(hipMemsetAsync(g_self, 0, (size_t)g->ngraphs * sizeof(int64_t), s));
   // few effective entries (at most one per 256 edges): the rebuild copies run
   // by run and needs no per-row deltas or touched flags
-  const bool few = nk * 256 <= g->m;
+  const bool few = nk * 256 <= g->slots;
   k_classify<<<grid_for(nk, 256, 65536), 256, 0, s>>>(
       ka, nk, b, g->out.off, g->out.idx, keep, few ? nullptr : g->delta_out, few ? nullptr : g->delta_in,
       few ? nullptr : g->touched_out, few ? nullptr : g->touched_in, g->pend_src, g->flag_cur, counters, g->gidv,
@@ -1430,22 +1617,7 @@ int graph_apply(dfpr_graph* g, int64_t nd, const int32_t* del_src, const int32_t
   }
   DFPR_TRY(scan_generic(LoadIsDel{eff_out, cnt}, StoreI64b{pre_out}, nk, tmp, s));
 
-  // ---- out-CSR (few effective entries: offsets shifted run by run, as the
-  // index arrays are copied; otherwise a scan of the row-length deltas)
-  const int32_t off_rows = run_offset_rows(n);
-  const unsigned off_blocks = grid_for((int64_t)n + 1, off_rows, 65536);
-  const unsigned pos_blocks = grid_for(nk, 256, 4096);
-  if (few)
-    k_run_offsets<<<off_blocks + pos_blocks, 256, 0, s>>>(g->out.off, g->out2.off, g->out.idx, opos, eff_out, pre_out,
-                                                          cnt, b, n, off_rows, (int32_t)off_blocks);
-  else
-    DFPR_TRY(scan_row_offsets(g->out.off, g->delta_out, g->out2.off, n, g->scan_tmp, s));
-  DFPR_TRY(ep.start(&tok));
-  DFPR_TRY(rebuild_csr(g, g->out, g->out2, g->touched_out, eff_out, pre_out, opos, cnt, nk, ni, counters + 4,
-                       nullptr, nullptr, s));
-  DFPR_TRY(ep.stop(kTRebuildOut, tok));
-
-  // ---- in-CSR: the same entries ordered by (v, u)
+  // ---- in-side entries: the same entries ordered by (v, u)
   k_in_order_keys<<<grid_for(nk, 256, 65536), 256, 0, s>>>(eff_out, cnt, nk, b, ka);
   uint64_t* eff_in = ka;
   uint64_t* alt = kc;
@@ -1455,40 +1627,136 @@ int graph_apply(dfpr_graph* g, int64_t nd, const int32_t* del_src, const int32_t
   DFPR_TRY(radix_sort(&eff_in, &alt, nk, 2 * b + 1, hist, tmp, s, b + 1));
   DFPR_TRY(ep.stop(kTSort, tok));
   DFPR_TRY(scan_generic(LoadIsDel{eff_in, cnt}, StoreI64b{pre_in}, nk, tmp, s));
-  if (few)
-    k_run_offsets<<<off_blocks + pos_blocks, 256, 0, s>>>(g->in.off, g->in2.off, g->in.idx, opos, eff_in, pre_in, cnt,
-                                                          b, n, off_rows, (int32_t)off_blocks);
-  else
-    DFPR_TRY(scan_row_offsets(g->in.off, g->delta_in, g->in2.off, n, g->scan_tmp, s));
-  DFPR_TRY(ep.start(&tok));
-  // (few entries: the in-side copy also records the new edge count)
-  DFPR_TRY(rebuild_csr(g, g->in, g->in2, g->touched_in, eff_in, pre_in, opos, cnt, nk, ni, counters + 4,
-                       g->out2.off, counters + 5, s));
-  DFPR_TRY(ep.stop(kTRebuildIn, tok));
-  if (!few) {
-    k_clear_rows<<<grid_for(nk, 256, 65536), 256, 0, s>>>(eff_out, cnt, b, g->delta_out, g->delta_in,
-                                                          g->touched_out, g->touched_in);
-    k_finish_apply<<<1, 1, 0, s>>>(g->out2.off, n, counters);
+
+  // Three ways to write the new CSRs:
+  //   row-local (rows with free slots, few entries, every touched row has
+  //     room): merge each touched row in place, offsets unchanged;
+  //   re-laid out (rows with free slots, few entries, some row without room):
+  //     every row moves to a new layout with fresh free slots, the touched
+  //     rows merged on the way;
+  //   rebuilt (otherwise): the run-by-run or group rebuild below, which
+  //     carries free slots along as ordinary entries.
+  enum { kRebuilt, kRowLocal, kRelaid } path = kRebuilt;
+  const int64_t* h = g->ctl_host->n_apply;
+  int64_t* nl = g->ctl->n_local;
+  int64_t* heads_out = opos;  // the run-by-run rebuild's positions are not needed on these paths
+  int64_t* heads_in = reinterpret_cast<int64_t*>(alt);  // free once the in-side sort is done
+  if (few && g->slack > 0) {
+    DFPR_HIP(hipMemsetAsync(nl, 0, 3 * sizeof(int64_t), s));
+    const unsigned gk = grid_for(nk, 256, 65536);
+    k_local_rows<<<gk, 256, 0, s>>>(eff_out, cnt, pre_out, b, g->out.off, g->out_deg, heads_out, nl, nl + 2,
+                                    g->touched_out);
+    k_local_rows<<<gk, 256, 0, s>>>(eff_in, cnt, pre_in, b, g->in.off, g->in_deg, heads_in, nl + 1, nl + 2,
+                                    g->touched_in);
+    DFPR_HIP(hipGetLastError());
+    DFPR_HIP(hipMemcpyAsync(g->ctl_host->n_apply, counters, 6 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    DFPR_HIP(hipMemcpyAsync(g->ctl_host->n_local, nl, 3 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    DFPR_HIP(hipStreamSynchronize(s));
+    if (h[4] & 1) {  // nothing was touched: a rejected batch has no effective entries
+      set_error("vertex id outside [0, %d) in batch", n);
+      return DFPR_ERANGE;
+    }
+    path = g->ctl_host->n_local[2] == 0 ? kRowLocal : kRelaid;
   }
-  k_update_degrees<<<grid_for(nk, 256, 65536), 256, 0, s>>>(eff_out, cnt, b, counters + 4, g->out_deg, g->in_deg);
+  const int64_t rows_out = g->ctl_host->n_local[0], rows_in = g->ctl_host->n_local[1];
+  const int32_t pad = n;
+  if (path == kRowLocal) {
+    // old neighbours of the touched rows go to the idle rebuild targets
+    DFPR_TRY(ep.start(&tok));
+    k_row_merge<<<grid_for(rows_out, 1, 65536), 256, 0, s>>>(heads_out, nl, eff_out, cnt, pre_out, b, g->out_deg, 0,
+                                                             g->out.off, g->out.idx, g->out2.idx, g->out.off,
+                                                             g->out.idx, pad);
+    DFPR_TRY(ep.stop(kTRebuildOut, tok));
+    DFPR_TRY(ep.start(&tok));
+    k_row_merge<<<grid_for(rows_in, 1, 65536), 256, 0, s>>>(heads_in, nl + 1, eff_in, cnt, pre_in, b, g->in_deg, 0,
+                                                            g->in.off, g->in.idx, g->in2.idx, g->in.off, g->in.idx,
+                                                            pad);
+    DFPR_TRY(ep.stop(kTRebuildIn, tok));
+    k_update_degrees<<<grid_for(nk, 256, 65536), 256, 0, s>>>(eff_out, cnt, b, counters + 4, g->out_deg, g->in_deg);
+  } else if (path == kRelaid) {
+    // new degrees first: they size the new rows (untouched rows keep theirs)
+    k_update_degrees<<<grid_for(nk, 256, 65536), 256, 0, s>>>(eff_out, cnt, b, counters + 4, g->out_deg, g->in_deg);
+    const unsigned gr = grid_for(n, 256, 65536);
+    DFPR_TRY(ep.start(&tok));
+    DFPR_TRY(scan_generic(LoadPadded{g->out_deg, g->slack}, StoreOff{g->out2.off}, n, g->scan_tmp, s));
+    k_relayout<<<gr, 256, 0, s>>>(g->out.off, g->out.idx, g->out_deg, g->out2.off, g->out2.idx, n, pad,
+                                  g->touched_out);
+    k_row_merge<<<grid_for(rows_out, 1, 65536), 256, 0, s>>>(heads_out, nl, eff_out, cnt, pre_out, b, g->out_deg, 1,
+                                                             g->out.off, g->out.idx, nullptr, g->out2.off,
+                                                             g->out2.idx, pad);
+    DFPR_TRY(ep.stop(kTRebuildOut, tok));
+    DFPR_TRY(ep.start(&tok));
+    DFPR_TRY(scan_generic(LoadPadded{g->in_deg, g->slack}, StoreOff{g->in2.off}, n, g->scan_tmp, s));
+    k_relayout<<<gr, 256, 0, s>>>(g->in.off, g->in.idx, g->in_deg, g->in2.off, g->in2.idx, n, pad, g->touched_in);
+    k_row_merge<<<grid_for(rows_in, 1, 65536), 256, 0, s>>>(heads_in, nl + 1, eff_in, cnt, pre_in, b, g->in_deg, 1,
+                                                            g->in.off, g->in.idx, nullptr, g->in2.off, g->in2.idx,
+                                                            pad);
+    DFPR_TRY(ep.stop(kTRebuildIn, tok));
+    k_finish_apply<<<1, 1, 0, s>>>(g->out2.off, n, counters);
+  } else {
+    // ---- out-CSR (few effective entries: offsets shifted run by run, as the
+    // index arrays are copied; otherwise a scan of the row-length deltas)
+    const int32_t off_rows = run_offset_rows(n);
+    const unsigned off_blocks = grid_for((int64_t)n + 1, off_rows, 65536);
+    const unsigned pos_blocks = grid_for(nk, 256, 4096);
+    if (few)
+      k_run_offsets<<<off_blocks + pos_blocks, 256, 0, s>>>(g->out.off, g->out2.off, g->out.idx, opos, eff_out,
+                                                            pre_out, cnt, b, n, off_rows, (int32_t)off_blocks);
+    else
+      DFPR_TRY(scan_row_offsets(g->out.off, g->delta_out, g->out2.off, n, g->scan_tmp, s));
+    DFPR_TRY(ep.start(&tok));
+    DFPR_TRY(rebuild_csr(g, g->out, g->out2, g->touched_out, eff_out, pre_out, opos, cnt, nk, ni, counters + 4,
+                         nullptr, nullptr, s));
+    DFPR_TRY(ep.stop(kTRebuildOut, tok));
+
+    // ---- in-CSR
+    if (few)
+      k_run_offsets<<<off_blocks + pos_blocks, 256, 0, s>>>(g->in.off, g->in2.off, g->in.idx, opos, eff_in, pre_in,
+                                                            cnt, b, n, off_rows, (int32_t)off_blocks);
+    else
+      DFPR_TRY(scan_row_offsets(g->in.off, g->delta_in, g->in2.off, n, g->scan_tmp, s));
+    DFPR_TRY(ep.start(&tok));
+    // (few entries: the in-side copy also records the new slot count)
+    DFPR_TRY(rebuild_csr(g, g->in, g->in2, g->touched_in, eff_in, pre_in, opos, cnt, nk, ni, counters + 4,
+                         g->out2.off, counters + 5, s));
+    DFPR_TRY(ep.stop(kTRebuildIn, tok));
+    if (!few) {
+      k_clear_rows<<<grid_for(nk, 256, 65536), 256, 0, s>>>(eff_out, cnt, b, g->delta_out, g->delta_in,
+                                                            g->touched_out, g->touched_in);
+      k_finish_apply<<<1, 1, 0, s>>>(g->out2.off, n, counters);
+    }
+    k_update_degrees<<<grid_for(nk, 256, 65536), 256, 0, s>>>(eff_out, cnt, b, counters + 4, g->out_deg, g->in_deg);
+  }
+  if (path != kRebuilt) {
+    k_clear_touched<<<grid_for(rows_out, 256, 4096), 256, 0, s>>>(heads_out, nl, eff_out, b, g->touched_out);
+    k_clear_touched<<<grid_for(rows_in, 256, 4096), 256, 0, s>>>(heads_in, nl + 1, eff_in, b, g->touched_in);
+  }
   DFPR_HIP(hipGetLastError());
   DFPR_HIP(hipMemcpyAsync(g->ctl_host->n_apply, counters, 6 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
   DFPR_TRY(ep.stop(kTTotal, t_total));
   DFPR_HIP(hipStreamSynchronize(s));
 
-  const int64_t* h = g->ctl_host->n_apply;
   if (h[4] & 1) {
     set_error("vertex id outside [0, %d) in batch", n);
     return DFPR_ERANGE;
   }
-  if (h[4] != 0 || h[5] != g->m + h[0] - h[1]) {
-    set_error("internal inconsistency in the CSR rebuild (flag %lld, m %lld -> %lld)", (long long)h[4],
-              (long long)g->m, (long long)h[5]);
+  const int64_t m_new = g->m + h[0] - h[1];
+  // slot count of the new CSRs (row-local: unchanged; re-laid out: the new
+  // degrees plus the free slots; rebuilt: the old count plus the net change)
+  const int64_t slots_new = path == kRowLocal ? g->slots
+                            : path == kRelaid ? m_new + (int64_t)n * g->slack
+                                              : g->slots + h[0] - h[1];
+  if (h[4] != 0 || (path != kRowLocal && h[5] != slots_new)) {
+    set_error("internal inconsistency in the CSR rebuild (flag %lld, slots %lld -> %lld, expected %lld)",
+              (long long)h[4], (long long)g->slots, (long long)h[5], (long long)slots_new);
     return DFPR_EHIP;
   }
-  std::swap(g->out, g->out2);
-  std::swap(g->in, g->in2);
-  g->m = h[5];
+  if (path != kRowLocal) {
+    std::swap(g->out, g->out2);
+    std::swap(g->in, g->in2);
+  }
+  g->m = m_new;
+  g->slots = slots_new;
   g->all_bins_valid = false;
   if (h[3] > 0) g->pending_any = true;
   if (info) {
@@ -1496,6 +1764,7 @@ int graph_apply(dfpr_graph* g, int64_t nd, const int32_t* del_src, const int32_t
     info->del_effective = h[1];
     info->self_loop_dels_ignored = h[2];
     info->m_after = g->m;
+    info->row_local = path == kRowLocal ? 1 : 0;
   }
   if (ep.on) {
     double ms[kTNum] = {0};
@@ -1539,9 +1808,9 @@ int graph_apply_noalloc(dfpr_graph* g, int64_t nd, const int32_t* del_src, const
     set_error("allocation-free apply: %lld batch pairs exceed the limit of %d", (long long)nk, DFPR_NOALLOC_MAX_PAIRS);
     return DFPR_EINVAL;
   }
-  if (g->m + ni > g->cap) {
-    set_error("allocation-free apply: %lld insertions could exceed the edge capacity (%lld edges of %lld)",
-              (long long)ni, (long long)g->m, (long long)g->cap);
+  if (slots_bound(g, ni) > g->cap) {
+    set_error("allocation-free apply: %lld insertions could exceed the edge capacity (%lld slots of %lld)",
+              (long long)ni, (long long)g->slots, (long long)g->cap);
     return DFPR_ENOMEM;
   }
   const int dev = g->device;
@@ -1728,6 +1997,7 @@ int batch_apply(dfpr_graph* g, const int64_t* n_del, const int32_t* const* del_s
       info[k].ms_sort = total.ms_sort;
       info[k].ms_rebuild[0] = total.ms_rebuild[0];
       info[k].ms_rebuild[1] = total.ms_rebuild[1];
+      info[k].row_local = total.row_local;  // the arena's rows take one path together
     }
   }
   return DFPR_OK;

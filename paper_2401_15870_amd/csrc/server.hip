@@ -226,7 +226,7 @@ Request* pick(dfpr_server* sv) {
     Resident& r = sv->graphs[q->gid];
     if (r.busy) continue;
     const dfpr_graph* g = r.g;  // idle: no request changes it meanwhile
-    const int64_t need = g->m + (int64_t)q->is.size();
+    const int64_t need = slots_bound(g, (int64_t)q->is.size());
     q->target_cap = need <= g->cap ? g->cap : std::min<int64_t>(need + need / 4, INT32_MAX);
     for (int attempt = 0; attempt < 2; attempt++) {
       q->scratch = sv->heap.alloc(r.scratch);

@@ -71,6 +71,7 @@ def test_invalid_arguments_rejected_before_device_work(lib):
     assert lib.dfpr_batch_member(None, 0, ctypes.byref(b), ctypes.byref(n)) == _capi.DFPR_EINVAL
     assert lib.dfpr_apply_batch_many(None, None, None, None, None, None, None, 0, None, None) == _capi.DFPR_EINVAL
     assert lib.dfpr_update_ranks_many(None, 3, None, None, None, None, None, None) == _capi.DFPR_EINVAL
+    assert lib.dfpr_set_row_slack(None, 2, None) == _capi.DFPR_EINVAL
     # serving form
     assert lib.dfpr_server_create(0, 4, 3, None, ctypes.byref(h)) == _capi.DFPR_EINVAL
     assert lib.dfpr_server_create(1 << 20, 0, 3, None, ctypes.byref(h)) == _capi.DFPR_EINVAL
@@ -88,6 +89,6 @@ def test_invalid_arguments_rejected_before_device_work(lib):
 def test_struct_layouts_match_header():
     # field counts and sizes of the ABI structs as declared in include/dfpr.h
     assert ctypes.sizeof(_capi.Params) == 5 * 8 + 4 * 4
-    assert ctypes.sizeof(_capi.BatchInfo) == 6 * 8 + 4 * 8
+    assert ctypes.sizeof(_capi.BatchInfo) == 6 * 8 + 4 * 8 + 2 * 4
     assert ctypes.sizeof(_capi.Stats) == 4 + 4 + 8 + 3 * 8 + 12 * 8 + 8 + 8 + 4 + 4 + 3 * 8 + 8 + 4 + 4
     assert ctypes.sizeof(_capi.ServerStats) == 5 * 8 + 4 * 4 + 3 * 8

@@ -186,7 +186,7 @@ int dfpr_apply_batch(dfpr_graph* g, int64_t n_del, const int32_t* del_src, const
  * allocate device memory (code under HIP graph capture, tight serving loops,
  * harnesses that forbid allocation).  Same arguments, effect, results and
  * errors as dfpr_apply_batch, but the batch's sort and staging buffers come
- * from a fixed scratch array inside the library (32 MiB of device memory per
+ * from a fixed scratch array inside the library (40 MiB of device memory per
  * device the library runs on, held until the process ends) and the call makes
  * no device allocation.  Limits: n_del + n_ins <= DFPR_NOALLOC_MAX_PAIRS (else
  * EINVAL), and the insertions must fit the graph's edge capacity (m + n_ins

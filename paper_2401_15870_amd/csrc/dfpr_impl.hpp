@@ -172,7 +172,8 @@ struct IterCtl {
   int64_t bin_end[kBins];    // worklist end offset of each bin
   int64_t bin_edges[kBins];  // summed in-degree of each bin
   int64_t n_apply[6];        // apply: eff ins, eff del, self dels, eff count, error flag, m_new
-  int64_t n_local[4];        // row-local apply: touched rows (out, in), rows without room
+  int64_t n_local[6];        // row-local apply: touched rows (out, in), rows without room,
+                             // merge work items (out, in)
   int64_t big_count;         // entries in the long out-row list
   int64_t ever_count;        // vertices processed at least once in this update
   int64_t dense_cnt;         // dense pull: affected vertices of the last iteration
@@ -291,6 +292,7 @@ struct dfpr_graph {
   int64_t* big_pre = nullptr;        // n+1: chunk prefix of big_list
   // growable batch scratch
   dfpr::DevBuf keys_a, keys_b, keys_c, sort_hist, eff_pre, batch_in, keys_in;
+  dfpr::DevBuf row_work;  // row-local apply: work-item prefixes of the touched rows
   bool pending_any = false;  // an apply happened since the last DF/DF-P update
   int32_t bounds[5] = {4, 16, 128, 2048, 32768};  // in-degree bin limits (dfpr_set_tuning)
   int32_t* arrive = nullptr;  // n: per-vertex chunk arrival counters of bin 5

@@ -218,36 +218,67 @@ struct StoreOff {
   __device__ void operator()(int64_t i, int64_t v) const { a[i] = (int32_t)v; }
 };
 
-// Copy every row's neighbours to its place in a new layout (offsets noff) and
-// pad the rest of the new row.  Rows flagged in `skip` are left to the merge
-// below.  One lane per row; rows of more than 32 slots are then copied by the
-// whole wavefront, one after another.
-__global__ void k_relayout(const int32_t* __restrict__ ooff, const int32_t* __restrict__ oidx,
-                           const int32_t* __restrict__ deg, const int32_t* __restrict__ noff,
-                           int32_t* __restrict__ nidx, int32_t n, int32_t pad, const uint8_t* __restrict__ skip) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t base = blockIdx.x * (int64_t)blockDim.x + (threadIdx.x & ~(kWave - 1)); base < n; base += stride) {
-    const int64_t v = base + lane_id();
-    int32_t os = 0, d = 0, ns = 0, ne = 0;
-    if (v < n && !(skip && skip[v])) {
-      os = ooff[v];
-      d = deg[v];
-      ns = noff[v];
-      ne = noff[v + 1];
+// Largest i in [lo, hi) with a[i] <= x, given a[lo] <= x < a[hi] and `a`
+// ascending; called by a whole wavefront (64 probes per round).
+template <class T>
+__device__ int64_t wave_last_le(const T* a, int64_t lo, int64_t hi, int64_t x) {
+  while (hi - lo > 1) {
+    const int64_t step = (hi - lo + kWave - 1) / kWave;
+    const int64_t p = lo + (int64_t)lane_id() * step;
+    const uint64_t le = __ballot(p < hi && (int64_t)a[p] <= x);  // a prefix of the lanes, lane 0 included
+    lo += (int64_t)(63 - __builtin_clzll(le)) * step;
+    hi = min(hi, lo + step);
+  }
+  return lo;
+}
+
+// Copy every row's neighbours to its place in a new layout (offsets noff,
+// `total` slots) and pad the rest of the new row; rows flagged in `skip` are
+// left to the merge below.  Each workgroup writes a tile of consecutive new
+// slots: its first wavefront finds the rows the tile covers, their offsets
+// and degrees go to LDS, and every slot looks its row up there.  Every row
+// holds at least one slot (its self-loop), so a tile covers at most
+// kRelayTile rows.
+constexpr int kRelayTile = 2048;
+__global__ void __launch_bounds__(256) k_relayout(const int32_t* __restrict__ ooff, const int32_t* __restrict__ oidx,
+                                                  const int32_t* __restrict__ deg, const int32_t* __restrict__ noff,
+                                                  int32_t* __restrict__ nidx, int32_t n, int64_t total, int32_t pad,
+                                                  const uint8_t* __restrict__ skip) {
+  __shared__ int32_t s_noff[kRelayTile + 1];
+  __shared__ int32_t s_src[kRelayTile];
+  __shared__ int32_t s_deg[kRelayTile];
+  __shared__ int64_t s_rows[2];
+  for (int64_t q0 = (int64_t)blockIdx.x * kRelayTile; q0 < total; q0 += (int64_t)gridDim.x * kRelayTile) {
+    const int64_t q1 = min(q0 + (int64_t)kRelayTile, total);
+    if (threadIdx.x < kWave) {
+      const int64_t r0 = wave_last_le(noff, 0, n, q0);
+      const int64_t r1 = wave_last_le(noff, r0, min((int64_t)n, r0 + kRelayTile), q1 - 1);
+      if (threadIdx.x == 0) {
+        s_rows[0] = r0;
+        s_rows[1] = min(r1 - r0 + 1, (int64_t)kRelayTile);
+      }
     }
-    const bool big = ne - ns > 32;
-    if (!big) {
-      for (int32_t j = 0; j < d; j++) nidx[ns + j] = oidx[os + j];
-      for (int32_t p = ns + d; p < ne; p++) nidx[p] = pad;
+    __syncthreads();
+    const int64_t r0 = s_rows[0];
+    const int32_t nr = (int32_t)s_rows[1];
+    for (int32_t i = threadIdx.x; i <= nr; i += blockDim.x) s_noff[i] = noff[r0 + i];
+    for (int32_t i = threadIdx.x; i < nr; i += blockDim.x) {
+      s_src[i] = (skip && skip[r0 + i]) ? -1 : ooff[r0 + i];
+      s_deg[i] = deg[r0 + i];
     }
-    uint64_t todo = __ballot(big);
-    while (todo) {
-      const int l = __builtin_ctzll(todo);
-      todo &= todo - 1;
-      const int32_t bos = __shfl(os, l, kWave), bd = __shfl(d, l, kWave);
-      const int32_t bns = __shfl(ns, l, kWave), bne = __shfl(ne, l, kWave);
-      for (int32_t j = lane_id(); j < bne - bns; j += kWave) nidx[bns + j] = j < bd ? oidx[bos + j] : pad;
+    __syncthreads();
+    for (int64_t q = q0 + threadIdx.x; q < q1; q += blockDim.x) {
+      int32_t lo = 0, hi = nr - 1;  // the row of slot q: last i with s_noff[i] <= q
+      while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (s_noff[mid] <= q) lo = mid; else hi = mid - 1;
+      }
+      const int32_t src = s_src[lo];
+      if (src < 0) continue;
+      const int32_t j = (int32_t)(q - s_noff[lo]);
+      nidx[q] = j < s_deg[lo] ? oidx[src + j] : pad;
     }
+    __syncthreads();
   }
 }
 
@@ -272,56 +303,107 @@ __global__ void k_local_rows(const uint64_t* __restrict__ eff, const int64_t* co
   }
 }
 
-// Row-local apply, second pass: one workgroup per listed row merges its old
-// neighbours (row r of soff/sidx) with the row's entries (a deletion drops an
-// old neighbour, an insertion adds one) into row r of doff/didx, ascending,
-// and pads the rest of that row.  The position of each result follows from
+// Work items of the second pass: each touched row in chunks of kMergeChunk
+// old neighbours (at least one item per row); prefix over the row list.
+constexpr int64_t kMergeChunk = 4096;
+struct LoadRowChunks {
+  const int64_t* heads;
+  const int64_t* nheads;
+  const uint64_t* eff;
+  int b;
+  const int32_t* deg;  // old degrees
+  __device__ int64_t operator()(int64_t q) const {
+    if (q >= *nheads) return 0;
+    const int64_t d = deg[eff[heads[q]] >> (b + 1)];
+    return d > kMergeChunk ? (d + kMergeChunk - 1) / kMergeChunk : 1;
+  }
+};
+
+// One work item of the second pass, located by the block's first wavefront.
+struct MergeItem {
+  int64_t h, end, dels, ins, r;
+  int32_t d, lo, hi;  // old degree; the item's old neighbours [lo, hi)
+  bool first;         // the row's first item (also places insertions and pads)
+};
+__device__ void merge_item(int64_t w, const int64_t* heads, int64_t nr, const int64_t* cpre, const uint64_t* eff,
+                           int64_t t, const int64_t* delpre, int b, const int32_t* deg, int deg_new, MergeItem* it) {
+  __shared__ int64_t s_q;
+  __syncthreads();  // the previous item is done with s_q
+  if (threadIdx.x < kWave) {
+    const int64_t q = wave_last_le(cpre, 0, nr, w);
+    if (threadIdx.x == 0) s_q = q;
+  }
+  __syncthreads();
+  const int64_t q = s_q;
+  it->h = heads[q];
+  it->r = (int64_t)(eff[it->h] >> (b + 1));
+  it->end = lower_bound_u64(eff, it->h + 1, t, (uint64_t)(it->r + 1) << (b + 1));
+  it->dels = delpre[it->end] - delpre[it->h];
+  it->ins = (it->end - it->h) - it->dels;
+  it->d = deg_new ? (int32_t)(deg[it->r] - it->ins + it->dels) : deg[it->r];
+  const int64_t c = w - cpre[q];
+  it->lo = (int32_t)min(c * kMergeChunk, (int64_t)it->d);
+  it->hi = (int32_t)min((c + 1) * kMergeChunk, (int64_t)it->d);
+  it->first = c == 0;
+}
+
+// In place, first: the old neighbours of the touched rows go to `cp` at
+// their own offsets (the merge then reads them there).
+__global__ void __launch_bounds__(256) k_row_save(const int64_t* __restrict__ heads, const int64_t* nheads,
+                                                  const int64_t* __restrict__ cpre, const uint64_t* __restrict__ eff,
+                                                  const int64_t* count, const int64_t* __restrict__ delpre, int b,
+                                                  const int32_t* __restrict__ deg, const int32_t* __restrict__ off,
+                                                  const int32_t* __restrict__ idx, int32_t* __restrict__ cp) {
+  const int64_t nr = *nheads, t = *count, items = cpre[nr];
+  for (int64_t w = blockIdx.x; w < items; w += gridDim.x) {
+    MergeItem it;
+    merge_item(w, heads, nr, cpre, eff, t, delpre, b, deg, 0, &it);
+    const int32_t os = off[it.r];
+    for (int32_t i = it.lo + threadIdx.x; i < it.hi; i += blockDim.x) cp[os + i] = idx[os + i];
+  }
+}
+
+// Row-local apply, second pass: per work item, the old neighbours [lo, hi)
+// of a touched row r (row r of soff/sidx) are merged with the row's entries
+// (a deletion drops an old neighbour, an insertion adds one) into row r of
+// doff/didx, ascending; the row's first item also places its insertions and
+// pads the rest of the row.  The position of each result follows from
 // counts: an old neighbour x moves by the insertions minus the deletions
-// before it in the row's entries, an insertion y lands after the old
+// before it in the row's entries; an insertion y lands after the old
 // neighbours below y, less the deletions and plus the insertions before it.
-// In place (didx == sidx) the old neighbours are first copied to `cp` at the
-// same offsets.  `deg` holds the old degrees, or the new ones when deg_new.
+// `deg` holds the old degrees, or the new ones when deg_new.
 __global__ void __launch_bounds__(256) k_row_merge(const int64_t* __restrict__ heads, const int64_t* nheads,
-                                                   const uint64_t* __restrict__ eff, const int64_t* count,
-                                                   const int64_t* __restrict__ delpre, int b,
-                                                   const int32_t* __restrict__ deg, int deg_new, const int32_t* soff,
-                                                   const int32_t* sidx, int32_t* cp, const int32_t* doff,
-                                                   int32_t* didx, int32_t pad) {
+                                                   const int64_t* __restrict__ cpre, const uint64_t* __restrict__ eff,
+                                                   const int64_t* count, const int64_t* __restrict__ delpre, int b,
+                                                   const int32_t* __restrict__ deg, int deg_new,
+                                                   const int32_t* __restrict__ soff, const int32_t* sidx,
+                                                   const int32_t* __restrict__ doff, int32_t* didx, int32_t pad) {
   const uint64_t mask = (1ull << b) - 1;
-  const int64_t t = *count, nr = *nheads;
-  for (int64_t q = blockIdx.x; q < nr; q += gridDim.x) {
-    const int64_t h = heads[q];
-    const int64_t r = (int64_t)(eff[h] >> (b + 1));
-    const int64_t end = lower_bound_u64(eff, h + 1, t, (uint64_t)(r + 1) << (b + 1));
-    const int64_t dels = delpre[end] - delpre[h];
-    const int64_t ins = (end - h) - dels;
-    const int32_t d = deg_new ? (int32_t)(deg[r] - ins + dels) : deg[r];
-    const int32_t os = soff[r];
-    const int32_t* old = sidx + os;
-    if (cp) {
-      for (int32_t i = threadIdx.x; i < d; i += blockDim.x) cp[os + i] = old[i];
-      __syncthreads();
-      old = cp + os;
-    }
-    const int32_t ds = doff[r];
-    const int32_t len = doff[r + 1] - ds;
-    const uint64_t rk = (uint64_t)r << (b + 1);
-    for (int32_t i = threadIdx.x; i < d; i += blockDim.x) {
+  const int64_t nr = *nheads, t = *count, items = cpre[nr];
+  for (int64_t w = blockIdx.x; w < items; w += gridDim.x) {
+    MergeItem it;
+    merge_item(w, heads, nr, cpre, eff, t, delpre, b, deg, deg_new, &it);
+    const int32_t* old = sidx + soff[it.r];
+    const int32_t ds = doff[it.r];
+    const uint64_t rk = (uint64_t)it.r << (b + 1);
+    for (int32_t i = it.lo + threadIdx.x; i < it.hi; i += blockDim.x) {
       const int32_t x = old[i];
       const uint64_t kx = rk | ((uint64_t)x << 1);  // the deletion key of (r, x)
-      const int64_t e = lower_bound_u64(eff, h, end, kx);
-      if (e < end && eff[e] == kx) continue;
-      const int64_t dl = delpre[e] - delpre[h];
-      didx[ds + i + (e - h) - 2 * dl] = x;
+      const int64_t e = lower_bound_u64(eff, it.h, it.end, kx);
+      if (e < it.end && eff[e] == kx) continue;
+      const int64_t dl = delpre[e] - delpre[it.h];
+      didx[ds + i + (e - it.h) - 2 * dl] = x;
     }
-    for (int64_t j = h + threadIdx.x; j < end; j += blockDim.x) {
+    if (!it.first) continue;
+    for (int64_t j = it.h + threadIdx.x; j < it.end; j += blockDim.x) {
       const uint64_t k = eff[j];
       if (!(k & 1ull)) continue;
       const int32_t y = (int32_t)((k >> 1) & mask);
-      const int64_t dl = delpre[j] - delpre[h];
-      didx[ds + lower_bound_i32(old, 0, d, y) + (j - h) - 2 * dl] = y;
+      const int64_t dl = delpre[j] - delpre[it.h];
+      didx[ds + lower_bound_i32(old, 0, it.d, y) + (j - it.h) - 2 * dl] = y;
     }
-    for (int32_t p = (int32_t)(d + ins - dels) + threadIdx.x; p < len; p += blockDim.x) didx[ds + p] = pad;
+    const int32_t len = doff[it.r + 1] - ds;
+    for (int32_t p = (int32_t)(it.d + it.ins - it.dels) + threadIdx.x; p < len; p += blockDim.x) didx[ds + p] = pad;
   }
 }
 
@@ -1053,6 +1135,7 @@ size_t apply_buffer_bytes(int64_t nk, bool host_input) {
   t += r((radix_hist_elems(nk) + std::max(radix_scan_tmp_elems(nk), scan_tmp_elems(nk + 1))) * sizeof(int64_t) +
          64);                                                                     // sort_hist
   t += r(3 * (nk + 1) * sizeof(int64_t));                                         // eff_pre
+  t += r(2 * (nk + 1) * sizeof(int64_t));                                         // row_work
   if (host_input) t += r(2 * nk * sizeof(int32_t));                               // batch_in
   return t + 8 * Heap::kAlign;
 }
@@ -1195,6 +1278,7 @@ int graph_destroy(dfpr_graph* g) {
   g->eff_pre.release();
   g->batch_in.release();
   g->keys_in.release();
+  g->row_work.release();
   g->pool.destroy();
   delete g;
   return DFPR_OK;
@@ -1396,7 +1480,7 @@ int graph_export(const dfpr_graph* g, int in_csr, int32_t* off, int32_t* idx, df
     pos = doff;
   }
   if (!g->perm) {
-    k_relayout<<<grid_for(n, 256, 65536), 256, 0, s>>>(c.off, c.idx, deg, doff, didx, n, n, nullptr);
+    k_relayout<<<grid_for(m, kRelayTile, 65536), 256, 0, s>>>(c.off, c.idx, deg, doff, didx, n, m, n, nullptr);
     DFPR_HIP(hipGetLastError());
   } else {
     // caller numbering: map both ends of every edge back and sort again
@@ -1509,11 +1593,11 @@ int graph_set_row_slack(dfpr_graph* g, int32_t slack, hipStream_t s) {
     return DFPR_EINVAL;
   }
   if (want > g->cap) DFPR_TRY(grow_capacity(g, want, s));
-  const unsigned gr = grid_for(n, 256, 65536);
+  const unsigned gr = grid_for(want, kRelayTile, 65536);
   DFPR_TRY(scan_generic(LoadPadded{g->out_deg, slack}, StoreOff{g->out2.off}, n, g->scan_tmp, s));
-  k_relayout<<<gr, 256, 0, s>>>(g->out.off, g->out.idx, g->out_deg, g->out2.off, g->out2.idx, n, n, nullptr);
+  k_relayout<<<gr, 256, 0, s>>>(g->out.off, g->out.idx, g->out_deg, g->out2.off, g->out2.idx, n, want, n, nullptr);
   DFPR_TRY(scan_generic(LoadPadded{g->in_deg, slack}, StoreOff{g->in2.off}, n, g->scan_tmp, s));
-  k_relayout<<<gr, 256, 0, s>>>(g->in.off, g->in.idx, g->in_deg, g->in2.off, g->in2.idx, n, n, nullptr);
+  k_relayout<<<gr, 256, 0, s>>>(g->in.off, g->in.idx, g->in_deg, g->in2.off, g->in2.idx, n, want, n, nullptr);
   DFPR_HIP(hipGetLastError());
   DFPR_HIP(hipStreamSynchronize(s));
   std::swap(g->out, g->out2);
@@ -1641,7 +1725,12 @@ int graph_apply(dfpr_graph* g, int64_t nd, const int32_t* del_src, const int32_t
   int64_t* nl = g->ctl->n_local;
   int64_t* heads_out = opos;  // the run-by-run rebuild's positions are not needed on these paths
   int64_t* heads_in = reinterpret_cast<int64_t*>(alt);  // free once the in-side sort is done
+  int64_t* cpre_out = g->row_work.as<int64_t>();  // merge work-item prefixes (rows_out + 1, rows_in + 1)
+  int64_t* cpre_in = cpre_out + (nk + 1);
   if (few && g->slack > 0) {
+    DFPR_TRY(g->row_work.ensure(2 * (nk + 1) * sizeof(int64_t)));
+    cpre_out = g->row_work.as<int64_t>();
+    cpre_in = cpre_out + (nk + 1);
     DFPR_HIP(hipMemsetAsync(nl, 0, 3 * sizeof(int64_t), s));
     const unsigned gk = grid_for(nk, 256, 65536);
     k_local_rows<<<gk, 256, 0, s>>>(eff_out, cnt, pre_out, b, g->out.off, g->out_deg, heads_out, nl, nl + 2,
@@ -1649,8 +1738,12 @@ int graph_apply(dfpr_graph* g, int64_t nd, const int32_t* del_src, const int32_t
     k_local_rows<<<gk, 256, 0, s>>>(eff_in, cnt, pre_in, b, g->in.off, g->in_deg, heads_in, nl + 1, nl + 2,
                                     g->touched_in);
     DFPR_HIP(hipGetLastError());
+    DFPR_TRY(scan_generic(LoadRowChunks{heads_out, nl, eff_out, b, g->out_deg}, StoreI64b{cpre_out}, nk, tmp, s));
+    DFPR_TRY(scan_generic(LoadRowChunks{heads_in, nl + 1, eff_in, b, g->in_deg}, StoreI64b{cpre_in}, nk, tmp, s));
     DFPR_HIP(hipMemcpyAsync(g->ctl_host->n_apply, counters, 6 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
     DFPR_HIP(hipMemcpyAsync(g->ctl_host->n_local, nl, 3 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    DFPR_HIP(hipMemcpyAsync(g->ctl_host->n_local + 3, cpre_out + nk, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    DFPR_HIP(hipMemcpyAsync(g->ctl_host->n_local + 4, cpre_in + nk, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     DFPR_HIP(hipStreamSynchronize(s));
     if (h[4] & 1) {  // nothing was touched: a rejected batch has no effective entries
       set_error("vertex id outside [0, %d) in batch", n);
@@ -1660,37 +1753,42 @@ int graph_apply(dfpr_graph* g, int64_t nd, const int32_t* del_src, const int32_t
   }
   const int64_t rows_out = g->ctl_host->n_local[0], rows_in = g->ctl_host->n_local[1];
   const int32_t pad = n;
+  const unsigned g_out = grid_for(g->ctl_host->n_local[3], 1, 16384);  // one workgroup per work item
+  const unsigned g_in = grid_for(g->ctl_host->n_local[4], 1, 16384);
   if (path == kRowLocal) {
-    // old neighbours of the touched rows go to the idle rebuild targets
+    // the old neighbours of the touched rows are saved to the idle rebuild
+    // targets, then merged back into their rows
     DFPR_TRY(ep.start(&tok));
-    k_row_merge<<<grid_for(rows_out, 1, 65536), 256, 0, s>>>(heads_out, nl, eff_out, cnt, pre_out, b, g->out_deg, 0,
-                                                             g->out.off, g->out.idx, g->out2.idx, g->out.off,
-                                                             g->out.idx, pad);
+    k_row_save<<<g_out, 256, 0, s>>>(heads_out, nl, cpre_out, eff_out, cnt, pre_out, b, g->out_deg, g->out.off,
+                                     g->out.idx, g->out2.idx);
+    k_row_merge<<<g_out, 256, 0, s>>>(heads_out, nl, cpre_out, eff_out, cnt, pre_out, b, g->out_deg, 0, g->out.off,
+                                      g->out2.idx, g->out.off, g->out.idx, pad);
     DFPR_TRY(ep.stop(kTRebuildOut, tok));
     DFPR_TRY(ep.start(&tok));
-    k_row_merge<<<grid_for(rows_in, 1, 65536), 256, 0, s>>>(heads_in, nl + 1, eff_in, cnt, pre_in, b, g->in_deg, 0,
-                                                            g->in.off, g->in.idx, g->in2.idx, g->in.off, g->in.idx,
-                                                            pad);
+    k_row_save<<<g_in, 256, 0, s>>>(heads_in, nl + 1, cpre_in, eff_in, cnt, pre_in, b, g->in_deg, g->in.off,
+                                    g->in.idx, g->in2.idx);
+    k_row_merge<<<g_in, 256, 0, s>>>(heads_in, nl + 1, cpre_in, eff_in, cnt, pre_in, b, g->in_deg, 0, g->in.off,
+                                     g->in2.idx, g->in.off, g->in.idx, pad);
     DFPR_TRY(ep.stop(kTRebuildIn, tok));
     k_update_degrees<<<grid_for(nk, 256, 65536), 256, 0, s>>>(eff_out, cnt, b, counters + 4, g->out_deg, g->in_deg);
   } else if (path == kRelaid) {
     // new degrees first: they size the new rows (untouched rows keep theirs)
     k_update_degrees<<<grid_for(nk, 256, 65536), 256, 0, s>>>(eff_out, cnt, b, counters + 4, g->out_deg, g->in_deg);
-    const unsigned gr = grid_for(n, 256, 65536);
+    const int64_t total = g->m + h[0] - h[1] + (int64_t)n * g->slack;
+    const unsigned gr = grid_for(total, kRelayTile, 65536);
     DFPR_TRY(ep.start(&tok));
     DFPR_TRY(scan_generic(LoadPadded{g->out_deg, g->slack}, StoreOff{g->out2.off}, n, g->scan_tmp, s));
-    k_relayout<<<gr, 256, 0, s>>>(g->out.off, g->out.idx, g->out_deg, g->out2.off, g->out2.idx, n, pad,
+    k_relayout<<<gr, 256, 0, s>>>(g->out.off, g->out.idx, g->out_deg, g->out2.off, g->out2.idx, n, total, pad,
                                   g->touched_out);
-    k_row_merge<<<grid_for(rows_out, 1, 65536), 256, 0, s>>>(heads_out, nl, eff_out, cnt, pre_out, b, g->out_deg, 1,
-                                                             g->out.off, g->out.idx, nullptr, g->out2.off,
-                                                             g->out2.idx, pad);
+    k_row_merge<<<g_out, 256, 0, s>>>(heads_out, nl, cpre_out, eff_out, cnt, pre_out, b, g->out_deg, 1, g->out.off,
+                                      g->out.idx, g->out2.off, g->out2.idx, pad);
     DFPR_TRY(ep.stop(kTRebuildOut, tok));
     DFPR_TRY(ep.start(&tok));
     DFPR_TRY(scan_generic(LoadPadded{g->in_deg, g->slack}, StoreOff{g->in2.off}, n, g->scan_tmp, s));
-    k_relayout<<<gr, 256, 0, s>>>(g->in.off, g->in.idx, g->in_deg, g->in2.off, g->in2.idx, n, pad, g->touched_in);
-    k_row_merge<<<grid_for(rows_in, 1, 65536), 256, 0, s>>>(heads_in, nl + 1, eff_in, cnt, pre_in, b, g->in_deg, 1,
-                                                            g->in.off, g->in.idx, nullptr, g->in2.off, g->in2.idx,
-                                                            pad);
+    k_relayout<<<gr, 256, 0, s>>>(g->in.off, g->in.idx, g->in_deg, g->in2.off, g->in2.idx, n, total, pad,
+                                  g->touched_in);
+    k_row_merge<<<g_in, 256, 0, s>>>(heads_in, nl + 1, cpre_in, eff_in, cnt, pre_in, b, g->in_deg, 1, g->in.off,
+                                     g->in.idx, g->in2.off, g->in2.idx, pad);
     DFPR_TRY(ep.stop(kTRebuildIn, tok));
     k_finish_apply<<<1, 1, 0, s>>>(g->out2.off, n, counters);
   } else {
@@ -1791,7 +1889,7 @@ namespace dfpr {
 // that device current) and only that address reaches kernels.  Every call on
 // a device uses the same array; a per-device lock, held until the call's work
 // has finished on its stream, serialises the calls of this process.
-constexpr size_t kNoallocBytes = (size_t)32 << 20;
+constexpr size_t kNoallocBytes = (size_t)40 << 20;
 __device__ __align__(256) unsigned char noalloc_scratch[kNoallocBytes];
 
 namespace {
@@ -1825,7 +1923,8 @@ int graph_apply_noalloc(dfpr_graph* g, int64_t nd, const int32_t* del_src, const
       r((radix_hist_elems(nk) + std::max(radix_scan_tmp_elems(nk), scan_tmp_elems(nk + 1))) * sizeof(int64_t));
   const size_t b_pre = r(3 * (size_t)(nk + 1) * sizeof(int64_t));
   const size_t b_in = where == DFPR_HOST ? r(2 * (size_t)nk * sizeof(int32_t)) : 0;
-  const size_t need = 2 * r(n8) + b_keys_c + b_hist + b_pre + b_in;
+  const size_t b_work = g->slack > 0 ? r(2 * (size_t)(nk + 1) * sizeof(int64_t)) : 0;
+  const size_t need = 2 * r(n8) + b_keys_c + b_hist + b_pre + b_in + b_work;
   if (need > kNoallocBytes) {
     set_error("allocation-free apply: %zu scratch bytes needed, %zu available", need, kNoallocBytes);
     return DFPR_EINVAL;
@@ -1839,11 +1938,11 @@ int graph_apply_noalloc(dfpr_graph* g, int64_t nd, const int32_t* del_src, const
   char* base = static_cast<char*>(g_noalloc_ptr[dev]);
   // views over the array, sized as the apply's ensure() calls ask, so none of
   // them allocates; the handle's own buffers are put back afterwards
-  DevBuf* bufs[6] = {&g->keys_a, &g->keys_b, &g->keys_c, &g->sort_hist, &g->eff_pre, &g->batch_in};
-  const size_t sizes[6] = {r(n8), r(n8), b_keys_c, b_hist, b_pre, b_in};
-  DevBuf saved[6];
+  DevBuf* bufs[7] = {&g->keys_a, &g->keys_b, &g->keys_c, &g->sort_hist, &g->eff_pre, &g->batch_in, &g->row_work};
+  const size_t sizes[7] = {r(n8), r(n8), b_keys_c, b_hist, b_pre, b_in, b_work};
+  DevBuf saved[7];
   size_t off = 0;
-  for (int i = 0; i < 6; i++) {
+  for (int i = 0; i < 7; i++) {
     saved[i] = *bufs[i];
     bufs[i]->p = sizes[i] ? base + off : nullptr;
     bufs[i]->bytes = sizes[i];
@@ -1855,7 +1954,7 @@ int graph_apply_noalloc(dfpr_graph* g, int64_t nd, const int32_t* del_src, const
   const int rc = graph_apply(g, nd, del_src, del_dst, ni, ins_src, ins_dst, where, s, info);
   (void)hipStreamSynchronize(s);  // the array is free for the next call only once this one's work is done
   g->timing = timing;
-  for (int i = 0; i < 6; i++) *bufs[i] = saved[i];
+  for (int i = 0; i < 7; i++) *bufs[i] = saved[i];
   return rc;
 }
 

@@ -250,7 +250,7 @@ Request* pick(dfpr_server* sv) {
 
 const std::initializer_list<DevBuf dfpr_graph::*> kApplyBufs = {
     &dfpr_graph::keys_a, &dfpr_graph::keys_b, &dfpr_graph::keys_c, &dfpr_graph::sort_hist,
-    &dfpr_graph::eff_pre, &dfpr_graph::batch_in, &dfpr_graph::keys_in};
+    &dfpr_graph::eff_pre, &dfpr_graph::batch_in, &dfpr_graph::keys_in, &dfpr_graph::row_work};
 
 int serve(dfpr_server* sv, Request* q, hipStream_t s) {
   Resident& r = sv->graphs[q->gid];

@@ -199,3 +199,36 @@ def test_slack_batched_members():
         g.apply_batch(*batches[k])
         rk, st = g.update_ranks("dfp", bg.member(r_prev, k).clone())
         assert torch.equal(bg.member(r, k), rk), k
+
+
+def test_slack_long_rows_in_chunks():
+    """A hub row longer than one merge work item (4096 neighbours) in both
+    CSRs: changed in place, then past its free slots (re-laid out)."""
+    torch_cuda()
+    n, s, d = hub_graph(20000, 9000, 10000, 20000, seed=40)
+    t = Twin(n, s, d, 2)
+    og = t.slack.og
+    hub_out = og.out_idx[og.out_off[0]:og.out_off[1]]
+    hub_in = og.in_idx[og.in_off[0]:og.in_off[1]]
+    assert len(hub_out) > 2 * 4096 and len(hub_in) > 2 * 4096
+    new_out = np.setdiff1d(np.arange(1, n), hub_out)[[3, 500, 9000]]
+    new_in = np.setdiff1d(np.arange(1, n), hub_in)[[7, 800]]
+    ds = np.concatenate([np.zeros(4, np.int32), hub_in[[100, 5000, 8000]]])
+    dd = np.concatenate([hub_out[[50, 4100, 4097, 9999]], np.zeros(3, np.int32)])
+    is_ = np.concatenate([np.zeros(3, np.int32), new_in])
+    id_ = np.concatenate([new_out, np.zeros(2, np.int32)])
+    info = t.apply(ds, dd, is_, id_)
+    assert info["row_local"] == 1
+    r = O.rank("static", t.slack.og).ranks
+    t.rank("dfp", r)
+    og = t.slack.og
+    hub_out = og.out_idx[og.out_off[0]:og.out_off[1]]
+    new_out = np.setdiff1d(np.arange(1, n), hub_out)[[1, 2, 4000, 7000, 9000]]
+    info = t.apply([0], [hub_out[6000]], np.zeros(5, np.int32), new_out, device=True)
+    assert info["row_local"] == 0  # 4 net insertions, 2 free slots: laid out again
+    t.rank("dfp", r)
+    og = t.slack.og
+    hub_in = og.in_idx[og.in_off[0]:og.in_off[1]]
+    info = t.apply([], [], np.setdiff1d(np.arange(1, n), hub_in)[[11, 12]], np.zeros(2, np.int32))
+    assert info["row_local"] == 1  # fresh free slots after the re-layout
+    t.rank("df", r)

@@ -371,7 +371,8 @@ def bench_serving(args):
             n, s, d = W.rmat_graph(sc, 16, seed=args.seed * 131 + k)
             mine = np.nonzero(owners == k)[0]
             ch = chained_batches(n, s, d, fracs[mine], len(mine), seed=args.seed * 7 + k)
-            g = dfpr.Graph.from_coo(n, torch.from_numpy(s).to("cuda"), torch.from_numpy(d).to("cuda"))
+            g = dfpr.Graph.from_coo(n, torch.from_numpy(s).to("cuda"), torch.from_numpy(d).to("cuda"),
+                                    row_slack=args.row_slack)
             m_res += g.m
             gid = srv.add_graph(g)
             graphs.append((gid, n, ch))
@@ -414,17 +415,19 @@ def bench_serving(args):
         th = threading.Thread(target=submitter)
         t_begin = time.perf_counter()
         th.start()
+        local = 0
         for i in range(per_run):
             while tickets[i] is None:
                 time.sleep(0.0002)
             _, st, info, lat[i], _ = srv.wait(tickets[i])
+            local += info["row_local"]
         t_end = time.perf_counter()
         th.join()
         el = t_end - t_begin
         return {"rate_per_s": rate, "arrival_rate_actual": per_run / max(span[1] - span[0], 1e-9), "lanes": lanes,
                 "requests": per_run, "p50_ms": pct(lat, 50),
                 "p99_ms": pct(lat, 99), "mean_ms": float(np.mean(lat)), "updates_per_s": per_run / el,
-                "batch_edges_per_s": sum(edges) / el, "elapsed_s": el}
+                "batch_edges_per_s": sum(edges) / el, "elapsed_s": el, "row_local_applies": local}
 
     results = []
     for rate in rates:
@@ -454,7 +457,8 @@ def bench_serving(args):
                                + ", ".join(f"{c}x{sc}" for sc, c in mix) + "), Poisson arrivals, graph uniform, "
                                "batch f log-uniform in [1e-6, 1e-3] of |E|, 80/20, DF-P per request",
                    "edges_resident": int(m_res), "lanes": args.lanes, "heap_gib": args.heap_gb,
-                   "requests_per_rate": per_run, "parallelism": "1 GPU"},
+                   "requests_per_rate": per_run, "parallelism": "1 GPU",
+                   **({"row_slack": args.row_slack} if args.row_slack else {})},
         "by_rate": results,
         "server_stats": st,
     }

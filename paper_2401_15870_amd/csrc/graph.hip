@@ -1592,7 +1592,11 @@ int graph_set_row_slack(dfpr_graph* g, int32_t slack, hipStream_t s) {
     set_error("%lld slots exceed int32 edge offsets", (long long)want);
     return DFPR_EINVAL;
   }
-  if (want > g->cap) DFPR_TRY(grow_capacity(g, want, s));
+  if (want + want / 8 > g->cap) DFPR_TRY(grow_capacity(g, want, s));  // room for insertions, as at create
+  // the general rebuild packs every row entry, pads included, into a batch
+  // key with id_bits per column: the pad id n must fit, or its key would read
+  // as the first key of the next row
+  if (slack > 0) g->id_bits = std::max(g->id_bits, bits_for((int64_t)n + 1));
   const unsigned gr = grid_for(want, kRelayTile, 65536);
   DFPR_TRY(scan_generic(LoadPadded{g->out_deg, slack}, StoreOff{g->out2.off}, n, g->scan_tmp, s));
   k_relayout<<<gr, 256, 0, s>>>(g->out.off, g->out.idx, g->out_deg, g->out2.off, g->out2.idx, n, want, n, nullptr);

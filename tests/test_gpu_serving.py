@@ -63,17 +63,17 @@ def _alone(graphs, chains, fused_limit=None):
     return res
 
 
-def _handle(m, n, s, d, fused_limit):
-    g = m.Graph.from_coo(n, s, d)
+def _handle(m, n, s, d, fused_limit, row_slack=0):
+    g = m.Graph.from_coo(n, s, d, row_slack=row_slack)
     if fused_limit is not None:
         g.set_fused_limit(fused_limit)
     return g
 
 
-def _serve(graphs, chains, heap_bytes, lanes, fused_limit=None):
+def _serve(graphs, chains, heap_bytes, lanes, fused_limit=None, row_slack=0):
     m = dfpr()
     srv = m.Server(heap_bytes, lanes=lanes)
-    gids = [srv.add_graph(_handle(m, n, s, d, fused_limit)) for n, s, d in graphs]
+    gids = [srv.add_graph(_handle(m, n, s, d, fused_limit, row_slack)) for n, s, d in graphs]
     resident = srv.stats()["heap_used"]  # the graphs' CSRs live in the heap
     r0 = [srv.ranks(g) for g in gids]
     tickets = []
@@ -83,12 +83,15 @@ def _serve(graphs, chains, heap_bytes, lanes, fused_limit=None):
             tickets.append((k, t, srv.submit(gid, *chains[k][t], want_ranks=True)))
     out = [[r0[k]] + [None] * steps for k in range(len(graphs))]
     lat = []
+    local = 0
     for k, t, tk in tickets:
         r, st, info, ms, qms = srv.wait(tk)
         out[k][t + 1] = r
         lat.append(ms)
+        local += info["row_local"]
     stats = srv.stats()
     stats["resident_bytes"] = resident
+    stats["row_local_applies"] = local
     final = [srv.ranks(g) for g in gids]
     srv.close()
     return out, stats, final, lat
@@ -126,6 +129,26 @@ def test_serving_alone_vs_mix_multilaunch():
     assert stats["completed"] == stats["submitted"] == len(graphs) * len(chains[0])
     assert stats["failed"] == 0 and stats["heap_used"] == stats["resident_bytes"]
     assert stats["peak_in_flight"] > 1
+    for k in range(len(graphs)):
+        for t in range(len(chains[k]) + 1):
+            assert np.array_equal(got[k][t], ref[k][t]), (k, t, float(np.abs(got[k][t] - ref[k][t]).max()))
+        assert np.array_equal(final[k], ref[k][-1])
+
+
+def test_serving_alone_vs_mix_row_slack():
+    """Served graphs laid out with free slots per row: small batches merge
+    into the rows they touch (in the heap-held CSRs, saving old neighbours in
+    the request's borrowed targets); results equal the packed plain handles'
+    bit for bit."""
+    torch_cuda()
+    graphs = _graphs(5)
+    chains = _chains(graphs, 4, seed=5)
+    ref = _alone(graphs, chains)
+    got, stats, final, lat = _serve(graphs, chains, heap_bytes=256 << 20, lanes=4, row_slack=2)
+    _print("  serving with row slack: stats", stats)
+    assert stats["completed"] == stats["submitted"] == len(graphs) * len(chains[0])
+    assert stats["failed"] == 0 and stats["heap_used"] == stats["resident_bytes"]
+    assert stats["row_local_applies"] > 0
     for k in range(len(graphs)):
         for t in range(len(chains[k]) + 1):
             assert np.array_equal(got[k][t], ref[k][t]), (k, t, float(np.abs(got[k][t] - ref[k][t]).max()))

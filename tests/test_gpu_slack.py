@@ -232,3 +232,32 @@ def test_slack_long_rows_in_chunks():
     info = t.apply([], [], np.setdiff1d(np.arange(1, n), hub_in)[[11, 12]], np.zeros(2, np.int32))
     assert info["row_local"] == 1  # fresh free slots after the re-layout
     t.rank("df", r)
+
+
+def test_slack_power_of_two_vertex_count():
+    """n a power of two: the pad id n needs one id bit more than the vertices.
+    Rows next to rows that lose their edge to vertex 0 in a large batch (the
+    general rebuild, which keys pads like entries) keep their pads, and later
+    small batches and large batches still give the oracle's CSRs."""
+    torch_cuda()
+    n, s, d = hub_graph(4096, 900, 1200, 8000, seed=41)
+    t = Twin(n, s, d, 2)
+    og = t.slack.og
+    to0 = og.in_idx[og.in_off[0]:og.in_off[1]]
+    to0 = to0[to0 > 0][:60]
+    for step in range(3):
+        og = t.slack.og
+        ds, dd, is_, id_ = W.batch_8020(n, og.esrc, og.edst, 3e-2, seed=42 + step)
+        if step == 0:
+            ds = np.concatenate([ds, to0]).astype(np.int32)
+            dd = np.concatenate([dd, np.zeros(len(to0), np.int32)])
+        info = t.apply(ds, dd, is_, id_)
+        assert info["row_local"] == 0
+        og = t.slack.og
+        ds, dd, is_, id_ = W.batch_8020(n, og.esrc, og.edst, 2e-4, seed=52 + step)
+        t.apply(ds, dd, is_, id_)
+    r = O.rank("static", t.slack.og).ranks
+    og = t.slack.og
+    ds, dd, is_, id_ = W.batch_8020(n, og.esrc, og.edst, 1e-3, seed=60)
+    t.apply(ds, dd, is_, id_)
+    t.rank("dfp", r)

@@ -486,10 +486,18 @@ def bench_temporal(args):
     s0, d0 = torch.from_numpy(src[:k0]).to(dev), torch.from_numpy(dst[:k0]).to(dev)
     modes = ("dfp", "df", "nd")
     gs = {m: dfpr.Graph.from_coo(n, s0, d0, row_slack=args.row_slack) for m in modes + ("static",)}
-    if not args.no_autotune:
+    if args.fused_limit is not None:
+        for g in gs.values():
+            g.set_fused_limit(args.fused_limit)
+    if args.bounds:
+        bounds = [int(x) for x in args.bounds.split(",")]
+        for m in modes + ("static",):
+            gs[m].set_tuning(bounds)
+    elif not args.no_autotune:
         bounds, _ = gs["dfp"].autotune()
         for m in modes + ("static",):
             gs[m].set_tuning(bounds)
+    log(f"bin bounds {gs['dfp'].get_tuning()}")
     m0 = gs["dfp"].m
     r0, _ = gs["static"].update_ranks("static", None)
     ranks = {m: r0.clone() for m in modes}
@@ -525,6 +533,7 @@ def bench_temporal(args):
             it[m].append(st["iterations"])
             if m == "dfp":
                 ever.append(st["ever_affected"])
+                dfp_st = st
         if b < oracle_steps:
             og2, ob = O.apply(og, [], [], ins_s, ins_d)
             r_or = O.rank("dfp", og2, r_or, og, ob).ranks
@@ -532,7 +541,9 @@ def bench_temporal(args):
             drift.append(float(np.abs(ranks["dfp"].cpu().numpy() - r_or).max()))
         if b % 10 == 0 or b + 1 == steps:
             log(f"batch {b}: apply {apply_ms[-1]:.2f} ms, dfp {ms['dfp'][-1]:.2f} ({it['dfp'][-1]} it), "
-                f"df {ms['df'][-1]:.2f}, nd {ms['nd'][-1]:.2f}, static {ms['static'][-1]:.2f} ms"
+                f"df {ms['df'][-1]:.2f}, nd {ms['nd'][-1]:.2f}, static {ms['static'][-1]:.2f} ms; dfp "
+                f"processed {dfp_st['vertex_updates']} pulled {dfp_st['edges_pulled']} "
+                f"dense its {dfp_st['dense_iterations']} bins {dfp_st['bin_edges']}"
                 + (f", drift vs oracle chain {drift[-1]:.2e}" if b < oracle_steps else ""))
     step = [a + r for a, r in zip(apply_ms, ms["dfp"])]
     res = {
@@ -797,6 +808,9 @@ def main():
                          "(default: the library's)")
     ap.add_argument("--row-slack", type=int, default=0,
                     help="free slots after every CSR row: small batches then merge into the rows they touch")
+    ap.add_argument("--fused-limit", type=int, default=None,
+                    help="edge count up to which a rank update runs in one cooperative launch (library default)")
+    ap.add_argument("--bounds", default=None, help="temporal: in-degree bin thresholds a,b,c,d,e instead of autotuning")
     ap.add_argument("--static-runs", type=int, default=3)
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--calib", action="store_true",
@@ -868,6 +882,8 @@ def main():
     g = dfpr.Graph.from_coo(n, torch.from_numpy(src).to(dev), torch.from_numpy(dst).to(dev),
                             row_slack=args.row_slack)
     m0 = g.m
+    if args.fused_limit is not None:
+        g.set_fused_limit(args.fused_limit)
     torch.cuda.synchronize()
     log(f"create: m={m0} row slack {args.row_slack} {time.time() - t0:.2f}s")
     dev_batches = [tuple(torch.from_numpy(a).to(dev) for a in b) for b in batches]

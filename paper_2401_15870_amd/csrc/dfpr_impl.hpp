@@ -162,7 +162,8 @@ enum AccRow : int {
   kAccXEdges = kBins + 3,  // dense pull: summed out-degree of the expanding vertices
   kAccStayEdges = kBins + 4,  // dense pull: summed in-degree of the kept vertices
   kAccOutEdges = kBins + 5,   // binning pass: summed out-degree of the binned vertices
-  kAccRows = kBins + 6
+  kAccCarry = kBins + 6,      // dense pull: unprocessed vertices whose rank was copied over
+  kAccRows = kBins + 7
 };
 
 // Per-update control block in device memory.  The compact head is read back
@@ -182,6 +183,7 @@ struct IterCtl {
   int64_t dense_sedges;      // dense pull: summed in-degree of its kept vertices
   int64_t active;            // member graphs not yet converged (1/0 for a plain graph)
   int64_t bin_out_edges;     // summed out-degree of the vertices of the last binning pass
+  int64_t dense_carry;       // dense pull: unprocessed vertices whose rank was copied over
   // single-launch loop outcome: iterations, converged, last L-inf change (bits)
   int64_t fused_iters, fused_converged;
   unsigned long long fused_last;

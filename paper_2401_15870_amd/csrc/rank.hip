@@ -44,7 +44,9 @@ struct PullArgs {
   const uint8_t* x_in;
   uint8_t* stay_out;
   uint8_t* x_out;
-  uint8_t* ever;
+  uint8_t* ever;    // processed in this update: the stamp of the last dense iteration that did (else 1)
+  int stamp;        // dense: this iteration's stamp (1 .. 255)
+  int carry;        // dense: the previous dense iteration's stamp, 0 before the first one
   int use_x;
   unsigned long long* gslots;  // spread L-inf slots: member g, sub j at (g * gsub + j) * kSlotStride
   int gsub;
@@ -60,6 +62,10 @@ struct PullArgs {
   int crit;      // DFPR_CRIT_*
   double* cmut;  // frontier form, asynchronous: contributions updated in the pull (else null)
 };
+
+// Stamp of dense iteration `it` in the ever array: nonzero, 254 values in turn
+// (a vertex last processed 254 iterations back only costs a needless copy).
+__host__ __device__ inline int dense_stamp(int it) { return 2 + it % 254; }
 
 // Bin k covers worklist [lo[k], hi[k]) and workgroups [blk[k], blk[k+1]).
 struct PullLayout {
@@ -126,6 +132,7 @@ struct Acc {
   double mx = 0.0;                          // L-inf change (plain graph)
   int64_t cnt = 0, aedges = 0, xedges = 0, sedges = 0;  // dense: affected, their in-edges, expander
                                                         // out-edges, kept vertices' in-edges
+  int64_t carry = 0;                                    // dense: unprocessed vertices copied over
   GTab* tab = nullptr;                      // per-member maxima (batch)
 };
 __device__ __forceinline__ void acc_dr(Acc& acc, const PullArgs& a, int g, double dr) {
@@ -140,9 +147,17 @@ __device__ __forceinline__ bool member_done(const PullArgs& a, int g) { return a
 template <int MODE, bool DENSE>
 __device__ __forceinline__ void vertex_finish(const PullArgs& a, const VCtx& x, double c, bool aff, Acc& acc) {
   if (!aff) {  // not processed (unaffected, or its member converged): carry over
-    if (DENSE || MODE == kSync) {
+    // The dense form ping-pongs its rank and contribution vectors, so the
+    // vector written now already holds the vertex's current values unless
+    // the previous iteration processed it (its ever stamp) or this is the
+    // first dense iteration since the vectors were last in step (carry 0).
+    if (MODE == kSync) {
       a.Rw[x.v] = x.Rv;
       a.cw[x.v] = x.selfc;
+    } else if (DENSE && (a.carry == 0 || a.ever[x.v] == (uint8_t)a.carry)) {
+      a.Rw[x.v] = x.Rv;
+      a.cw[x.v] = x.selfc;
+      acc.carry++;
     }
     if (DENSE) {
       a.stay_out[x.v] = 0;
@@ -173,7 +188,7 @@ __device__ __forceinline__ void vertex_finish(const PullArgs& a, const VCtx& x, 
     a.cw[x.v] = r / d;
     a.stay_out[x.v] = stay;
     a.x_out[x.v] = expand;
-    a.ever[x.v] = 1;
+    a.ever[x.v] = (uint8_t)a.stamp;
     acc.cnt++;
     acc.aedges += x.e - x.s;
     if (expand) acc.xedges += (int64_t)d;
@@ -194,15 +209,16 @@ __device__ __forceinline__ void vertex_finish(const PullArgs& a, const VCtx& x, 
 template <bool DENSE>
 __device__ __forceinline__ void block_acc_to_slots(Acc acc, const PullArgs& a) {
   __shared__ double shm[1024 / kWave];
-  __shared__ int64_t shc[4][1024 / kWave];
+  __shared__ int64_t shc[5][1024 / kWave];
   const int w = threadIdx.x / kWave;
   const double m = wave_max(acc.mx);
-  int64_t c0 = 0, c1 = 0, c3 = 0;
+  int64_t c0 = 0, c1 = 0, c3 = 0, c4 = 0;
   const int64_t c2 = wave_sum_i64(acc.xedges);  // both forms: out-degree sum of the expanding vertices
   if (DENSE) {
     c0 = wave_sum_i64(acc.cnt);
     c1 = wave_sum_i64(acc.aedges);
     c3 = wave_sum_i64(acc.sedges);
+    c4 = wave_sum_i64(acc.carry);
   }
   if (lane_id() == 0) {
     shm[w] = m;
@@ -210,6 +226,7 @@ __device__ __forceinline__ void block_acc_to_slots(Acc acc, const PullArgs& a) {
     shc[1][w] = c1;
     shc[2][w] = c2;
     shc[3][w] = c3;
+    shc[4][w] = c4;
   }
   __syncthreads();
   if (acc.tab) {  // batch: flush the per-member maxima (all threads reached the barrier above)
@@ -219,13 +236,14 @@ __device__ __forceinline__ void block_acc_to_slots(Acc acc, const PullArgs& a) {
   }
   if (threadIdx.x == 0) {
     double mm = 0.0;
-    int64_t t0 = 0, t1 = 0, t2 = 0, t3 = 0;
+    int64_t t0 = 0, t1 = 0, t2 = 0, t3 = 0, t4 = 0;
     for (int i = 0; i < (int)(blockDim.x / kWave); i++) {
       mm = fmax(mm, shm[i]);
       t0 += shc[0][i];
       t1 += shc[1][i];
       t2 += shc[2][i];
       t3 += shc[3][i];
+      t4 += shc[4][i];
     }
     const int slot = (blockIdx.x % kSlots) * kSlotStride;
     if (mm > 0.0)
@@ -236,6 +254,7 @@ __device__ __forceinline__ void block_acc_to_slots(Acc acc, const PullArgs& a) {
       if (t0) atomicAdd(&a.acc[kAccCnt * kRow + slot], (unsigned long long)t0);
       if (t1) atomicAdd(&a.acc[kAccAffEdges * kRow + slot], (unsigned long long)t1);
       if (t3) atomicAdd(&a.acc[kAccStayEdges * kRow + slot], (unsigned long long)t3);
+      if (t4) atomicAdd(&a.acc[kAccCarry * kRow + slot], (unsigned long long)t4);
     }
   }
 }
@@ -647,6 +666,8 @@ __global__ void __launch_bounds__(256) k_fused_loop(PullArgs a0, const int32_t* 
       c->fused_act[((it + 1) % 3) * kSlotStride] = 0ull;
     }
     if (!batch) a.gslots = &c->fused_dr[(it % 3) * kSlotStride];
+    a.stamp = dense_stamp(it);
+    a.carry = it == 0 ? 0 : dense_stamp(it - 1);  // the vectors are in step after the first iteration
     for (int vb = blockIdx.x; vb < total; vb += gridDim.x) {
       if (BATCH) {
         int p = 0, b = vb;
@@ -1137,6 +1158,7 @@ __global__ void __launch_bounds__(kSlots) k_iter_finish(IterCtl* c) {
     c->dense_xedges = r[kAccXEdges];
     c->dense_sedges = r[kAccStayEdges];
     c->bin_out_edges = r[kAccOutEdges];
+    c->dense_carry = r[kAccCarry];
     c->big_count = 0;
   }
 }
@@ -1180,10 +1202,17 @@ __global__ void k_scatter_ranks(const double* R, const int32_t* __restrict__ inv
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     r_ext[inv[i]] = R[i];
 }
+// Nonzero bytes of a word.
+__device__ __forceinline__ int nonzero_bytes(unsigned long long w) {
+  w |= w >> 4;
+  w |= w >> 2;
+  w |= w >> 1;
+  return __popcll(w & 0x0101010101010101ull);
+}
 // End of an update: clears up to four byte-flag arrays of n entries (null ones
-// skipped) and, when `ever` is given, counts its set entries (each 0 or 1)
-// into the ever accumulator and clears it, 16 bytes per thread (the arrays
-// are 256-byte aligned), in one pass.
+// skipped) and, when `ever` is given, counts its nonzero entries (processed
+// vertices; a dense iteration leaves its stamp) into the ever accumulator and
+// clears it, 16 bytes per thread (the arrays are 256-byte aligned), in one pass.
 __global__ void __launch_bounds__(256) k_clear_flags(uint8_t* f0, uint8_t* f1, uint8_t* f2, uint8_t* f3, uint8_t* ever,
                                                      int32_t n, unsigned long long* acc) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -1198,7 +1227,7 @@ __global__ void __launch_bounds__(256) k_clear_flags(uint8_t* f0, uint8_t* f1, u
     if (f3) reinterpret_cast<uint4*>(f3)[i] = z;
     if (ever) {
       const uint4 e = reinterpret_cast<const uint4*>(ever)[i];
-      c += __popcll(((unsigned long long)e.y << 32) | e.x) + __popcll(((unsigned long long)e.w << 32) | e.z);
+      c += nonzero_bytes(((unsigned long long)e.y << 32) | e.x) + nonzero_bytes(((unsigned long long)e.w << 32) | e.z);
       reinterpret_cast<uint4*>(ever)[i] = z;
     }
   }
@@ -1208,7 +1237,7 @@ __global__ void __launch_bounds__(256) k_clear_flags(uint8_t* f0, uint8_t* f1, u
     if (f2) f2[v] = 0;
     if (f3) f3[v] = 0;
     if (ever) {
-      c += ever[v];
+      c += ever[v] != 0;
       ever[v] = 0;
     }
   }
@@ -1385,6 +1414,8 @@ static PullArgs make_args(dfpr_graph* g, const dfpr_params& p) {
   a.tf = p.frontier_tol;
   a.tp = p.prune_tol;
   a.crit = p.criterion;
+  a.stamp = 1;
+  a.carry = 0;  // every unprocessed vertex is copied over unless a dense loop says otherwise
   return a;
 }
 
@@ -1748,7 +1779,8 @@ static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_pre
     const IterCtl* h = g->ctl_host;
     st->vertex_updates += h->dense_cnt;
     st->edges_pulled += h->dense_edges;
-    st->pull_bytes += (double)fr.iters * (31.0 * n + 5.0 * (double)m) + 8.0 * (double)h->dense_edges;
+    st->pull_bytes += (double)fr.iters * (24.0 * n + 5.0 * (double)m) +
+                      8.0 * (double)(h->dense_cnt + h->dense_carry) + 8.0 * (double)h->dense_edges;
     st->dense_iterations += fr.iters;
     st->iterations = fr.iters;
     st->converged = fr.converged ? 1 : 0;
@@ -1771,10 +1803,12 @@ static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_pre
   int it = 0;
   double dR = 0.0;
   bool conv = false;
+  int carry = 0;  // stamp of the previous dense iteration (0: the vectors are not in step)
   for (it = 0; it < p.max_iters; it++) {
     if (!dense && front_cnt > 0 && prefer_dense(p.dense_switch, m, n, front_edges, mark_edges)) {
       dense = true;  // the complete frontier is in `cur`; no expand flags to read
       use_x = false;
+      carry = 0;     // the frontier form updated one vector in place
     }
     if (dense) {
       DFPR_TRY(ensure_all_bins(g, s));
@@ -1789,14 +1823,18 @@ static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_pre
       a.x_out = xb;
       a.ever = g->ever;
       a.use_x = use_x ? 1 : 0;
+      a.stamp = dense_stamp(it);
+      a.carry = async ? 0 : carry;
       DFPR_TRY((pull_parts<MODE, true>(g, a, s, st, false)));
+      carry = a.stamp;
       DFPR_TRY(dr_finish(g, p, it, s));
       DFPR_TRY(finish_and_read(g, s));
       const IterCtl* h = g->ctl_host;
       dR = bits_to_double(h->dR);
       st->vertex_updates += h->dense_cnt;
       st->edges_pulled += h->dense_edges;
-      st->pull_bytes += 31.0 * n + 5.0 * (double)m + 8.0 * (double)h->dense_edges;
+      st->pull_bytes += 24.0 * n + 8.0 * (double)(h->dense_cnt + h->dense_carry) + 5.0 * (double)m +
+                        8.0 * (double)h->dense_edges;
       st->dense_iterations++;
       if (!async) {
         std::swap(Ra, Rb);

@@ -237,6 +237,33 @@ def test_ranks_parity(mode, scale, frac, keep_ids):
     assert (r >= (1 - 0.85) / p.n).all()
 
 
+@pytest.mark.parametrize("fused", [False, True])
+def test_dense_form_long_runs(fused):
+    """A long dense run (the dense form copies an unprocessed vertex over only
+    when the previous iteration processed it, by the iteration stamps it keeps
+    in the ever array, 254 values in turn): with a rank tolerance of 1e-300 and
+    frontier and prune thresholds near the rounding level, DF-P runs until its
+    frontier dies out or for 300 iterations, pruning and re-marking vertices
+    all along; the dense form (in one launch, or per iteration) gives the
+    frontier form's bits and statistics."""
+    torch = torch_cuda()
+    p, r0 = _setup(11, 1e-2, seed=93)
+    kw = dict(tol=1e-300, max_iters=300, frontier_tol=1e-15, prune_tol=1e-15)
+    outs = {}
+    for sw in (float("inf"), 0.0):
+        p2 = Pair(p.n, p.og_prev.esrc, p.og_prev.edst, fused=fused and sw != 0.0)
+        p2.apply(p.batch.dm_src, p.batch.dm_dst, p.batch.dp_src, p.batch.dp_dst)
+        rp = torch.from_numpy(np.ascontiguousarray(r0)).cuda()
+        r, st = p2.g.update_ranks("dfp", rp, dense_switch=sw, **kw)
+        outs[sw] = (r.cpu().numpy(), st)
+    (rd, sd), (rf, sf) = outs[float("inf")], outs[0.0]
+    _print("long runs: iterations", sd["iterations"], "ever", sd["ever_affected"], "updates", sd["vertex_updates"])
+    assert sd["iterations"] == sf["iterations"] >= 100
+    for key in ("ever_affected", "vertex_updates", "edges_pulled"):
+        assert sd[key] == sf[key], key
+    assert np.array_equal(rd, rf)
+
+
 @pytest.mark.parametrize("frac", [1e-3, 1e-1])
 @pytest.mark.parametrize("mode", ["df", "dfp"])
 def test_dense_and_frontier_forms_agree(mode, frac):

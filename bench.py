@@ -804,8 +804,8 @@ def main():
                     help="DF/DF-P update ranks in place during iterations (not bit-reproducible)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (R0 from GPU Static)")
     ap.add_argument("--dense-switch", type=float, default=None,
-                    help="DF/DF-P: frontier in-edge share above which an iteration runs in the dense form "
-                         "(default: the library's)")
+                    help="DF/DF-P: weight of the cost rule that picks the dense form for an iteration "
+                         "(library default 1; inf: always dense, 0: never)")
     ap.add_argument("--row-slack", type=int, default=0,
                     help="free slots after every CSR row: small batches then merge into the rows they touch")
     ap.add_argument("--fused-limit", type=int, default=None,

@@ -16,6 +16,7 @@ import atexit
 import ctypes
 import sys
 import weakref
+from collections.abc import Sequence
 
 import numpy as np
 
@@ -236,6 +237,24 @@ class Graph:
         _check(lib().dfpr_set_timing(self._h, 1 if on else 0))
 
 
+class _Records(Sequence):
+    """Per-member results of a batch call, one dict per member, made when read
+    (a batch of hundreds of members returns without building them all)."""
+
+    __slots__ = ("_arr",)
+
+    def __init__(self, arr):
+        self._arr = arr
+
+    def __len__(self):
+        return len(self._arr)
+
+    def __getitem__(self, k):
+        if isinstance(k, slice):
+            return [self._arr[i].as_dict() for i in range(*k.indices(len(self._arr)))]
+        return self._arr[k].as_dict()
+
+
 def _ptr_array(items):
     """(void* array, where, keepalive) for a list of int32 id arrays (numpy or torch)."""
     parts = [_ids(a) for a in items]
@@ -310,7 +329,7 @@ class BatchGraph(Graph):
         _check(lib().dfpr_apply_batch_many(self._h, (ctypes.c_int64 * self.count)(*nds), ds, dd,
                                            (ctypes.c_int64 * self.count)(*nis), is_, id_, where,
                                            _stream_ptr(stream), info))
-        return [x.as_dict() for x in info]
+        return _Records(info)
 
     def update_ranks_many(self, mode, r_prev=None, out=None, stream=None, timing=False, **kw):
         """Update every member; returns (arena ranks, total stats, per-member stats)."""
@@ -332,7 +351,7 @@ class BatchGraph(Graph):
         rp = ctypes.c_void_p(r_prev.data_ptr()) if r_prev is not None else None
         _check(lib().dfpr_update_ranks_many(self._h, m, ctypes.byref(p), rp, ctypes.c_void_p(out.data_ptr()),
                                             _stream_ptr(stream), ctypes.byref(st), per))
-        return out, st.as_dict(), [x.as_dict() for x in per]
+        return out, st.as_dict(), _Records(per)
 
 
 class Server:

@@ -41,11 +41,17 @@ class BatchInfo(ctypes.Structure):
                 ("ms_rebuild", ctypes.c_double * 2), ("row_local", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
-        out = {}
-        for k, _ in self._fields_:
-            v = getattr(self, k)
-            out[k] = list(v) if hasattr(v, "__len__") else v
-        return out
+        return _as_dict(self)
+
+
+def _as_dict(rec, drop=("reserved", "reserved2")):
+    """Fields of a ctypes struct as a dict (arrays as lists), reserved fields left out."""
+    cls = type(rec)
+    names = cls.__dict__.get("_names")
+    if names is None:  # per class, once: (field, is_array)
+        names = tuple((k, hasattr(t, "_length_")) for k, t in cls._fields_ if k not in drop)
+        cls._names = names
+    return {k: (list(getattr(rec, k)) if arr else getattr(rec, k)) for k, arr in names}
 
 
 BINS = 6
@@ -61,13 +67,7 @@ class Stats(ctypes.Structure):
                 ("dense_iterations", ctypes.c_int32), ("reserved2", ctypes.c_int32)]
 
     def as_dict(self):
-        out = {}
-        for k, _ in self._fields_:
-            v = getattr(self, k)
-            out[k] = list(v) if hasattr(v, "__len__") else v
-        out.pop("reserved", None)
-        out.pop("reserved2", None)
-        return out
+        return _as_dict(self)
 
 
 class ServerStats(ctypes.Structure):

@@ -281,7 +281,16 @@ int dfpr_set_timing(dfpr_graph* g, int on);
  *
  * On a batch handle, dfpr_apply_batch is refused (EINVAL: its ids could join
  * members); dfpr_update_ranks works and reports totals only; dfpr_graph_size,
- * dfpr_graph_export and the tuning calls see the arena. */
+ * dfpr_graph_export and the tuning calls see the arena.
+ *
+ * Why an arena built at create, rather than calls over a list of existing
+ * plain handles: one launch can cover many members only when their CSRs,
+ * ranks and flags are one contiguous address range with one vertex numbering
+ * (the bins, worklists and chunk tables of the pull span all members), and
+ * gathering separately allocated graphs into such a range on every call would
+ * copy every graph every step.  The member set is therefore fixed for the
+ * handle's life: to add or drop members, create a new batch handle (a plain
+ * handle's graph can be exported and passed in). */
 
 /* Create a batch handle from `count` >= 1 member edge lists.  Member k has
  * n[k] >= 1 vertices and m[k] >= 0 pairs src[k][i] -> dst[k][i] with ids in
@@ -340,7 +349,14 @@ int dfpr_update_ranks_many(dfpr_graph* g, dfpr_mode mode, const dfpr_params* p, 
  * whose blocks exceed what the heap can ever free fails with ENOMEM.
  * Single-launch updates of different lanes share the device's budget of
  * resident workgroups.  Results are those of the plain entry points: a
- * graph's ranks do not depend on what else is in flight. */
+ * graph's ranks do not depend on what else is in flight.
+ *
+ * The mode and parameters are fixed at create and every graph's ranks stay
+ * resident in the server (each request continues from the result of the
+ * previous one on its graph, like the consecutive batch updates of Section
+ * 5.1.4); a request
+ * names the host array that receives a copy of its result, if any, instead of
+ * passing rank vectors in and out as dfpr_update_ranks does. */
 typedef struct dfpr_server dfpr_server;
 
 typedef struct {

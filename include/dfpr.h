@@ -354,9 +354,9 @@ int dfpr_update_ranks_many(dfpr_graph* g, dfpr_mode mode, const dfpr_params* p, 
  * The mode and parameters are fixed at create and every graph's ranks stay
  * resident in the server (each request continues from the result of the
  * previous one on its graph, like the consecutive batch updates of Section
- * 5.1.4); a request
- * names the host array that receives a copy of its result, if any, instead of
- * passing rank vectors in and out as dfpr_update_ranks does. */
+ * 5.1.4); a request names the host array that receives a copy of its result,
+ * if any, instead of passing rank vectors in and out as dfpr_update_ranks
+ * does. */
 typedef struct dfpr_server dfpr_server;
 
 typedef struct {

@@ -127,8 +127,9 @@ typedef struct {
   double ms_mark;                  /* initial marking kernels                           */
   /* Algorithmic bytes of all pull launches (every gather counted): frontier
    * pull 30 B per processed vertex + 12 B per pulled edge; Static/ND 36 B per
-   * vertex + 12 B per edge; dense DF/DF-P pull 31 B per vertex + 5 B per edge
-   * (index + expand flag) + 8 B per pulled edge. */
+   * vertex + 12 B per edge; dense DF/DF-P pull 24 B per vertex + 8 B per
+   * vertex whose rank it writes (processed, or copied over from the other
+   * vector) + 5 B per edge (index + expand flag) + 8 B per pulled edge. */
   double pull_bytes;
   int32_t dense_iterations;        /* iterations run in dense (all-vertex) mode         */
   int32_t reserved2;

@@ -92,3 +92,27 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(_capi.BatchInfo) == 6 * 8 + 4 * 8 + 2 * 4
     assert ctypes.sizeof(_capi.Stats) == 4 + 4 + 8 + 3 * 8 + 12 * 8 + 8 + 8 + 4 + 4 + 3 * 8 + 8 + 4 + 4
     assert ctypes.sizeof(_capi.ServerStats) == 5 * 8 + 4 * 4 + 3 * 8
+
+
+def test_per_member_records_and_struct_dicts():
+    """Per-member results of batch calls: one dict per member, made when read,
+    arrays as lists, reserved fields left out."""
+    import paper_2401_15870_amd as m
+    info = (_capi.BatchInfo * 3)()
+    for k in range(3):
+        info[k].ins_in = 10 + k
+        info[k].ms_rebuild[1] = 0.5 * k
+        info[k].row_local = k % 2
+    rec = m._Records(info)
+    assert len(rec) == 3
+    assert rec[1]["ins_in"] == 11 and rec[1]["row_local"] == 1 and rec[2]["ms_rebuild"] == [0.0, 1.0]
+    assert rec[-1]["ins_in"] == 12
+    assert [r["ins_in"] for r in rec] == [10, 11, 12]
+    assert [r["ins_in"] for r in rec[1:]] == [11, 12]
+    assert "reserved" not in rec[0]
+    st = _capi.Stats()
+    st.iterations = 7
+    st.bin_edges[5] = 9
+    d = st.as_dict()
+    assert d["iterations"] == 7 and d["bin_edges"] == [0, 0, 0, 0, 0, 9]
+    assert "reserved" not in d and "reserved2" not in d

@@ -346,11 +346,32 @@ __device__ __forceinline__ void pull_groups(const PullArgs& a, const int32_t* __
 
 // Strided sum (and expand-flag OR when want_x) over in_idx[s, e) by the 256
 // threads of a workgroup, combined in a fixed order; valid in thread 0.
+template <bool DEEP>
 __device__ __forceinline__ double block_row_sum(const PullArgs& a, const VCtx& x, int32_t s, int32_t e, bool want_sum,
                                                 bool want_x, int* any_out, double* sh, int* shx) {
   double part = 0.0;
   int any = 0;
   int32_t p = s + (int32_t)threadIdx.x;
+  // DEEP: eight loads in flight per thread (a workgroup on one long row has no
+  // other work to hide its latency; the dense form keeps four, its flag checks
+  // leave no registers for more); the thread's additions keep the order of its
+  // elements, so the sum is the same either way
+  for (; DEEP && p + 7 * 256 < e; p += 8 * 256) {
+    int32_t u[8];
+#pragma unroll
+    for (int t = 0; t < 8; t++) u[t] = ld_idx(a, p + t * 256);
+    if (want_x) {
+#pragma unroll
+      for (int t = 0; t < 8; t++) any |= a.x_in[u[t]];
+    }
+    if (want_sum) {
+      double xs[8];
+#pragma unroll
+      for (int t = 0; t < 8; t++) xs[t] = gx(a, u[t], x);
+#pragma unroll
+      for (int t = 0; t < 8; t++) part += xs[t];
+    }
+  }
   for (; p + 3 * 256 < e; p += 4 * 256) {
     const int32_t u0 = ld_idx(a, p), u1 = ld_idx(a, p + 256), u2 = ld_idx(a, p + 512), u3 = ld_idx(a, p + 768);
     if (want_x) any |= a.x_in[u0] | a.x_in[u1] | a.x_in[u2] | a.x_in[u3];
@@ -413,7 +434,7 @@ __device__ __forceinline__ void pull_block(const PullArgs& a, const int32_t* __r
       }
     }
     int dummy;
-    const double c = aff ? block_row_sum(a, x, x.s, x.e, true, false, &dummy, sh, shx) : 0.0;
+    const double c = aff ? block_row_sum<!DENSE>(a, x, x.s, x.e, true, false, &dummy, sh, shx) : 0.0;
     if (threadIdx.x == 0) vertex_finish<MODE, DENSE>(a, x, c, aff, acc);
   }
 }
@@ -459,7 +480,7 @@ __device__ __forceinline__ void pull_chunks(const PullArgs& a, const int32_t* __
     const int32_t cs = x.s + (int32_t)((q - cj) * kPullChunk);
     const int32_t ce = min(cs + kPullChunk, x.e);
     int any = 0;
-    const double part = block_row_sum(a, x, cs, ce, true, want_x, &any, sh, shx);
+    const double part = block_row_sum<!DENSE>(a, x, cs, ce, true, want_x, &any, sh, shx);
     if (threadIdx.x == 0) {
       a.partial[q] = part;
       if (DENSE) a.partial_x[q] = any;

@@ -442,11 +442,14 @@ __device__ __forceinline__ void pull_block(const PullArgs& a, const int32_t* __r
 // ---- bin 5: rows split in kPullChunk-edge chunks.  chunk_pre[j] is the
 // first chunk of the bin's j-th vertex (exclusive scan of the chunk counts);
 // workgroup lb takes the contiguous chunk range [lb*T/nb, (lb+1)*T/nb).  Each
-// chunk's sum goes to `partial`; the workgroup that finishes a vertex's last
-// chunk (arrival counter) adds the partials (thread t takes chunks t, t+256,
-// ..., then a fixed reduction tree: the same bits whatever the arrival order)
-// and computes the rank.  DENSE: each chunk also reports whether an
-// in-neighbour expanded.
+// chunk's sum goes to `partial`.  A row's partials are added by 256 threads
+// (thread t takes chunks t, t+256, ..., then a fixed reduction tree) before
+// the rank is computed: in a launch of its own after the pull (DEFER; the
+// launch boundary orders the partials before the reads), or, inside the
+// single-launch loop, by the workgroup that finishes the row's last chunk
+// (arrival counter; a device-scope fence before each arrival).  Both add in
+// the same order, so give the same bits.  DENSE: each chunk also reports
+// whether an in-neighbour expanded.
 __device__ __forceinline__ int64_t upper_bound_i64(const int64_t* a, int64_t lo, int64_t hi, int64_t x) {
   while (lo < hi) {
     int64_t mid = lo + ((hi - lo) >> 1);
@@ -455,7 +458,7 @@ __device__ __forceinline__ int64_t upper_bound_i64(const int64_t* a, int64_t lo,
   return lo;
 }
 
-template <int MODE, bool DENSE>
+template <int MODE, bool DENSE, bool DEFER>
 __device__ __forceinline__ void pull_chunks(const PullArgs& a, const int32_t* __restrict__ wl, int64_t lo, int64_t hi,
                                             int lb, int nb, Acc& acc) {
   __shared__ double sh[256 / kWave];
@@ -481,6 +484,13 @@ __device__ __forceinline__ void pull_chunks(const PullArgs& a, const int32_t* __
     const int32_t ce = min(cs + kPullChunk, x.e);
     int any = 0;
     const double part = block_row_sum<!DENSE>(a, x, cs, ce, true, want_x, &any, sh, shx);
+    if (DEFER) {
+      if (threadIdx.x == 0) {
+        a.partial[q] = part;
+        if (DENSE) a.partial_x[q] = any;
+      }
+      continue;
+    }
     if (threadIdx.x == 0) {
       a.partial[q] = part;
       if (DENSE) a.partial_x[q] = any;
@@ -516,7 +526,52 @@ __device__ __forceinline__ void pull_chunks(const PullArgs& a, const int32_t* __
   }
 }
 
+// The chunked rows of a pull launch that deferred them: one workgroup per row
+// adds its partials and updates the vertex.
 template <int MODE, bool DENSE>
+__global__ void __launch_bounds__(256) k_chunk_finish(PullArgs a, const int32_t* __restrict__ wl, int64_t lo,
+                                                      int64_t nv) {
+  __shared__ double sh[256 / kWave];
+  __shared__ int shx[256 / kWave];
+  __shared__ GTab tab;
+  Acc acc;
+  if (a.gid) {
+    for (int i = threadIdx.x; i < kGTab; i += blockDim.x) {
+      tab.key[i] = -1;
+      tab.val[i] = 0ull;
+    }
+    __syncthreads();
+    acc.tab = &tab;
+  }
+  for (int64_t j = blockIdx.x; j < nv; j += gridDim.x) {
+    const int64_t cj = a.chunk_pre[j], cj1 = a.chunk_pre[j + 1];
+    double c = 0.0;
+    int anyx = 0;
+    for (int64_t t = cj + threadIdx.x; t < cj1; t += blockDim.x) {
+      c += a.partial[t];
+      if (DENSE) anyx |= a.partial_x[t];
+    }
+    c = wave_sum(c);
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) anyx |= __shfl_xor(anyx, o, kWave);
+    if (lane_id() == 0) {
+      sh[threadIdx.x / kWave] = c;
+      shx[threadIdx.x / kWave] = anyx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      c = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+      anyx = shx[0] | shx[1] | shx[2] | shx[3];
+      const VCtx x = load_vertex(a, wl[lo + j]);
+      const bool aff = !member_done(a, x.g) && (!DENSE || a.stay_in[x.v] || (a.use_x && anyx));
+      vertex_finish<MODE, DENSE>(a, x, aff ? c : 0.0, aff, acc);
+    }
+    __syncthreads();
+  }
+  block_acc_to_slots<DENSE>(acc, a);
+}
+
+template <int MODE, bool DENSE, bool DEFER = false>
 __device__ __forceinline__ void pull_virtual_block(const PullArgs& a, const int32_t* __restrict__ wl,
                                                    const PullLayout& L, int b);
 
@@ -527,7 +582,7 @@ __device__ __forceinline__ void pull_virtual_block(const PullArgs& a, const int3
 // does not change how the item is summed.
 template <int MODE, bool DENSE>
 __global__ void __launch_bounds__(256, 8) k_pull(PullArgs a, const int32_t* __restrict__ wl, PullLayout L) {
-  pull_virtual_block<MODE, DENSE>(a, wl, L, (int)(gridDim.x - 1 - blockIdx.x));
+  pull_virtual_block<MODE, DENSE, true>(a, wl, L, (int)(gridDim.x - 1 - blockIdx.x));
 }
 
 // Whole update in one cooperative launch (small graphs, where launch and
@@ -778,7 +833,7 @@ __global__ void __launch_bounds__(256) k_fused_loop(PullArgs a0, const int32_t* 
   }
 }
 
-template <int MODE, bool DENSE>
+template <int MODE, bool DENSE, bool DEFER>
 __device__ __forceinline__ void pull_virtual_block(const PullArgs& a, const int32_t* __restrict__ wl,
                                                    const PullLayout& L, int b) {
   int k = 0;
@@ -800,7 +855,7 @@ __device__ __forceinline__ void pull_virtual_block(const PullArgs& a, const int3
     case 2: pull_groups<MODE, 16, DENSE>(a, wl, L.lo[2], L.hi[2], lb, nb, acc); break;
     case 3: pull_groups<MODE, 64, DENSE>(a, wl, L.lo[3], L.hi[3], lb, nb, acc); break;
     case 4: pull_block<MODE, DENSE>(a, wl, L.lo[4], L.hi[4], lb, nb, acc); break;
-    default: pull_chunks<MODE, DENSE>(a, wl, L.lo[5], L.hi[5], lb, nb, acc); break;
+    default: pull_chunks<MODE, DENSE, DEFER>(a, wl, L.lo[5], L.hi[5], lb, nb, acc); break;
   }
   block_acc_to_slots<DENSE>(acc, a);
 }
@@ -1402,6 +1457,8 @@ static int pull_all(dfpr_graph* g, PullArgs a, const int32_t* wl, const int64_t*
     DFPR_TRY(scan_generic(LoadChunks{wl, g->in_deg, L.lo[kBins - 1]}, StoreChunk{chunk_pre}, n5, g->scan_tmp, s));
   a.chunk_pre = chunk_pre;
   k_pull<MODE, DENSE><<<(unsigned)L.blk[kBins], 256, 0, s>>>(a, wl, L);
+  if (n5 > 0)  // the chunked rows' sums and updates, after every chunk's partial is stored
+    k_chunk_finish<MODE, DENSE><<<(unsigned)std::min<int64_t>(n5, 4096), 256, 0, s>>>(a, wl, L.lo[kBins - 1], n5);
   DFPR_HIP(hipGetLastError());
   DFPR_TRY(g->pool.stop(kTPull0, tok));
   st->pull_launches++;

@@ -185,19 +185,27 @@ __global__ void k_deg_from_off(const int32_t* off, int32_t n, int32_t* deg) {
     deg[v] = off[v + 1] - off[v];
 }
 // Degrees after an accepted batch: every effective insertion (u, v) adds one to
-// |out(u)| and |in(v)|, every effective deletion takes one off.  Nothing
-// changes when the batch was rejected (err set).
-__global__ void k_update_degrees(const uint64_t* eff, const int64_t* count, int b, const int64_t* err,
+// |out(u)| and |in(v)|, every effective deletion takes one off.  One atomic per
+// row: the first entry of each row's run in the (u, v) order (out-degrees)
+// and in the (v, u) order (in-degrees) adds the run's insertions minus its
+// deletions (pre_*: prefix counts of the deletions), so a hub that many
+// entries touch is not one hot address.  Nothing changes when the batch was
+// rejected (err set).
+__global__ void k_update_degrees(const uint64_t* eff_out, const uint64_t* eff_in, const int64_t* count,
+                                 const int64_t* pre_out, const int64_t* pre_in, int b, const int64_t* err,
                                  int32_t* out_deg, int32_t* in_deg) {
   if (*err) return;
-  const uint64_t mask = (1ull << b) - 1;
   const int64_t t = *count;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < t; i += (int64_t)gridDim.x * blockDim.x) {
-    const uint64_t k = eff[i];
-    const int32_t u = (int32_t)(k >> (b + 1)), v = (int32_t)((k >> 1) & mask);
-    const int32_t d = (k & 1ull) ? 1 : -1;
-    atomicAdd(&out_deg[u], d);
-    atomicAdd(&in_deg[v], d);
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < 2 * t; i += (int64_t)gridDim.x * blockDim.x) {
+    const bool in_side = i >= t;
+    const int64_t e = in_side ? i - t : i;
+    const uint64_t* eff = in_side ? eff_in : eff_out;
+    const int64_t* pre = in_side ? pre_in : pre_out;
+    const int64_t r = (int64_t)(eff[e] >> (b + 1));
+    if (e > 0 && (int64_t)(eff[e - 1] >> (b + 1)) == r) continue;
+    const int64_t end = lower_bound_u64(eff, e + 1, t, (uint64_t)(r + 1) << (b + 1));
+    const int32_t net = (int32_t)((end - e) - 2 * (pre[end] - pre[e]));
+    if (net) atomicAdd(&(in_side ? in_deg : out_deg)[r], net);
   }
 }
 // ---- rows with free slots
@@ -820,6 +828,100 @@ __global__ void __launch_bounds__(kCopyBlock) k_run_copy(const int32_t* __restri
       q = max(z, run_begin(eff, opos, delpre, e + 1));
       e++;
     }
+  }
+}
+
+// The same copy when the entries cut the old array into short runs (under
+// kShortRun elements on average): wavefront w takes run w - 1 (run e holds the
+// old elements between entries e and e + 1), copies it with its shift and
+// writes entry e + 1's insertion behind it, so the runs go in parallel with
+// no search for a chunk's first run and no run-after-run walk.  A run longer
+// than `piece` elements (runs can be very uneven: entries that cluster leave
+// one long run) is cut into pieces listed in `pieces` (run + 1 above bit 20,
+// piece number below), which k_run_copy_pieces then copies a workgroup each.
+constexpr int64_t kShortRun = 4096;
+constexpr int kPieceBits = 20;
+__global__ void __launch_bounds__(256) k_run_copy_waves(const int32_t* __restrict__ oidx, int32_t* __restrict__ nidx,
+                                                        const uint64_t* eff, const int64_t* delpre,
+                                                        const int64_t* opos, const int64_t* count, int b,
+                                                        const int32_t* noff, int32_t n, int64_t m_old, int64_t* err,
+                                                        const int32_t* m_off, int64_t* m_new, int64_t piece,
+                                                        int64_t* pieces, int64_t piece_cap, int64_t* npieces) {
+  const uint64_t mask = (1ull << b) - 1;
+  const int64_t mnew = noff[n];
+  const int64_t T = *count;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (m_new) *m_new = m_off[n];
+    if (T > 0 && run_begin(eff, opos, delpre, T - 1) > mnew) atomicOr((unsigned long long*)err, 2ull);
+  }
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
+  const int lane = lane_id();
+  for (int64_t e = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave - 1; e < T; e += waves) {
+    const int64_t start = run_begin(eff, opos, delpre, e);
+    const int64_t end = e + 1 < T ? run_cut(opos, delpre, e + 1) : mnew;
+    const int64_t shift = e < 0 ? 0 : (e + 1) - 2 * delpre[e + 1];
+    if (start < end) {
+      if (start - shift < 0 || end - shift > m_old || end > mnew) {  // runs disagree with the array: refuse to write
+        if (lane == 0) atomicOr((unsigned long long*)err, 2ull);
+        continue;
+      }
+      if (end - start <= piece) {
+        int64_t p = start + lane;
+        for (; p + 3 * kWave < end; p += 4 * kWave) {
+          int32_t x[4];
+#pragma unroll
+          for (int k = 0; k < 4; k++) x[k] = __builtin_nontemporal_load(oidx + (p + k * kWave - shift));
+#pragma unroll
+          for (int k = 0; k < 4; k++) nidx[p + k * kWave] = x[k];
+        }
+        for (; p < end; p += kWave) nidx[p] = __builtin_nontemporal_load(oidx + (p - shift));
+      } else {
+        const int64_t np = (end - start + piece - 1) / piece;
+        int64_t base = 0;
+        if (lane == 0) base = (int64_t)atomicAdd((unsigned long long*)npieces, (unsigned long long)np);
+        base = __shfl(base, 0, kWave);
+        if (base + np > piece_cap) {  // the piece size is chosen so that the list holds every piece
+          if (lane == 0) atomicOr((unsigned long long*)err, 2ull);
+        } else {
+          for (int64_t j = lane; j < np; j += kWave) pieces[base + j] = ((e + 1) << kPieceBits) | j;
+        }
+      }
+    }
+    if (e + 1 < T && lane == 0) {
+      const uint64_t k = eff[e + 1];
+      if (k & 1ull) {
+        if (end < 0 || end >= mnew) atomicOr((unsigned long long*)err, 2ull);
+        else nidx[end] = (int32_t)((k >> 1) & mask);
+      }
+    }
+  }
+}
+
+// The pieces of the long runs listed by k_run_copy_waves, a workgroup each.
+__global__ void __launch_bounds__(256) k_run_copy_pieces(const int32_t* __restrict__ oidx,
+                                                         int32_t* __restrict__ nidx, const uint64_t* eff,
+                                                         const int64_t* delpre, const int64_t* opos,
+                                                         const int64_t* count, const int32_t* noff, int32_t n,
+                                                         int64_t piece, const int64_t* pieces,
+                                                         const int64_t* npieces) {
+  const int64_t mnew = noff[n];
+  const int64_t T = *count, total = *npieces;
+  for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
+    const int64_t it = pieces[w];
+    const int64_t e = (it >> kPieceBits) - 1, j = it & ((1ll << kPieceBits) - 1);
+    const int64_t start = run_begin(eff, opos, delpre, e);
+    const int64_t end = e + 1 < T ? run_cut(opos, delpre, e + 1) : mnew;
+    const int64_t shift = e < 0 ? 0 : (e + 1) - 2 * delpre[e + 1];
+    const int64_t a = start + j * piece, z = min(a + piece, end);
+    int64_t p = a + threadIdx.x;
+    for (; p + 3 * 256 < z; p += 4 * 256) {
+      int32_t x[4];
+#pragma unroll
+      for (int k = 0; k < 4; k++) x[k] = __builtin_nontemporal_load(oidx + (p + k * 256 - shift));
+#pragma unroll
+      for (int k = 0; k < 4; k++) nidx[p + k * 256] = x[k];
+    }
+    for (; p < z; p += 256) nidx[p] = __builtin_nontemporal_load(oidx + (p - shift));
   }
 }
 
@@ -1556,6 +1658,24 @@ static int rebuild_csr(dfpr_graph* g, const Csr& o, const Csr& nw, const uint8_t
   while (chunk < 16384 && (int64_t)chunk * 2048 < g->slots) chunk <<= 1;
   const int64_t m_bound = g->slots + ni;  // the new slot count is at most this
   if (nk * 256 <= g->slots) {  // the same test as the offsets in graph_apply
+    // many short runs (a workgroup would walk dozens of them one after the
+    // other): one wavefront per run, and the long runs' pieces after them.
+    // The piece list uses the group-rebuild scratch (idle on this path); the
+    // piece size keeps every piece in it (long runs are at most m_bound/piece,
+    // their pieces at most twice that).
+    if (g->slots < (int64_t)kShortRun * nk) {
+      const int64_t cap = (int64_t)n / kWave + 2;
+      const int64_t piece = std::max<int64_t>(kShortRun, (2 * m_bound + cap - 1) / cap);
+      int64_t* npieces = g->ctl->n_local + 5;
+      DFPR_HIP(hipMemsetAsync(npieces, 0, sizeof(int64_t), s));
+      k_run_copy_waves<<<grid_for(nk + 1, 256 / kWave, 1u << 16), 256, 0, s>>>(
+          o.idx, nw.idx, eff, delpre, opos, cnt, g->id_bits, nw.off, n, g->slots, err, m_off, m_new, piece,
+          g->piece_pre, cap, npieces);
+      k_run_copy_pieces<<<grid_for(2 * m_bound / piece + 1, 1, 8192), 256, 0, s>>>(
+          o.idx, nw.idx, eff, delpre, opos, cnt, nw.off, n, piece, g->piece_pre, npieces);
+      DFPR_HIP(hipGetLastError());
+      return DFPR_OK;
+    }
     k_run_copy<<<grid_for(m_bound, chunk, 1u << 16), kCopyBlock, 0, s>>>(o.idx, nw.idx, eff, delpre, opos, cnt,
                                                                        g->id_bits, nw.off, n, g->slots, chunk, err,
                                                                        m_off, m_new);
@@ -1774,10 +1894,12 @@ int graph_apply(dfpr_graph* g, int64_t nd, const int32_t* del_src, const int32_t
     k_row_merge<<<g_in, 256, 0, s>>>(heads_in, nl + 1, cpre_in, eff_in, cnt, pre_in, b, g->in_deg, 0, g->in.off,
                                      g->in2.idx, g->in.off, g->in.idx, pad);
     DFPR_TRY(ep.stop(kTRebuildIn, tok));
-    k_update_degrees<<<grid_for(nk, 256, 65536), 256, 0, s>>>(eff_out, cnt, b, counters + 4, g->out_deg, g->in_deg);
+    k_update_degrees<<<grid_for(2 * nk, 256, 65536), 256, 0, s>>>(eff_out, eff_in, cnt, pre_out, pre_in, b,
+                                                                    counters + 4, g->out_deg, g->in_deg);
   } else if (path == kRelaid) {
     // new degrees first: they size the new rows (untouched rows keep theirs)
-    k_update_degrees<<<grid_for(nk, 256, 65536), 256, 0, s>>>(eff_out, cnt, b, counters + 4, g->out_deg, g->in_deg);
+    k_update_degrees<<<grid_for(2 * nk, 256, 65536), 256, 0, s>>>(eff_out, eff_in, cnt, pre_out, pre_in, b,
+                                                                    counters + 4, g->out_deg, g->in_deg);
     const int64_t total = g->m + h[0] - h[1] + (int64_t)n * g->slack;
     const unsigned gr = grid_for(total, kRelayTile, 65536);
     DFPR_TRY(ep.start(&tok));
@@ -1827,7 +1949,8 @@ int graph_apply(dfpr_graph* g, int64_t nd, const int32_t* del_src, const int32_t
                                                             g->touched_out, g->touched_in);
       k_finish_apply<<<1, 1, 0, s>>>(g->out2.off, n, counters);
     }
-    k_update_degrees<<<grid_for(nk, 256, 65536), 256, 0, s>>>(eff_out, cnt, b, counters + 4, g->out_deg, g->in_deg);
+    k_update_degrees<<<grid_for(2 * nk, 256, 65536), 256, 0, s>>>(eff_out, eff_in, cnt, pre_out, pre_in, b,
+                                                                    counters + 4, g->out_deg, g->in_deg);
   }
   if (path != kRebuilt) {
     k_clear_touched<<<grid_for(rows_out, 256, 4096), 256, 0, s>>>(heads_out, nl, eff_out, b, g->touched_out);

@@ -144,21 +144,24 @@ def test_apply_runs_in_one_row():
 
 
 @pytest.mark.parametrize("side", ["out", "in"])
-def test_apply_entries_at_copy_chunk_edges(side):
+@pytest.mark.parametrize("scale,step", [(14, 1024), (15, 16384)])
+def test_apply_entries_at_copy_chunk_edges(side, scale, step):
     """Run-by-run copy where the cuts sit on the copy workgroups' chunk edges
     (1024 positions of the new index array on a graph under 2M edges): the
-    batch inserts the edges that end up at positions q-1 and q of every chunk
-    edge q (and the first and last positions) of the out- or in-CSR, and
-    deletes, at every other chunk edge, an extra edge that sorts just before
-    position q, so a deletion's cut, an empty run and an insertion meet there.
+    batch inserts the edges that end up at positions q-1 and q of every
+    step-th position q (and the first and last positions) of the out- or
+    in-CSR, and deletes, at every other such q, an extra edge that sorts just
+    before position q, so a deletion's cut, an empty run and an insertion meet
+    there.  Cuts every 1024 positions make short runs (under 4096 on average:
+    one wavefront per run); every 16384, long ones (runs walked per chunk).
     Caller ids are kept, so the positions are those of the canonical CSR."""
     torch_cuda()
-    n, s, d = rmat(14, seed=91)
+    n, s, d = rmat(scale, seed=91)
     full = O.graph(n, s, d)  # the graph after the batch
     m = full.m
     off, idx = (full.out_off, full.out_idx) if side == "out" else (full.in_off, full.in_idx)
     row_of = np.repeat(np.arange(n, dtype=np.int64), np.diff(off))
-    edges = list(range(1024, m, 1024))
+    edges = list(range(step, m, step))
     pos = sorted({p for q in edges + [0, m - 1] for p in (q - 1, q) if 0 <= p < m and row_of[p] != idx[p]})
     extra = []
     for q in edges[::2]:
@@ -167,7 +170,7 @@ def test_apply_entries_at_copy_chunk_edges(side):
         cand = [c for c in range(lo, int(idx[q])) if c != r]
         if cand:
             extra.append((r, cand[0]))
-    assert len(extra) > 20
+    assert len(extra) > len(edges) // 4
     keep = np.ones(m, bool)
     keep[pos] = False
     rows = np.concatenate([row_of[keep], [r for r, _ in extra]]).astype(np.int32)
@@ -180,7 +183,8 @@ def test_apply_entries_at_copy_chunk_edges(side):
         src, dst, ins_src, ins_dst, del_src, del_dst = cols, rows, idx[pos], row_of[pos], xc, xr
     p = Pair(n, src, dst, keep_ids=True)
     assert len(pos) + len(extra) <= p.og.m // 256  # the run-by-run copy
-    _print("chunk edges", side, len(pos), len(extra), p.og.m)
+    assert (p.og.m < 4096 * (len(pos) + len(extra))) == (step == 1024)  # short runs, or long ones
+    _print("chunk edges", side, scale, step, len(pos), len(extra), p.og.m)
     info = p.apply(del_src, del_dst, ins_src.astype(np.int32), ins_dst.astype(np.int32))
     assert info["ins_effective"] == len(pos) and info["del_effective"] == len(extra)
     assert_csr_equal(p.g, p.og)

@@ -97,30 +97,37 @@ template <class Load, class Store>
 __global__ void __launch_bounds__(kScanBlock) k_scan_one_tile(Load ld, Store st, int64_t n) {
   __shared__ int64_t tile[kScanTile];
   __shared__ int64_t sh[kScanBlock / kWave + 1];
+  int64_t carry = 0;  // total of the tiles before
+  for (int64_t base = 0; base < n; base += kScanTile) {
 #pragma unroll
-  for (int j = 0; j < kScanItems; j++) {
-    const int64_t i = j * kScanBlock + threadIdx.x;
-    tile[i] = (i < n) ? ld(i) : 0;
-  }
-  __syncthreads();
-  int64_t v[kScanItems];
-  int64_t run = 0;
+    for (int j = 0; j < kScanItems; j++) {
+      const int64_t i = base + j * kScanBlock + threadIdx.x;
+      tile[j * kScanBlock + threadIdx.x] = (i < n) ? ld(i) : 0;
+    }
+    __syncthreads();
+    int64_t v[kScanItems];
+    int64_t run = 0;
 #pragma unroll
-  for (int j = 0; j < kScanItems; j++) {
-    v[j] = run;
-    run += tile[threadIdx.x * kScanItems + j];
-  }
-  int64_t tot;
-  const int64_t pre = block_exclusive_scan(run, sh, &tot);
+    for (int j = 0; j < kScanItems; j++) {
+      v[j] = run;
+      run += tile[threadIdx.x * kScanItems + j];
+    }
+    int64_t tot;
+    const int64_t pre = block_exclusive_scan(run, sh, &tot);  // ends with a barrier: the tile is free again
 #pragma unroll
-  for (int j = 0; j < kScanItems; j++) {
-    const int64_t i = threadIdx.x * kScanItems + j;
-    if (i < n) st(i, pre + v[j]);
+    for (int j = 0; j < kScanItems; j++) {
+      const int64_t i = base + threadIdx.x * kScanItems + j;
+      if (i < n) st(i, carry + pre + v[j]);
+    }
+    carry += tot;
   }
-  if (threadIdx.x == 0) st(n, tot);
+  if (threadIdx.x == 0) st(n, carry);
 }
 
-// Exclusive scan of ld(0..n) into st(0..n) (st(n, total) included).
+// Exclusive scan of ld(0..n) into st(0..n) (st(n, total) included).  Up to
+// kScanFewTiles tiles: one workgroup, tile after tile (one launch instead of
+// three).
+constexpr int64_t kScanFewTiles = 4;
 template <class Load, class Store>
 int scan_generic(Load ld, Store st, int64_t n, int64_t* tmp, hipStream_t s) {
   const int64_t nb = (n + kScanTile - 1) / kScanTile;
@@ -128,7 +135,7 @@ int scan_generic(Load ld, Store st, int64_t n, int64_t* tmp, hipStream_t s) {
     k_scan_empty<<<1, 1, 0, s>>>(st);
     return hipGetLastError() == hipSuccess ? DFPR_OK : DFPR_EHIP;
   }
-  if (nb == 1) {
+  if (nb <= kScanFewTiles) {
     k_scan_one_tile<<<1, kScanBlock, 0, s>>>(ld, st, n);
     return hipGetLastError() == hipSuccess ? DFPR_OK : DFPR_EHIP;
   }

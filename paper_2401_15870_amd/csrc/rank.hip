@@ -1157,9 +1157,8 @@ __global__ void __launch_bounds__(256) k_bin_scatter(const uint8_t* flags, const
 // member graph on its own).  head.dR = largest change among the members still
 // running, head.active = members not yet converged.  One workgroup; a wave
 // per member, a lane per slot.
-__global__ void __launch_bounds__(256) k_dr_finish(unsigned long long* gslots, int gsub, int32_t G, uint8_t* done,
-                                                   double* g_dr, int32_t* g_iters, int32_t it, double tol,
-                                                   IterCtl* c) {
+__device__ __forceinline__ void dr_fold(unsigned long long* gslots, int gsub, int32_t G, uint8_t* done,
+                                        double* g_dr, int32_t* g_iters, int32_t it, double tol, IterCtl* c) {
   __shared__ unsigned long long shm[256 / kWave];
   __shared__ int64_t sha[256 / kWave];
   const int w = threadIdx.x / kWave, lane = lane_id();
@@ -1200,6 +1199,11 @@ __global__ void __launch_bounds__(256) k_dr_finish(unsigned long long* gslots, i
     c->active = active;
   }
 }
+__global__ void __launch_bounds__(256) k_dr_finish(unsigned long long* gslots, int gsub, int32_t G, uint8_t* done,
+                                                   double* g_dr, int32_t* g_iters, int32_t it, double tol,
+                                                   IterCtl* c) {
+  dr_fold(gslots, gsub, G, done, g_dr, g_iters, it, tol, c);
+}
 
 // Reset of the per-member state at the start of an update.
 __global__ void k_member_reset(int32_t G, int gsub, unsigned long long* gslots, uint8_t* done, double* g_dr,
@@ -1217,7 +1221,7 @@ __global__ void k_member_reset(int32_t G, int gsub, unsigned long long* gslots, 
 
 // Fold the spread accumulator rows into the compact head and clear them; also
 // clears the long-row list count for the next marking pass.
-__global__ void __launch_bounds__(kSlots) k_iter_finish(IterCtl* c) {
+__device__ __forceinline__ void iter_finish_body(IterCtl* c) {  // one wavefront (kSlots lanes)
   const int t = threadIdx.x;
   int64_t r[kAccRows];
 #pragma unroll
@@ -1237,6 +1241,16 @@ __global__ void __launch_bounds__(kSlots) k_iter_finish(IterCtl* c) {
     c->dense_carry = r[kAccCarry];
     c->big_count = 0;
   }
+}
+__global__ void __launch_bounds__(kSlots) k_iter_finish(IterCtl* c) { iter_finish_body(c); }
+// The same for a plain graph together with the L-inf change of iteration `it`
+// (a batch folds the members' changes before binning instead, so that
+// converged members drop out of it).
+__global__ void __launch_bounds__(256) k_iter_finish_dr(unsigned long long* gslots, int gsub, uint8_t* done,
+                                                        double* g_dr, int32_t* g_iters, int32_t it, double tol,
+                                                        IterCtl* c) {
+  dr_fold(gslots, gsub, 1, done, g_dr, g_iters, it, tol, c);
+  if (threadIdx.x < kSlots) iter_finish_body(c);
 }
 
 __global__ void k_reset_ctl(IterCtl* c) {
@@ -1391,8 +1405,12 @@ static int dr_finish(dfpr_graph* g, const dfpr_params& p, int it, hipStream_t s)
   return DFPR_OK;
 }
 
-static int finish_and_read(dfpr_graph* g, hipStream_t s) {
-  k_iter_finish<<<1, kSlots, 0, s>>>(g->ctl);
+// p (plain graphs): also fold the L-inf change of iteration it (dr_finish).
+static int finish_and_read(dfpr_graph* g, hipStream_t s, const dfpr_params* p = nullptr, int it = 0) {
+  if (p)
+    k_iter_finish_dr<<<1, 256, 0, s>>>(g->gslots, g->gsub, g->done, g->g_dr, g->g_iters, it, p->tol, g->ctl);
+  else
+    k_iter_finish<<<1, kSlots, 0, s>>>(g->ctl);
   DFPR_HIP(hipGetLastError());
   DFPR_HIP(hipMemcpyAsync(g->ctl_host, g->ctl, kCtlHead, hipMemcpyDeviceToHost, s));
   DFPR_HIP(hipStreamSynchronize(s));
@@ -1726,8 +1744,8 @@ static int run_sync(dfpr_graph* g, bool cold, const dfpr_params& p, const double
     a.Rw = Rb;
     a.cw = cb;
     DFPR_TRY((pull_parts<kSync, false>(g, a, s, st, true)));
-    DFPR_TRY(dr_finish(g, p, it, s));
-    DFPR_TRY(finish_and_read(g, s));
+    if (g->ngraphs > 1) DFPR_TRY(dr_finish(g, p, it, s));
+    DFPR_TRY(finish_and_read(g, s, g->ngraphs > 1 ? nullptr : &p, it));
     dR = bits_to_double(g->ctl_host->dR);
     st->vertex_updates += n;
     st->edges_pulled += g->m;
@@ -1905,8 +1923,8 @@ static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_pre
       a.carry = async ? 0 : carry;
       DFPR_TRY((pull_parts<MODE, true>(g, a, s, st, false)));
       carry = a.stamp;
-      DFPR_TRY(dr_finish(g, p, it, s));
-      DFPR_TRY(finish_and_read(g, s));
+      if (g->ngraphs > 1) DFPR_TRY(dr_finish(g, p, it, s));
+      DFPR_TRY(finish_and_read(g, s, g->ngraphs > 1 ? nullptr : &p, it));
       const IterCtl* h = g->ctl_host;
       dR = bits_to_double(h->dR);
       st->vertex_updates += h->dense_cnt;
@@ -1980,10 +1998,10 @@ static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_pre
     DFPR_HIP(hipGetLastError());
     DFPR_TRY(mark_big(g, next, s));
     DFPR_TRY(g->pool.stop(kTCommit, tok));
-    DFPR_TRY(dr_finish(g, p, it, s));  // before binning: converged members drop out
+    if (g->ngraphs > 1) DFPR_TRY(dr_finish(g, p, it, s));  // before binning: converged members drop out
     std::swap(cur, next);
     DFPR_TRY(bin_vertices(g, cur, g->worklist, g->ever, s));
-    DFPR_TRY(finish_and_read(g, s));
+    DFPR_TRY(finish_and_read(g, s, g->ngraphs > 1 ? nullptr : &p, it));
     dR = bits_to_double(g->ctl_host->dR);
     front_edges = 0;
     for (int k = 0; k < kBins; k++) front_edges += g->ctl_host->bin_edges[k];

@@ -808,6 +808,8 @@ def main():
                          "(library default 1; inf: always dense, 0: never)")
     ap.add_argument("--row-slack", type=int, default=0,
                     help="free slots after every CSR row: small batches then merge into the rows they touch")
+    ap.add_argument("--two-phase", action="store_true",
+                    help="rmat/temporal: dense-form DF/DF-P iterations through the two-phase pull (dfpr_set_two_phase)")
     ap.add_argument("--fused-limit", type=int, default=None,
                     help="edge count up to which a rank update runs in one cooperative launch (library default)")
     ap.add_argument("--bounds", default=None, help="temporal: in-degree bin thresholds a,b,c,d,e instead of autotuning")
@@ -884,6 +886,8 @@ def main():
     m0 = g.m
     if args.fused_limit is not None:
         g.set_fused_limit(args.fused_limit)
+    if args.two_phase:
+        g.set_two_phase(True)
     torch.cuda.synchronize()
     log(f"create: m={m0} row slack {args.row_slack} {time.time() - t0:.2f}s")
     dev_batches = [tuple(torch.from_numpy(a).to(dev) for a in b) for b in batches]
@@ -932,9 +936,10 @@ def main():
     rank_kw = {} if args.dense_switch is None else {"dense_switch": args.dense_switch}
     g.set_timing(True)
     step_ms, apply_ms, rank_ms, iters, ever, row_local = [], [], [], [], [], []
-    kern = {"pull": 0.0, "commit": 0.0, "bin": 0.0, "mark": 0.0, "sort": 0.0, "rebuild_out": 0.0,
-            "rebuild_in": 0.0}
+    kern = {"pull": 0.0, "two_phase": 0.0, "commit": 0.0, "bin": 0.0, "mark": 0.0, "sort": 0.0,
+            "rebuild_out": 0.0, "rebuild_in": 0.0}
     pull_launches, v_upd, e_pull, pull_bytes = 0, 0, 0, 0.0
+    tp_passes, tp_bytes = 0, 0.0
     m_sum = 0
     total = args.warmup + args.steps
     torch.cuda.synchronize()
@@ -965,6 +970,9 @@ def main():
             row_local.append(info["row_local"])
             kern["pull"] += st["ms_pull"]
             pull_launches += st["pull_launches"]
+            kern["two_phase"] += st["ms_two_phase"]
+            tp_passes += st["two_phase_passes"]
+            tp_bytes += st["two_phase_bytes"]
             v_upd += st["vertex_updates"]
             e_pull += st["edges_pulled"]
             pull_bytes += st["pull_bytes"]
@@ -978,6 +986,7 @@ def main():
                 f"{' row-local' if info['row_local'] else ''}, rank {rank_ms[-1]:.2f}) "
                 f"it={st['iterations']} dense={st['dense_iterations']} ever={st['ever_affected']} "
                 f"upd={st['vertex_updates']} pulled={st['edges_pulled']} pull {st['ms_pull']:.2f} "
+                f"{'two-phase %d x %.2f ' % (st['two_phase_passes'], st['ms_two_phase']) if st['two_phase_passes'] else ''}"
                 f"commit {st['ms_commit']:.2f} bin {st['ms_bin']:.2f} mark {st['ms_mark']:.2f}")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_begin
@@ -1003,6 +1012,8 @@ def main():
     rebuild_bytes = K * (8 * m_mean + 9 * n)
     cand = {"k_pull": (kern["pull"], pull_bytes, max(pull_launches, 1)),
             "k_rebuild": (kern["rebuild_out"] + kern["rebuild_in"], 2 * rebuild_bytes, 2 * K)}
+    if tp_passes:  # one pass = k_tp_scatter + k_tp_accum + k_tp_finish
+        cand["two_phase"] = (kern["two_phase"], tp_bytes, tp_passes)
     dom = max(cand, key=lambda k: cand[k][0])
     ms_k, bytes_k, nl = cand[dom]
     achieved = (bytes_k / nl) / (ms_k / nl * 1e-3) / 1e9 if ms_k > 0 else 0.0
@@ -1043,6 +1054,7 @@ def main():
                    "mode": args.mode + (" asynchronous" if args.asynchronous else ""), "parallelism": "1 GPU",
                    "bin_bounds": g.get_tuning(),
                    **({"dense_switch": args.dense_switch} if args.dense_switch is not None else {}),
+                   **({"two_phase": True} if args.two_phase else {}),
                    **({"row_slack": args.row_slack, "row_local_steps": int(sum(row_local))}
                       if args.row_slack else {})},
         "p50_ms": pct(step_ms, 50),

@@ -133,6 +133,17 @@ typedef struct {
   double pull_bytes;
   int32_t dense_iterations;        /* iterations run in dense (all-vertex) mode         */
   int32_t reserved2;
+  /* Dense iterations run by the two-phase pull (dfpr_set_two_phase), counted
+   * here and not in the pull fields above: duration of the three kernels of
+   * each pass, and algorithmic bytes: 22 B per edge (index word 4, value
+   * written 8, destination slot 2, value read 8) + 65 B per vertex
+   * (contribution, expand flag, accumulators written and read, the update's
+   * offsets, degrees, rank and flags) + 8 B per vertex whose rank it writes +
+   * 4 B per pair offset loaded by each phase-one work item. */
+  double ms_two_phase;
+  double two_phase_bytes;
+  int32_t two_phase_passes;
+  int32_t reserved3;
 } dfpr_stats;
 
 typedef struct dfpr_graph dfpr_graph;
@@ -258,6 +269,27 @@ int dfpr_set_fused_limit(dfpr_graph* g, int64_t max_edges);
  * graph keeps the layout it had when added.  Errors: EINVAL (slack outside
  * [0, 65536], or more slots than int32 offsets reach), ENOMEM. */
 int dfpr_set_row_slack(dfpr_graph* g, int32_t slack, void* stream);
+
+/* Dense-form iterations of DF and DF-P (Algorithm 1; Equations 1 and 2) in
+ * two phases instead of one gathering pull (on = 1; 0, the default, turns it
+ * off and frees its memory).  Phase one writes every edge's contribution
+ * R[u]/|out(u)| into an array ordered by destination range, reading the
+ * contributions of one source range at a time from LDS; phase two streams
+ * each destination range once and adds into accumulators in LDS.  The sums
+ * are exact: each contribution is taken as an integer multiple of 2^-96
+ * (exactly, for contributions of at least 2^-44) and the 128-bit integers
+ * are added, so the order of additions does not matter and each sum is
+ * rounded to FP64 once.  Results are reproducible bit for bit but differ from
+ * the gather pull's FP64 sums by rounding (the affected sets follow from
+ * them).  The layout (14 bytes per edge: 6 of layout, 8 of values) is built
+ * from the in-CSR before the first dense iteration after every change of the
+ * graph.  On R-MAT graphs of 2^24 vertices a pass takes longer than the gather
+ * pull and the rebuild adds to every batch, so the gather pull stays the
+ * default.  Frontier-form iterations, the single-launch loop (dfpr_set_fused_limit)
+ * and the asynchronous mode keep the gather pull.  Contributions must lie in
+ * [0, 2^31): an update whose ranks leave that range fails with EINVAL.
+ * Errors: EINVAL (batch handle, or more than 2^25 vertices). */
+int dfpr_set_two_phase(dfpr_graph* g, int on);
 
 /* Turn HIP-event timing of every apply and update on this graph on (1) or
  * off (0).  Events are recorded between kernels and read after the call's

@@ -233,6 +233,11 @@ class Graph:
         that small batches merge into the rows they touch (0: packed rows)."""
         _check(lib().dfpr_set_row_slack(self._h, int(slack), _stream_ptr(stream)))
 
+    def set_two_phase(self, on=True):
+        """Dense-form DF/DF-P iterations through the two-phase pull (exact
+        sums, streamed phases) instead of the gathering pull; off frees its layout."""
+        _check(lib().dfpr_set_two_phase(self._h, 1 if on else 0))
+
     def set_timing(self, on=True):
         _check(lib().dfpr_set_timing(self._h, 1 if on else 0))
 

@@ -20,7 +20,7 @@ CREATE_KEEP_IDS = 1
 EXPORTS = ("dfpr_params_default", "dfpr_graph_create", "dfpr_graph_destroy", "dfpr_graph_size",
            "dfpr_graph_export", "dfpr_apply_batch", "dfpr_apply_batch_noalloc", "dfpr_update_ranks", "dfpr_set_tuning",
            "dfpr_get_tuning", "dfpr_autotune", "dfpr_set_timing", "dfpr_set_fused_limit",
-           "dfpr_set_row_slack", "dfpr_batch_create", "dfpr_batch_count",
+           "dfpr_set_row_slack", "dfpr_set_two_phase", "dfpr_batch_create", "dfpr_batch_count",
            "dfpr_batch_member", "dfpr_apply_batch_many", "dfpr_update_ranks_many", "dfpr_server_create",
            "dfpr_server_destroy", "dfpr_server_add_graph", "dfpr_server_submit", "dfpr_server_wait",
            "dfpr_server_ranks", "dfpr_server_graph_size", "dfpr_server_get_stats", "dfpr_server_set_active_lanes",
@@ -44,7 +44,7 @@ class BatchInfo(ctypes.Structure):
         return _as_dict(self)
 
 
-def _as_dict(rec, drop=("reserved", "reserved2")):
+def _as_dict(rec, drop=("reserved", "reserved2", "reserved3")):
     """Fields of a ctypes struct as a dict (arrays as lists), reserved fields left out."""
     cls = type(rec)
     names = cls.__dict__.get("_names")
@@ -64,7 +64,9 @@ class Stats(ctypes.Structure):
                 ("bin_edges", ctypes.c_int64 * BINS), ("ms_total", ctypes.c_double), ("ms_pull", ctypes.c_double),
                 ("pull_launches", ctypes.c_int32), ("reserved", ctypes.c_int32), ("ms_commit", ctypes.c_double),
                 ("ms_bin", ctypes.c_double), ("ms_mark", ctypes.c_double), ("pull_bytes", ctypes.c_double),
-                ("dense_iterations", ctypes.c_int32), ("reserved2", ctypes.c_int32)]
+                ("dense_iterations", ctypes.c_int32), ("reserved2", ctypes.c_int32),
+                ("ms_two_phase", ctypes.c_double), ("two_phase_bytes", ctypes.c_double),
+                ("two_phase_passes", ctypes.c_int32), ("reserved3", ctypes.c_int32)]
 
     def as_dict(self):
         return _as_dict(self)
@@ -111,6 +113,8 @@ def declare(lib):
     lib.dfpr_set_fused_limit.restype = ctypes.c_int
     lib.dfpr_set_row_slack.argtypes = [P, i32, P]
     lib.dfpr_set_row_slack.restype = ctypes.c_int
+    lib.dfpr_set_two_phase.argtypes = [P, ctypes.c_int]
+    lib.dfpr_set_two_phase.restype = ctypes.c_int
     lib.dfpr_set_timing.argtypes = [P, ctypes.c_int]
     lib.dfpr_set_timing.restype = ctypes.c_int
     PP = ctypes.POINTER(P)

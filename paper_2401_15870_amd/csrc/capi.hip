@@ -441,6 +441,25 @@ int dfpr_set_row_slack(dfpr_graph* g, int32_t slack, void* stream) {
   return guarded(g, [&] { return graph_set_row_slack(g, slack, (hipStream_t)stream); });
 }
 
+int dfpr_set_two_phase(dfpr_graph* g, int on) {
+  clear_error();
+  return guarded(g, [&] {
+    if (!on) {
+      delete g->tp;
+      g->tp = nullptr;
+      return (int)DFPR_OK;
+    }
+    const char* why = nullptr;
+    if (!tp_supported(g, &why)) {
+      set_error("%s", why);
+      return (int)DFPR_EINVAL;
+    }
+    if (!g->tp) g->tp = new TwoPhase();
+    g->tp->on = true;
+    return (int)DFPR_OK;
+  });
+}
+
 int dfpr_set_fused_limit(dfpr_graph* g, int64_t max_edges) {
   clear_error();
   if (max_edges < 0) {

@@ -213,6 +213,61 @@ constexpr int64_t kPartVertices = (int64_t)8 << 20;  // 64 MB of contributions p
 // faster (frontier-form iterations, twice the occupancy of the pull).
 constexpr int64_t kFusedBatchEdges = (int64_t)1 << 26;
 
+// ---- two-phase dense pull (twophase.hip): blocks of 8192 sources, buckets
+// of 4096 destinations, at most kTpMaxB buckets (2^25 vertices)
+constexpr int kTpSrcBits = 13, kTpSrc = 1 << kTpSrcBits;
+constexpr int kTpDstBits = 12, kTpDst = 1 << kTpDstBits;
+constexpr int kTpMaxB = 8192, kTpMaxS = kTpMaxB / 2;
+constexpr int64_t kTpItemBuild = 65536;  // in-CSR slots per layout-build work item
+constexpr int64_t kTpItem1 = 131072;     // edges per phase-one work item
+constexpr int64_t kTpItem2 = 65536;      // edges per phase-two work item
+constexpr int kTpFixBits = 96;           // contributions on a grid of 2^-96
+
+// A non-negative double below 2^31 as the integer nearest to x * 2^96
+// (ties to even), in two 64-bit words.  Exact for x >= 2^-44.
+struct Fix128 {
+  uint64_t lo, hi;
+};
+__device__ __forceinline__ Fix128 fix128(uint64_t bits) {
+  Fix128 x{0, 0};
+  const int e = (int)(bits >> 52);
+  if (e == 0) return x;  // zero or subnormal: far below half a grid step
+  const uint64_t mnt = (bits & ((1ull << 52) - 1)) | (1ull << 52);
+  const int sh = e - (1075 - kTpFixBits);  // x * 2^96 = mnt * 2^sh
+  if (sh >= 64) {
+    x.hi = mnt << (sh - 64);
+  } else if (sh > 0) {
+    x.lo = mnt << sh;
+    x.hi = mnt >> (64 - sh);
+  } else if (sh == 0) {
+    x.lo = mnt;
+  } else if (sh > -54) {
+    const int t = -sh;
+    const uint64_t q = mnt >> t, r = mnt & ((1ull << t) - 1), h = 1ull << (t - 1);
+    x.lo = q + (uint64_t)(r > h || (r == h && (q & 1)));
+  }
+  return x;
+}
+// hi * 2^-32 + lo * 2^-96 rounded to the nearest double (ties to even): the
+// top 64 bits with a sticky bit for the rest, converted once.
+__device__ __forceinline__ double unfix128(uint64_t lo, uint64_t hi) {
+  if (hi == 0) return (double)lo * 0x1p-96;
+  const int z = __clzll((long long)hi);
+  const uint64_t top = z ? (hi << z) | (lo >> (64 - z)) : hi;
+  const uint64_t rest = z ? lo << z : lo;
+  return ldexp((double)(top | (uint64_t)(rest != 0)), -32 - z);
+}
+
+struct TwoPhase {
+  bool on = false;
+  uint64_t built = ~0ull;  // csr_version the layout was built from
+  int32_t nS = 0, nB = 0;
+  int64_t m = 0;
+  int n1 = 0, n2 = 0;  // work items of phase one and two
+  DevBuf p1, dstl, val, cnt, tabB, tabS, delta, tmp, glo, ghi, gfl, split, starts, bad, bitems, items1, items2;
+  ~TwoPhase();
+};
+
 }  // namespace dfpr
 
 struct dfpr_graph {
@@ -307,6 +362,8 @@ struct dfpr_graph {
   void* fused_parts_host = nullptr;  // pinned mirror of the part table last copied
   bool fused_parts_stale = true;
   dfpr::EventPool pool;
+  uint64_t csr_version = 0;      // bumped whenever the CSRs' contents change
+  dfpr::TwoPhase* tp = nullptr;  // two-phase dense pull (dfpr_set_two_phase), null when off
   // vertex-proportional scratch of apply and rank updates, carved from one block
   void* scratch = nullptr;
   size_t scratch_bytes = 0;
@@ -369,6 +426,10 @@ int graph_apply(dfpr_graph* g, int64_t n_del, const int32_t* del_src, const int3
 // then merge into rows that have room, without moving the others).
 constexpr int32_t kMaxRowSlack = 1 << 16;
 int graph_set_row_slack(dfpr_graph* g, int32_t slack, hipStream_t s);
+// two-phase dense pull (twophase.hip)
+bool tp_supported(const dfpr_graph* g, const char** why);
+int tp_build(dfpr_graph* g, hipStream_t s);
+int tp_phases(dfpr_graph* g, const double* contrib, const uint8_t* xflag, hipStream_t s);
 // Slots an apply of n_ins insertions may need in each index array.
 int64_t slots_bound(const dfpr_graph* g, int64_t n_ins);
 // graph_apply with its sort and staging buffers in the library's fixed device

@@ -1373,6 +1373,8 @@ int graph_destroy(dfpr_graph* g) {
   dfree(g->in_deg);
   if (g->fused_parts_host) (void)hipHostFree(g->fused_parts_host);
   g->fused_parts_host = nullptr;
+  delete g->tp;
+  g->tp = nullptr;
   g->keys_a.release();
   g->keys_b.release();
   g->keys_c.release();
@@ -1729,6 +1731,7 @@ int graph_set_row_slack(dfpr_graph* g, int32_t slack, hipStream_t s) {
   g->slots = want;
   g->slack = slack;
   g->all_bins_valid = false;
+  g->csr_version++;
   return DFPR_OK;
 }
 
@@ -1983,6 +1986,7 @@ int graph_apply(dfpr_graph* g, int64_t nd, const int32_t* del_src, const int32_t
   g->m = m_new;
   g->slots = slots_new;
   g->all_bins_valid = false;
+  g->csr_version++;
   if (h[3] > 0) g->pending_any = true;
   if (info) {
     info->ins_effective = h[0];

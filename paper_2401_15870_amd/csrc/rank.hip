@@ -571,6 +571,37 @@ __global__ void __launch_bounds__(256) k_chunk_finish(PullArgs a, const int32_t*
   block_acc_to_slots<DENSE>(acc, a);
 }
 
+// Dense form with the two-phase pull (dfpr_set_two_phase): the in-neighbour
+// sums and "an in-neighbour expanded" bits come from the phase-two
+// accumulators; one thread per vertex converts its sum and updates the
+// vertex as the gather pull would.  A block's 256 vertices are 8 whole flag
+// words, so the words of split buckets are cleared after the barrier.
+template <int MODE>
+__global__ void __launch_bounds__(256) k_tp_finish(PullArgs a, int32_t n, uint64_t* glo, uint64_t* ghi, uint32_t* gfl,
+                                                   const uint8_t* __restrict__ split) {
+  Acc acc;
+  const int32_t v = (int32_t)(blockIdx.x * 256 + threadIdx.x);
+  const bool in = v < n;
+  double c = 0.0;
+  bool anyx = false;
+  if (in) {
+    c = unfix128(glo[v], ghi[v]);
+    anyx = ((gfl[v >> 5] >> (v & 31)) & 1u) != 0;
+  }
+  __syncthreads();
+  if (in) {
+    if (split[v >> kTpDstBits]) {  // several workgroups added into these: clear for the next iteration
+      glo[v] = 0;
+      ghi[v] = 0;
+      if ((v & 31) == 0) gfl[v >> 5] = 0u;
+    }
+    const VCtx x = load_vertex(a, v);
+    const bool aff = a.stay_in[v] != 0 || (a.use_x && anyx);
+    vertex_finish<MODE, true>(a, x, aff ? c : 0.0, aff, acc);
+  }
+  block_acc_to_slots<true>(acc, a);
+}
+
 template <int MODE, bool DENSE, bool DEFER = false>
 __device__ __forceinline__ void pull_virtual_block(const PullArgs& a, const int32_t* __restrict__ wl,
                                                    const PullLayout& L, int b);
@@ -1805,6 +1836,27 @@ static int pull_parts(dfpr_graph* g, const PullArgs& a, hipStream_t s, dfpr_stat
   return DFPR_OK;
 }
 
+// One dense iteration through the two-phase pull; the layout is rebuilt first
+// when the graph changed since it was built (timed with the binning work).
+template <int MODE>
+static int tp_pull(dfpr_graph* g, const PullArgs& a, bool use_x, hipStream_t s, dfpr_stats* st) {
+  TwoPhase& t = *g->tp;
+  size_t tok;
+  if (t.built != g->csr_version) {
+    DFPR_TRY(g->pool.start(&tok));
+    DFPR_TRY(tp_build(g, s));
+    DFPR_TRY(g->pool.stop(kTBin, tok));
+  }
+  DFPR_TRY(g->pool.start(&tok));
+  DFPR_TRY(tp_phases(g, a.contrib, use_x ? a.x_in : nullptr, s));
+  k_tp_finish<MODE><<<(unsigned)((g->n + 255) / 256), 256, 0, s>>>(a, g->n, t.glo.as<uint64_t>(), t.ghi.as<uint64_t>(),
+                                                                    t.gfl.as<uint32_t>(), t.split.as<uint8_t>());
+  DFPR_HIP(hipGetLastError());
+  DFPR_TRY(g->pool.stop(kTPull1, tok));
+  st->two_phase_passes++;
+  return DFPR_OK;
+}
+
 // DF / DF-P.  Each iteration runs in one of two forms with the same result:
 //  frontier: pull over the binned worklist of affected vertices (ranks in
 //    place), commit their contributions and push-mark the out-rows of the
@@ -1900,6 +1952,8 @@ static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_pre
   double dR = 0.0;
   bool conv = false;
   int carry = 0;  // stamp of the previous dense iteration (0: the vectors are not in step)
+  const bool use_tp = g->tp && g->tp->on && g->ngraphs == 1 && !async;
+  bool tp_ran = false;
   for (it = 0; it < p.max_iters; it++) {
     if (!dense && front_cnt > 0 && prefer_dense(p.dense_switch, m, n, front_edges, mark_edges)) {
       dense = true;  // the complete frontier is in `cur`; no expand flags to read
@@ -1907,7 +1961,7 @@ static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_pre
       carry = 0;     // the frontier form updated one vector in place
     }
     if (dense) {
-      DFPR_TRY(ensure_all_bins(g, s));
+      if (!use_tp) DFPR_TRY(ensure_all_bins(g, s));  // the gather pull's all-vertex bins
       a.contrib = ca;
       a.R = Ra;
       a.Rw = async ? Ra : Rb;
@@ -1921,7 +1975,12 @@ static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_pre
       a.use_x = use_x ? 1 : 0;
       a.stamp = dense_stamp(it);
       a.carry = async ? 0 : carry;
-      DFPR_TRY((pull_parts<MODE, true>(g, a, s, st, false)));
+      const bool two = use_tp;
+      tp_ran = tp_ran || two;
+      if (two)
+        DFPR_TRY(tp_pull<MODE>(g, a, use_x, s, st));
+      else
+        DFPR_TRY((pull_parts<MODE, true>(g, a, s, st, false)));
       carry = a.stamp;
       if (g->ngraphs > 1) DFPR_TRY(dr_finish(g, p, it, s));
       DFPR_TRY(finish_and_read(g, s, g->ngraphs > 1 ? nullptr : &p, it));
@@ -1929,8 +1988,12 @@ static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_pre
       dR = bits_to_double(h->dR);
       st->vertex_updates += h->dense_cnt;
       st->edges_pulled += h->dense_edges;
-      st->pull_bytes += 24.0 * n + 8.0 * (double)(h->dense_cnt + h->dense_carry) + 5.0 * (double)m +
-                        8.0 * (double)h->dense_edges;
+      if (two)
+        st->two_phase_bytes += 22.0 * (double)m + 65.0 * n + 8.0 * (double)(h->dense_cnt + h->dense_carry) +
+                               4.0 * (double)g->tp->n1 * g->tp->nB;
+      else
+        st->pull_bytes += 24.0 * n + 8.0 * (double)(h->dense_cnt + h->dense_carry) + 5.0 * (double)m +
+                          8.0 * (double)h->dense_edges;
       st->dense_iterations++;
       if (!async) {
         std::swap(Ra, Rb);
@@ -2034,6 +2097,16 @@ static int run_frontier(dfpr_graph* g, const dfpr_params& p, const double* r_pre
   g->flag_next = next;
   g->xflag = xa;
   g->xflag2 = xb;
+  if (tp_ran) {  // phase one flags contributions outside [0, 2^31)
+    int32_t bad = 0;
+    DFPR_HIP(hipMemcpyAsync(&bad, g->tp->bad.p, sizeof(bad), hipMemcpyDeviceToHost, s));
+    DFPR_HIP(hipStreamSynchronize(s));
+    if (bad) {
+      DFPR_HIP(hipMemsetAsync(g->tp->bad.p, 0, sizeof(bad), s));
+      set_error("two-phase pull: a contribution outside [0, 2^31) (ranks must be non-negative and below 2^31)");
+      return DFPR_EINVAL;
+    }
+  }
   st->iterations = it;
   st->converged = conv ? 1 : 0;
   st->last_delta = dR;
@@ -2085,6 +2158,7 @@ int update_ranks(dfpr_graph* g, dfpr_mode mode, const dfpr_params& p, const doub
     DFPR_TRY(ep.collect(ms, cnt));
     st.ms_total = ms[kTTotal];
     st.ms_pull = ms[kTPull0];
+    st.ms_two_phase = ms[kTPull1];
     st.ms_commit = ms[kTCommit];
     st.ms_bin = ms[kTBin];
     st.ms_mark = ms[kTMark];

@@ -90,7 +90,7 @@ def test_struct_layouts_match_header():
     # field counts and sizes of the ABI structs as declared in include/dfpr.h
     assert ctypes.sizeof(_capi.Params) == 5 * 8 + 4 * 4
     assert ctypes.sizeof(_capi.BatchInfo) == 6 * 8 + 4 * 8 + 2 * 4
-    assert ctypes.sizeof(_capi.Stats) == 4 + 4 + 8 + 3 * 8 + 12 * 8 + 8 + 8 + 4 + 4 + 3 * 8 + 8 + 4 + 4
+    assert ctypes.sizeof(_capi.Stats) == 4 + 4 + 8 + 3 * 8 + 12 * 8 + 8 + 8 + 4 + 4 + 3 * 8 + 8 + 4 + 4 + 8 + 8 + 4 + 4
     assert ctypes.sizeof(_capi.ServerStats) == 5 * 8 + 4 * 4 + 3 * 8
 
 
@@ -115,4 +115,4 @@ def test_per_member_records_and_struct_dicts():
     st.bin_edges[5] = 9
     d = st.as_dict()
     assert d["iterations"] == 7 and d["bin_edges"] == [0, 0, 0, 0, 0, 9]
-    assert "reserved" not in d and "reserved2" not in d
+    assert "reserved" not in d and "reserved2" not in d and "reserved3" not in d

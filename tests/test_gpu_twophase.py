@@ -1,0 +1,138 @@
+"""The two-phase dense pull (dfpr_set_two_phase) against the oracle: ranks
+within L-inf 1e-9 from the same R_prev bits, on graphs that span several
+source blocks (8192 vertices) and destination buckets (4096), with buckets
+split over several workgroups; bit-identical on repeated runs; rebuilt after
+every batch; packed and slack rows; error paths."""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from gpu_common import LINF, Pair, rmat, torch_cuda
+
+pytestmark = pytest.mark.gpu
+INF = float("inf")
+
+
+def _print(*a):
+    print(*a, flush=True)
+
+
+def _setup(scale, frac, seed, **kw):
+    """A graph and one batch; each call of the returned maker gives a fresh
+    pair with the batch applied (an update consumes the batch's marks)."""
+    n, s, d = rmat(scale, seed=seed)
+    batch = W.batch_8020(n, s, d, frac, seed=seed + 100)
+    r0 = None
+
+    def make(two_phase):
+        nonlocal r0
+        p = Pair(n, s, d, **kw)
+        if r0 is None:
+            r0 = O.rank("static", p.og).ranks
+        p.apply(*batch)
+        if two_phase:
+            p.g.set_two_phase(True)
+        return p
+
+    make(False)
+    return make, r0
+
+
+def _check(st, ref, r, what):
+    err = float(np.abs(r - ref.ranks).max())
+    _print(f"  {what}: linf={err:.3e} it gpu={st['iterations']} oracle={ref.iterations} "
+           f"dense={st['dense_iterations']} ever gpu={st['ever_affected']} oracle={ref.ever_affected}")
+    assert err <= LINF
+    assert st["converged"] == ref.converged == 1
+    assert abs(st["iterations"] - ref.iterations) <= 1
+    return err
+
+
+@pytest.mark.parametrize("mode", ["df", "dfp"])
+@pytest.mark.parametrize("scale,frac", [(11, 1e-2), (15, 1e-3), (16, 1e-2)])
+def test_two_phase_matches_oracle(mode, scale, frac):
+    """Every iteration in the dense form through the two-phase pull; the
+    gather pull on the same input agrees to rounding."""
+    torch_cuda()
+    _print("two-phase", mode, scale, frac)
+    make, r0 = _setup(scale, frac, seed=scale + 7)
+    r_g, st_g, _ = make(False).rank(mode, r0, dense_switch=INF)
+    r, st, ref = make(True).rank(mode, r0, dense_switch=INF)
+    _check(st, ref, r, "two-phase")
+    assert st["dense_iterations"] == st["iterations"] and st["two_phase_passes"] == st["iterations"]
+    diff = float(np.abs(r - r_g).max())
+    _print(f"  vs gather pull: {diff:.3e}, iterations {st['iterations']} / {st_g['iterations']}")
+    assert diff <= LINF
+
+
+def test_two_phase_bit_identical_runs():
+    """Integer sums do not depend on which workgroup adds first."""
+    torch_cuda()
+    make, r0 = _setup(15, 1e-2, seed=31)
+    r1, st1, _ = make(True).rank("dfp", r0, dense_switch=INF)
+    r2, st2, _ = make(True).rank("dfp", r0, dense_switch=INF)
+    assert np.array_equal(r1, r2)
+    assert st1["iterations"] == st2["iterations"] and st1["ever_affected"] == st2["ever_affected"]
+
+
+@pytest.mark.parametrize("slack", [0, 2])
+def test_two_phase_chained_batches(slack):
+    """Chained batches: the layout is rebuilt from the new in-CSR after each
+    apply (packed rows and rows with free slots); the default switch mixes
+    frontier-form (gather) and dense-form (two-phase) iterations."""
+    torch_cuda()
+    n, s, d = rmat(15, seed=41)
+    for sw in (INF, 1.0):
+        p = Pair(n, s, d, row_slack=slack)
+        p.g.set_two_phase(True)
+        r = O.rank("static", p.og).ranks
+        es, ed = s, d
+        for step, frac in enumerate((1e-2, 1e-4, 3e-2)):
+            ds, dd, is_, id_ = W.batch_8020(n, es, ed, frac, seed=500 + step)
+            p.apply(ds, dd, is_, id_)
+            es, ed = p.og.esrc, p.og.edst
+            rg, st, ref = p.rank("dfp", r, dense_switch=sw)
+            _check(st, ref, rg, f"step {step} f={frac} switch={sw}")
+            r = ref.ranks
+
+
+def test_two_phase_hub_split_buckets():
+    """One destination with ~150 K in-edges: its bucket is split over several
+    phase-two workgroups that combine through 128-bit atomic adds."""
+    torch_cuda()
+    from gpu_common import hub_graph
+    n, s, d = hub_graph(200000, 150000, 2000, 600000, seed=5)
+    batch = W.batch_8020(n, s, d, 1e-2, seed=77)
+    r0 = None
+    for mode in ("df", "dfp"):
+        p = Pair(n, s, d)
+        if r0 is None:
+            r0 = O.rank("static", p.og).ranks
+        p.apply(*batch)
+        p.g.set_two_phase(True)
+        r, st, ref = p.rank(mode, r0, dense_switch=INF)
+        _check(st, ref, r, mode)
+
+
+def test_two_phase_errors_and_recovery():
+    """Batch handles are refused; an update whose ranks leave [0, 2^31) is
+    reported, and the graph still updates correctly afterwards."""
+    torch = torch_cuda()
+    from gpu_common import dfpr
+    m = dfpr()
+    n, s, d = rmat(10, seed=3)
+    bg = m.BatchGraph.from_coo([(n, s, d), (n, s, d)])
+    with pytest.raises(m.DfprError):
+        bg.set_two_phase(True)
+    bg.close()
+    make, r0 = _setup(12, 1e-2, seed=9)
+    p = make(True)
+    bad = torch.from_numpy(-np.ascontiguousarray(r0)).cuda()
+    with pytest.raises(m.DfprError):
+        p.g.update_ranks("dfp", bad, dense_switch=INF)
+    # the refused update used up the batch's marks: the next batch is checked
+    es, ed = p.og.esrc, p.og.edst
+    p.apply(*W.batch_8020(p.n, es, ed, 1e-2, seed=10))
+    r, st, ref = p.rank("dfp", r0, dense_switch=INF)
+    _check(st, ref, r, "after the refused update")

@@ -287,7 +287,9 @@ int dfpr_set_row_slack(dfpr_graph* g, int32_t slack, void* stream);
  * pull and the rebuild adds to every batch, so the gather pull stays the
  * default.  Frontier-form iterations, the single-launch loop (dfpr_set_fused_limit)
  * and the asynchronous mode keep the gather pull.  Contributions must lie in
- * [0, 2^31): an update whose ranks leave that range fails with EINVAL.
+ * [0, 2^31) and in-neighbour sums below 2^32 (any rank vector with entries
+ * in [0, 1] qualifies): an update with a contribution outside [0, 2^31) fails
+ * with EINVAL.
  * Errors: EINVAL (batch handle, or more than 2^25 vertices). */
 int dfpr_set_two_phase(dfpr_graph* g, int on);
 

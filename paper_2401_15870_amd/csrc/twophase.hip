@@ -6,15 +6,18 @@
 // source block (8192 sources, whose contributions sit in LDS) and writes each
 // edge's contribution into a value array ordered by destination bucket (4096
 // destinations); phase two streams every bucket once and adds its values
-// into LDS accumulators.  Both phases read and write only streams and LDS.
+// into LDS accumulators.  Global memory is touched in streams and in the
+// contiguous runs of each (source block, bucket) pair; the random accesses
+// are in LDS.
 //
 // Sums are formed exactly: each contribution is taken on a grid of 2^-96
 // (exactly, for contributions of at least 2^-44) as a 128-bit integer and the
 // integers are added, so the sum does not depend on the order of the
 // additions; the total is rounded to FP64 once.  A bucket split over several
 // workgroups is combined with 64-bit atomics whose returned old value
-// carries into the high word.  Contributions must lie in [0, 2^31) (ranks of
-// a probability vector always do); others are reported.
+// carries into the high word.  Contributions must lie in [0, 2^31) and each
+// vertex's sum below 2^32 (ranks of a probability vector always do); a
+// contribution outside the range is reported.
 //
 // Layout (rebuilt from the in-CSR whenever the graph changed):
 //   pair (S, b): the edges from source block S into destination bucket b;

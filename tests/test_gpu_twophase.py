@@ -136,3 +136,31 @@ def test_two_phase_errors_and_recovery():
     p.apply(*W.batch_8020(p.n, es, ed, 1e-2, seed=10))
     r, st, ref = p.rank("dfp", r0, dense_switch=INF)
     _check(st, ref, r, "after the refused update")
+
+
+@pytest.mark.parametrize("mode", ["df", "dfp"])
+def test_two_phase_sums_are_correctly_rounded(mode):
+    """One dense iteration: every processed vertex's rank equals Equation 1
+    (DF) or 2 (DF-P) evaluated on the correctly rounded exact sum of its
+    in-neighbours' FP64 contributions (math.fsum), bit for bit; the other
+    vertices keep R_prev.  (All contributions here exceed 2^-44, where the
+    2^-96 grid is exact.)"""
+    import math
+    torch_cuda()
+    make, r0 = _setup(12, 1e-2, seed=61)
+    p = make(True)
+    r, st, ref = p.rank(mode, r0, dense_switch=INF, max_iters=1)
+    assert st["iterations"] == 1 and st["two_phase_passes"] == 1
+    og, n, alpha = p.og, p.n, 0.85
+    deg = np.diff(og.out_off).astype(np.float64)
+    contrib = r0 / deg
+    assert contrib.min() > 2.0 ** -44
+    c0 = (1.0 - alpha) / n
+    done = np.flatnonzero(ref.ranks != r0)  # the oracle's processed vertices
+    assert np.array_equal(np.flatnonzero(r != r0), done)
+    for v in done:
+        c = math.fsum(contrib[og.in_idx[og.in_off[v]:og.in_off[v + 1]]].tolist())
+        d, rv = float(deg[v]), float(r0[v])
+        want = (1.0 / (1.0 - alpha / d)) * (c0 + alpha * (c - rv / d)) if mode == "dfp" else c0 + alpha * c
+        assert r[v] == want, (int(v), float(r[v]), want)
+    _print(f"  {mode}: {len(done)} processed vertices, every rank from the correctly rounded sum")

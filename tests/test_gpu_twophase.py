@@ -164,3 +164,23 @@ def test_two_phase_sums_are_correctly_rounded(mode):
         want = (1.0 / (1.0 - alpha / d)) * (c0 + alpha * (c - rv / d)) if mode == "dfp" else c0 + alpha * c
         assert r[v] == want, (int(v), float(r[v]), want)
     _print(f"  {mode}: {len(done)} processed vertices, every rank from the correctly rounded sum")
+
+
+def test_two_phase_more_than_4096_buckets():
+    """Just over 2^24 vertices (4098 buckets of 4096): phase one keeps the
+    larger table of pair offsets in LDS.  Few edges, so the oracle stays quick."""
+    torch_cuda()
+    n = (1 << 24) + 5000
+    rng = np.random.default_rng(71)
+    m = 3_000_000
+    s = rng.integers(0, n, m).astype(np.int32)
+    d = rng.integers(0, n, m).astype(np.int32)
+    d[: m // 20] = 7  # a hub destination
+    batch = W.batch_8020(n, s, d, 1e-3, seed=72)
+    p = Pair(n, s, d)
+    r0 = O.rank("static", p.og).ranks
+    p.apply(*batch)
+    p.g.set_two_phase(True)
+    r, st, ref = p.rank("dfp", r0, dense_switch=INF)
+    _check(st, ref, r, "n > 2^24")
+    assert st["two_phase_passes"] == st["iterations"]

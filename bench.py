@@ -812,7 +812,7 @@ def main():
                     help="rmat/temporal: dense-form DF/DF-P iterations through the two-phase pull (dfpr_set_two_phase)")
     ap.add_argument("--fused-limit", type=int, default=None,
                     help="edge count up to which a rank update runs in one cooperative launch (library default)")
-    ap.add_argument("--bounds", default=None, help="temporal: in-degree bin thresholds a,b,c,d,e instead of autotuning")
+    ap.add_argument("--bounds", default=None, help="rmat, temporal: in-degree bin thresholds a,b,c,d,e instead of autotuning")
     ap.add_argument("--static-runs", type=int, default=3)
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--calib", action="store_true",
@@ -891,7 +891,10 @@ def main():
     torch.cuda.synchronize()
     log(f"create: m={m0} row slack {args.row_slack} {time.time() - t0:.2f}s")
     dev_batches = [tuple(torch.from_numpy(a).to(dev) for a in b) for b in batches]
-    if not args.no_autotune:
+    if args.bounds:
+        g.set_tuning([int(x) for x in args.bounds.split(",")])
+        log(f"bounds: {g.get_tuning()}")
+    elif not args.no_autotune:
         t0 = time.time()
         bounds, tune_ms = g.autotune()
         log(f"autotune: bounds {bounds} pull {tune_ms:.3f} ms ({time.time() - t0:.1f}s)")

@@ -91,18 +91,20 @@ __global__ void __launch_bounds__(kScanBlock) k_scan_apply(Load ld, Store st, in
 template <class Store>
 __global__ void k_scan_empty(Store st) { st(0, 0); }
 
-// The whole scan in one workgroup when the input fits one tile (small
-// batches, short bin tables): one launch instead of three.
-template <class Load, class Store>
-__global__ void __launch_bounds__(kScanBlock) k_scan_one_tile(Load ld, Store st, int64_t n) {
-  __shared__ int64_t tile[kScanTile];
-  __shared__ int64_t sh[kScanBlock / kWave + 1];
+// The whole scan in one workgroup of B threads (small batches, short bin
+// tables): one launch instead of three.  With B = 1024 a tile holds 8192
+// elements, so every input scan_generic sends here is one tile.
+template <class Load, class Store, int B = kScanBlock>
+__global__ void __launch_bounds__(B) k_scan_one_tile(Load ld, Store st, int64_t n) {
+  constexpr int kTile = B * kScanItems;
+  __shared__ int64_t tile[kTile];
+  __shared__ int64_t sh[B / kWave + 1];
   int64_t carry = 0;  // total of the tiles before
-  for (int64_t base = 0; base < n; base += kScanTile) {
+  for (int64_t base = 0; base < n; base += kTile) {
 #pragma unroll
     for (int j = 0; j < kScanItems; j++) {
-      const int64_t i = base + j * kScanBlock + threadIdx.x;
-      tile[j * kScanBlock + threadIdx.x] = (i < n) ? ld(i) : 0;
+      const int64_t i = base + j * B + threadIdx.x;
+      tile[j * B + threadIdx.x] = (i < n) ? ld(i) : 0;
     }
     __syncthreads();
     int64_t v[kScanItems];
@@ -125,8 +127,8 @@ __global__ void __launch_bounds__(kScanBlock) k_scan_one_tile(Load ld, Store st,
 }
 
 // Exclusive scan of ld(0..n) into st(0..n) (st(n, total) included).  Up to
-// kScanFewTiles tiles: one workgroup, tile after tile (one launch instead of
-// three).
+// kScanFewTiles tiles of 2048: one workgroup of 1024 threads (one launch
+// instead of three).
 constexpr int64_t kScanFewTiles = 4;
 template <class Load, class Store>
 int scan_generic(Load ld, Store st, int64_t n, int64_t* tmp, hipStream_t s) {
@@ -136,7 +138,7 @@ int scan_generic(Load ld, Store st, int64_t n, int64_t* tmp, hipStream_t s) {
     return hipGetLastError() == hipSuccess ? DFPR_OK : DFPR_EHIP;
   }
   if (nb <= kScanFewTiles) {
-    k_scan_one_tile<<<1, kScanBlock, 0, s>>>(ld, st, n);
+    k_scan_one_tile<Load, Store, 1024><<<1, 1024, 0, s>>>(ld, st, n);
     return hipGetLastError() == hipSuccess ? DFPR_OK : DFPR_EHIP;
   }
   k_scan_reduce<<<(unsigned)nb, kScanBlock, 0, s>>>(ld, n, tmp);

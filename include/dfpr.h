@@ -237,10 +237,14 @@ int dfpr_get_tuning(const dfpr_graph* g, int32_t bounds[5]);
 
 /* Autotuner: choose the in-degree thresholds of the pull kernel for this
  * graph by timing a few Static iterations (HIP events) for each candidate, one
- * threshold at a time (coordinate descent from the current setting).  The
- * best setting is installed and written to bounds_out (nullable); ms_out
- * (nullable) receives the best average pull time.  Uses temporary device
- * memory for one rank vector; pending batch marks are left untouched. */
+ * threshold at a time (coordinate descent from the current setting; a change
+ * must win by 3 %).  On a plain graph each candidate's time also includes a
+ * pull over the rows of more than 128 in-edges alone, the part of the graph
+ * a hub-heavy DF/DF-P frontier keeps pulling, where long rows cannot hide
+ * behind other work.  The best setting is installed and written to
+ * bounds_out (nullable); ms_out (nullable) receives its average Static pull
+ * time.  Uses temporary device memory for one rank vector (and n bytes of
+ * flags); pending batch marks are left untouched. */
 int dfpr_autotune(dfpr_graph* g, void* stream, int32_t bounds_out[5], double* ms_out);
 
 /* Graphs of at most max_edges edges (self-loops included) run a whole rank

@@ -2234,12 +2234,82 @@ static int time_pull(dfpr_graph* g, double* r, hipStream_t s, double* ms) {
   return DFPR_OK;
 }
 
+// Rows of more than `t` in-edges: the tuner's stand-in for a frontier that
+// keeps a graph's hubs (on hub-heavy graphs a DF-P frontier is mostly these
+// rows plus short ones, and its pull is set by how the long rows are split).
+__global__ void k_flag_long_rows(const int32_t* __restrict__ in_deg, int32_t n, int32_t t, uint8_t* flags) {
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+    flags[v] = in_deg[v] > t ? 1 : 0;
+}
+
+// Pull launch over the flagged rows alone (Equation 1 into the scratch
+// vectors): the minimum launch time over repeats, then the change slots
+// folded and cleared as after any iteration.
+static int time_pull_rows(dfpr_graph* g, double* r, const uint8_t* flags, hipStream_t s, double* ms) {
+  DFPR_TRY(bin_vertices(g, flags, g->worklist, nullptr, s));
+  DFPR_TRY(finish_and_read(g, s));
+  int64_t be[kBins], bedges[kBins];
+  std::copy(g->ctl_host->bin_end, g->ctl_host->bin_end + kBins, be);
+  std::copy(g->ctl_host->bin_edges, g->ctl_host->bin_edges + kBins, bedges);
+  *ms = 0.0;
+  if (be[kBins - 1] == 0) return DFPR_OK;
+  dfpr_params p;
+  p.alpha = 0.85;
+  p.tol = 1e-300;
+  p.frontier_tol = p.prune_tol = 1e-6;
+  p.dense_switch = 0.4;
+  p.max_iters = 1;
+  p.flags = 0;
+  p.criterion = DFPR_CRIT_RELATIVE;
+  p.reserved = 0;
+  PullArgs a = make_args(g, p);
+  a.R = r;
+  a.Rw = g->rn;
+  a.contrib = g->contrib;
+  a.cw = g->contrib2;
+  hipEvent_t e0, e1;
+  DFPR_HIP(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return DFPR_EHIP;
+  }
+  dfpr_stats st{};
+  double best = 0.0, timed = 0.0;
+  int rc = DFPR_OK;
+  for (int rep = 0; rep < 32 && rc == DFPR_OK && (rep < 3 || timed < 2.0); rep++) {
+    float t = 0.0f;
+    if (hipEventRecord(e0, s) != hipSuccess) rc = DFPR_EHIP;
+    if (rc == DFPR_OK) rc = pull_all<kSync, false>(g, a, g->worklist, be, bedges, g->chunk_pre, rep > 0, s, &st);
+    if (rc == DFPR_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                          hipEventElapsedTime(&t, e0, e1) != hipSuccess))
+      rc = DFPR_EHIP;
+    best = rep == 0 ? t : std::min(best, (double)t);
+    timed += t;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc == DFPR_OK) rc = finish_and_read(g, s, &p, 0);
+  *ms = best;
+  return rc;
+}
+
 int autotune(dfpr_graph* g, hipStream_t s, int32_t* bounds_out, double* ms_out) {
   double* r = nullptr;
-  if (hipMalloc((void**)&r, (size_t)g->n * sizeof(double)) != hipSuccess) {
+  uint8_t* longf = nullptr;  // rows of more than 128 in-edges (plain graphs)
+  if (hipMalloc((void**)&r, (size_t)g->n * sizeof(double)) != hipSuccess ||
+      (g->ngraphs == 1 && hipMalloc((void**)&longf, (size_t)g->n) != hipSuccess)) {
     (void)hipGetLastError();
+    if (r) (void)hipFree(r);
     set_error("autotune: device allocation failed");
     return DFPR_ENOMEM;
+  }
+  if (longf) {
+    k_flag_long_rows<<<grid_for(g->n, 256, 65536), 256, 0, s>>>(g->in_deg, g->n, 128, longf);
+    if (hipGetLastError() != hipSuccess) {
+      (void)hipFree(r);
+      (void)hipFree(longf);
+      return DFPR_EHIP;
+    }
   }
   static const int32_t cand[5][6] = {{2, 4, 8, 16, 0, 0},
                                      {8, 16, 32, 64, 0, 0},
@@ -2248,7 +2318,7 @@ int autotune(dfpr_graph* g, hipStream_t s, int32_t* bounds_out, double* ms_out) 
                                      {4096, 8192, 16384, 32768, 131072, 1 << 20}};
   int32_t best[5];
   std::copy(g->bounds, g->bounds + 5, best);
-  double best_ms = 0.0;
+  double best_ms = 0.0, best_static = 0.0, last_static = 0.0;
   int rc = DFPR_OK;
   auto eval = [&](const int32_t* b, double* ms) {
     const int32_t keep[5] = {g->bounds[0], g->bounds[1], g->bounds[2], g->bounds[3], g->bounds[4]};
@@ -2256,11 +2326,19 @@ int autotune(dfpr_graph* g, hipStream_t s, int32_t* bounds_out, double* ms_out) 
     g->all_bins_valid = false;
     int e = time_pull(g, r, s, ms);  // first call rebuilds the bins
     if (e == DFPR_OK) e = time_pull(g, r, s, ms);
+    // plain graphs: plus the pull over the long rows alone, which the
+    // all-vertex pull hides (its other rows keep the device busy while a
+    // workgroup walks a long row) and a hub-heavy frontier does not
+    double ml = 0.0;
+    if (e == DFPR_OK && longf) e = time_pull_rows(g, r, longf, s, &ml);
+    last_static = *ms;
+    *ms += ml;
     std::copy(keep, keep + 5, g->bounds);
     g->all_bins_valid = false;
     return e;
   };
   rc = eval(best, &best_ms);
+  best_static = last_static;
   for (int pass = 0; pass < 2 && rc == DFPR_OK; pass++) {
     for (int k = 4; k >= 0 && rc == DFPR_OK; k--) {
       for (int c = 0; c < 6 && rc == DFPR_OK; c++) {
@@ -2277,17 +2355,19 @@ int autotune(dfpr_graph* g, hipStream_t s, int32_t* bounds_out, double* ms_out) 
         // a change must win by 3 %: timing noise alone does not move the thresholds
         if (rc == DFPR_OK && ms < 0.97 * best_ms) {
           best_ms = ms;
+          best_static = last_static;
           std::copy(b, b + 5, best);
         }
       }
     }
   }
   (void)hipFree(r);
+  if (longf) (void)hipFree(longf);
   if (rc != DFPR_OK) return rc;
   std::copy(best, best + 5, g->bounds);
   g->all_bins_valid = false;
   if (bounds_out) std::copy(best, best + 5, bounds_out);
-  if (ms_out) *ms_out = best_ms;
+  if (ms_out) *ms_out = best_static;
   return DFPR_OK;
 }
 
